@@ -1,0 +1,172 @@
+/*
+ * subap.h -- C ABI of the MI355X (gfx950) SubApSnap library.
+ *
+ * SubApSnap (Jones & Nakatsukasa, arXiv 2510.04825) solves the family of
+ * linear systems A(p) x(p) = b(p), p in Omega (Section 1, eq. (1.1)), for
+ * many parameters p* by (Algorithm 3.1):
+ *   offline  1. snapshots X = [x(p_1) ... x(p_r)];
+ *            2. orthonormalise X <- Q (Section 3.1, thin QR);
+ *            3. choose s >= r rows S by pivoting on (A(p_sel) X)^T (Section 5.3);
+ *   online   4. for each p*: form S A(p*) X (s x r, eq. (3.4)) from the s
+ *               selected rows only, solve min_c |S A(p*) X c - S b(p*)|
+ *               (eq. (3.3)) and output x = X c.
+ *
+ * The problem is never given as a matrix: the library generates the rows it
+ * needs (Section 3.1, "Computing S A(p*) X") for one of these families:
+ *   SUBAP_FAMILY_DIFF2D   -div(a grad u) = f on (0,1)^2, 5-point finite
+ *                         differences, N x N interior nodes, Dirichlet 0,
+ *                         a = exp(p1 sin 2 pi x + p2 cos 2 pi y), d = 2;
+ *   SUBAP_FAMILY_DIFF3D   same on (0,1)^3, 7-point stencil, d = 4,
+ *                         a = exp(p1 s_x c_y + p2 s_y c_z + p3 s_z c_x + p4 c_x c_y c_z)
+ *                         with s_x = sin 2 pi x, c_x = cos 2 pi x, ...;
+ *   SUBAP_FAMILY_KRR      kernel ridge regression (Section 6.3, eqs.
+ *                         (6.3)-(6.4)): A(p) = K_p + lambda I,
+ *                         K_p[i,j] = exp(-|t_i - t_j|^2 / (2 p^2)), d = 1.
+ * Finite-difference layout: node (ix, iy[, iz]) sits at ((ix+1) h, ...),
+ * h = 1/(N+1), index ix + N iy (+ N^2 iz); the face coefficient is a at
+ * the face midpoint; row i holds sum_f a_f / h^2 on the diagonal and
+ * -a_f / h^2 for each in-domain neighbour.
+ *
+ * Conventions for every entry point
+ *   - Return value: SUBAP_OK or an error code; arguments are validated
+ *     before any device work, and on error nothing has been enqueued.
+ *     subap_last_error() gives a message for the calling thread.
+ *   - "host" pointers are read during the call and may be freed after it.
+ *     "device" pointers are HIP device memory owned by the caller.
+ *   - Device work is enqueued on the given HIP stream (NULL = default
+ *     stream) and is asynchronous unless stated otherwise.  One model must
+ *     not be used by two streams at once.
+ *   - Matrices are FP64 unless stated; "col-major n x r" means element
+ *     (i, c) at [i + n c]; "row-major m x d" means (k, q) at [k d + q].
+ *   - The library never prints and never aborts.
+ */
+#ifndef SUBAP_H
+#define SUBAP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SUBAP_OK = 0,
+  SUBAP_E_INVALID = 1,     /* bad argument (NULL, size, range)               */
+  SUBAP_E_NOMEM = 2,       /* device or host allocation failed               */
+  SUBAP_E_HIP = 3,         /* a HIP runtime call failed                      */
+  SUBAP_E_RANK = 4,        /* per-p: S A(p) X numerically rank deficient     */
+  SUBAP_E_NOCONV = 5,      /* snapshot solver did not reach its tolerance    */
+  SUBAP_E_NONFINITE = 6,   /* per-p: non-finite parameter or coefficient     */
+  SUBAP_E_UNSUPPORTED = 7  /* valid request this build does not implement    */
+} subap_status;
+
+typedef enum {
+  SUBAP_FAMILY_DIFF2D = 1,
+  SUBAP_FAMILY_DIFF3D = 2,
+  SUBAP_FAMILY_KRR = 3
+} subap_family;
+
+/* Arithmetic of the bulk contraction S A(p) X.  The least-squares solve is
+ * always FP64 Householder QR. */
+typedef enum {
+  SUBAP_FP64 = 0,    /* FP64 rows, FP64 contraction                           */
+  SUBAP_FP32 = 1,    /* FP32 rows and contraction (FP32 MFMA for KRR)          */
+  SUBAP_BF16X3 = 2   /* KRR only: bf16 hi/lo split operands, three MFMA
+                        products hi*hi + hi*lo + lo*hi, FP32 accumulation     */
+} subap_precision;
+
+typedef struct {
+  int32_t family;          /* subap_family                                   */
+  int32_t grid;            /* DIFF2D/3D: interior nodes per axis N (>= 2)    */
+  int64_t n;               /* KRR: number of points (ignored for DIFF*)       */
+  int32_t dim;             /* KRR: point dimension (1..16)                    */
+  const double* points;    /* KRR: host, n x dim row-major                    */
+  const double* rhs;       /* host, n entries; NULL = all ones (DIFF* only)   */
+  double lambda;           /* KRR ridge parameter (> 0)                       */
+} subap_problem_desc;
+
+typedef struct subap_model_s* subap_model;   /* opaque; owns device buffers */
+
+typedef struct {
+  int32_t r;                   /* snapshots / basis columns (1..64)           */
+  int32_t s;                   /* selected rows, r <= s <= min(n, 256)        */
+  const double* snap_params;   /* host, r x d row-major (ignored with basis_in) */
+  const double* select_param;  /* host, d: p at which rows are selected       */
+  double snap_tol;             /* snapshot solver relative residual; 0 = 1e-12 */
+  int32_t snap_maxiter;        /* snapshot solver iteration cap; 0 = default  */
+  const double* basis_in;      /* optional host n x r col-major: use instead of
+                                  snapshot solves (still orthonormalised)     */
+  const int64_t* rows_in;      /* optional host s row indices: use instead of
+                                  pivoted-QR selection                        */
+} subap_offline_opts;
+
+/*
+ * subap_offline -- Algorithm 3.1 steps 1-3 on the GPU.
+ *   1. Snapshot solves A(p_i) x_i = b(p_i) by conjugate gradients (all
+ *      three families are symmetric positive definite) to relative residual
+ *      snap_tol; the paper allows approximate snapshots (Algorithm 3.1).
+ *   2. Householder QR of X with diag(R) > 0; X <- Q (Section 3.1).
+ *   3. Rows: rounds of column-pivoted QR on M = (A(select_param) Q)^T (r x n),
+ *      each round a fresh pivoted QR over the rows not chosen yet, taking
+ *      min(r, s - chosen) pivots; pivot = smallest index whose residual norm
+ *      is >= (1 - 1e-6) max (Section 5.3 names pivoted QR on (A(p_i) X)^T;
+ *      the round and tie rules are this library's reading for s > r).
+ *   Then builds the per-row tables the online kernels read.
+ * Blocks until the model is complete.  On success *out owns device memory;
+ * release it with subap_model_free.  SUBAP_E_NOCONV if a snapshot solve
+ * stalls (the model is not created).
+ */
+subap_status subap_offline(const subap_problem_desc* problem,
+                           const subap_offline_opts* opts,
+                           void* hip_stream, subap_model* out);
+
+typedef struct {
+  int32_t contraction;   /* subap_precision of S A(p) X                        */
+  int32_t refine_steps;  /* FP64 refinement steps after the solve (0..4): the
+                            residual S(A(p) X y - b) is re-evaluated in FP64
+                            and the correction solved with the same QR        */
+} subap_solve_opts;
+
+/*
+ * subap_solve_batch -- Algorithm 3.1 step 4 for m parameters.
+ *   params_dev  device, m x d row-major FP64 parameters p*;
+ *   y_dev       device, m x r row-major FP64 output coefficients c(p*)
+ *               in the orthonormal basis Q (x = Q c);
+ *   rho_dev     device or NULL, m: sketched relative residual
+ *               |S(A(p) Q y - b)|_2 / |S b|_2 in FP64 after the last step;
+ *   status_dev  device or NULL, m int32: SUBAP_OK, SUBAP_E_RANK (some
+ *               |R_jj| <= 1e-13 |R_11| in the QR of S A(p) Q; y is NaN) or
+ *               SUBAP_E_NONFINITE (non-finite p or coefficient; y is NaN).
+ *   opts        host or NULL (= FP64, no refinement).
+ * m = 0 is a no-op.  Asynchronous on hip_stream.
+ */
+subap_status subap_solve_batch(subap_model model, const double* params_dev, int64_t m,
+                               double* y_dev, double* rho_dev, int32_t* status_dev,
+                               const subap_solve_opts* opts, void* hip_stream);
+
+/*
+ * subap_lift -- x = Q y (Algorithm 3.1 step 4, output X c) for k coefficient
+ * vectors.  y_dev: device k x r row-major FP64.  x_dev: device n x k
+ * col-major, FP64 (precision = SUBAP_FP64) or FP32 (SUBAP_FP32).
+ */
+subap_status subap_lift(subap_model model, const double* y_dev, int64_t k,
+                        void* x_dev, int32_t precision, void* hip_stream);
+
+/* Model queries (blocking, host outputs). */
+subap_status subap_model_dims(subap_model model, int64_t* n, int32_t* r,
+                              int32_t* s, int32_t* d);
+/* rows_host: s indices in selection order. */
+subap_status subap_model_rows(subap_model model, int64_t* rows_host);
+/* Q_host: n x r col-major orthonormal basis. */
+subap_status subap_model_basis(subap_model model, double* Q_host);
+
+subap_status subap_model_free(subap_model model);
+
+const char* subap_status_string(subap_status status);
+/* Message of the last failing call on this thread ("" if none). */
+const char* subap_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SUBAP_H */

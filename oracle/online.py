@@ -1,0 +1,87 @@
+"""Online phase of SubApSnap (Algorithm 3.1, step 4), FP64 CPU oracle.
+
+Test infrastructure only (see the package docstring).
+
+For each new parameter p*:
+
+1. generate the selected rows S A(p*) and entries S b(p*) (Section 3.1:
+   only s rows of A and s entries of b are needed);
+2. form the s x r matrix S A(p*) X (eq. (3.4));
+3. solve min_c |S A(p*) X c - S b(p*)| (eq. (3.3)) by Householder QR
+   (numpy.linalg.qr, LAPACK dgeqrf) and back substitution;
+4. lift x = X c.
+
+Also: ApSnap, the full-sampling problem of eq. (3.1); the paper's relative
+residual |A(p) x - b(p)| / |b(p)|; the sketched residual
+|S(A(p) X y - b)| / |S b|; and delta_res(p) = |A(p) X (y1 - y2)| / |b(p)|,
+the residual-norm distance between two coefficient vectors that the GPU
+parity tests use.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+
+def reduced_matrix(family, Q, rows, p):
+    """S A(p) Q (s x r): the selected rows of A(p), times Q (eq. (3.4))."""
+    A_S = family.rows(p, rows)
+    return np.asarray(A_S @ Q)
+
+
+def householder_lsq(G, b):
+    """argmin_y |G y - b| by thin Householder QR; returns (y, R, rho).
+
+    rho = |G y - b| is the least-squares residual norm.
+    """
+    Qg, Rg = np.linalg.qr(G, mode="reduced")
+    y = sla.solve_triangular(Rg, Qg.T @ b, lower=False)
+    rho = float(np.linalg.norm(G @ y - b))
+    return y, Rg, rho
+
+
+def solve_one(family, Q, rows, p):
+    """SubApSnap coefficients y(p) for one parameter (eq. (3.3))."""
+    G = reduced_matrix(family, Q, rows, p)
+    bS = family.rhs_rows(p, rows)
+    y, _, _ = householder_lsq(G, bS)
+    return y
+
+
+def solve(family, Q, rows, params):
+    """y for every parameter row of ``params`` (m x d) -> (m x r)."""
+    P = np.atleast_2d(np.asarray(params, dtype=np.float64))
+    return np.stack([solve_one(family, Q, rows, p) for p in P])
+
+
+def lift(Q, y):
+    """x = Q y (n,) or Q Y^T for a batch y (m x r) -> (n x m)."""
+    y = np.asarray(y, dtype=np.float64)
+    return Q @ (y if y.ndim == 1 else y.T)
+
+
+def apsnap_solve(family, Q, p):
+    """ApSnap (eq. (3.1)): argmin_c |A(p) Q c - b(p)| over all n rows."""
+    B = np.asarray(family.matvec(p, Q))
+    c, *_ = np.linalg.lstsq(B, family.rhs(p), rcond=None)
+    return c
+
+
+def residual(family, x, p):
+    """|A(p) x - b(p)|_2 / |b(p)|_2 (the measure of Tables 3-4)."""
+    b = family.rhs(p)
+    return float(np.linalg.norm(family.matvec(p, x) - b) / np.linalg.norm(b))
+
+
+def delta_res(family, Q, p, y1, y2):
+    """|A(p) Q (y1 - y2)|_2 / |b(p)|_2."""
+    dy = np.asarray(y1, dtype=np.float64) - np.asarray(y2, dtype=np.float64)
+    b = family.rhs(p)
+    return float(np.linalg.norm(family.matvec(p, Q @ dy)) / np.linalg.norm(b))
+
+
+def sketched_residual(family, Q, rows, p, y):
+    """|S(A(p) Q y - b(p))|_2 / |S b(p)|_2, from the s selected rows only."""
+    A_S = family.rows(p, rows)
+    bS = family.rhs_rows(p, rows)
+    return float(np.linalg.norm(A_S @ (Q @ np.asarray(y)) - bS) / np.linalg.norm(bS))

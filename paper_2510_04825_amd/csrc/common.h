@@ -1,0 +1,103 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "subap.h"
+
+namespace subap {
+
+void set_error(const std::string& msg);
+void clear_error();
+
+#define SUBAP_HIP_TRY(expr)                                                        \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      subap::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));       \
+      return SUBAP_E_HIP;                                                          \
+    }                                                                              \
+  } while (0)
+
+#define SUBAP_TRY(expr)                 \
+  do {                                  \
+    subap_status s_ = (expr);           \
+    if (s_ != SUBAP_OK) return s_;      \
+  } while (0)
+
+constexpr int kMaxR = 64;
+constexpr int kMaxS = 256;
+constexpr double kRankTol = 1e-13;   // |R_jj| <= kRankTol |R_11| -> rank deficient
+constexpr double kTieRtol = 1e-6;    // pivot tie window
+
+// Device allocation with the library's error convention.
+subap_status dmalloc(void** p, size_t bytes);
+template <class T>
+subap_status dalloc(T** p, size_t count) {
+  return dmalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+}
+void dfree(void* p);
+
+}  // namespace subap
+
+// The opaque model.  All device pointers are owned by the model.
+struct subap_model_s {
+  int family = 0;
+  int N = 0;          // FD: nodes per axis
+  int dimx = 0;       // FD: spatial dimension (2/3); KRR: point dimension
+  int64_t n = 0;
+  int r = 0, s = 0, d = 0;
+  int F = 0;          // FD: faces per row (2 * dimx)
+  double h = 0.0, inv_h2 = 0.0;
+  double lambda = 0.0;
+  double bS_norm = 0.0;               // |S b|_2 (b is p-independent in every family)
+  std::vector<int64_t> rows;          // host copy, selection order
+
+  // basis and selection (device)
+  double* Q = nullptr;                // n x r col-major, orthonormal
+  int* rows_d = nullptr;              // s
+  double* bS = nullptr;               // s
+  double* QS = nullptr;               // s x r row-major: Q[rows[k], c]
+  double* rhs = nullptr;              // n (device copy of b)
+
+  // finite-difference tables, layouts [(f * r + c) * s + k] and [(f * d + q) * s + k]
+  double* phi = nullptr;              // s x F x d  mode values at face midpoints
+  double* delta64 = nullptr;          // s x F x r  Q[i_k] - Q[nb_f(i_k)] (0 outside)
+  float* delta32 = nullptr;
+
+  // kernel ridge regression tables
+  double* points = nullptr;           // n x dimx row-major
+  double* Dt64 = nullptr;             // n x s: |t_j - t_{i_k}|^2 at [j * s + k]
+  float* D32 = nullptr;               // s x n: same, FP32, at [k * n + j]
+  double* Qrm = nullptr;              // n x r row-major FP64 copy of Q
+  float* Q32 = nullptr;               // n x r col-major FP32
+  uint16_t* Qhi = nullptr;            // n x r col-major bf16 (round to nearest even)
+  uint16_t* Qlo = nullptr;            // bf16(Q32 - hi)
+
+  // online workspaces (grown on demand)
+  void* work = nullptr;
+  size_t work_bytes = 0;
+};
+
+namespace subap {
+
+// ---- offline (offline.hip) ----
+subap_status offline_build(const subap_problem_desc* pd, const subap_offline_opts* o,
+                           hipStream_t st, subap_model_s* M);
+subap_status build_tables(subap_model_s* M, hipStream_t st);
+
+// ---- online ----
+subap_status fd_solve(subap_model_s* M, const double* params, int64_t m, double* y,
+                      double* rho, int32_t* status, int prec, int refine, hipStream_t st);
+subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double* y,
+                       double* rho, int32_t* status, int prec, int refine, hipStream_t st);
+subap_status lift(subap_model_s* M, const double* y, int64_t k, void* x, int prec,
+                  hipStream_t st);
+
+subap_status ensure_work(subap_model_s* M, size_t bytes);
+
+}  // namespace subap

@@ -1,0 +1,167 @@
+// Team-level FP64 Householder least squares for the s x r problem of
+// eq. (3.3): min_y |G y - b|, G = S A(p) Q.
+//
+// A "team" is TEAM consecutive lanes of one wavefront (TEAM in {16, 32, 64});
+// one team owns one parameter p.  Lane t of the team holds rows
+// i = t + TEAM * q, q = 0..R-1, of G and b in registers (rows >= s are zero).
+// Column loops are unrolled up to RM >= r (columns >= r are zero), so every
+// register index is a compile-time constant.  Dot products over rows are
+// team reductions by xor-butterfly shuffles; IEEE addition is commutative,
+// so every lane ends with a bitwise identical sum.
+//
+// Factorisation (LAPACK dgeqr2 convention): step j builds the reflector
+// H_j = I - tau_j v_j v_j^T with v_j = 1 at row j and v_j = 0 above it, so
+// that H_j G[:, j] = beta_j e_j.  Afterwards a[q][c] holds R above and on
+// the diagonal and v below it; tau lives in team-private LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace subap {
+
+template <int TEAM>
+__device__ __forceinline__ double team_sum(double v) {
+#pragma unroll
+  for (int off = TEAM / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, TEAM);
+  return v;
+}
+
+template <int TEAM>
+__device__ __forceinline__ double team_bcast(double v, int src) {
+  return __shfl(v, src, TEAM);
+}
+
+template <int TEAM, int R, int RM>
+struct TeamQR {
+  double a[R][RM];   // rows of G, then R and the reflectors
+  double b[R];       // right-hand side, then Q^T b
+  double r00;        // |R_11|
+  bool full_rank;
+
+  __device__ __forceinline__ int row(int lane, int q) const { return lane + TEAM * q; }
+
+  // Householder QR of a, applied to b at the same time.  tau_s: RM doubles of
+  // team-private LDS.
+  __device__ __forceinline__ void factor(int r, int lane, double* tau_s) {
+    full_rank = true;
+    r00 = 0.0;
+#pragma unroll
+    for (int j = 0; j < RM; ++j) {
+      if (j < r) {
+        constexpr int dummy = 0;
+        (void)dummy;
+        const int qj = j / TEAM, lj = j % TEAM;
+        double ss = 0.0;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const double x = (row(lane, q) > j) ? a[q][j] : 0.0;
+          ss += x * x;
+        }
+        ss = team_sum<TEAM>(ss);
+        const double alpha = team_bcast<TEAM>(a[qj][j], lj);
+        double tau = 0.0, scale = 0.0, beta = alpha;
+        if (ss > 0.0) {
+          const double norm = sqrt(alpha * alpha + ss);
+          beta = (alpha >= 0.0) ? -norm : norm;
+          tau = (beta - alpha) / beta;
+          scale = 1.0 / (alpha - beta);
+        }
+        double v[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const int i = row(lane, q);
+          v[q] = (i > j) ? a[q][j] * scale : (i == j ? 1.0 : 0.0);
+        }
+        // w_c = v^T a[:, c] for the trailing columns and for b
+        double w[RM + 1];
+#pragma unroll
+        for (int c = 0; c <= RM; ++c) {
+          w[c] = 0.0;
+          if (c > j) {
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < R; ++q) t += v[q] * (c < RM ? a[q][c] : b[q]);
+            w[c] = t;
+          }
+        }
+#pragma unroll
+        for (int off = TEAM / 2; off > 0; off >>= 1) {
+#pragma unroll
+          for (int c = 0; c <= RM; ++c)
+            if (c > j) w[c] += __shfl_xor(w[c], off, TEAM);
+        }
+#pragma unroll
+        for (int c = 0; c <= RM; ++c) {
+          if (c > j) {
+            const double tw = tau * w[c];
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+              if (c < RM) a[q][c] -= tw * v[q];
+              else b[q] -= tw * v[q];
+            }
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const int i = row(lane, q);
+          if (i == j) a[q][j] = beta;
+          else if (i > j) a[q][j] = v[q];
+        }
+        if (lane == 0) tau_s[j] = tau;
+        const double ab = fabs(beta);
+        if (j == 0) r00 = ab;
+        if (!(ab > kRankTol * r00)) full_rank = false;
+      }
+    }
+  }
+
+  // x <- Q^T x using the stored reflectors (x distributed like b).
+  __device__ __forceinline__ void apply_qt(double (&x)[R], int r, int lane, const double* tau_s) const {
+#pragma unroll
+    for (int j = 0; j < RM; ++j) {
+      if (j < r) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const int i = row(lane, q);
+          const double v = (i > j) ? a[q][j] : (i == j ? 1.0 : 0.0);
+          t += v * x[q];
+        }
+        t = team_sum<TEAM>(t) * tau_s[j];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const int i = row(lane, q);
+          const double v = (i > j) ? a[q][j] : (i == j ? 1.0 : 0.0);
+          x[q] -= t * v;
+        }
+      }
+    }
+  }
+
+  // Solve R y = x[0:r] (x distributed like b, already multiplied by Q^T).
+  // y_s: RM doubles of team-private LDS receiving y (every lane may read it
+  // after the call; the team is one wavefront or part of one).
+  __device__ __forceinline__ void back_substitute(double (&x)[R], int r, int lane, double* y_s) const {
+#pragma unroll
+    for (int c = RM - 1; c >= 0; --c) {
+      if (c < r) {
+        const int qc = c / TEAM, lc = c % TEAM;
+        const double yc = team_bcast<TEAM>(x[qc], lc) / team_bcast<TEAM>(a[qc][c], lc);
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+          if (row(lane, q) < c) x[q] -= a[q][c] * yc;
+        if (lane == 0) y_s[c] = yc;
+      }
+    }
+  }
+
+  // |x[r:s]|_2 for x distributed like b (x = Q^T b gives the LSQ residual).
+  __device__ __forceinline__ double tail_norm(const double (&x)[R], int r, int lane) const {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) t += (row(lane, q) >= r) ? x[q] * x[q] : 0.0;
+    return sqrt(team_sum<TEAM>(t));
+  }
+};
+
+}  // namespace subap
