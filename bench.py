@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Online-solve throughput of SubApSnap on one MI355X.
+
+Workload: kernel ridge regression A(p) = K_p + lambda I with a Gaussian
+kernel of length scale p (the paper's Section 6.3 problem class), n = 16384
+points in R^8 from a seeded 8-component Gaussian mixture, r = 32 snapshots,
+s = 128 selected rows, a batch of 4096 parameters p* log-uniform in [0.5, 2],
+lambda = 1e-2.  All inputs are synthetic and seeded (subap_inputs.krr).
+
+A step is one call of subap_solve_batch on the resident batch: kernel rows
+generated on the fly and contracted with Q (split-bf16 MFMA, FP32
+accumulation), FP64 Householder least squares, and one FP64 refinement step.
+A solve counts toward the metric when its status is OK and its sketched
+distance |S A(p) Q (y - y_fp64)| / |S b| to the FP64 plain solve is <= 1e-6
+(both residual vectors come from subap_sketched_residual, with FP64-accurate
+kernel entries).  The plain per-parameter FP64 solve (one call per p) and the
+other batched forms are timed on the same inputs.
+
+Prints one JSON line.  --gpus N with N > 1 exits: this benchmark uses one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+TOL = 1e-6
+PEAKS = {  # MI355X published dense peaks
+    "bf16_mfma_tflops": 2500.0,
+    "fp32_mfma_tflops": 157.3,
+    "fp64_tflops": 78.6,
+    "hbm_gbs": 8000.0,
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-sample", type=int, default=256, help="parameters solved one per call")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle timing budget")
+    return ap.parse_args()
+
+
+def timed(fn, steps, stream):
+    import torch
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps
+
+
+def cpu_baseline(w, budget_s):
+    """The FP64 oracle's online solve, timed on this host on a bounded sample."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import families as F
+    from oracle import offline as O
+    from oracle import online as On
+
+    fam = F.from_workload(w)
+    rng = np.random.default_rng(99)
+    Q, _ = O.orthonormalise(rng.standard_normal((w["n"], w["r"])))
+    rows = np.sort(rng.choice(w["n"], size=w["s"], replace=False))
+    P = w["test_params"]
+    On.solve(fam, Q, rows, P[:2])  # warm caches
+    t0 = time.perf_counter()
+    k = 8
+    On.solve(fam, Q, rows, P[:k])
+    dt = time.perf_counter() - t0
+    per = dt / k
+    k2 = int(max(8, min(len(P), budget_s / max(per, 1e-6))))
+    t0 = time.perf_counter()
+    On.solve(fam, Q, rows, P[:k2])
+    dt = time.perf_counter() - t0
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    return {
+        "value": k2 / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+        "sample": (f"{k2} of the {len(P)} parameters at the full sizes (n={w['n']}, r={w['r']}, s={w['s']}): "
+                   "FP64 NumPy row generation, S A(p) Q and Householder least squares per parameter, "
+                   "with a seeded orthonormal basis and seeded rows (the online cost does not depend on "
+                   "their values)"),
+        "seconds": dt,
+    }
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures the single-GPU online solve; multi-GPU runs are not part of this "
+              "benchmark (the batch shards over parameters with no exchange).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import subap_inputs as si
+    from paper_2510_04825_amd import binding as B
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    w = si.krr()
+    m, n, r, s = w["m"], w["n"], w["r"], w["s"]
+
+    t0 = time.perf_counter()
+    M = B.Model(w, snap_tol=1e-10)
+    torch.cuda.synchronize()
+    offline_s = time.perf_counter() - t0
+
+    P = torch.tensor(w["test_params"], dtype=torch.float64, device=dev)
+    y = torch.empty((m, r), dtype=torch.float64, device=dev)
+    rho = torch.empty(m, dtype=torch.float64, device=dev)
+    st = torch.empty(m, dtype=torch.int32, device=dev)
+
+    def solve(prec, refine, out=y):
+        B.subap_solve_batch(M.handle, P, out, rho, st, prec, refine, stream)
+
+    # reference FP64 plain batched solution and validity of the headline form
+    y64 = torch.empty_like(y)
+    solve(B.FP64, 0, y64)
+    res64, nrm64 = M.sketched_residual(P, y64, vector=True)
+    solve(B.BF16X3, 1)
+    torch.cuda.synchronize()
+    resb, _ = M.sketched_residual(P, y, vector=True)
+    status_ok = (st == 0)
+    bS_norm = float(torch.median(torch.linalg.norm(res64, dim=1) / nrm64))
+    dist = torch.linalg.norm(resb - res64, dim=1) / bS_norm
+    valid = status_ok & (dist <= TOL)
+    n_valid = int(valid.sum())
+
+    # headline timing, per-kernel HIP-event profile over the same region
+    for _ in range(args.warmup):
+        solve(B.BF16X3, 1)
+    B.subap_profile_reset()
+    B.subap_profile_enable(True)
+    ms = timed(lambda: solve(B.BF16X3, 1), args.steps, stream)
+    B.subap_profile_enable(False)
+    prof = B.subap_profile_read()
+
+    # other forms on the same inputs
+    forms = {}
+    for name, prec, ref in (("fp64_batched", B.FP64, 0), ("fp32_refine1", B.FP32, 1),
+                            ("bf16x3_norefine", B.BF16X3, 0), ("bf16x3_refine1", B.BF16X3, 1)):
+        solve(prec, ref)
+        t = ms if name == "bf16x3_refine1" else timed(lambda: solve(prec, ref), 3, stream)
+        forms[name] = {"ms_per_batch": t, "solves_per_s": m / (t / 1e3)}
+    # plain per-parameter FP64 solve: one library call per p
+    k = min(args.plain_sample, m)
+    y1 = torch.empty((1, r), dtype=torch.float64, device=dev)
+    r1 = torch.empty(1, dtype=torch.float64, device=dev)
+    s1 = torch.empty(1, dtype=torch.int32, device=dev)
+    singles = [P[i:i + 1] for i in range(k)]
+
+    def plain():
+        for pi in singles:
+            B.subap_solve_batch(M.handle, pi, y1, r1, s1, B.FP64, 0, stream)
+    plain()
+    tp = timed(plain, 1, stream)
+    forms["fp64_per_p_plain"] = {"ms_per_batch": tp * m / k, "solves_per_s": k / (tp / 1e3),
+                                 "sample": k}
+
+    # roofline of the dominant kernel of the timed step
+    dom = max(prof.items(), key=lambda kv: kv[1][1])
+    dname, (calls, tot_ms) = dom
+    avg_ms = tot_ms / max(calls, 1)
+    flops_contract = 2.0 * m * s * n * r
+    if dname == "krr_contract_bf16x3":
+        roof = {"bound": "mfma", "achieved": flops_contract / (avg_ms * 1e-3) / 1e12,
+                "peak": PEAKS["bf16_mfma_tflops"], "unit": "TFLOP/s"}
+    elif dname == "krr_refine_partial":
+        # one FP64 kernel entry and one fused multiply-add per (p, selected row, point)
+        flops = m * (2.0 * s * n + 2.0 * n * r)
+        roof = {"bound": "alu", "achieved": flops / (avg_ms * 1e-3) / 1e12,
+                "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "alu", "achieved": None, "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s"}
+    if roof["achieved"] is not None:
+        roof["frac"] = roof["achieved"] / roof["peak"]
+    roof.update({"kernel": dname, "avg_ms": avg_ms, "traffic": None})
+
+    out = {
+        "metric": "online solves/s at rel. residual <=1e-6: batched/learned vs plain, 1 MI355X",
+        "value": n_valid / (ms / 1e3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3+f64",
+        "data": "synthetic",
+        "config": {"workload": "krr_gauss_n16384_d8_r32_s128_m4096", "n": n, "r": r, "s": s, "batch": m,
+                   "form": "bf16x3 MFMA contraction + FP64 Householder LSQ + 1 FP64 refinement"},
+        "valid": {"count": n_valid, "of": m, "max_sketched_distance": float(dist.max()),
+                  "tolerance": TOL},
+        "forms": forms,
+        "speedup_vs_plain": forms["bf16x3_refine1"]["solves_per_s"] / forms["fp64_per_p_plain"]["solves_per_s"],
+        "kernels_ms_per_step": {k2: v[1] / max(args.steps, 1) for k2, v in prof.items()},
+        "roofline": roof,
+        "offline_s": offline_s,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    M.free()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

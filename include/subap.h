@@ -49,6 +49,12 @@
 extern "C" {
 #endif
 
+#if defined(__GNUC__)
+#define SUBAP_API __attribute__((visibility("default")))
+#else
+#define SUBAP_API
+#endif
+
 typedef enum {
   SUBAP_OK = 0,
   SUBAP_E_INVALID = 1,     /* bad argument (NULL, size, range)               */
@@ -116,7 +122,7 @@ typedef struct {
  * release it with subap_model_free.  SUBAP_E_NOCONV if a snapshot solve
  * stalls (the model is not created).
  */
-subap_status subap_offline(const subap_problem_desc* problem,
+SUBAP_API subap_status subap_offline(const subap_problem_desc* problem,
                            const subap_offline_opts* opts,
                            void* hip_stream, subap_model* out);
 
@@ -140,7 +146,7 @@ typedef struct {
  *   opts        host or NULL (= FP64, no refinement).
  * m = 0 is a no-op.  Asynchronous on hip_stream.
  */
-subap_status subap_solve_batch(subap_model model, const double* params_dev, int64_t m,
+SUBAP_API subap_status subap_solve_batch(subap_model model, const double* params_dev, int64_t m,
                                double* y_dev, double* rho_dev, int32_t* status_dev,
                                const subap_solve_opts* opts, void* hip_stream);
 
@@ -149,22 +155,52 @@ subap_status subap_solve_batch(subap_model model, const double* params_dev, int6
  * vectors.  y_dev: device k x r row-major FP64.  x_dev: device n x k
  * col-major, FP64 (precision = SUBAP_FP64) or FP32 (SUBAP_FP32).
  */
-subap_status subap_lift(subap_model model, const double* y_dev, int64_t k,
+SUBAP_API subap_status subap_lift(subap_model model, const double* y_dev, int64_t k,
                         void* x_dev, int32_t precision, void* hip_stream);
 
+/*
+ * subap_sketched_residual -- FP64 sketched residual of given coefficients,
+ * from the s selected rows only (Section 5.3.1 uses |S(B c - b)| as the
+ * estimate of the full residual):
+ *   res_dev[p s + k] = (A(p) Q y_p - b(p))_{i_k}        (device, m x s, or NULL)
+ *   norm_dev[p]      = |res_p|_2 / |S b|_2               (device, m, or NULL)
+ * Rows are generated with FP64-accurate entries and applied to z = Q y_p, an
+ * s x n matrix-vector product per parameter; S A(p) Q is never formed.  This
+ * is the acceptance test of a predicted y and the reference for comparing
+ * two coefficient vectors: |res(y1) - res(y2)| = |S A(p) Q (y1 - y2)|.
+ * At least one output must be given.  Asynchronous on hip_stream.
+ */
+SUBAP_API subap_status subap_sketched_residual(subap_model model, const double* params_dev, int64_t m,
+                                               const double* y_dev, double* res_dev, double* norm_dev,
+                                               void* hip_stream);
+
+/*
+ * Per-kernel timing for benchmarks.  While enabled, the library records a
+ * HIP event pair on the launching stream around every kernel it enqueues.
+ * subap_profile_count() waits for the recorded events and returns the
+ * number of distinct kernel names; subap_profile_entry(i, ...) gives the
+ * name (valid until the next profile call), the number of launches and
+ * their total duration in milliseconds.  Process-wide; thread-safe.
+ */
+SUBAP_API subap_status subap_profile_enable(int32_t on);
+SUBAP_API subap_status subap_profile_reset(void);
+SUBAP_API int32_t subap_profile_count(void);
+SUBAP_API subap_status subap_profile_entry(int32_t i, const char** name, int64_t* calls,
+                                           double* total_ms);
+
 /* Model queries (blocking, host outputs). */
-subap_status subap_model_dims(subap_model model, int64_t* n, int32_t* r,
+SUBAP_API subap_status subap_model_dims(subap_model model, int64_t* n, int32_t* r,
                               int32_t* s, int32_t* d);
 /* rows_host: s indices in selection order. */
-subap_status subap_model_rows(subap_model model, int64_t* rows_host);
+SUBAP_API subap_status subap_model_rows(subap_model model, int64_t* rows_host);
 /* Q_host: n x r col-major orthonormal basis. */
-subap_status subap_model_basis(subap_model model, double* Q_host);
+SUBAP_API subap_status subap_model_basis(subap_model model, double* Q_host);
 
-subap_status subap_model_free(subap_model model);
+SUBAP_API subap_status subap_model_free(subap_model model);
 
-const char* subap_status_string(subap_status status);
+SUBAP_API const char* subap_status_string(subap_status status);
 /* Message of the last failing call on this thread ("" if none). */
-const char* subap_last_error(void);
+SUBAP_API const char* subap_last_error(void);
 
 #ifdef __cplusplus
 }

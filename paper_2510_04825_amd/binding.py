@@ -1,0 +1,292 @@
+"""ctypes binding of libsubap.so (include/subap.h).
+
+Argument marshalling only: every step of SubApSnap runs inside the HIP
+library.  Device buffers are torch tensors on the GPU (their data pointers
+are passed through); the HIP stream is torch's current stream unless one is
+given.  Functions keep the C names; ``Model`` is a small owner of a
+``subap_model`` handle built from a ``subap_inputs`` workload dict.
+
+Loading fails loudly if the library has not been built: there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsubap.so")
+
+# subap_status
+OK, E_INVALID, E_NOMEM, E_HIP, E_RANK, E_NOCONV, E_NONFINITE, E_UNSUPPORTED = range(8)
+# subap_family
+FAMILY_DIFF2D, FAMILY_DIFF3D, FAMILY_KRR = 1, 2, 3
+# subap_precision
+FP64, FP32, BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+FAMILIES = {"diff2d": FAMILY_DIFF2D, "diff3d": FAMILY_DIFF3D, "krr": FAMILY_KRR}
+
+EXPORTS = ("subap_offline", "subap_solve_batch", "subap_lift", "subap_sketched_residual", "subap_model_dims",
+           "subap_model_rows", "subap_model_basis", "subap_model_free", "subap_profile_enable",
+           "subap_profile_reset", "subap_profile_entry", "subap_profile_count", "subap_status_string",
+           "subap_last_error")
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("family", C.c_int32), ("grid", C.c_int32), ("n", C.c_int64), ("dim", C.c_int32),
+                ("points", C.c_void_p), ("rhs", C.c_void_p), ("lam", C.c_double)]
+
+
+class OfflineOpts(C.Structure):
+    _fields_ = [("r", C.c_int32), ("s", C.c_int32), ("snap_params", C.c_void_p),
+                ("select_param", C.c_void_p), ("snap_tol", C.c_double), ("snap_maxiter", C.c_int32),
+                ("basis_in", C.c_void_p), ("rows_in", C.c_void_p)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("contraction", C.c_int32), ("refine_steps", C.c_int32)]
+
+
+class SubapError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"subap error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libsubap.so once and declare its signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
+                          "(python -m paper_2510_04825_amd.build); there is no CPU fallback")
+    lib = C.CDLL(path)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.subap_offline.argtypes = [C.POINTER(ProblemDesc), C.POINTER(OfflineOpts), vp, C.POINTER(vp)]
+    lib.subap_solve_batch.argtypes = [vp, vp, i64, vp, vp, vp, C.POINTER(SolveOpts), vp]
+    lib.subap_lift.argtypes = [vp, vp, i64, vp, i32, vp]
+    lib.subap_sketched_residual.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+    lib.subap_profile_enable.argtypes = [i32]
+    lib.subap_profile_reset.argtypes = []
+    lib.subap_profile_count.argtypes = []
+    lib.subap_profile_count.restype = i32
+    lib.subap_profile_entry.argtypes = [i32, C.POINTER(C.c_char_p), C.POINTER(i64), C.POINTER(C.c_double)]
+    lib.subap_model_dims.argtypes = [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    lib.subap_model_rows.argtypes = [vp, vp]
+    lib.subap_model_basis.argtypes = [vp, vp]
+    lib.subap_model_free.argtypes = [vp]
+    for name in EXPORTS[:11]:
+        getattr(lib, name).restype = C.c_int
+    lib.subap_status_string.argtypes = [C.c_int]
+    lib.subap_status_string.restype = C.c_char_p
+    lib.subap_last_error.argtypes = []
+    lib.subap_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        lib = load()
+        raise SubapError(rc, f"{lib.subap_status_string(rc).decode()}: {lib.subap_last_error().decode()}")
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _expect(t, shape, dtype, name):
+    """Host-side check that a device tensor has the layout the kernels assume."""
+    if tuple(t.shape) != tuple(shape) or str(t.dtype) != f"torch.{dtype}" or not t.is_contiguous() \
+            or not t.is_cuda:
+        raise ValueError(f"{name}: expected a contiguous cuda {dtype} tensor of shape {tuple(shape)}, "
+                         f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+
+
+def _host(a, dtype):
+    return None if a is None else np.ascontiguousarray(a, dtype=dtype)
+
+
+# ---------------------------------------------------------------------------
+# C entry points
+# ---------------------------------------------------------------------------
+def subap_offline(family, grid=0, n=0, dim=0, points=None, rhs=None, lam=0.0, r=1, s=1,
+                  snap_params=None, select_param=None, snap_tol=0.0, snap_maxiter=0,
+                  basis_in=None, rows_in=None, stream=None):
+    """Run the offline phase; returns the opaque model handle (int)."""
+    lib = load()
+    keep = [_host(points, np.float64), _host(rhs, np.float64), _host(snap_params, np.float64),
+            _host(select_param, np.float64), _host(basis_in, np.float64), _host(rows_in, np.int64)]
+    addr = [None if a is None else a.ctypes.data for a in keep]
+    pd = ProblemDesc(family, grid, n, dim, addr[0], addr[1], lam)
+    op = OfflineOpts(r, s, addr[2], addr[3], snap_tol, snap_maxiter, addr[4], addr[5])
+    h = C.c_void_p()
+    _check(lib.subap_offline(C.byref(pd), C.byref(op), _stream(stream), C.byref(h)))
+    return h.value
+
+
+def subap_solve_batch(model, params, y, rho=None, status=None, contraction=FP64, refine_steps=0,
+                      stream=None):
+    """params: (m, d) float64 cuda tensor; y: (m, r) float64; rho: (m,) float64; status: (m,) int32."""
+    lib = load()
+    m = params.shape[0]
+    _, r, _, d = subap_model_dims(model)
+    _expect(params, (m, d), "float64", "params")
+    _expect(y, (m, r), "float64", "y")
+    if rho is not None:
+        _expect(rho, (m,), "float64", "rho")
+    if status is not None:
+        _expect(status, (m,), "int32", "status")
+    opts = SolveOpts(int(contraction), int(refine_steps))
+    _check(lib.subap_solve_batch(C.c_void_p(model), _ptr(params), m, _ptr(y), _ptr(rho), _ptr(status),
+                                 C.byref(opts), _stream(stream)))
+
+
+def subap_lift(model, y, x, precision=FP64, stream=None):
+    """y: (k, r) float64 cuda tensor; x: (k, n) tensor (column i of x is row i), float64 or float32."""
+    lib = load()
+    n, r, _, _ = subap_model_dims(model)
+    k = y.shape[0]
+    _expect(y, (k, r), "float64", "y")
+    _expect(x, (k, n), "float64" if precision == FP64 else "float32", "x")
+    _check(lib.subap_lift(C.c_void_p(model), _ptr(y), k, _ptr(x), int(precision), _stream(stream)))
+
+
+def subap_sketched_residual(model, params, y, res=None, norm=None, stream=None):
+    """FP64 sketched residual of coefficients y: res (m, s) and/or norm (m,) float64 cuda tensors."""
+    lib = load()
+    m = params.shape[0]
+    _, r, s, d = subap_model_dims(model)
+    _expect(params, (m, d), "float64", "params")
+    _expect(y, (m, r), "float64", "y")
+    if res is not None:
+        _expect(res, (m, s), "float64", "res")
+    if norm is not None:
+        _expect(norm, (m,), "float64", "norm")
+    _check(lib.subap_sketched_residual(C.c_void_p(model), _ptr(params), m, _ptr(y), _ptr(res), _ptr(norm),
+                                       _stream(stream)))
+
+
+def subap_profile_enable(on=True):
+    _check(load().subap_profile_enable(1 if on else 0))
+
+
+def subap_profile_reset():
+    _check(load().subap_profile_reset())
+
+
+def subap_profile_read():
+    """{kernel name: (launches, total ms)} recorded since the last reset."""
+    lib = load()
+    out = {}
+    for i in range(lib.subap_profile_count()):
+        name, calls, ms = C.c_char_p(), C.c_int64(), C.c_double()
+        _check(lib.subap_profile_entry(i, C.byref(name), C.byref(calls), C.byref(ms)))
+        out[name.value.decode()] = (calls.value, ms.value)
+    return out
+
+
+def subap_model_dims(model):
+    lib = load()
+    n, r, s, d = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib.subap_model_dims(C.c_void_p(model), C.byref(n), C.byref(r), C.byref(s), C.byref(d)))
+    return n.value, r.value, s.value, d.value
+
+
+def subap_model_rows(model):
+    lib = load()
+    _, _, s, _ = subap_model_dims(model)
+    out = np.empty(s, dtype=np.int64)
+    _check(lib.subap_model_rows(C.c_void_p(model), out.ctypes.data))
+    return out
+
+
+def subap_model_basis(model):
+    lib = load()
+    n, r, _, _ = subap_model_dims(model)
+    out = np.empty((r, n), dtype=np.float64)  # column-major n x r == row-major r x n
+    _check(lib.subap_model_basis(C.c_void_p(model), out.ctypes.data))
+    return out.T
+
+
+def subap_model_free(model):
+    _check(load().subap_model_free(C.c_void_p(model)))
+
+
+# ---------------------------------------------------------------------------
+# convenience owner
+# ---------------------------------------------------------------------------
+class Model:
+    """Owns a subap_model built from a ``subap_inputs`` workload dict."""
+
+    def __init__(self, workload: dict, basis=None, rows=None, snap_tol=0.0, snap_maxiter=0, stream=None):
+        w = workload
+        fam = FAMILIES[w["family"]]
+        kw = dict(r=w["r"], s=w["s"], snap_params=w.get("snap_params"), select_param=w.get("select_param"),
+                  snap_tol=snap_tol, snap_maxiter=snap_maxiter, basis_in=None, rows_in=rows, stream=stream)
+        if basis is not None:
+            kw["basis_in"] = np.asfortranarray(basis, dtype=np.float64).T  # column-major n x r
+        if fam == FAMILY_KRR:
+            self.handle = subap_offline(fam, n=w["n"], dim=w["dim"], points=w["points"], rhs=w["rhs"],
+                                        lam=w["lam"], **kw)
+        else:
+            self.handle = subap_offline(fam, grid=w["grid"][0], rhs=w.get("rhs"), **kw)
+        self.n, self.r, self.s, self.d = subap_model_dims(self.handle)
+
+    def rows(self):
+        return subap_model_rows(self.handle)
+
+    def basis(self):
+        return subap_model_basis(self.handle)
+
+    def solve(self, params, contraction=FP64, refine_steps=0, stream=None, with_status=True):
+        """params: (m, d) float64 cuda tensor -> (y, rho, status) cuda tensors."""
+        import torch
+        m = params.shape[0]
+        y = torch.empty((m, self.r), dtype=torch.float64, device=params.device)
+        rho = torch.empty(m, dtype=torch.float64, device=params.device)
+        st = torch.empty(m, dtype=torch.int32, device=params.device) if with_status else None
+        subap_solve_batch(self.handle, params, y, rho, st, contraction, refine_steps, stream)
+        return y, rho, st
+
+    def sketched_residual(self, params, y, vector=False, stream=None):
+        """(res (m, s) or None, norm (m,)) cuda tensors."""
+        import torch
+        m = params.shape[0]
+        norm = torch.empty(m, dtype=torch.float64, device=params.device)
+        res = torch.empty((m, self.s), dtype=torch.float64, device=params.device) if vector else None
+        subap_sketched_residual(self.handle, params, y, res, norm, stream)
+        return res, norm
+
+    def lift(self, y, precision=FP64, stream=None):
+        import torch
+        dt = torch.float64 if precision == FP64 else torch.float32
+        x = torch.empty((y.shape[0], self.n), dtype=dt, device=y.device)
+        subap_lift(self.handle, y, x, precision, stream)
+        return x
+
+    def free(self):
+        if getattr(self, "handle", None):
+            subap_model_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

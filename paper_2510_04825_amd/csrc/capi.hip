@@ -1,0 +1,341 @@
+// C ABI entry points (include/subap.h): argument validation, model
+// lifetime, and dispatch to the offline and online kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "common.h"
+#include "profile.h"
+
+namespace subap {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+void clear_error() { g_last_error.clear(); }
+
+subap_status dmalloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? SUBAP_E_NOMEM : SUBAP_E_HIP;
+  }
+  return SUBAP_OK;
+}
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+// ---- per-kernel timing registry ----
+namespace {
+struct ProfPending {
+  const char* name;
+  hipEvent_t a, b;
+};
+struct ProfTotal {
+  int64_t calls = 0;
+  double ms = 0.0;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfPending> g_prof_pending;
+std::vector<hipEvent_t> g_prof_pool;
+std::map<std::string, ProfTotal> g_prof_totals;
+std::vector<std::string> g_prof_names;
+
+// Fold finished event pairs into the totals (caller holds the lock).
+void prof_drain() {
+  for (const ProfPending& e : g_prof_pending) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(e.b) == hipSuccess && hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+      ProfTotal& t = g_prof_totals[e.name];
+      t.calls += 1;
+      t.ms += ms;
+    }
+    g_prof_pool.push_back(e.a);
+    g_prof_pool.push_back(e.b);
+  }
+  g_prof_pending.clear();
+  g_prof_names.clear();
+  for (const auto& kv : g_prof_totals) g_prof_names.push_back(kv.first);
+}
+}  // namespace
+
+bool profiling_enabled() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  return g_prof_on;
+}
+
+hipEvent_t profile_event() {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (!g_prof_pool.empty()) {
+    hipEvent_t e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void profile_push(const char* name, hipEvent_t a, hipEvent_t b) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_pending.push_back({name, a, b});
+  if (g_prof_pending.size() > 4096) prof_drain();
+}
+
+subap_status ensure_work(subap_model_s* M, size_t bytes) {
+  if (M->work_bytes >= bytes) return SUBAP_OK;
+  dfree(M->work);
+  M->work = nullptr;
+  M->work_bytes = 0;
+  SUBAP_TRY(dmalloc(&M->work, bytes));
+  M->work_bytes = bytes;
+  return SUBAP_OK;
+}
+
+namespace {
+
+void free_model(subap_model_s* M) {
+  if (!M) return;
+  void* bufs[] = {M->Q, M->rows_d, M->bS, M->QS, M->rhs, M->phi, M->delta64, M->delta32, M->points,
+                  M->Dt64, M->D32, M->Qrm, M->Q32, M->Qhi, M->Qlo, M->work};
+  for (void* b : bufs) dfree(b);
+  delete M;
+}
+
+subap_status invalid(const std::string& msg) {
+  set_error(msg);
+  return SUBAP_E_INVALID;
+}
+
+bool all_finite(const double* v, int64_t len) {
+  for (int64_t i = 0; i < len; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+}  // namespace
+}  // namespace subap
+
+using namespace subap;
+
+extern "C" {
+
+const char* subap_status_string(subap_status s) {
+  switch (s) {
+    case SUBAP_OK: return "ok";
+    case SUBAP_E_INVALID: return "invalid argument";
+    case SUBAP_E_NOMEM: return "out of memory";
+    case SUBAP_E_HIP: return "HIP runtime error";
+    case SUBAP_E_RANK: return "rank deficient";
+    case SUBAP_E_NOCONV: return "no convergence";
+    case SUBAP_E_NONFINITE: return "non-finite value";
+    case SUBAP_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* subap_last_error(void) { return g_last_error.c_str(); }
+
+subap_status subap_offline(const subap_problem_desc* pd, const subap_offline_opts* o, void* hip_stream,
+                           subap_model* out) {
+  clear_error();
+  if (!pd || !o || !out) return invalid("problem, opts and out must not be NULL");
+  *out = nullptr;
+  subap_model_s tmp;
+  tmp.family = pd->family;
+  if (pd->family == SUBAP_FAMILY_DIFF2D || pd->family == SUBAP_FAMILY_DIFF3D) {
+    const int dimx = pd->family == SUBAP_FAMILY_DIFF2D ? 2 : 3;
+    if (pd->grid < 2 || pd->grid > 46340) return invalid("grid must be in [2, 46340]");
+    double nn = std::pow(static_cast<double>(pd->grid), dimx);
+    if (nn > 2147483647.0) return invalid("grid^dim exceeds 2^31 - 1 unknowns");
+    tmp.N = pd->grid;
+    tmp.dimx = dimx;
+    tmp.n = static_cast<int64_t>(nn);
+    tmp.d = dimx == 2 ? 2 : 4;
+    tmp.F = 2 * dimx;
+    tmp.h = 1.0 / (pd->grid + 1);
+    tmp.inv_h2 = 1.0 / (tmp.h * tmp.h);
+    if (pd->rhs && !all_finite(pd->rhs, tmp.n)) return invalid("rhs has non-finite entries");
+  } else if (pd->family == SUBAP_FAMILY_KRR) {
+    if (pd->n < 1 || pd->n > 2147483647LL) return invalid("KRR n must be in [1, 2^31 - 1]");
+    if (pd->dim < 1 || pd->dim > 16) return invalid("KRR point dimension must be in [1, 16]");
+    if (!pd->points || !pd->rhs) return invalid("KRR needs points and rhs");
+    if (!(pd->lambda > 0.0) || !std::isfinite(pd->lambda)) return invalid("KRR lambda must be finite and > 0");
+    tmp.n = pd->n;
+    tmp.dimx = pd->dim;
+    tmp.d = 1;
+    tmp.lambda = pd->lambda;
+    if (!all_finite(pd->points, pd->n * pd->dim) || !all_finite(pd->rhs, pd->n))
+      return invalid("points or rhs have non-finite entries");
+  } else {
+    return invalid("unknown family");
+  }
+  if (o->r < 1 || o->r > kMaxR) return invalid("r must be in [1, 64]");
+  if (o->s < o->r || o->s > kMaxS || o->s > tmp.n) return invalid("s must satisfy r <= s <= min(n, 256)");
+  if (o->snap_tol < 0.0 || !std::isfinite(o->snap_tol)) return invalid("snap_tol must be finite and >= 0");
+  if (o->snap_maxiter < 0) return invalid("snap_maxiter must be >= 0");
+  tmp.r = o->r;
+  tmp.s = o->s;
+  if (!o->basis_in) {
+    if (!o->snap_params) return invalid("snap_params needed without basis_in");
+    if (!all_finite(o->snap_params, static_cast<int64_t>(o->r) * tmp.d)) return invalid("snap_params not finite");
+    if (pd->family == SUBAP_FAMILY_KRR)
+      for (int i = 0; i < o->r; ++i)
+        if (!(o->snap_params[i] > 0.0)) return invalid("KRR length scales must be > 0");
+  } else if (!all_finite(o->basis_in, tmp.n * o->r)) {
+    return invalid("basis_in has non-finite entries");
+  }
+  if (!o->rows_in) {
+    if (!o->select_param) return invalid("select_param needed without rows_in");
+    if (!all_finite(o->select_param, tmp.d)) return invalid("select_param not finite");
+    if (pd->family == SUBAP_FAMILY_KRR && !(o->select_param[0] > 0.0)) return invalid("KRR select_param must be > 0");
+  } else {
+    std::unordered_set<int64_t> seen;
+    for (int k = 0; k < o->s; ++k) {
+      const int64_t v = o->rows_in[k];
+      if (v < 0 || v >= tmp.n) return invalid("rows_in index out of range");
+      if (!seen.insert(v).second) return invalid("rows_in has duplicates");
+    }
+  }
+  subap_model_s* M = new (std::nothrow) subap_model_s(tmp);
+  if (!M) return SUBAP_E_NOMEM;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  subap_status rc = offline_build(pd, o, st, M);
+  if (rc != SUBAP_OK) {
+    (void)hipStreamSynchronize(st);
+    free_model(M);
+    return rc;
+  }
+  *out = M;
+  return SUBAP_OK;
+}
+
+subap_status subap_solve_batch(subap_model M, const double* params, int64_t m, double* y, double* rho,
+                               int32_t* status, const subap_solve_opts* opts, void* hip_stream) {
+  clear_error();
+  if (!M) return invalid("model must not be NULL");
+  if (m < 0) return invalid("m must be >= 0");
+  if (m == 0) return SUBAP_OK;
+  if (!params || !y) return invalid("params and y must not be NULL");
+  const int prec = opts ? opts->contraction : SUBAP_FP64;
+  const int refine = opts ? opts->refine_steps : 0;
+  if (prec < SUBAP_FP64 || prec > SUBAP_BF16X3) return invalid("unknown contraction precision");
+  if (refine < 0 || refine > 4) return invalid("refine_steps must be in [0, 4]");
+  if (m > (int64_t(1) << 31) / 64) return invalid("m too large for one call");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (M->family == SUBAP_FAMILY_KRR) return krr_solve(M, params, m, y, rho, status, prec, refine, st);
+  if (prec == SUBAP_BF16X3) {
+    set_error("the split-bf16 contraction is implemented for the kernel family only");
+    return SUBAP_E_UNSUPPORTED;
+  }
+  return fd_solve(M, params, m, y, rho, status, prec, refine, st);
+}
+
+subap_status subap_lift(subap_model M, const double* y, int64_t k, void* x, int32_t precision, void* hip_stream) {
+  clear_error();
+  if (!M) return invalid("model must not be NULL");
+  if (k < 0) return invalid("k must be >= 0");
+  if (k == 0) return SUBAP_OK;
+  if (!y || !x) return invalid("y and x must not be NULL");
+  if (precision != SUBAP_FP64 && precision != SUBAP_FP32) return invalid("lift precision must be FP64 or FP32");
+  return lift(M, y, k, x, precision, static_cast<hipStream_t>(hip_stream));
+}
+
+subap_status subap_model_dims(subap_model M, int64_t* n, int32_t* r, int32_t* s, int32_t* d) {
+  clear_error();
+  if (!M) return invalid("model must not be NULL");
+  if (n) *n = M->n;
+  if (r) *r = M->r;
+  if (s) *s = M->s;
+  if (d) *d = M->d;
+  return SUBAP_OK;
+}
+
+subap_status subap_model_rows(subap_model M, int64_t* rows_host) {
+  clear_error();
+  if (!M || !rows_host) return invalid("model and rows_host must not be NULL");
+  std::memcpy(rows_host, M->rows.data(), sizeof(int64_t) * M->rows.size());
+  return SUBAP_OK;
+}
+
+subap_status subap_model_basis(subap_model M, double* Q_host) {
+  clear_error();
+  if (!M || !Q_host) return invalid("model and Q_host must not be NULL");
+  SUBAP_HIP_TRY(hipDeviceSynchronize());
+  SUBAP_HIP_TRY(hipMemcpy(Q_host, M->Q, sizeof(double) * M->n * M->r, hipMemcpyDeviceToHost));
+  return SUBAP_OK;
+}
+
+subap_status subap_sketched_residual(subap_model M, const double* params, int64_t m, const double* y, double* res,
+                                     double* norm, void* hip_stream) {
+  clear_error();
+  if (!M) return invalid("model must not be NULL");
+  if (m < 0) return invalid("m must be >= 0");
+  if (m == 0) return SUBAP_OK;
+  if (!params || !y) return invalid("params and y must not be NULL");
+  if (!res && !norm) return invalid("at least one of res and norm must be given");
+  if (m > (int64_t(1) << 31) / 64) return invalid("m too large for one call");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (M->family == SUBAP_FAMILY_KRR) return krr_residual(M, params, m, y, res, norm, st);
+  return fd_residual(M, params, m, y, res, norm, st);
+}
+
+subap_status subap_profile_enable(int32_t on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return SUBAP_OK;
+}
+
+subap_status subap_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  prof_drain();
+  g_prof_totals.clear();
+  g_prof_names.clear();
+  return SUBAP_OK;
+}
+
+int32_t subap_profile_count(void) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  prof_drain();
+  return static_cast<int32_t>(g_prof_names.size());
+}
+
+subap_status subap_profile_entry(int32_t i, const char** name, int64_t* calls, double* total_ms) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (i < 0 || i >= static_cast<int32_t>(g_prof_names.size())) {
+    set_error("profile entry index out of range");
+    return SUBAP_E_INVALID;
+  }
+  const std::string& nm = g_prof_names[i];
+  const ProfTotal& t = g_prof_totals[nm];
+  if (name) *name = nm.c_str();
+  if (calls) *calls = t.calls;
+  if (total_ms) *total_ms = t.ms;
+  return SUBAP_OK;
+}
+
+subap_status subap_model_free(subap_model M) {
+  clear_error();
+  if (!M) return SUBAP_OK;
+  (void)hipDeviceSynchronize();
+  free_model(M);
+  return SUBAP_OK;
+}
+
+}  // extern "C"

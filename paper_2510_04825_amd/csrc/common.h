@@ -97,6 +97,10 @@ subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double
                        double* rho, int32_t* status, int prec, int refine, hipStream_t st);
 subap_status lift(subap_model_s* M, const double* y, int64_t k, void* x, int prec,
                   hipStream_t st);
+subap_status fd_residual(subap_model_s* M, const double* params, int64_t m, const double* y, double* res,
+                         double* norm, hipStream_t st);
+subap_status krr_residual(subap_model_s* M, const double* params, int64_t m, const double* y, double* res,
+                          double* norm, hipStream_t st);
 
 subap_status ensure_work(subap_model_s* M, size_t bytes);
 

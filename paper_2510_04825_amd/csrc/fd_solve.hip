@@ -1,0 +1,257 @@
+// Online solve for the finite-difference diffusion families, fully fused:
+// one team of lanes per parameter p* generates the s selected rows of A(p*)
+// (face coefficients a_f = exp(sum_q p_q phi_q) at the s x F faces, Section
+// 3.1 "Computing S A(p*) X"), contracts them with the face-difference table
+// Delta_{k,f} = Q[i_k] - Q[nb_f(i_k)] into S A(p*) Q (eq. (3.4)), solves the
+// s x r least-squares problem (eq. (3.3)) by Householder QR in registers and
+// optionally refines in FP64.  Row k of S A(p) Q is sum_f a_f Delta_{k,f} / h^2
+// because the diagonal of row i_k is the sum of its face coefficients.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "profile.h"
+#include "team_qr.h"
+
+namespace subap {
+namespace {
+
+struct FDArgs {
+  const double* params;
+  int64_t m;
+  int r, s;
+  const double* phi;
+  const double* delta64;
+  const float* delta32;
+  const double* bS;
+  double inv_h2, bS_norm;
+  double* y;
+  double* rho;
+  int32_t* status;
+  int prec;
+  int refine;
+};
+
+template <int TEAM, int R, int RM, int F, int DP>
+__global__ __launch_bounds__(256) void k_fd_solve(FDArgs A) {
+  constexpr int TEAMS = 256 / TEAM;
+  __shared__ double s_tau[TEAMS][RM];
+  __shared__ double s_y[TEAMS][RM];
+  __shared__ double s_dy[TEAMS][RM];
+  const int team = threadIdx.x / TEAM, lane = threadIdx.x % TEAM;
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * TEAMS + team;
+  if (p >= A.m) return;  // uniform across the team
+  const int r = A.r, s = A.s;
+  double* tau = s_tau[team];
+  double* yv = s_y[team];
+  double* dy = s_dy[team];
+
+  double pv[DP];
+  bool finite = true;
+#pragma unroll
+  for (int q = 0; q < DP; ++q) {
+    pv[q] = A.params[p * DP + q];
+    finite = finite && isfinite(pv[q]);
+  }
+  // A1: face coefficients of my rows (scaled by 1/h^2)
+  double af[R][F];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = lane + TEAM * q;
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      double t = 0.0;
+      if (k < s) {
+#pragma unroll
+        for (int qq = 0; qq < DP; ++qq) t += pv[qq] * A.phi[(f * DP + qq) * s + k];
+      }
+      af[q][f] = (k < s) ? exp(t) * A.inv_h2 : 0.0;
+    }
+  }
+  // A2: S A(p) Q from the face differences
+  TeamQR<TEAM, R, RM> qr;
+  double b0[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = lane + TEAM * q;
+#pragma unroll
+    for (int c = 0; c < RM; ++c) qr.a[q][c] = 0.0;
+    if (k < s) {
+      if (A.prec == SUBAP_FP64) {
+#pragma unroll 1
+        for (int f = 0; f < F; ++f)
+#pragma unroll
+          for (int c = 0; c < RM; ++c)
+            if (c < r) qr.a[q][c] += af[q][f] * A.delta64[(f * r + c) * s + k];
+      } else {
+        float acc[RM];
+#pragma unroll
+        for (int c = 0; c < RM; ++c) acc[c] = 0.0f;
+#pragma unroll 1
+        for (int f = 0; f < F; ++f) {
+          const float a32 = static_cast<float>(af[q][f]);
+#pragma unroll
+          for (int c = 0; c < RM; ++c)
+            if (c < r) acc[c] = fmaf(a32, A.delta32[(f * r + c) * s + k], acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < RM; ++c) qr.a[q][c] = acc[c];
+      }
+    }
+    b0[q] = (k < s) ? A.bS[k] : 0.0;
+    qr.b[q] = b0[q];
+  }
+  // A3: Householder least squares
+  qr.factor(r, lane, tau);
+  const double tail = qr.tail_norm(qr.b, r, lane);
+  {
+    double x[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) x[q] = qr.b[q];
+    qr.back_substitute(x, r, lane, yv);
+  }
+  // FP64 residual S(A(p) Q y - b) of the current y, distributed like b
+  auto residual = [&](double (&res)[R]) {
+    // Re-read the table on every use: an opaque copy of the pointer stops the
+    // compiler from hoisting F x r loads per row into registers across the
+    // factorisation and the refinement loop.
+    const double* D64 = A.delta64;
+    asm volatile("" : "+s"(D64));
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int k = lane + TEAM * q;
+      double t = 0.0;
+      if (k < s) {
+#pragma unroll 1
+        for (int f = 0; f < F; ++f) {
+          double u = 0.0;
+#pragma unroll
+          for (int c = 0; c < RM; ++c)
+            if (c < r) u += D64[(f * r + c) * s + k] * yv[c];
+          t += af[q][f] * u;
+        }
+      }
+      res[q] = t - b0[q];
+    }
+  };
+  // A4: refinement steps with the same factorisation
+  for (int it = 0; it < A.refine; ++it) {
+    double res[R];
+    residual(res);
+    qr.apply_qt(res, r, lane, tau);
+    qr.back_substitute(res, r, lane, dy);
+#pragma unroll
+    for (int c = 0; c < RM; ++c)
+      if (c < r) yv[c] -= dy[c];
+  }
+  double rho;
+  if (A.refine > 0 || A.prec != SUBAP_FP64) {
+    double res[R];
+    residual(res);
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) t += res[q] * res[q];
+    rho = sqrt(team_sum<TEAM>(t));
+  } else {
+    rho = tail;
+  }
+  bool yfin = true;
+  for (int c = 0; c < r; ++c) yfin = yfin && isfinite(yv[c]);
+  int32_t code = SUBAP_OK;
+  if (!finite) code = SUBAP_E_NONFINITE;
+  else if (!qr.full_rank) code = SUBAP_E_RANK;
+  else if (!yfin) code = SUBAP_E_NONFINITE;
+  for (int c = lane; c < r; c += TEAM) A.y[p * r + c] = (code == SUBAP_OK) ? yv[c] : __longlong_as_double(0x7ff8000000000000LL);
+  if (lane == 0) {
+    if (A.rho) A.rho[p] = rho / A.bS_norm;
+    if (A.status) A.status[p] = code;
+  }
+}
+
+// Sketched residual S(A(p) Q y - b) of given coefficients, FP64: one
+// wavefront per parameter, lanes over the selected rows.
+template <int F, int DP>
+__global__ __launch_bounds__(256) void k_fd_resid(const double* params, int64_t m, int r, int s,
+                                                   const double* phi, const double* delta64, const double* bS,
+                                                   double inv_h2, double bS_norm, const double* y, double* res,
+                                                   double* norm) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (p >= m) return;
+  double pv[DP];
+  bool finite = true;
+  for (int q = 0; q < DP; ++q) {
+    pv[q] = params[p * DP + q];
+    finite = finite && isfinite(pv[q]);
+  }
+  double ss = 0.0;
+  for (int k = lane; k < s; k += 64) {
+    double t = 0.0;
+    for (int f = 0; f < F; ++f) {
+      double arg = 0.0;
+      for (int q = 0; q < DP; ++q) arg += pv[q] * phi[(f * DP + q) * s + k];
+      double u = 0.0;
+      for (int c = 0; c < r; ++c) u += delta64[(f * r + c) * s + k] * y[p * r + c];
+      t += exp(arg) * inv_h2 * u;
+    }
+    t -= bS[k];
+    if (!finite) t = __longlong_as_double(0x7ff8000000000000LL);
+    if (res) res[p * s + k] = t;
+    ss += t * t;
+  }
+  ss = team_sum<64>(ss);
+  if (lane == 0 && norm) norm[p] = sqrt(ss) / bS_norm;
+}
+
+template <int TEAM, int R, int RM, int F, int DP>
+subap_status launch(const FDArgs& a, hipStream_t st) {
+  constexpr int TEAMS = 256 / TEAM;
+  const int64_t nb = (a.m + TEAMS - 1) / TEAMS;
+  if (nb > 0x7fffffff) {
+    set_error("batch too large");
+    return SUBAP_E_INVALID;
+  }
+  ProfScope prof("fd_solve", st);
+  hipLaunchKernelGGL((k_fd_solve<TEAM, R, RM, F, DP>), dim3(static_cast<unsigned>(nb)), dim3(256), 0, st, a);
+  SUBAP_HIP_TRY(hipGetLastError());
+  return SUBAP_OK;
+}
+
+// Instantiated shapes: (TEAM, R) from s, RM from r.
+template <int F, int DP>
+subap_status dispatch(const FDArgs& a, hipStream_t st) {
+  const int s = a.s, r = a.r;
+#define SUBAP_FD(TEAM, R, RM) \
+  if (s <= TEAM * R && r <= RM) return launch<TEAM, R, RM, F, DP>(a, st);
+  // s <= 16 / 32 / 64 / 128 / 192 rows; r up to 40 columns
+  SUBAP_FD(16, 1, 8) SUBAP_FD(32, 1, 8) SUBAP_FD(32, 1, 16)
+  SUBAP_FD(64, 1, 16) SUBAP_FD(64, 2, 32) SUBAP_FD(64, 3, 40)
+#undef SUBAP_FD
+  set_error("no finite-difference solve kernel for this (s, r)");
+  return SUBAP_E_UNSUPPORTED;
+}
+
+}  // namespace
+
+subap_status fd_solve(subap_model_s* M, const double* params, int64_t m, double* y, double* rho,
+                      int32_t* status, int prec, int refine, hipStream_t st) {
+  FDArgs a{params, m, M->r, M->s, M->phi, M->delta64, M->delta32, M->bS, M->inv_h2, M->bS_norm,
+           y, rho, status, prec, refine};
+  if (M->dimx == 2) return dispatch<4, 2>(a, st);
+  return dispatch<6, 4>(a, st);
+}
+
+subap_status fd_residual(subap_model_s* M, const double* params, int64_t m, const double* y, double* res,
+                         double* norm, hipStream_t st) {
+  const unsigned grid = static_cast<unsigned>((m + 3) / 4);
+  ProfScope prof("fd_residual", st);
+  if (M->dimx == 2)
+    hipLaunchKernelGGL((k_fd_resid<4, 2>), dim3(grid), dim3(256), 0, st, params, m, M->r, M->s, M->phi, M->delta64,
+                       M->bS, M->inv_h2, M->bS_norm, y, res, norm);
+  else
+    hipLaunchKernelGGL((k_fd_resid<6, 4>), dim3(grid), dim3(256), 0, st, params, m, M->r, M->s, M->phi, M->delta64,
+                       M->bS, M->inv_h2, M->bS_norm, y, res, norm);
+  SUBAP_HIP_TRY(hipGetLastError());
+  return SUBAP_OK;
+}
+
+}  // namespace subap

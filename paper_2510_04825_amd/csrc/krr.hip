@@ -1,0 +1,707 @@
+// Online solve for kernel ridge regression (Section 6.3): A(p) = K_p + lambda I,
+// K_p[i, j] = exp(-|t_i - t_j|^2 / (2 p^2)).  Only the s selected rows of K_p
+// are generated (Section 3.1 "Computing S A(p*) X"), on the fly from the
+// precomputed squared distances D[k, j] = |t_{i_k} - t_j|^2, and contracted
+// with Q:  S A(p) Q = K_S(p) Q + lambda Q_S  (eq. (3.4)).
+//
+// Contraction forms:
+//   FP64      exp and products in FP64 (vector ALU);
+//   FP32      v_exp_f32 rows, FP32 MFMA 32x32x2, FP32 accumulation;
+//   BF16X3    v_exp_f32 rows split as bf16 hi + lo, Q split likewise, three
+//             MFMA 32x32x16 products hi*hi + hi*lo + lo*hi, FP32 accumulation.
+// Then the FP64 Householder least squares (team_qr.h), and optional FP64
+// refinement: r_S = K_S(p) (Q y) + lambda (Q y)_S - b_S with FP64-accurate
+// kernel entries, correction from the stored factorisation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "common.h"
+#include "family.h"
+#include "profile.h"
+#include "team_qr.h"
+
+namespace subap {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr double kLog2e = 1.4426950408889634074;
+
+__device__ __forceinline__ bool krr_param_ok(double sig) { return isfinite(sig) && sig > 0.0; }
+
+__device__ __forceinline__ void load_exp_table(double* tab) {
+  for (int j = threadIdx.x; j < 64; j += blockDim.x) tab[j] = exp2(static_cast<double>(j) / 64.0);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 contraction, many parameters: lanes = parameters, one wave per KR rows.
+// G[(p s + k) r + c] = sum_j exp(-D[k, j] / (2 p^2)) Q[j, c]
+// ---------------------------------------------------------------------------
+constexpr int kJC = 64;  // points per LDS chunk
+
+template <int KR, int RM>
+__global__ __launch_bounds__(256) void k_contract_f64(const double* params, int64_t m, int64_t n, int r,
+                                                       int s, const double* Dt64, const double* Qrm,
+                                                       double* G) {
+  __shared__ double s_tab[64];
+  __shared__ double s_q[kJC][RM];
+  __shared__ double s_d[kJC][4 * KR];
+  const int wave = threadIdx.x / 64, l = threadIdx.x % 64;
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * 64 + l;
+  const int kbase = blockIdx.y * 4 * KR;
+  load_exp_table(s_tab);
+  const double sig = p < m ? params[p] : 1.0;
+  const double cexp = krr_param_ok(sig) ? -0.5 / (sig * sig) : 0.0;
+  double acc[KR][RM];
+#pragma unroll
+  for (int kr = 0; kr < KR; ++kr)
+#pragma unroll
+    for (int c = 0; c < RM; ++c) acc[kr][c] = 0.0;
+  for (int64_t j0 = 0; j0 < n; j0 += kJC) {
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < kJC * RM; idx += 256) {
+      const int jj = idx / RM, c = idx % RM;
+      const int64_t j = j0 + jj;
+      s_q[jj][c] = (j < n && c < r) ? Qrm[j * r + c] : 0.0;
+    }
+    for (int idx = threadIdx.x; idx < kJC * 4 * KR; idx += 256) {
+      const int jj = idx / (4 * KR), kk = idx % (4 * KR);
+      const int64_t j = j0 + jj;
+      const int k = kbase + kk;
+      s_d[jj][kk] = (j < n && k < s) ? Dt64[j * s + k] : 1e300;
+    }
+    __syncthreads();
+    const int cnt = static_cast<int>(std::min<int64_t>(kJC, n - j0));
+    for (int jj = 0; jj < cnt; ++jj) {
+#pragma unroll
+      for (int kr = 0; kr < KR; ++kr) {
+        const double e = exp_tab(cexp * s_d[jj][wave * KR + kr], s_tab);
+#pragma unroll
+        for (int c = 0; c < RM; ++c) acc[kr][c] = fma(e, s_q[jj][c], acc[kr][c]);
+      }
+    }
+  }
+  if (p < m) {
+#pragma unroll
+    for (int kr = 0; kr < KR; ++kr) {
+      const int k = kbase + wave * KR + kr;
+      if (k < s)
+#pragma unroll
+        for (int c = 0; c < RM; ++c)
+          if (c < r) G[(p * s + k) * r + c] = acc[kr][c];
+    }
+  }
+}
+
+// FP64 contraction for few parameters (the per-p plain solve): one block per
+// (p, k), threads split the points, block reduction of the r sums.
+template <int RM>
+__global__ __launch_bounds__(256) void k_contract_f64_small(const double* params, int64_t n, int r, int s,
+                                                             const double* Dt64, const double* Qrm, double* G) {
+  __shared__ double s_tab[64];
+  __shared__ double s_red[4][RM];
+  const int64_t p = blockIdx.x;
+  const int k = blockIdx.y;
+  load_exp_table(s_tab);
+  __syncthreads();
+  const double sig = params[p];
+  const double cexp = krr_param_ok(sig) ? -0.5 / (sig * sig) : 0.0;
+  double acc[RM];
+#pragma unroll
+  for (int c = 0; c < RM; ++c) acc[c] = 0.0;
+  for (int64_t j = threadIdx.x; j < n; j += 256) {
+    const double e = exp_tab(cexp * Dt64[j * s + k], s_tab);
+#pragma unroll
+    for (int c = 0; c < RM; ++c)
+      if (c < r) acc[c] = fma(e, Qrm[j * r + c], acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < RM; ++c) acc[c] = team_sum<64>(acc[c]);
+  const int wave = threadIdx.x / 64;
+  if (threadIdx.x % 64 == 0)
+#pragma unroll
+    for (int c = 0; c < RM; ++c) s_red[wave][c] = acc[c];
+  __syncthreads();
+  for (int c = threadIdx.x; c < r; c += 256)
+    G[(p * s + k) * r + c] = (s_red[0][c] + s_red[1][c]) + (s_red[2][c] + s_red[3][c]);
+}
+
+// ---------------------------------------------------------------------------
+// MFMA contraction with fused row generation.  A wave owns 32 rows of S
+// (k0..k0+31) and PW parameters; per 16 points it loads its 32 x 16 distance
+// tile once and the 16 x 32 tile of Q per column block once, and reuses both
+// for all PW parameters.  MFMA 32x32 operand layout (64 lanes): lane l holds
+// row/column (l mod 32) and the 8 (bf16) or 1 (fp32) reduction indices of
+// half (l / 32); A and B use the same reduction index for the same element.
+// Accumulator element i of lane l is (row 8 (i/4) + 4 (l/32) + i mod 4,
+// column l mod 32).
+// ---------------------------------------------------------------------------
+struct MArgs {
+  const double* params;
+  int64_t m, n;
+  int r, s;
+  const float* D32;       // s x n
+  const uint16_t* Qhi;    // n x r col-major bf16
+  const uint16_t* Qlo;
+  const float* Q32;       // n x r col-major fp32
+  float* G;               // m x s x r
+};
+
+__device__ __forceinline__ void load_dist8(const float* Drow, int64_t j, int64_t n, bool vec, float (&dv)[8]) {
+  if (vec && j + 8 <= n) {
+    const f32x4 a = *reinterpret_cast<const f32x4*>(Drow + j);
+    const f32x4 b = *reinterpret_cast<const f32x4*>(Drow + j + 4);
+    dv[0] = a[0]; dv[1] = a[1]; dv[2] = a[2]; dv[3] = a[3];
+    dv[4] = b[0]; dv[5] = b[1]; dv[6] = b[2]; dv[7] = b[3];
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) dv[e] = (j + e < n) ? Drow[j + e] : __builtin_inff();
+  }
+}
+
+template <int PW, int NB>
+__global__ __launch_bounds__(256) void k_contract_bf16x3(MArgs A) {
+  const int wave = threadIdx.x / 64, l = threadIdx.x % 64;
+  const int k0 = (blockIdx.y * 4 + wave) * 32;
+  if (k0 >= A.s) return;  // uniform per wave
+  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * PW;
+  const int row = k0 + (l & 31);
+  const bool row_ok = row < A.s;
+  const float* Drow = A.D32 + static_cast<int64_t>(row_ok ? row : 0) * A.n;
+  const int jo = 8 * (l >> 5);
+  const bool vec = (A.n & 7) == 0;
+  float cexp[PW];
+#pragma unroll
+  for (int w = 0; w < PW; ++w) {
+    const int64_t p = p0 + w;
+    const double sig = p < A.m ? A.params[p] : 1.0;
+    cexp[w] = krr_param_ok(sig) ? static_cast<float>(-0.5 * kLog2e / (sig * sig)) : 0.0f;
+  }
+  f32x16 acc[PW][NB];
+#pragma unroll
+  for (int w = 0; w < PW; ++w)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[w][nb][i] = 0.0f;
+  for (int64_t j0 = 0; j0 < A.n; j0 += 16) {
+    const int64_t j = j0 + jo;
+    float dv[8];
+    load_dist8(Drow, j, A.n, vec, dv);
+    if (!row_ok)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) dv[e] = __builtin_inff();
+    bf16x8 qh[NB], ql[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int c = nb * 32 + (l & 31);
+      if (c < A.r && vec && j + 8 <= A.n) {
+        qh[nb] = *reinterpret_cast<const bf16x8*>(A.Qhi + static_cast<int64_t>(c) * A.n + j);
+        ql[nb] = *reinterpret_cast<const bf16x8*>(A.Qlo + static_cast<int64_t>(c) * A.n + j);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const bool ok = c < A.r && j + e < A.n;
+          const uint16_t hb = ok ? A.Qhi[static_cast<int64_t>(c) * A.n + j + e] : 0;
+          const uint16_t lb = ok ? A.Qlo[static_cast<int64_t>(c) * A.n + j + e] : 0;
+          qh[nb][e] = __builtin_bit_cast(__bf16, hb);
+          ql[nb][e] = __builtin_bit_cast(__bf16, lb);
+        }
+      }
+    }
+#pragma unroll
+    for (int w = 0; w < PW; ++w) {
+      bf16x8 kh, kl;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float kv = __builtin_amdgcn_exp2f(cexp[w] * dv[e]);
+        const __bf16 h = static_cast<__bf16>(kv);
+        kh[e] = h;
+        kl[e] = static_cast<__bf16>(kv - static_cast<float>(h));
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        acc[w][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kh, qh[nb], acc[w][nb], 0, 0, 0);
+        acc[w][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kh, ql[nb], acc[w][nb], 0, 0, 0);
+        acc[w][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kl, qh[nb], acc[w][nb], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int w = 0; w < PW; ++w) {
+    const int64_t p = p0 + w;
+    if (p >= A.m) continue;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int c = nb * 32 + (l & 31);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int rr = k0 + 8 * (i / 4) + 4 * (l >> 5) + (i & 3);
+        if (rr < A.s && c < A.r) A.G[(p * A.s + rr) * A.r + c] = acc[w][nb][i];
+      }
+    }
+  }
+}
+
+template <int PW, int NB>
+__global__ __launch_bounds__(256) void k_contract_f32(MArgs A) {
+  const int wave = threadIdx.x / 64, l = threadIdx.x % 64;
+  const int k0 = (blockIdx.y * 4 + wave) * 32;
+  if (k0 >= A.s) return;
+  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * PW;
+  const int row = k0 + (l & 31);
+  const bool row_ok = row < A.s;
+  const float* Drow = A.D32 + static_cast<int64_t>(row_ok ? row : 0) * A.n;
+  const int jo = 8 * (l >> 5);
+  const bool vec = (A.n & 7) == 0;
+  float cexp[PW];
+#pragma unroll
+  for (int w = 0; w < PW; ++w) {
+    const int64_t p = p0 + w;
+    const double sig = p < A.m ? A.params[p] : 1.0;
+    cexp[w] = krr_param_ok(sig) ? static_cast<float>(-0.5 * kLog2e / (sig * sig)) : 0.0f;
+  }
+  f32x16 acc[PW][NB];
+#pragma unroll
+  for (int w = 0; w < PW; ++w)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[w][nb][i] = 0.0f;
+  for (int64_t j0 = 0; j0 < A.n; j0 += 16) {
+    const int64_t j = j0 + jo;
+    float dv[8];
+    load_dist8(Drow, j, A.n, vec, dv);
+    if (!row_ok)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) dv[e] = __builtin_inff();
+    float qv[NB][8];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int c = nb * 32 + (l & 31);
+      const float* qc = A.Q32 + static_cast<int64_t>(c < A.r ? c : 0) * A.n;
+      float tmp[8];
+      load_dist8(qc, j, A.n, vec, tmp);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) qv[nb][e] = (c < A.r && j + e < A.n) ? tmp[e] : 0.0f;
+    }
+#pragma unroll
+    for (int w = 0; w < PW; ++w) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float kv = __builtin_amdgcn_exp2f(cexp[w] * dv[e]);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[w][nb] = __builtin_amdgcn_mfma_f32_32x32x2f32(kv, qv[nb][e], acc[w][nb], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int w = 0; w < PW; ++w) {
+    const int64_t p = p0 + w;
+    if (p >= A.m) continue;
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int c = nb * 32 + (l & 31);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int rr = k0 + 8 * (i / 4) + 4 * (l >> 5) + (i & 3);
+        if (rr < A.s && c < A.r) A.G[(p * A.s + rr) * A.r + c] = acc[w][nb][i];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Least squares from a contraction in global memory: one team per p.
+// G_full = G + lambda Q_S.  Stores the factorisation for refinement.
+// ---------------------------------------------------------------------------
+struct LArgs {
+  const double* params;
+  int64_t m;
+  int r, s;
+  const void* G;          // float or double, m x s x r
+  const double* QS;       // s x r
+  const double* bS;
+  double lambda, bS_norm;
+  double* y;
+  double* rho;
+  int32_t* status;
+  double* fac;            // m x fac_stride, or nullptr
+  int fac_stride;
+};
+
+template <int TEAM, int R, int RM>
+__device__ __forceinline__ int fac_index(int q, int c, int lane) {
+  return (q * RM + c) * TEAM + lane;
+}
+
+template <int TEAM, int R, int RM, typename GT>
+__global__ __launch_bounds__(256) void k_lsq(LArgs A) {
+  constexpr int TEAMS = 256 / TEAM;
+  __shared__ double s_tau[TEAMS][RM];
+  __shared__ double s_y[TEAMS][RM];
+  const int team = threadIdx.x / TEAM, lane = threadIdx.x % TEAM;
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * TEAMS + team;
+  if (p >= A.m) return;
+  const int r = A.r, s = A.s;
+  const GT* G = static_cast<const GT*>(A.G);
+  TeamQR<TEAM, R, RM> qr;
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = lane + TEAM * q;
+#pragma unroll
+    for (int c = 0; c < RM; ++c)
+      qr.a[q][c] = (k < s && c < r)
+                       ? static_cast<double>(G[(p * s + k) * r + c]) + A.lambda * A.QS[k * r + c]
+                       : 0.0;
+    qr.b[q] = k < s ? A.bS[k] : 0.0;
+  }
+  qr.factor(r, lane, s_tau[team]);
+  const double tail = qr.tail_norm(qr.b, r, lane);
+  double x[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) x[q] = qr.b[q];
+  qr.back_substitute(x, r, lane, s_y[team]);
+  const double sig = A.params[p];
+  bool yfin = true;
+  for (int c = 0; c < r; ++c) yfin = yfin && isfinite(s_y[team][c]);
+  int32_t code = SUBAP_OK;
+  if (!krr_param_ok(sig)) code = SUBAP_E_NONFINITE;
+  else if (!qr.full_rank) code = SUBAP_E_RANK;
+  else if (!yfin) code = SUBAP_E_NONFINITE;
+  for (int c = lane; c < r; c += TEAM)
+    A.y[p * r + c] = code == SUBAP_OK ? s_y[team][c] : __longlong_as_double(0x7ff8000000000000LL);
+  if (lane == 0) {
+    if (A.rho) A.rho[p] = tail / A.bS_norm;
+    if (A.status) A.status[p] = code;
+  }
+  if (A.fac) {
+    double* f = A.fac + p * A.fac_stride;
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+#pragma unroll
+      for (int c = 0; c < RM; ++c) f[fac_index<TEAM, R, RM>(q, c, lane)] = qr.a[q][c];
+    for (int j = lane; j < RM; j += TEAM) f[TEAM * R * RM + j] = s_tau[team][j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Refinement, part 1: partial sums of K_S(p) z, z = Q y, over a range of
+// points, with FP64-accurate kernel entries.  Block: PB parameters x one
+// point range; thread = selected row k.
+// ---------------------------------------------------------------------------
+constexpr int kRefPB = 8;      // parameters per block
+constexpr int kRefNJ = 256;    // points per LDS chunk
+constexpr int kRefSplit = 8;   // point ranges (grid.y)
+
+template <int RM>
+__global__ __launch_bounds__(256) void k_refine_partial(const double* params, int64_t m, int64_t n, int r,
+                                                         int s, const double* Dt64, const double* Qrm,
+                                                         const double* y, double* part) {
+  __shared__ double s_tab[64];
+  __shared__ double s_y[kRefPB][RM];
+  __shared__ double s_z[kRefNJ][kRefPB];
+  const int t = threadIdx.x;
+  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * kRefPB;
+  load_exp_table(s_tab);
+  for (int idx = t; idx < kRefPB * RM; idx += blockDim.x) {
+    const int w = idx / RM, c = idx % RM;
+    s_y[w][c] = (p0 + w < m && c < r) ? y[(p0 + w) * r + c] : 0.0;
+  }
+  double cexp[kRefPB];
+#pragma unroll
+  for (int w = 0; w < kRefPB; ++w) {
+    const double sig = p0 + w < m ? params[p0 + w] : 1.0;
+    cexp[w] = krr_param_ok(sig) ? -0.5 / (sig * sig) : 0.0;
+  }
+  double acc[kRefPB];
+#pragma unroll
+  for (int w = 0; w < kRefPB; ++w) acc[w] = 0.0;
+  const int64_t per = (n + kRefSplit - 1) / kRefSplit;
+  const int64_t jb = blockIdx.y * per, je = std::min<int64_t>(n, jb + per);
+  for (int64_t j0 = jb; j0 < je; j0 += kRefNJ) {
+    __syncthreads();
+    for (int idx = t; idx < kRefNJ * kRefPB; idx += blockDim.x) {
+      const int jj = idx / kRefPB, w = idx % kRefPB;
+      const int64_t j = j0 + jj;
+      double z = 0.0;
+      if (j < je)
+        for (int c = 0; c < r; ++c) z = fma(Qrm[j * r + c], s_y[w][c], z);
+      s_z[jj][w] = z;
+    }
+    __syncthreads();
+    if (t < s) {
+      const int cnt = static_cast<int>(std::min<int64_t>(kRefNJ, je - j0));
+      for (int jj = 0; jj < cnt; ++jj) {
+        const double d = Dt64[(j0 + jj) * s + t];
+#pragma unroll
+        for (int w = 0; w < kRefPB; ++w) acc[w] = fma(exp_tab(cexp[w] * d, s_tab), s_z[jj][w], acc[w]);
+      }
+    }
+  }
+  if (t < s)
+#pragma unroll
+    for (int w = 0; w < kRefPB; ++w)
+      if (p0 + w < m) part[(static_cast<int64_t>(blockIdx.y) * m + p0 + w) * s + t] = acc[w];
+}
+
+// Refinement, part 2: r_S = sum of partials + lambda Q_S y - b_S; y -= R^{-1} Q^T r_S.
+struct CArgs {
+  int64_t m;
+  int r, s;
+  const double* part;
+  const double* QS;
+  const double* bS;
+  double lambda, bS_norm;
+  const double* fac;
+  int fac_stride;
+  double* y;
+  double* rho;
+  const int32_t* status;
+};
+
+template <int TEAM, int R, int RM>
+__global__ __launch_bounds__(256) void k_correct(CArgs A) {
+  constexpr int TEAMS = 256 / TEAM;
+  __shared__ double s_tau[TEAMS][RM];
+  __shared__ double s_y[TEAMS][RM];
+  __shared__ double s_dy[TEAMS][RM];
+  const int team = threadIdx.x / TEAM, lane = threadIdx.x % TEAM;
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * TEAMS + team;
+  if (p >= A.m) return;
+  if (A.status && A.status[p] != SUBAP_OK) return;  // y already NaN
+  const int r = A.r, s = A.s;
+  TeamQR<TEAM, R, RM> qr;
+  const double* f = A.fac + p * A.fac_stride;
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+#pragma unroll
+    for (int c = 0; c < RM; ++c) qr.a[q][c] = f[fac_index<TEAM, R, RM>(q, c, lane)];
+  for (int j = 0; j < RM; ++j) s_tau[team][j] = f[TEAM * R * RM + j];
+  for (int c = 0; c < RM; ++c) s_y[team][c] = c < r ? A.y[p * r + c] : 0.0;
+  double res[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = lane + TEAM * q;
+    double t = 0.0;
+    if (k < s) {
+      for (int sp = 0; sp < kRefSplit; ++sp) t += A.part[(static_cast<int64_t>(sp) * A.m + p) * s + k];
+      double zs = 0.0;
+      for (int c = 0; c < r; ++c) zs = fma(A.QS[k * r + c], s_y[team][c], zs);
+      t += A.lambda * zs - A.bS[k];
+    }
+    res[q] = k < s ? t : 0.0;
+  }
+  qr.apply_qt(res, r, lane, s_tau[team]);
+  const double tail = qr.tail_norm(res, r, lane);
+  qr.back_substitute(res, r, lane, s_dy[team]);
+  for (int c = lane; c < r; c += TEAM) A.y[p * r + c] = s_y[team][c] - s_dy[team][c];
+  if (lane == 0 && A.rho) A.rho[p] = tail / A.bS_norm;
+}
+
+// Sketched residual from the partial sums: one wavefront per parameter.
+__global__ __launch_bounds__(256) void k_resid_finish(const double* params, int64_t m, int r, int s,
+                                                       const double* part, const double* QS, const double* bS,
+                                                       double lambda, double bS_norm, const double* y,
+                                                       double* res, double* norm) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  if (p >= m) return;
+  const bool ok = krr_param_ok(params[p]);
+  double ss = 0.0;
+  for (int k = lane; k < s; k += 64) {
+    double t = 0.0;
+    for (int sp = 0; sp < kRefSplit; ++sp) t += part[(static_cast<int64_t>(sp) * m + p) * s + k];
+    double zs = 0.0;
+    for (int c = 0; c < r; ++c) zs = fma(QS[k * r + c], y[p * r + c], zs);
+    t += lambda * zs - bS[k];
+    if (!ok) t = __longlong_as_double(0x7ff8000000000000LL);
+    if (res) res[p * s + k] = t;
+    ss += t * t;
+  }
+  ss = team_sum<64>(ss);
+  if (lane == 0 && norm) norm[p] = sqrt(ss) / bS_norm;
+}
+
+// ---------------------------------------------------------------------------
+// dispatch helpers
+// ---------------------------------------------------------------------------
+struct Shape {
+  int team, R, RM;
+};
+
+bool pick_shape(int s, int r, Shape* out) {
+  static const Shape kShapes[] = {
+      {16, 1, 8}, {16, 1, 16}, {32, 1, 8}, {32, 1, 16}, {32, 1, 32}, {64, 1, 16},
+      {64, 1, 32}, {64, 1, 40}, {64, 2, 16}, {64, 2, 32}, {64, 2, 40}, {64, 3, 32}, {64, 3, 40},
+      {64, 4, 40}};
+  for (const Shape& sh : kShapes)
+    if (s <= sh.team * sh.R && r <= sh.RM) {
+      *out = sh;
+      return true;
+    }
+  return false;
+}
+
+template <typename GT>
+subap_status launch_lsq(const Shape& sh, const LArgs& a, hipStream_t st) {
+  const unsigned grid = static_cast<unsigned>((a.m * sh.team + 255) / 256);
+#define SUBAP_LSQ(T_, R_, M_)                                                              \
+  if (sh.team == T_ && sh.R == R_ && sh.RM == M_) {                                      \
+    hipLaunchKernelGGL((k_lsq<T_, R_, M_, GT>), dim3(grid), dim3(256), 0, st, a);        \
+    SUBAP_HIP_TRY(hipGetLastError());                                                    \
+    return SUBAP_OK;                                                                     \
+  }
+  SUBAP_LSQ(16, 1, 8) SUBAP_LSQ(16, 1, 16) SUBAP_LSQ(32, 1, 8) SUBAP_LSQ(32, 1, 16) SUBAP_LSQ(32, 1, 32)
+  SUBAP_LSQ(64, 1, 16) SUBAP_LSQ(64, 1, 32) SUBAP_LSQ(64, 1, 40)
+  SUBAP_LSQ(64, 2, 16) SUBAP_LSQ(64, 2, 32) SUBAP_LSQ(64, 2, 40)
+  SUBAP_LSQ(64, 3, 32) SUBAP_LSQ(64, 3, 40) SUBAP_LSQ(64, 4, 40)
+#undef SUBAP_LSQ
+  set_error("no least-squares kernel for this (s, r)");
+  return SUBAP_E_UNSUPPORTED;
+}
+
+subap_status launch_correct(const Shape& sh, const CArgs& a, hipStream_t st) {
+  const unsigned grid = static_cast<unsigned>((a.m * sh.team + 255) / 256);
+#define SUBAP_COR(T_, R_, M_)                                                        \
+  if (sh.team == T_ && sh.R == R_ && sh.RM == M_) {                                \
+    hipLaunchKernelGGL((k_correct<T_, R_, M_>), dim3(grid), dim3(256), 0, st, a);  \
+    SUBAP_HIP_TRY(hipGetLastError());                                              \
+    return SUBAP_OK;                                                               \
+  }
+  SUBAP_COR(16, 1, 8) SUBAP_COR(16, 1, 16) SUBAP_COR(32, 1, 8) SUBAP_COR(32, 1, 16) SUBAP_COR(32, 1, 32)
+  SUBAP_COR(64, 1, 16) SUBAP_COR(64, 1, 32) SUBAP_COR(64, 1, 40)
+  SUBAP_COR(64, 2, 16) SUBAP_COR(64, 2, 32) SUBAP_COR(64, 2, 40)
+  SUBAP_COR(64, 3, 32) SUBAP_COR(64, 3, 40) SUBAP_COR(64, 4, 40)
+#undef SUBAP_COR
+  set_error("no correction kernel for this (s, r)");
+  return SUBAP_E_UNSUPPORTED;
+}
+
+int rm_of(int r) { return r <= 8 ? 8 : r <= 16 ? 16 : r <= 32 ? 32 : r <= 40 ? 40 : 64; }
+
+}  // namespace
+
+subap_status launch_refine_partial(subap_model_s* M, const double* params, int64_t m, const double* y,
+                                   double* part, hipStream_t st);
+
+subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double* y, double* rho,
+                       int32_t* status, int prec, int refine, hipStream_t st) {
+  const int r = M->r, s = M->s;
+  const int64_t n = M->n;
+  Shape sh;
+  if (!pick_shape(s, r, &sh)) {
+    set_error("no least-squares kernel for this (s, r)");
+    return SUBAP_E_UNSUPPORTED;
+  }
+  const int RM = rm_of(r);
+  const size_t gbytes = static_cast<size_t>(m) * s * r * (prec == SUBAP_FP64 ? 8 : 4);
+  const int fac_stride = sh.team * sh.R * sh.RM + sh.RM;
+  const size_t fbytes = refine > 0 ? static_cast<size_t>(m) * fac_stride * 8 : 0;
+  const size_t pbytes = refine > 0 ? static_cast<size_t>(kRefSplit) * m * s * 8 : 0;
+  const size_t stbytes = static_cast<size_t>(m) * 4;
+  auto al = [](size_t b) { return (b + 255) & ~static_cast<size_t>(255); };
+  SUBAP_TRY(ensure_work(M, al(gbytes) + al(fbytes) + al(pbytes) + al(stbytes)));
+  char* w = static_cast<char*>(M->work);
+  void* G = w;
+  double* fac = refine > 0 ? reinterpret_cast<double*>(w + al(gbytes)) : nullptr;
+  double* part = refine > 0 ? reinterpret_cast<double*>(w + al(gbytes) + al(fbytes)) : nullptr;
+  int32_t* stat = status ? status : reinterpret_cast<int32_t*>(w + al(gbytes) + al(fbytes) + al(pbytes));
+
+  // A1 + A2: rows and contraction
+  if (prec == SUBAP_FP64) {
+    double* Gd = static_cast<double*>(G);
+    if (m >= 32) {
+      ProfScope prof("krr_contract_fp64", st);
+      constexpr int KR = 2;
+      dim3 grid(static_cast<unsigned>((m + 63) / 64), static_cast<unsigned>((s + 4 * KR - 1) / (4 * KR)));
+      switch (RM) {
+        case 8: hipLaunchKernelGGL((k_contract_f64<KR, 8>), grid, dim3(256), 0, st, params, m, n, r, s, M->Dt64, M->Qrm, Gd); break;
+        case 16: hipLaunchKernelGGL((k_contract_f64<KR, 16>), grid, dim3(256), 0, st, params, m, n, r, s, M->Dt64, M->Qrm, Gd); break;
+        case 32: hipLaunchKernelGGL((k_contract_f64<KR, 32>), grid, dim3(256), 0, st, params, m, n, r, s, M->Dt64, M->Qrm, Gd); break;
+        case 40: hipLaunchKernelGGL((k_contract_f64<1, 40>), dim3(grid.x, (s + 3) / 4), dim3(256), 0, st, params, m, n, r, s, M->Dt64, M->Qrm, Gd); break;
+        default: hipLaunchKernelGGL((k_contract_f64<1, 64>), dim3(grid.x, (s + 3) / 4), dim3(256), 0, st, params, m, n, r, s, M->Dt64, M->Qrm, Gd); break;
+      }
+    } else {
+      ProfScope prof("krr_contract_fp64_small", st);
+      dim3 grid(static_cast<unsigned>(m), static_cast<unsigned>(s));
+      switch (RM) {
+        case 8: hipLaunchKernelGGL((k_contract_f64_small<8>), grid, dim3(256), 0, st, params, n, r, s, M->Dt64, M->Qrm, Gd); break;
+        case 16: hipLaunchKernelGGL((k_contract_f64_small<16>), grid, dim3(256), 0, st, params, n, r, s, M->Dt64, M->Qrm, Gd); break;
+        case 32: hipLaunchKernelGGL((k_contract_f64_small<32>), grid, dim3(256), 0, st, params, n, r, s, M->Dt64, M->Qrm, Gd); break;
+        case 40: hipLaunchKernelGGL((k_contract_f64_small<40>), grid, dim3(256), 0, st, params, n, r, s, M->Dt64, M->Qrm, Gd); break;
+        default: hipLaunchKernelGGL((k_contract_f64_small<64>), grid, dim3(256), 0, st, params, n, r, s, M->Dt64, M->Qrm, Gd); break;
+      }
+    }
+  } else {
+    MArgs a{params, m, n, r, s, M->D32, M->Qhi, M->Qlo, M->Q32, static_cast<float*>(G)};
+    constexpr int PW = 8;
+    dim3 grid(static_cast<unsigned>((m + PW - 1) / PW), static_cast<unsigned>((s + 127) / 128));
+    if (prec == SUBAP_BF16X3) {
+      ProfScope prof("krr_contract_bf16x3", st);
+      if (r <= 32) hipLaunchKernelGGL((k_contract_bf16x3<PW, 1>), grid, dim3(256), 0, st, a);
+      else hipLaunchKernelGGL((k_contract_bf16x3<4, 2>), dim3((m + 3) / 4, grid.y), dim3(256), 0, st, a);
+    } else {
+      ProfScope prof("krr_contract_fp32", st);
+      if (r <= 32) hipLaunchKernelGGL((k_contract_f32<PW, 1>), grid, dim3(256), 0, st, a);
+      else hipLaunchKernelGGL((k_contract_f32<4, 2>), dim3((m + 3) / 4, grid.y), dim3(256), 0, st, a);
+    }
+  }
+  SUBAP_HIP_TRY(hipGetLastError());
+  // A3: least squares
+  LArgs la{params, m, r, s, G, M->QS, M->bS, M->lambda, M->bS_norm, y, rho, stat, fac, fac_stride};
+  {
+    ProfScope prof("lsq_householder", st);
+    if (prec == SUBAP_FP64) SUBAP_TRY(launch_lsq<double>(sh, la, st));
+    else SUBAP_TRY(launch_lsq<float>(sh, la, st));
+  }
+  // A4: refinement
+  for (int it = 0; it < refine; ++it) {
+    SUBAP_TRY(launch_refine_partial(M, params, m, y, part, st));
+    CArgs ca{m, r, s, part, M->QS, M->bS, M->lambda, M->bS_norm, fac, fac_stride, y, rho, stat};
+    ProfScope prof("lsq_correct", st);
+    SUBAP_TRY(launch_correct(sh, ca, st));
+  }
+  return SUBAP_OK;
+}
+
+subap_status krr_residual(subap_model_s* M, const double* params, int64_t m, const double* y, double* res,
+                          double* norm, hipStream_t st) {
+  const int s = M->s;
+  SUBAP_TRY(ensure_work(M, static_cast<size_t>(kRefSplit) * m * s * 8));
+  double* part = static_cast<double*>(M->work);
+  SUBAP_TRY(launch_refine_partial(M, params, m, y, part, st));
+  ProfScope prof("krr_resid_finish", st);
+  hipLaunchKernelGGL(k_resid_finish, dim3(static_cast<unsigned>((m + 3) / 4)), dim3(256), 0, st, params, m,
+                     M->r, s, part, M->QS, M->bS, M->lambda, M->bS_norm, y, res, norm);
+  SUBAP_HIP_TRY(hipGetLastError());
+  return SUBAP_OK;
+}
+
+// (refinement partial-sum launcher, shared by the solve and the residual)
+subap_status launch_refine_partial(subap_model_s* M, const double* params, int64_t m, const double* y,
+                                   double* part, hipStream_t st) {
+  const int r = M->r, s = M->s;
+  const int64_t n = M->n;
+  const int RM = rm_of(r);
+  {
+    ProfScope prof("krr_refine_partial", st);
+    dim3 grid(static_cast<unsigned>((m + kRefPB - 1) / kRefPB), kRefSplit);
+    const int threads = std::max(64, (s + 63) / 64 * 64);
+    switch (RM) {
+      case 8: hipLaunchKernelGGL((k_refine_partial<8>), grid, dim3(threads), 0, st, params, m, n, r, s, M->Dt64, M->Qrm, y, part); break;
+      case 16: hipLaunchKernelGGL((k_refine_partial<16>), grid, dim3(threads), 0, st, params, m, n, r, s, M->Dt64, M->Qrm, y, part); break;
+      case 32: hipLaunchKernelGGL((k_refine_partial<32>), grid, dim3(threads), 0, st, params, m, n, r, s, M->Dt64, M->Qrm, y, part); break;
+      case 40: hipLaunchKernelGGL((k_refine_partial<40>), grid, dim3(threads), 0, st, params, m, n, r, s, M->Dt64, M->Qrm, y, part); break;
+      default: hipLaunchKernelGGL((k_refine_partial<64>), grid, dim3(threads), 0, st, params, m, n, r, s, M->Dt64, M->Qrm, y, part); break;
+    }
+  }
+  SUBAP_HIP_TRY(hipGetLastError());
+  return SUBAP_OK;
+}
+
+}  // namespace subap

@@ -1,0 +1,754 @@
+// Offline phase of SubApSnap on the GPU (Algorithm 3.1, steps 1-3):
+//   1. snapshot solves A(p_i) x_i = b(p_i) by (Jacobi-)preconditioned
+//      conjugate gradients, all r systems advanced together;
+//   2. Householder QR of the n x r snapshot matrix, Q formed explicitly,
+//      signs fixed so that diag(R) > 0 (Section 3.1);
+//   3. row selection by rounds of column-pivoted QR on M = (A(p_sel) Q)^T
+//      (Section 5.3), and the per-row tables of the online kernels.
+// Reductions are two-stage (fixed block partials, then one ordered pass) so
+// every result is bitwise reproducible from run to run.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "family.h"
+
+namespace subap {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kMaxPartials = 512;
+
+// ----------------------------------------------------------------------------
+// Operator application Y[:, c] = A(p_c) X[:, c], one parameter per column.
+// ----------------------------------------------------------------------------
+struct OpArgs {
+  int family;
+  int N;           // FD nodes per axis
+  int dimx;        // FD spatial dim / KRR point dim
+  int64_t n;
+  int d;
+  double h, inv_h2;
+  double lambda;
+  const double* points;   // KRR n x dimx
+};
+
+__device__ __forceinline__ void fd_node(int64_t i, int N, int dimx, int* c) {
+  c[0] = static_cast<int>(i % N);
+  c[1] = static_cast<int>((i / N) % N);
+  c[2] = dimx == 3 ? static_cast<int>(i / (static_cast<int64_t>(N) * N)) : 0;
+}
+
+// coefficient a at the midpoint of face f (axis f/2, side f%2: 0 low, 1 high)
+__device__ __forceinline__ double fd_face_coeff(const int* c, int f, int dimx, double h, const double* p) {
+  double x[3];
+  for (int a = 0; a < 3; ++a) x[a] = (c[a] + 1) * h;
+  x[f / 2] += (f % 2 == 0 ? -0.5 : 0.5) * h;
+  double phi[4];
+  double t = 0.0;
+  if (dimx == 2) {
+    modes2d(x[0], x[1], phi);
+    t = p[0] * phi[0] + p[1] * phi[1];
+  } else {
+    modes3d(x[0], x[1], x[2], phi);
+    t = p[0] * phi[0] + p[1] * phi[1] + p[2] * phi[2] + p[3] * phi[3];
+  }
+  return exp(t);
+}
+
+__global__ void k_fd_apply(OpArgs A, const double* params, int ncol, const double* X,
+                           double* Y, double* diag_out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int col = blockIdx.y;
+  if (i >= A.n || col >= ncol) return;
+  const double* p = params + static_cast<int64_t>(col) * A.d;
+  int c[3];
+  fd_node(i, A.N, A.dimx, c);
+  const double* x = X + static_cast<int64_t>(col) * A.n;
+  const double xi = x[i];
+  double acc = 0.0, dg = 0.0;
+  const int F = 2 * A.dimx;
+  for (int f = 0; f < F; ++f) {
+    const double af = fd_face_coeff(c, f, A.dimx, A.h, p) * A.inv_h2;
+    dg += af;
+    const int axis = f / 2;
+    const int nbc = c[axis] + (f % 2 == 0 ? -1 : 1);
+    double xn = 0.0;
+    if (nbc >= 0 && nbc < A.N) {
+      int64_t stride = axis == 0 ? 1 : (axis == 1 ? A.N : static_cast<int64_t>(A.N) * A.N);
+      xn = x[i + (f % 2 == 0 ? -stride : stride)];
+    }
+    acc += af * (xi - xn);
+  }
+  if (Y) Y[static_cast<int64_t>(col) * A.n + i] = acc;
+  if (diag_out) diag_out[static_cast<int64_t>(col) * A.n + i] = dg;
+}
+
+// KRR: Y[i, c] = sum_j exp(-|t_i - t_j|^2 / (2 p_c^2)) X[j, c] + lambda X[i, c]
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_krr_apply(OpArgs A, const double* params, int ncol,
+                                                      const double* X, double* Y) {
+  __shared__ double tj[kBlock][DIM];
+  __shared__ double xj[kBlock];
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  const int col = blockIdx.y;
+  const double sig = params[col];
+  const double cexp = -1.0 / (2.0 * sig * sig);
+  const double* x = X + static_cast<int64_t>(col) * A.n;
+  double ti[DIM];
+  for (int q = 0; q < DIM; ++q) ti[q] = (i < A.n) ? A.points[i * DIM + q] : 0.0;
+  double acc = 0.0;
+  for (int64_t j0 = 0; j0 < A.n; j0 += kBlock) {
+    const int64_t j = j0 + threadIdx.x;
+    __syncthreads();
+    for (int q = 0; q < DIM; ++q) tj[threadIdx.x][q] = (j < A.n) ? A.points[j * DIM + q] : 0.0;
+    xj[threadIdx.x] = (j < A.n) ? x[j] : 0.0;
+    __syncthreads();
+    const int cnt = static_cast<int>(min<int64_t>(kBlock, A.n - j0));
+    for (int jj = 0; jj < cnt; ++jj) {
+      double d2 = 0.0;
+#pragma unroll
+      for (int q = 0; q < DIM; ++q) {
+        const double df = ti[q] - tj[jj][q];
+        d2 += df * df;
+      }
+      acc += exp(cexp * d2) * xj[jj];
+    }
+  }
+  if (i < A.n) Y[static_cast<int64_t>(col) * A.n + i] = acc + A.lambda * x[i];
+}
+
+subap_status apply_op(const OpArgs& A, const double* params_d, int ncol, const double* X,
+                      double* Y, double* diag, hipStream_t st) {
+  dim3 grid(static_cast<unsigned>((A.n + kBlock - 1) / kBlock), ncol);
+  if (A.family == SUBAP_FAMILY_KRR) {
+    switch (A.dimx) {
+#define SUBAP_KRR_CASE(D) \
+  case D: hipLaunchKernelGGL(k_krr_apply<D>, grid, dim3(kBlock), 0, st, A, params_d, ncol, X, Y); break;
+      SUBAP_KRR_CASE(1) SUBAP_KRR_CASE(2) SUBAP_KRR_CASE(3) SUBAP_KRR_CASE(4)
+      SUBAP_KRR_CASE(5) SUBAP_KRR_CASE(6) SUBAP_KRR_CASE(7) SUBAP_KRR_CASE(8)
+      SUBAP_KRR_CASE(9) SUBAP_KRR_CASE(10) SUBAP_KRR_CASE(11) SUBAP_KRR_CASE(12)
+      SUBAP_KRR_CASE(13) SUBAP_KRR_CASE(14) SUBAP_KRR_CASE(15) SUBAP_KRR_CASE(16)
+#undef SUBAP_KRR_CASE
+      default:
+        set_error("KRR point dimension must be 1..16");
+        return SUBAP_E_INVALID;
+    }
+  } else {
+    hipLaunchKernelGGL(k_fd_apply, grid, dim3(kBlock), 0, st, A, params_d, ncol, X, Y, diag);
+  }
+  SUBAP_HIP_TRY(hipGetLastError());
+  return SUBAP_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Column reductions: out[c] = sum_{i in [row0, n)} a[i + lda c] * b[i + ldb c]
+// (ldb = 0 broadcasts one vector against every column).
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < static_cast<int>(blockDim.x / 64); ++k) t += sh[k];
+  return t;  // valid in thread 0
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot_partial(const double* a, int64_t lda, const double* b,
+                                                        int64_t ldb, int64_t row0, int64_t n,
+                                                        double* part, int nblk) {
+  __shared__ double sh[kBlock / 64];
+  const int col = blockIdx.y;
+  const double* ac = a + lda * col;
+  const double* bc = b + ldb * col;
+  double acc = 0.0;
+  for (int64_t i = row0 + static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(nblk) * kBlock)
+    acc += ac[i] * bc[i];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[static_cast<int64_t>(col) * nblk + blockIdx.x] = acc;
+}
+
+__global__ void k_dot_finish(const double* part, int nblk, int ncol, double* out) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= ncol) return;
+  double t = 0.0;
+  for (int k = 0; k < nblk; ++k) t += part[static_cast<int64_t>(col) * nblk + k];
+  out[col] = t;
+}
+
+int nblocks_for(int64_t len) {
+  int64_t b = (len + kBlock * 8 - 1) / (kBlock * 8);
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(b, kMaxPartials)));
+}
+
+subap_status col_dots(const double* a, int64_t lda, const double* b, int64_t ldb, int64_t row0,
+                      int64_t n, int ncol, double* part, double* out, hipStream_t st) {
+  const int nb = nblocks_for(n - row0);
+  hipLaunchKernelGGL(k_dot_partial, dim3(nb, ncol), dim3(kBlock), 0, st, a, lda, b, ldb, row0, n, part, nb);
+  hipLaunchKernelGGL(k_dot_finish, dim3((ncol + 63) / 64), dim3(64), 0, st, part, nb, ncol, out);
+  SUBAP_HIP_TRY(hipGetLastError());
+  return SUBAP_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Conjugate gradients on r systems at once (column c has its own p_c).
+// Scalars live on the device; the host checks convergence every few steps.
+// ----------------------------------------------------------------------------
+__global__ void k_cg_init(int64_t n, int ncol, const double* b, int64_t ldb, const double* dinv,
+                          double* x, double* r, double* z, double* p) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n) return;
+  const int64_t k = static_cast<int64_t>(c) * n + i;
+  const double bi = b[ldb * c + i];
+  x[k] = 0.0;
+  r[k] = bi;
+  const double zi = dinv ? bi * dinv[k] : bi;
+  z[k] = zi;
+  p[k] = zi;
+}
+
+// alpha_c = rz_c / pq_c (0 once the column has converged)
+__global__ void k_cg_alpha(int ncol, const double* rz, const double* pq, const int* done, double* alpha) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  alpha[c] = (done[c] || pq[c] == 0.0) ? 0.0 : rz[c] / pq[c];
+}
+
+__global__ void k_cg_update_xr(int64_t n, const double* alpha, const double* p, const double* q,
+                               const double* dinv, double* x, double* r, double* z) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n) return;
+  const int64_t k = static_cast<int64_t>(c) * n + i;
+  const double a = alpha[c];
+  x[k] += a * p[k];
+  const double ri = r[k] - a * q[k];
+  r[k] = ri;
+  z[k] = dinv ? ri * dinv[k] : ri;
+}
+
+__global__ void k_cg_beta(int ncol, const double* rz_new, double* rz, const int* done, double* beta) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  beta[c] = (done[c] || rz[c] == 0.0) ? 0.0 : rz_new[c] / rz[c];
+  if (!done[c]) rz[c] = rz_new[c];
+}
+
+__global__ void k_cg_update_p(int64_t n, const double* beta, const int* done, const double* z, double* p) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n || done[c]) return;
+  const int64_t k = static_cast<int64_t>(c) * n + i;
+  p[k] = z[k] + beta[c] * p[k];
+}
+
+__global__ void k_recip(int64_t len, double* v) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < len) v[i] = 1.0 / v[i];
+}
+
+struct DevVec {
+  double* p = nullptr;
+  ~DevVec() { dfree(p); }
+};
+
+subap_status snapshot_cg(const OpArgs& A, const double* params_d, int r, const double* b_d,
+                         double tol, int maxiter, double* X, hipStream_t st) {
+  const int64_t n = A.n;
+  const int64_t nr = n * r;
+  DevVec R, Z, P, Qv, Dinv, scal;
+  SUBAP_TRY(dalloc(&R.p, nr));
+  SUBAP_TRY(dalloc(&Z.p, nr));
+  SUBAP_TRY(dalloc(&P.p, nr));
+  SUBAP_TRY(dalloc(&Qv.p, nr));
+  SUBAP_TRY(dalloc(&scal.p, 8 * r + static_cast<size_t>(kMaxPartials) * r + r));
+  double* rz = scal.p;
+  double* rz_new = rz + r;
+  double* pq = rz + 2 * r;
+  double* alpha = rz + 3 * r;
+  double* beta = rz + 4 * r;
+  double* rr = rz + 5 * r;
+  double* bb = rz + 6 * r;
+  int* done = reinterpret_cast<int*>(rz + 7 * r);
+  double* part = rz + 8 * r;
+  const double* dinv = nullptr;
+  if (A.family != SUBAP_FAMILY_KRR) {  // Jacobi: 1 / diag(A(p_c))
+    SUBAP_TRY(dalloc(&Dinv.p, nr));
+    SUBAP_TRY(apply_op(A, params_d, r, X, nullptr, Dinv.p, st));
+    hipLaunchKernelGGL(k_recip, dim3((nr + kBlock - 1) / kBlock), dim3(kBlock), 0, st, nr, Dinv.p);
+    dinv = Dinv.p;
+  }
+  SUBAP_HIP_TRY(hipMemsetAsync(done, 0, sizeof(int) * r, st));
+  dim3 g2(static_cast<unsigned>((n + kBlock - 1) / kBlock), r);
+  dim3 gs((r + 63) / 64);
+  hipLaunchKernelGGL(k_cg_init, g2, dim3(kBlock), 0, st, n, r, b_d, int64_t(0), dinv, X, R.p, Z.p, P.p);
+  SUBAP_TRY(col_dots(R.p, n, Z.p, n, 0, n, r, part, rz, st));
+  SUBAP_TRY(col_dots(b_d, 0, b_d, 0, 0, n, r, part, bb, st));
+  std::vector<double> h_rr(r), h_bb(r);
+  std::vector<int> h_done(r, 0);
+  SUBAP_HIP_TRY(hipMemcpyAsync(h_bb.data(), bb, sizeof(double) * r, hipMemcpyDeviceToHost, st));
+  SUBAP_HIP_TRY(hipStreamSynchronize(st));
+  const int check_every = 16;
+  bool all_done = false;
+  for (int it = 0; it < maxiter && !all_done; ++it) {
+    SUBAP_TRY(apply_op(A, params_d, r, P.p, Qv.p, nullptr, st));
+    SUBAP_TRY(col_dots(P.p, n, Qv.p, n, 0, n, r, part, pq, st));
+    hipLaunchKernelGGL(k_cg_alpha, gs, dim3(64), 0, st, r, rz, pq, done, alpha);
+    hipLaunchKernelGGL(k_cg_update_xr, g2, dim3(kBlock), 0, st, n, alpha, P.p, Qv.p, dinv, X, R.p, Z.p);
+    SUBAP_TRY(col_dots(R.p, n, Z.p, n, 0, n, r, part, rz_new, st));
+    hipLaunchKernelGGL(k_cg_beta, gs, dim3(64), 0, st, r, rz_new, rz, done, beta);
+    hipLaunchKernelGGL(k_cg_update_p, g2, dim3(kBlock), 0, st, n, beta, done, Z.p, P.p);
+    SUBAP_HIP_TRY(hipGetLastError());
+    if ((it + 1) % check_every == 0 || it + 1 == maxiter) {
+      SUBAP_TRY(col_dots(R.p, n, R.p, n, 0, n, r, part, rr, st));
+      SUBAP_HIP_TRY(hipMemcpyAsync(h_rr.data(), rr, sizeof(double) * r, hipMemcpyDeviceToHost, st));
+      SUBAP_HIP_TRY(hipStreamSynchronize(st));
+      all_done = true;
+      for (int c = 0; c < r; ++c) {
+        if (!h_done[c] && std::sqrt(h_rr[c]) <= tol * std::sqrt(h_bb[c])) h_done[c] = 1;
+        all_done = all_done && h_done[c];
+      }
+      SUBAP_HIP_TRY(hipMemcpyAsync(done, h_done.data(), sizeof(int) * r, hipMemcpyHostToDevice, st));
+    }
+  }
+  SUBAP_HIP_TRY(hipStreamSynchronize(st));
+  if (!all_done) {
+    set_error("snapshot conjugate gradients did not reach snap_tol within snap_maxiter");
+    return SUBAP_E_NOCONV;
+  }
+  return SUBAP_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Householder QR of X (n x r col-major), Q formed explicitly, diag(R) > 0.
+// Step j: v = X[j:, j] - beta e_j (LAPACK sign convention), reflect columns
+// j+1.., keep v in X[j:, j].  Then Q = H_0 ... H_{r-1} [I; 0].
+// ----------------------------------------------------------------------------
+// scal layout: [0] = sum_{i>j} x_i^2 (input), [1] = tau, [2] = scale, [3] = beta
+__global__ void k_house_make(double* X, int64_t n, int j, double* scal, double* diagR) {
+  const double ss = scal[0];
+  const double alpha = X[static_cast<int64_t>(j) * n + j];
+  double tau = 0.0, scale = 0.0, beta = alpha;
+  if (ss > 0.0) {
+    const double norm = sqrt(alpha * alpha + ss);
+    beta = alpha >= 0.0 ? -norm : norm;
+    tau = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+  scal[1] = tau;
+  scal[2] = scale;
+  scal[3] = beta;
+  diagR[j] = beta;
+}
+
+// v_i = X[i, j] * scale for i > j, v_j = 1 (written into column j)
+__global__ void k_house_scale(double* X, int64_t n, int j, const double* scal) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x + j;
+  if (i >= n) return;
+  double* col = X + static_cast<int64_t>(j) * n;
+  col[i] = (i == j) ? 1.0 : col[i] * scal[2];
+}
+
+// X[j:, c] -= tau * w_c * v for c in (j, r)  (w_c = v^T X[j:, c] precomputed)
+__global__ void k_house_apply(double* X, int64_t n, int j, const double* v, const double* w,
+                              const double* scal, int c0) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x + j;
+  const int c = c0 + blockIdx.y;
+  if (i >= n) return;
+  X[static_cast<int64_t>(c) * n + i] -= scal[1] * w[blockIdx.y] * v[i];
+}
+
+__global__ void k_set_identity(double* Qm, int64_t n, int r) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i < n) Qm[static_cast<int64_t>(c) * n + i] = (i == c) ? 1.0 : 0.0;
+}
+
+// flip column c of Q when R_cc < 0
+__global__ void k_sign_fix(double* Qm, int64_t n, const double* diagR) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i < n && diagR[c] < 0.0) Qm[static_cast<int64_t>(c) * n + i] = -Qm[static_cast<int64_t>(c) * n + i];
+}
+
+__global__ void k_store_tau(const double* scal, double* taus, int j) { taus[j] = scal[1]; }
+__global__ void k_load_tau(const double* taus, double* scal, int j) { scal[1] = taus[j]; }
+
+subap_status householder_q(double* X, int64_t n, int r, double* Qout, double* diagR_d,
+                           hipStream_t st) {
+  DevVec part, scal, w, taus;
+  SUBAP_TRY(dalloc(&part.p, static_cast<size_t>(kMaxPartials) * (r + 1)));
+  SUBAP_TRY(dalloc(&scal.p, 4));
+  SUBAP_TRY(dalloc(&w.p, r));
+  SUBAP_TRY(dalloc(&taus.p, r));
+  for (int j = 0; j < r; ++j) {
+    double* colj = X + static_cast<int64_t>(j) * n;
+    // sum_{i > j} x_i^2
+    SUBAP_TRY(col_dots(colj, 0, colj, 0, j + 1, n, 1, part.p, scal.p, st));
+    hipLaunchKernelGGL(k_house_make, dim3(1), dim3(1), 0, st, X, n, j, scal.p, diagR_d);
+    hipLaunchKernelGGL(k_house_scale, dim3(static_cast<unsigned>((n - j + kBlock - 1) / kBlock)), dim3(kBlock),
+                       0, st, X, n, j, scal.p);
+    hipLaunchKernelGGL(k_store_tau, dim3(1), dim3(1), 0, st, scal.p, taus.p, j);
+    if (j + 1 < r) {
+      SUBAP_TRY(col_dots(X + static_cast<int64_t>(j + 1) * n, n, colj, 0, j, n, r - j - 1, part.p, w.p, st));
+      hipLaunchKernelGGL(k_house_apply, dim3(static_cast<unsigned>((n - j + kBlock - 1) / kBlock), r - j - 1),
+                         dim3(kBlock), 0, st, X, n, j, colj, w.p, scal.p, j + 1);
+    }
+  }
+  // Q = H_0 ... H_{r-1} [I; 0], applied right to left
+  hipLaunchKernelGGL(k_set_identity, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock), r), dim3(kBlock), 0,
+                     st, Qout, n, r);
+  for (int j = r - 1; j >= 0; --j) {
+    const double* v = X + static_cast<int64_t>(j) * n;
+    const int ncol = r - j;  // columns j..r-1 of Q are touched (rows >= j)
+    SUBAP_TRY(col_dots(Qout + static_cast<int64_t>(j) * n, n, v, 0, j, n, ncol, part.p, w.p, st));
+    hipLaunchKernelGGL(k_load_tau, dim3(1), dim3(1), 0, st, taus.p, scal.p, j);
+    hipLaunchKernelGGL(k_house_apply, dim3(static_cast<unsigned>((n - j + kBlock - 1) / kBlock), ncol),
+                       dim3(kBlock), 0, st, Qout, n, j, v, w.p, scal.p, j);
+  }
+  hipLaunchKernelGGL(k_sign_fix, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock), r), dim3(kBlock), 0, st,
+                     Qout, n, diagR_d);
+  SUBAP_HIP_TRY(hipGetLastError());
+  return SUBAP_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Row selection: rounds of column-pivoted QR on M = W^T, W = A(p_sel) Q
+// (n x r col-major).  Row i of W is column i of M.  Residual norms are
+// recomputed exactly at every step; the pivot is the smallest row index whose
+// norm is >= (1 - kTieRtol) * max over the rows not chosen yet.
+// ----------------------------------------------------------------------------
+__global__ void k_row_norms(const double* W, int64_t n, int r, int j, const int* chosen, double* nrm) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double t = 0.0;
+  for (int c = j; c < r; ++c) {
+    const double v = W[static_cast<int64_t>(c) * n + i];
+    t += v * v;
+  }
+  nrm[i] = chosen[i] ? -1.0 : sqrt(t);
+}
+
+__global__ __launch_bounds__(kBlock) void k_max_partial(const double* v, int64_t n, double* part, int nblk) {
+  __shared__ double sh[kBlock];
+  double m = -2.0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(nblk) * kBlock)
+    m = fmax(m, v[i]);
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+// first index i with v[i] >= thr * max(part)   (partials of the max)
+__global__ __launch_bounds__(kBlock) void k_argfirst_partial(const double* v, int64_t n, const double* mpart,
+                                                             int nmp, double thr, int64_t* ipart, int nblk) {
+  __shared__ int64_t sh[kBlock];
+  double top = -2.0;
+  for (int k = 0; k < nmp; ++k) top = fmax(top, mpart[k]);
+  const double lim = thr * top;
+  int64_t best = INT64_MAX;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(nblk) * kBlock)
+    if (v[i] >= 0.0 && v[i] >= lim && i < best) best = i;
+  sh[threadIdx.x] = best;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = min(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ipart[blockIdx.x] = sh[0];
+}
+
+// Pick the pivot, record it, and build the reflector of its row (r - j entries).
+// piv_state: [0] pivot index.  refl: v (r) then tau.
+__global__ void k_pivot_reflector(const double* W, int64_t n, int r, int j, const int64_t* ipart, int nblk,
+                                  int* chosen, int64_t* piv_out, int slot, double* refl, int* bad) {
+  int64_t best = INT64_MAX;
+  for (int k = 0; k < nblk; ++k) best = min(best, ipart[k]);
+  if (best == INT64_MAX) {  // no candidate left (cannot happen for s <= n)
+    *bad = 1;
+    return;
+  }
+  chosen[best] = 1;
+  piv_out[slot] = best;
+  double ss = 0.0;
+  for (int c = j + 1; c < r; ++c) {
+    const double v = W[static_cast<int64_t>(c) * n + best];
+    ss += v * v;
+  }
+  const double alpha = W[static_cast<int64_t>(j) * n + best];
+  double tau = 0.0, scale = 0.0;
+  if (ss > 0.0) {
+    const double norm = sqrt(alpha * alpha + ss);
+    const double beta = alpha >= 0.0 ? -norm : norm;
+    tau = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+  for (int c = 0; c < r; ++c)
+    refl[c] = c < j ? 0.0 : (c == j ? 1.0 : W[static_cast<int64_t>(c) * n + best] * scale);
+  refl[r] = tau;
+}
+
+// W[i, j:] -= tau (v . W[i, j:]) v  for every row i
+__global__ void k_apply_reflector_rows(double* W, int64_t n, int r, int j, const double* refl) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double t = 0.0;
+  for (int c = j; c < r; ++c) t += refl[c] * W[static_cast<int64_t>(c) * n + i];
+  t *= refl[r];
+  for (int c = j; c < r; ++c) W[static_cast<int64_t>(c) * n + i] -= t * refl[c];
+}
+
+subap_status select_rows_gpu(const double* W0, int64_t n, int r, int s, int64_t* rows_d, hipStream_t st) {
+  DevVec W, nrm, mpart, refl;
+  int* chosen = nullptr;
+  int64_t* ipart = nullptr;
+  SUBAP_TRY(dalloc(&W.p, n * r));
+  SUBAP_TRY(dalloc(&nrm.p, n));
+  SUBAP_TRY(dalloc(&mpart.p, kMaxPartials));
+  SUBAP_TRY(dalloc(&refl.p, r + 1));
+  subap_status rc = dalloc(&chosen, n + 1);
+  if (rc != SUBAP_OK) return rc;
+  rc = dalloc(&ipart, kMaxPartials);
+  if (rc != SUBAP_OK) {
+    dfree(chosen);
+    return rc;
+  }
+  struct Guard {
+    int* a;
+    int64_t* b;
+    ~Guard() { dfree(a); dfree(b); }
+  } guard{chosen, ipart};
+  int* bad = chosen + n;
+  SUBAP_HIP_TRY(hipMemsetAsync(chosen, 0, sizeof(int) * (n + 1), st));
+  const unsigned gb = static_cast<unsigned>((n + kBlock - 1) / kBlock);
+  const int nb = nblocks_for(n);
+  int taken = 0;
+  while (taken < s) {
+    const int take = std::min(r, s - taken);
+    SUBAP_HIP_TRY(hipMemcpyAsync(W.p, W0, sizeof(double) * n * r, hipMemcpyDeviceToDevice, st));
+    for (int j = 0; j < take; ++j) {
+      hipLaunchKernelGGL(k_row_norms, dim3(gb), dim3(kBlock), 0, st, W.p, n, r, j, chosen, nrm.p);
+      hipLaunchKernelGGL(k_max_partial, dim3(nb), dim3(kBlock), 0, st, nrm.p, n, mpart.p, nb);
+      hipLaunchKernelGGL(k_argfirst_partial, dim3(nb), dim3(kBlock), 0, st, nrm.p, n, mpart.p, nb,
+                         1.0 - kTieRtol, ipart, nb);
+      hipLaunchKernelGGL(k_pivot_reflector, dim3(1), dim3(1), 0, st, W.p, n, r, j, ipart, nb, chosen, rows_d,
+                         taken + j, refl.p, bad);
+      if (j + 1 < take)
+        hipLaunchKernelGGL(k_apply_reflector_rows, dim3(gb), dim3(kBlock), 0, st, W.p, n, r, j, refl.p);
+    }
+    SUBAP_HIP_TRY(hipGetLastError());
+    taken += take;
+  }
+  int hbad = 0;
+  SUBAP_HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  SUBAP_HIP_TRY(hipStreamSynchronize(st));
+  if (hbad) {
+    set_error("row selection ran out of candidate rows");
+    return SUBAP_E_INVALID;
+  }
+  return SUBAP_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Tables for the online kernels.
+// ----------------------------------------------------------------------------
+__global__ void k_fd_tables(const double* Qm, int64_t n, int r, int s, int N, int dimx, int d, double h,
+                            const int* rows, const double* rhs, double* phi, double* delta64,
+                            float* delta32, double* bS, double* QS) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= s) return;
+  const int64_t i = rows[k];
+  int c[3];
+  fd_node(i, N, dimx, c);
+  const int F = 2 * dimx;
+  for (int f = 0; f < F; ++f) {
+    double x[3];
+    for (int a = 0; a < 3; ++a) x[a] = (c[a] + 1) * h;
+    x[f / 2] += (f % 2 == 0 ? -0.5 : 0.5) * h;
+    double ph[4];
+    if (dimx == 2) modes2d(x[0], x[1], ph);
+    else modes3d(x[0], x[1], x[2], ph);
+    for (int q = 0; q < d; ++q) phi[(static_cast<int64_t>(f) * d + q) * s + k] = ph[q];
+    const int axis = f / 2;
+    const int nbc = c[axis] + (f % 2 == 0 ? -1 : 1);
+    int64_t nb = -1;
+    if (nbc >= 0 && nbc < N) {
+      const int64_t stride = axis == 0 ? 1 : (axis == 1 ? N : static_cast<int64_t>(N) * N);
+      nb = i + (f % 2 == 0 ? -stride : stride);
+    }
+    for (int cc = 0; cc < r; ++cc) {
+      const double qi = Qm[static_cast<int64_t>(cc) * n + i];
+      const double qn = nb >= 0 ? Qm[static_cast<int64_t>(cc) * n + nb] : 0.0;
+      const double dv = qi - qn;
+      delta64[(static_cast<int64_t>(f) * r + cc) * s + k] = dv;
+      delta32[(static_cast<int64_t>(f) * r + cc) * s + k] = static_cast<float>(dv);
+    }
+  }
+  bS[k] = rhs[i];
+  for (int cc = 0; cc < r; ++cc) QS[static_cast<int64_t>(k) * r + cc] = Qm[static_cast<int64_t>(cc) * n + i];
+}
+
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return static_cast<uint16_t>(u >> 16);  // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+
+__global__ void k_krr_tables(const double* Qm, const double* pts, int64_t n, int r, int s, int dim,
+                             const int* rows, double* Dt64, float* D32, double* Qrm, float* Q32,
+                             uint16_t* Qhi, uint16_t* Qlo) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  for (int k = 0; k < s; ++k) {
+    const int64_t i = rows[k];
+    double d2 = 0.0;
+    for (int q = 0; q < dim; ++q) {
+      const double df = pts[j * dim + q] - pts[i * dim + q];
+      d2 += df * df;
+    }
+    Dt64[j * s + k] = d2;
+    D32[static_cast<int64_t>(k) * n + j] = static_cast<float>(d2);
+  }
+  for (int c = 0; c < r; ++c) {
+    const double v = Qm[static_cast<int64_t>(c) * n + j];
+    Qrm[j * r + c] = v;
+    const float v32 = static_cast<float>(v);
+    Q32[static_cast<int64_t>(c) * n + j] = v32;
+    const uint16_t hi = bf16_rne(v32);
+    const float hif = __uint_as_float(static_cast<uint32_t>(hi) << 16);
+    Qhi[static_cast<int64_t>(c) * n + j] = hi;
+    Qlo[static_cast<int64_t>(c) * n + j] = bf16_rne(v32 - hif);
+  }
+}
+
+__global__ void k_gather_rows(const double* Qm, int64_t n, int r, int s, const int* rows, const double* rhs,
+                              double* bS, double* QS) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= s) return;
+  const int64_t i = rows[k];
+  bS[k] = rhs[i];
+  for (int c = 0; c < r; ++c) QS[static_cast<int64_t>(k) * r + c] = Qm[static_cast<int64_t>(c) * n + i];
+}
+
+__global__ void k_copy_rows_i32(const int64_t* a, int* b, int s) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < s) b[k] = static_cast<int>(a[k]);
+}
+
+}  // namespace
+
+subap_status build_tables(subap_model_s* M, hipStream_t st) {
+  const int s = M->s, r = M->r;
+  const int64_t n = M->n;
+  SUBAP_TRY(dalloc(&M->bS, s));
+  SUBAP_TRY(dalloc(&M->QS, static_cast<size_t>(s) * r));
+  if (M->family == SUBAP_FAMILY_KRR) {
+    SUBAP_TRY(dalloc(&M->Dt64, static_cast<size_t>(n) * s));
+    SUBAP_TRY(dalloc(&M->D32, static_cast<size_t>(n) * s));
+    SUBAP_TRY(dalloc(&M->Qrm, static_cast<size_t>(n) * r));
+    SUBAP_TRY(dalloc(&M->Q32, static_cast<size_t>(n) * r));
+    SUBAP_TRY(dalloc(&M->Qhi, static_cast<size_t>(n) * r));
+    SUBAP_TRY(dalloc(&M->Qlo, static_cast<size_t>(n) * r));
+    hipLaunchKernelGGL(k_krr_tables, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                       M->Q, M->points, n, r, s, M->dimx, M->rows_d, M->Dt64, M->D32, M->Qrm, M->Q32, M->Qhi,
+                       M->Qlo);
+    hipLaunchKernelGGL(k_gather_rows, dim3((s + 63) / 64), dim3(64), 0, st, M->Q, n, r, s, M->rows_d, M->rhs,
+                       M->bS, M->QS);
+  } else {
+    const size_t tab = static_cast<size_t>(s) * M->F;
+    SUBAP_TRY(dalloc(&M->phi, tab * M->d));
+    SUBAP_TRY(dalloc(&M->delta64, tab * r));
+    SUBAP_TRY(dalloc(&M->delta32, tab * r));
+    hipLaunchKernelGGL(k_fd_tables, dim3((s + 63) / 64), dim3(64), 0, st, M->Q, n, r, s, M->N, M->dimx, M->d, M->h,
+                       M->rows_d, M->rhs, M->phi, M->delta64, M->delta32, M->bS, M->QS);
+  }
+  SUBAP_HIP_TRY(hipGetLastError());
+  std::vector<double> hb(s);
+  SUBAP_HIP_TRY(hipMemcpyAsync(hb.data(), M->bS, sizeof(double) * s, hipMemcpyDeviceToHost, st));
+  SUBAP_HIP_TRY(hipStreamSynchronize(st));
+  double t = 0.0;
+  for (double v : hb) t += v * v;
+  M->bS_norm = std::sqrt(t);
+  return SUBAP_OK;
+}
+
+subap_status offline_build(const subap_problem_desc* pd, const subap_offline_opts* o, hipStream_t st,
+                           subap_model_s* M) {
+  const int64_t n = M->n;
+  const int r = M->r, s = M->s, d = M->d;
+  // right-hand side and (KRR) points
+  SUBAP_TRY(dalloc(&M->rhs, n));
+  if (pd->rhs) {
+    SUBAP_HIP_TRY(hipMemcpyAsync(M->rhs, pd->rhs, sizeof(double) * n, hipMemcpyHostToDevice, st));
+  } else {
+    std::vector<double> ones(static_cast<size_t>(n), 1.0);
+    SUBAP_HIP_TRY(hipMemcpyAsync(M->rhs, ones.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+    SUBAP_HIP_TRY(hipStreamSynchronize(st));
+  }
+  if (M->family == SUBAP_FAMILY_KRR) {
+    SUBAP_TRY(dalloc(&M->points, static_cast<size_t>(n) * M->dimx));
+    SUBAP_HIP_TRY(hipMemcpyAsync(M->points, pd->points, sizeof(double) * n * M->dimx, hipMemcpyHostToDevice, st));
+  }
+  OpArgs A{M->family, M->N, M->dimx, n, d, M->h, M->inv_h2, M->lambda, M->points};
+
+  DevVec X, params, diagR, W, pdup;
+  SUBAP_TRY(dalloc(&X.p, static_cast<size_t>(n) * r));
+  if (o->basis_in) {
+    SUBAP_HIP_TRY(hipMemcpyAsync(X.p, o->basis_in, sizeof(double) * n * r, hipMemcpyHostToDevice, st));
+  } else {
+    SUBAP_TRY(dalloc(&params.p, static_cast<size_t>(r) * d));
+    SUBAP_HIP_TRY(hipMemcpyAsync(params.p, o->snap_params, sizeof(double) * r * d, hipMemcpyHostToDevice, st));
+    const double tol = o->snap_tol > 0.0 ? o->snap_tol : 1e-12;
+    const int maxit = o->snap_maxiter > 0 ? o->snap_maxiter : 20000;
+    SUBAP_TRY(snapshot_cg(A, params.p, r, M->rhs, tol, maxit, X.p, st));
+  }
+  // 2. orthonormalise
+  SUBAP_TRY(dalloc(&M->Q, static_cast<size_t>(n) * r));
+  SUBAP_TRY(dalloc(&diagR.p, r));
+  SUBAP_TRY(householder_q(X.p, n, r, M->Q, diagR.p, st));
+  // 3. rows
+  int64_t* rows64 = nullptr;
+  SUBAP_TRY(dalloc(&rows64, s));
+  struct G64 {
+    int64_t* p;
+    ~G64() { dfree(p); }
+  } g64{rows64};
+  if (o->rows_in) {
+    SUBAP_HIP_TRY(hipMemcpyAsync(rows64, o->rows_in, sizeof(int64_t) * s, hipMemcpyHostToDevice, st));
+  } else {
+    SUBAP_TRY(dalloc(&W.p, static_cast<size_t>(n) * r));
+    std::vector<double> pd_h(static_cast<size_t>(r) * d);
+    for (int c = 0; c < r; ++c)
+      for (int q = 0; q < d; ++q) pd_h[static_cast<size_t>(c) * d + q] = o->select_param[q];
+    SUBAP_TRY(dalloc(&pdup.p, pd_h.size()));
+    SUBAP_HIP_TRY(hipMemcpyAsync(pdup.p, pd_h.data(), sizeof(double) * pd_h.size(), hipMemcpyHostToDevice, st));
+    SUBAP_TRY(apply_op(A, pdup.p, r, M->Q, W.p, nullptr, st));
+    SUBAP_TRY(select_rows_gpu(W.p, n, r, s, rows64, st));
+  }
+  SUBAP_TRY(dalloc(&M->rows_d, s));
+  hipLaunchKernelGGL(k_copy_rows_i32, dim3((s + 63) / 64), dim3(64), 0, st, rows64, M->rows_d, s);
+  M->rows.resize(s);
+  SUBAP_HIP_TRY(hipMemcpyAsync(M->rows.data(), rows64, sizeof(int64_t) * s, hipMemcpyDeviceToHost, st));
+  SUBAP_HIP_TRY(hipStreamSynchronize(st));
+  SUBAP_TRY(build_tables(M, st));
+  SUBAP_HIP_TRY(hipStreamSynchronize(st));
+  return SUBAP_OK;
+}
+
+}  // namespace subap

@@ -12,10 +12,14 @@
 // Factorisation (LAPACK dgeqr2 convention): step j builds the reflector
 // H_j = I - tau_j v_j v_j^T with v_j = 1 at row j and v_j = 0 above it, so
 // that H_j G[:, j] = beta_j e_j.  Afterwards a[q][c] holds R above and on
-// the diagonal and v below it; tau lives in team-private LDS.
+// the diagonal and v below it; tau lives in team-private LDS.  Values kept
+// in that LDS (tau, y) are team-uniform and every lane stores them, so no
+// lane ever reads a value that only another lane wrote.
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include "common.h"
 
 namespace subap {
 
@@ -48,8 +52,6 @@ struct TeamQR {
 #pragma unroll
     for (int j = 0; j < RM; ++j) {
       if (j < r) {
-        constexpr int dummy = 0;
-        (void)dummy;
         const int qj = j / TEAM, lj = j % TEAM;
         double ss = 0.0;
 #pragma unroll
@@ -72,32 +74,40 @@ struct TeamQR {
           const int i = row(lane, q);
           v[q] = (i > j) ? a[q][j] * scale : (i == j ? 1.0 : 0.0);
         }
-        // w_c = v^T a[:, c] for the trailing columns and for b
-        double w[RM + 1];
+        // Trailing columns c > j (and b as column RM) in groups of 8:
+        // w_c = v^T a[:, c] by one batched butterfly per group, then the
+        // rank-1 update.  Grouping bounds the live registers while keeping
+        // 8 independent shuffle chains in flight.
 #pragma unroll
-        for (int c = 0; c <= RM; ++c) {
-          w[c] = 0.0;
-          if (c > j) {
-            double t = 0.0;
+        for (int c0 = 0; c0 <= RM; c0 += 8) {
+          if (c0 + 7 > j) {
+            double w[8];
 #pragma unroll
-            for (int q = 0; q < R; ++q) t += v[q] * (c < RM ? a[q][c] : b[q]);
-            w[c] = t;
-          }
-        }
+            for (int g = 0; g < 8; ++g) {
+              const int c = c0 + g;
+              w[g] = 0.0;
+              if (c > j && c <= RM) {
 #pragma unroll
-        for (int off = TEAM / 2; off > 0; off >>= 1) {
+                for (int q = 0; q < R; ++q) w[g] += v[q] * (c < RM ? a[q][c] : b[q]);
+              }
+            }
 #pragma unroll
-          for (int c = 0; c <= RM; ++c)
-            if (c > j) w[c] += __shfl_xor(w[c], off, TEAM);
-        }
+            for (int off = TEAM / 2; off > 0; off >>= 1) {
 #pragma unroll
-        for (int c = 0; c <= RM; ++c) {
-          if (c > j) {
-            const double tw = tau * w[c];
+              for (int g = 0; g < 8; ++g)
+                if (c0 + g > j && c0 + g <= RM) w[g] += __shfl_xor(w[g], off, TEAM);
+            }
 #pragma unroll
-            for (int q = 0; q < R; ++q) {
-              if (c < RM) a[q][c] -= tw * v[q];
-              else b[q] -= tw * v[q];
+            for (int g = 0; g < 8; ++g) {
+              const int c = c0 + g;
+              if (c > j && c <= RM) {
+                const double tw = tau * w[g];
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                  if (c < RM) a[q][c] -= tw * v[q];
+                  else b[q] -= tw * v[q];
+                }
+              }
             }
           }
         }
@@ -107,7 +117,7 @@ struct TeamQR {
           if (i == j) a[q][j] = beta;
           else if (i > j) a[q][j] = v[q];
         }
-        if (lane == 0) tau_s[j] = tau;
+        tau_s[j] = tau;  // every lane stores the same value: no cross-lane hazard
         const double ab = fabs(beta);
         if (j == 0) r00 = ab;
         if (!(ab > kRankTol * r00)) full_rank = false;
@@ -150,7 +160,7 @@ struct TeamQR {
 #pragma unroll
         for (int q = 0; q < R; ++q)
           if (row(lane, q) < c) x[q] -= a[q][c] * yc;
-        if (lane == 0) y_s[c] = yc;
+        y_s[c] = yc;  // team-uniform value, stored by every lane
       }
     }
   }

@@ -1,0 +1,103 @@
+"""The C-ABI library loads, exports every symbol include/subap.h declares,
+and rejects bad arguments with status codes before touching a device
+(these tests run without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2510_04825_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "subap.h")).read()
+    return sorted(set(re.findall(r"SUBAP_API\s+[\w\s\*]*?\b(subap_\w+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.skip("libsubap.so not built (run __graft_entry__.build())")
+    return B.load()
+
+
+def test_header_declares_the_binding_exports():
+    assert header_functions() == sorted(B.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in header_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    assert lib.subap_status_string(0) == b"ok"
+    assert lib.subap_status_string(4) == b"rank deficient"
+
+
+def _pd(**kw):
+    base = dict(family=B.FAMILY_DIFF2D, grid=16, n=0, dim=0, points=None, rhs=None, lam=0.0)
+    base.update(kw)
+    return B.ProblemDesc(**base)
+
+
+def _opts(**kw):
+    snap = np.zeros((4, 2))
+    sel = np.zeros(2)
+    base = dict(r=4, s=8, snap_params=snap.ctypes.data, select_param=sel.ctypes.data, snap_tol=0.0,
+                snap_maxiter=0, basis_in=None, rows_in=None)
+    base.update(kw)
+    return B.OfflineOpts(**base), (snap, sel)
+
+
+@pytest.mark.parametrize("pd_kw,opt_kw", [
+    (dict(family=9), {}),
+    (dict(grid=1), {}),
+    (dict(), dict(r=0)),
+    (dict(), dict(r=65)),
+    (dict(), dict(s=3)),
+    (dict(), dict(s=300)),
+    (dict(), dict(snap_params=None)),
+    (dict(), dict(select_param=None)),
+    (dict(), dict(snap_tol=-1.0)),
+    (dict(family=B.FAMILY_KRR, n=100, dim=8), {}),          # points/rhs missing
+])
+def test_offline_rejects_bad_arguments(lib, pd_kw, opt_kw):
+    pd = _pd(**pd_kw)
+    op, keep = _opts(**opt_kw)
+    h = C.c_void_p()
+    rc = lib.subap_offline(C.byref(pd), C.byref(op), None, C.byref(h))
+    assert rc == B.E_INVALID
+    assert h.value is None
+    assert len(lib.subap_last_error()) > 0
+
+
+def test_offline_rejects_bad_rows(lib):
+    pd = _pd()
+    rows = np.array([0, 1, 2, 3, 4, 5, 6, 6], dtype=np.int64)  # duplicate
+    op, keep = _opts(rows_in=rows.ctypes.data)
+    h = C.c_void_p()
+    assert lib.subap_offline(C.byref(pd), C.byref(op), None, C.byref(h)) == B.E_INVALID
+    rows[-1] = 16 * 16  # out of range
+    assert lib.subap_offline(C.byref(pd), C.byref(op), None, C.byref(h)) == B.E_INVALID
+
+
+def test_offline_rejects_nonfinite_inputs(lib):
+    pd = _pd()
+    op, keep = _opts()
+    keep[0][0, 0] = np.nan
+    h = C.c_void_p()
+    assert lib.subap_offline(C.byref(pd), C.byref(op), None, C.byref(h)) == B.E_INVALID
+
+
+def test_null_model_calls(lib):
+    assert lib.subap_offline(None, None, None, None) == B.E_INVALID
+    opts = B.SolveOpts(0, 0)
+    assert lib.subap_solve_batch(None, None, 4, None, None, None, C.byref(opts), None) == B.E_INVALID
+    assert lib.subap_lift(None, None, 1, None, 0, None) == B.E_INVALID
+    assert lib.subap_model_rows(None, None) == B.E_INVALID
+    assert lib.subap_model_free(None) == B.OK

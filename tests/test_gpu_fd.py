@@ -1,0 +1,186 @@
+"""GPU parity for the finite-difference families against the FP64 oracle.
+
+Bars: row indices bit-exact; FP64 solves within delta_res <= 1e-12 of the
+oracle (delta_res(p) = |A(p) Q (y_gpu - y_oracle)| / |b|), the residual-norm
+distance the oracle defines; full-chain runs (GPU snapshots by CG) within
+1e-8 because the snapshots themselves differ by the CG tolerance.
+"""
+import numpy as np
+import pytest
+
+import subap_inputs as si
+from oracle import offline as O
+from oracle import online as On
+from paper_2510_04825_amd import binding as B
+from tests.gpu_util import device, header, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c1():
+    w = si.diffusion2d()
+    return w, O.offline(w)
+
+
+def _dres(fam, Q, P, Yg, Yo):
+    return np.array([On.delta_res(fam, Q, p, a, b) for p, a, b in zip(P, Yg, Yo)])
+
+
+def test_c1_rows_from_oracle_basis_are_bit_exact(c1):
+    w, off = c1
+    header("c1 given-basis rows")
+    device()
+    M = B.Model(w, basis=off["Q"])
+    try:
+        assert np.array_equal(M.rows(), off["rows"])
+        assert np.abs(M.basis() - off["Q"]).max() < 1e-13
+    finally:
+        M.free()
+
+
+def test_c1_fp64_solve_matches_oracle(c1):
+    w, off = c1
+    fam, Q, rows = off["family"], off["Q"], off["rows"]
+    header("c1 fp64 solve given basis and rows")
+    M = B.Model(w, basis=Q, rows=rows)
+    try:
+        P = w["test_params"]
+        y, rho, st = M.solve(to_dev(P))
+        y = y.cpu().numpy()
+        assert np.all(st.cpu().numpy() == B.OK)
+        Yo = On.solve(fam, Q, rows, P)
+        dres = _dres(fam, Q, P, y, Yo)
+        assert dres.max() <= 1e-12, dres.max()
+        # rows come in mirror pairs here, so the sketched residual is rounding noise (~1e-12)
+        rho_o = [On.sketched_residual(fam, Q, rows, p, yo) for p, yo in zip(P, Yo)]
+        assert np.allclose(rho.cpu().numpy(), rho_o, rtol=1e-6, atol=1e-10)
+    finally:
+        M.free()
+
+
+def test_c1_full_chain(c1):
+    w, off = c1
+    fam = off["family"]
+    header("c1 full offline on GPU")
+    M = B.Model(w)
+    try:
+        sv = np.linalg.svd(off["X"], compute_uv=False)
+        assert sv[-1] / sv[0] > 1e-8
+        assert np.array_equal(M.rows(), off["rows"])
+        Qg = M.basis()
+        assert np.abs(Qg.T @ Qg - np.eye(w["r"])).max() < 1e-13
+        # same subspace as the oracle's snapshots
+        assert np.linalg.norm(Qg - off["Q"] @ (off["Q"].T @ Qg)) < 1e-8
+        P = w["test_params"]
+        y, _, st = M.solve(to_dev(P))
+        xg = Qg @ y.cpu().numpy().T
+        xo = off["Q"] @ On.solve(fam, off["Q"], off["rows"], P).T
+        b = fam.rhs()
+        for i, p in enumerate(P):
+            assert np.linalg.norm(fam.matvec(p, xg[:, i] - xo[:, i])) <= 1e-8 * np.linalg.norm(b)
+    finally:
+        M.free()
+
+
+def test_c1_refinement_and_fp32_forms(c1):
+    w, off = c1
+    fam, Q, rows = off["family"], off["Q"], off["rows"]
+    header("c1 fp32 contraction + refinement")
+    M = B.Model(w, basis=Q, rows=rows)
+    try:
+        P = w["test_params"]
+        Yo = On.solve(fam, Q, rows, P)
+        y1, _, _ = M.solve(to_dev(P), contraction=B.FP64, refine_steps=1)
+        assert _dres(fam, Q, P, y1.cpu().numpy(), Yo).max() <= 1e-12
+        y32, _, _ = M.solve(to_dev(P), contraction=B.FP32, refine_steps=0)
+        d32 = _dres(fam, Q, P, y32.cpu().numpy(), Yo)
+        y32r, _, _ = M.solve(to_dev(P), contraction=B.FP32, refine_steps=2)
+        d32r = _dres(fam, Q, P, y32r.cpu().numpy(), Yo)
+        assert d32r.max() <= 1e-6, (d32.max(), d32r.max())
+        assert d32r.max() <= d32.max()
+    finally:
+        M.free()
+
+
+def test_c1_edge_cases(c1):
+    import torch
+    w, off = c1
+    header("c1 edge cases")
+    M = B.Model(w, basis=off["Q"], rows=off["rows"])
+    try:
+        dev = device()
+        # m = 0 is a no-op
+        y, rho, st = M.solve(torch.empty((0, 2), dtype=torch.float64, device=dev))
+        assert y.shape == (0, 16)
+        # ragged batch, non-finite parameter
+        P = np.array(w["test_params"][:13])
+        P[5, 1] = np.nan
+        y, rho, st = M.solve(to_dev(P))
+        st = st.cpu().numpy()
+        y = y.cpu().numpy()
+        assert st[5] == B.E_NONFINITE and np.all(np.isnan(y[5]))
+        ok = np.arange(13) != 5
+        assert np.all(st[ok] == B.OK)
+        Yo = On.solve(off["family"], off["Q"], off["rows"], P[ok])
+        assert _dres(off["family"], off["Q"], P[ok], y[ok], Yo).max() <= 1e-12
+        # single parameter equals its batched value
+        y1, _, _ = M.solve(to_dev(P[:1]))
+        assert np.array_equal(y1.cpu().numpy()[0], y[0])
+    finally:
+        M.free()
+
+
+def test_rank_deficient_rows_report_rank_status():
+    # basis = unit vectors at nodes two or more cells away from the selected
+    # rows, so S A(p) Q = 0 and the least-squares problem has no unique solution
+    w = si.diffusion2d(N=16, r=4, s=8, m=6)
+    Q = np.zeros((256, 4))
+    for c, node in enumerate((150, 170, 200, 230)):
+        Q[node, c] = 1.0
+    rows = np.arange(8)
+    header("rank-deficient S A Q")
+    M = B.Model(w, basis=Q, rows=rows)
+    try:
+        y, _, st = M.solve(to_dev(w["test_params"]))
+        assert np.all(st.cpu().numpy() == B.E_RANK)
+        assert np.all(np.isnan(y.cpu().numpy()))
+    finally:
+        M.free()
+
+
+@pytest.mark.parametrize("N,r,s", [(16, 8, 32), (24, 40, 160)])
+def test_diffusion3d_given_basis(N, r, s):
+    w = si.diffusion3d(N=N, r=r, s=s, m=50)
+    off = O.offline(w)
+    fam, Q, rows = off["family"], off["Q"], off["rows"]
+    header(f"3-D N={N} r={r} s={s}")
+    M = B.Model(w, basis=Q)
+    try:
+        assert np.array_equal(M.rows(), rows)
+        P = w["test_params"]
+        y, _, st = M.solve(to_dev(P))
+        assert np.all(st.cpu().numpy() == B.OK)
+        Yo = On.solve(fam, Q, rows, P)
+        assert _dres(fam, Q, P, y.cpu().numpy(), Yo).max() <= 1e-12
+    finally:
+        M.free()
+
+
+def test_lift_matches_q_times_y(c1):
+    import torch
+    w, off = c1
+    header("lift")
+    M = B.Model(w, basis=off["Q"], rows=off["rows"])
+    try:
+        rng = np.random.default_rng(0)
+        Y = rng.standard_normal((70, 16))
+        x64 = M.lift(to_dev(Y), precision=B.FP64).cpu().numpy()
+        Qg = M.basis()
+        ref = (Qg @ Y.T).T
+        assert np.abs(x64 - ref).max() <= 1e-14 * np.abs(ref).max()
+        x32 = M.lift(to_dev(Y), precision=B.FP32).cpu().numpy()
+        bound = 4 * 2.0 ** -24 * (np.abs(Qg) @ np.abs(Y.T)).T
+        assert np.all(np.abs(x32 - ref) <= bound + 1e-30)
+    finally:
+        M.free()
