@@ -8,8 +8,9 @@ s = 128 selected rows, a batch of 4096 parameters p* log-uniform in [0.5, 2],
 lambda = 1e-2.  All inputs are synthetic and seeded (subap_inputs.krr).
 
 A step is one call of subap_solve_batch on the resident batch: kernel rows
-generated on the fly and contracted with Q (split-bf16 MFMA, FP32
-accumulation), FP64 Householder least squares, and one FP64 refinement step.
+generated on the fly and contracted with Q (split fp16 MFMA, FP32
+accumulation in four point ranges summed in FP64), FP64 Householder least
+squares, and one FP64 refinement step.
 A solve counts toward the metric when its status is OK and its sketched
 distance |S A(p) Q (y - y_fp64)| / |S b| to the FP64 plain solve is <= 1e-6
 (both residual vectors come from subap_sketched_residual, with FP64-accurate
@@ -31,6 +32,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 TOL = 1e-6
+# headline form: (contraction precision, FP64 refinement steps); see the design doc
+HEADLINE = (3, 1)   # FP16X3 split MFMA contraction + one FP64 refinement
 PEAKS = {  # MI355X published dense peaks
     "bf16_mfma_tflops": 2500.0,
     "fp32_mfma_tflops": 157.3,
@@ -47,6 +50,8 @@ def parse():
     ap.add_argument("--plain-sample", type=int, default=256, help="parameters solved one per call")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle timing budget")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run a device-to-device copy of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -131,35 +136,41 @@ def main():
     def solve(prec, refine, out=y):
         B.subap_solve_batch(M.handle, P, out, rho, st, prec, refine, stream)
 
-    # reference FP64 plain batched solution and validity of the headline form
+    # reference FP64 plain batched solution; validity of a form = status OK and
+    # sketched distance |S A Q (y - y_fp64)| / |S b| <= TOL
     y64 = torch.empty_like(y)
     solve(B.FP64, 0, y64)
     res64, nrm64 = M.sketched_residual(P, y64, vector=True)
-    solve(B.BF16X3, 1)
-    torch.cuda.synchronize()
-    resb, _ = M.sketched_residual(P, y, vector=True)
-    status_ok = (st == 0)
     bS_norm = float(torch.median(torch.linalg.norm(res64, dim=1) / nrm64))
-    dist = torch.linalg.norm(resb - res64, dim=1) / bS_norm
-    valid = status_ok & (dist <= TOL)
-    n_valid = int(valid.sum())
+
+    def validity(prec, ref):
+        solve(prec, ref)
+        torch.cuda.synchronize()
+        res, _ = M.sketched_residual(P, y, vector=True)
+        dist = torch.linalg.norm(res - res64, dim=1) / bS_norm
+        ok = (st == 0) & (dist <= TOL)
+        return {"valid": int(ok.sum()), "max_sketched_distance": float(dist.max())}
+
+    head_valid = validity(*HEADLINE)
+    n_valid = head_valid["valid"]
 
     # headline timing, per-kernel HIP-event profile over the same region
     for _ in range(args.warmup):
-        solve(B.BF16X3, 1)
+        solve(*HEADLINE)
     B.subap_profile_reset()
     B.subap_profile_enable(True)
-    ms = timed(lambda: solve(B.BF16X3, 1), args.steps, stream)
+    ms = timed(lambda: solve(*HEADLINE), args.steps, stream)
     B.subap_profile_enable(False)
     prof = B.subap_profile_read()
 
     # other forms on the same inputs
     forms = {}
     for name, prec, ref in (("fp64_batched", B.FP64, 0), ("fp32_refine1", B.FP32, 1),
-                            ("bf16x3_norefine", B.BF16X3, 0), ("bf16x3_refine1", B.BF16X3, 1)):
+                            ("bf16x3_norefine", B.BF16X3, 0), ("bf16x3_refine1", B.BF16X3, 1),
+                            ("fp16x3_norefine", B.FP16X3, 0), ("fp16x3_refine1", B.FP16X3, 1)):
         solve(prec, ref)
-        t = ms if name == "bf16x3_refine1" else timed(lambda: solve(prec, ref), 3, stream)
-        forms[name] = {"ms_per_batch": t, "solves_per_s": m / (t / 1e3)}
+        t = ms if (prec, ref) == HEADLINE else timed(lambda: solve(prec, ref), 3, stream)
+        forms[name] = {"ms_per_batch": t, "solves_per_s": m / (t / 1e3), **validity(prec, ref)}
     # plain per-parameter FP64 solve: one library call per p
     k = min(args.plain_sample, m)
     y1 = torch.empty((1, r), dtype=torch.float64, device=dev)
@@ -180,7 +191,7 @@ def main():
     dname, (calls, tot_ms) = dom
     avg_ms = tot_ms / max(calls, 1)
     flops_contract = 2.0 * m * s * n * r
-    if dname == "krr_contract_bf16x3":
+    if dname in ("krr_contract_bf16x3", "krr_contract_fp16x3"):
         roof = {"bound": "mfma", "achieved": flops_contract / (avg_ms * 1e-3) / 1e12,
                 "peak": PEAKS["bf16_mfma_tflops"], "unit": "TFLOP/s"}
     elif dname == "krr_refine_partial":
@@ -205,18 +216,26 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16x3+f64",
+        "dtype": "f16x3+f64",
         "data": "synthetic",
         "config": {"workload": "krr_gauss_n16384_d8_r32_s128_m4096", "n": n, "r": r, "s": s, "batch": m,
-                   "form": "bf16x3 MFMA contraction + FP64 Householder LSQ + 1 FP64 refinement"},
-        "valid": {"count": n_valid, "of": m, "max_sketched_distance": float(dist.max()),
+                   "form": "fp16x3 MFMA contraction + FP64 Householder LSQ + 1 FP64 refinement"},
+        "valid": {"count": n_valid, "of": m, "max_sketched_distance": head_valid["max_sketched_distance"],
                   "tolerance": TOL},
         "forms": forms,
-        "speedup_vs_plain": forms["bf16x3_refine1"]["solves_per_s"] / forms["fp64_per_p_plain"]["solves_per_s"],
+        "speedup_vs_plain": (n_valid / (ms / 1e3)) / forms["fp64_per_p_plain"]["solves_per_s"],
         "kernels_ms_per_step": {k2: v[1] / max(args.steps, 1) for k2, v in prof.items()},
         "roofline": roof,
         "offline_s": offline_s,
     }
+    if args.calibrate_copy > 0:
+        nb = args.calibrate_copy << 20
+        a = torch.empty(nb // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = nb
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     M.free()

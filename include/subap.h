@@ -77,8 +77,10 @@ typedef enum {
 typedef enum {
   SUBAP_FP64 = 0,    /* FP64 rows, FP64 contraction                           */
   SUBAP_FP32 = 1,    /* FP32 rows and contraction (FP32 MFMA for KRR)          */
-  SUBAP_BF16X3 = 2   /* KRR only: bf16 hi/lo split operands, three MFMA
+  SUBAP_BF16X3 = 2,  /* KRR only: bf16 hi/lo split operands, three MFMA
                         products hi*hi + hi*lo + lo*hi, FP32 accumulation     */
+  SUBAP_FP16X3 = 3   /* KRR only: as BF16X3 with fp16 halves (11-bit
+                        significands; Q columns scaled by powers of two)      */
 } subap_precision;
 
 typedef struct {
@@ -173,6 +175,98 @@ SUBAP_API subap_status subap_lift(subap_model model, const double* y_dev, int64_
 SUBAP_API subap_status subap_sketched_residual(subap_model model, const double* params_dev, int64_t m,
                                                const double* y_dev, double* res_dev, double* norm_dev,
                                                void* hip_stream);
+
+/*
+ * Batched solve over many models in one persistent launch (finite-difference
+ * families).  A plan fixes the models, the parameter counts and the device
+ * buffers; executing it runs Algorithm 3.1 step 4 for every parameter of
+ * every model.  All buffers keep the layouts of subap_solve_batch, one per
+ * model (rho_dev and status_dev may be NULL, or contain NULL entries).
+ *   flags  SUBAP_PLAN_GRAPH:    capture the launch in a hipGraph once and
+ *                               replay it on every execute;
+ *          SUBAP_PLAN_AUTOTUNE: time the candidate launch shapes (threads per
+ *                               block, resident blocks) on the plan and keep
+ *                               the fastest; the choice is cached in the file
+ *                               named by $SUBAP_AUTOTUNE_CACHE (default
+ *                               ~/.cache/subap_autotune.txt) under a key made
+ *                               of the shapes, and reused when the key recurs.
+ * Work items (one parameter each) are taken from a device counter, largest
+ * instances first.  Autotuning runs the plan, so it writes the outputs.
+ * Contraction FP64 or FP32; refine_steps 0..4.  The models and buffers must
+ * outlive the plan.  subap_solve_multi is create + execute + free.
+ */
+typedef struct subap_plan_s* subap_plan;
+#define SUBAP_PLAN_GRAPH 1
+#define SUBAP_PLAN_AUTOTUNE 2
+SUBAP_API subap_status subap_plan_create(const subap_model* models, int32_t k, const double* const* params_dev,
+                                         const int64_t* m, double* const* y_dev, double* const* rho_dev,
+                                         int32_t* const* status_dev, const subap_solve_opts* opts,
+                                         int32_t flags, void* hip_stream, subap_plan* out);
+SUBAP_API subap_status subap_plan_execute(subap_plan plan, void* hip_stream);
+/* Launch shape in use (after autotuning): threads per block, blocks. */
+SUBAP_API subap_status subap_plan_shape(subap_plan plan, int32_t* threads, int32_t* blocks);
+SUBAP_API subap_status subap_plan_free(subap_plan plan);
+SUBAP_API subap_status subap_solve_multi(const subap_model* models, int32_t k, const double* const* params_dev,
+                                         const int64_t* m, double* const* y_dev, double* const* rho_dev,
+                                         int32_t* const* status_dev, const subap_solve_opts* opts,
+                                         void* hip_stream);
+
+/*
+ * Learned surrogate p -> y (not in the paper): a multilayer perceptron
+ * d -> hidden -> hidden -> r with GELU activations, trained on (p, y) pairs
+ * produced by subap_solve_batch, with the library's own forward, backward and
+ * Adam kernels (BF16 MFMA products with FP32 accumulation, FP32 master
+ * weights; the output layer uses split bf16 hi/lo products).  Targets are
+ * standardised per component with the training mean and deviation.
+ *
+ * Weights (host, FP64, caller-drawn initial values) are laid out as
+ * [W1 (hidden x d) | b1 | W2 (hidden x hidden) | b2 | W3 (r x hidden) | b3],
+ * each W row-major (fan_out x fan_in); subap_surrogate_nparams gives the
+ * total length.
+ */
+typedef struct subap_surrogate_s* subap_surrogate;
+typedef struct {
+  int32_t epochs;    /* passes over the pairs (>= 1)                              */
+  int32_t batch;     /* mini-batch rows (1..65536); 0 = 4096                      */
+  double lr;         /* peak Adam step (betas 0.9, 0.999, eps 1e-8); 0 = 1e-3     */
+  double lr_min;     /* floor of the cosine decay over all steps                   */
+  uint64_t seed;     /* selects the per-epoch affine permutations of the pairs    */
+} subap_train_opts;
+SUBAP_API subap_status subap_surrogate_create(int32_t d, int32_t r, int32_t hidden, const double* weights_host,
+                                              subap_surrogate* out);
+SUBAP_API int64_t subap_surrogate_nparams(subap_surrogate s);
+/* Current master weights as FP64 (blocking). */
+SUBAP_API subap_status subap_surrogate_weights(subap_surrogate s, double* weights_host);
+/* Gradient of the mean-squared error of the network on (params, targets),
+ * targets already standardised (device, m x d and m x r; m <= 65536).  The
+ * weights are not changed.  Blocking; host outputs. */
+SUBAP_API subap_status subap_surrogate_gradient(subap_surrogate s, const double* params_dev,
+                                                const double* targets_dev, int64_t m, double* grad_host,
+                                                double* loss_host, void* hip_stream);
+/* Train on m pairs (device, m x d params and m x r coefficients from
+ * subap_solve_batch).  loss_host: optional, one mean-squared error per epoch
+ * (of the last mini-batch).  Blocking. */
+SUBAP_API subap_status subap_surrogate_train(subap_surrogate s, const double* params_dev, const double* y_dev,
+                                             int64_t m, const subap_train_opts* opts, double* loss_host,
+                                             void* hip_stream);
+/* Predicted coefficients (device, m x r FP64).  Asynchronous. */
+SUBAP_API subap_status subap_surrogate_predict(subap_surrogate s, const double* params_dev, int64_t m,
+                                               double* y_dev, void* hip_stream);
+/*
+ * Surrogate with fallback: predict y for every p, evaluate its FP64 sketched
+ * relative residual |S(A(p) Q y - b)| / |S b| (subap_sketched_residual) and
+ * accept the prediction when it is <= accept_tol; the rejected parameters
+ * are gathered and solved by subap_solve_batch with fallback_opts (NULL =
+ * FP64), and their results scattered back.  accepted_dev (m bytes) and
+ * status_dev (m) may be NULL.  *n_accepted receives the accepted count.
+ * Blocking (the host needs the rejected count).
+ */
+SUBAP_API subap_status subap_surrogate_solve_batch(subap_model model, subap_surrogate s, const double* params_dev,
+                                                   int64_t m, double accept_tol, double* y_dev,
+                                                   uint8_t* accepted_dev, int32_t* status_dev,
+                                                   const subap_solve_opts* fallback_opts, int64_t* n_accepted,
+                                                   void* hip_stream);
+SUBAP_API subap_status subap_surrogate_free(subap_surrogate s);
 
 /*
  * Per-kernel timing for benchmarks.  While enabled, the library records a

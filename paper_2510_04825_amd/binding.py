@@ -24,14 +24,18 @@ OK, E_INVALID, E_NOMEM, E_HIP, E_RANK, E_NOCONV, E_NONFINITE, E_UNSUPPORTED = ra
 # subap_family
 FAMILY_DIFF2D, FAMILY_DIFF3D, FAMILY_KRR = 1, 2, 3
 # subap_precision
-FP64, FP32, BF16X3 = 0, 1, 2
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+FP64, FP32, BF16X3, FP16X3 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3}
 FAMILIES = {"diff2d": FAMILY_DIFF2D, "diff3d": FAMILY_DIFF3D, "krr": FAMILY_KRR}
 
 EXPORTS = ("subap_offline", "subap_solve_batch", "subap_lift", "subap_sketched_residual", "subap_model_dims",
            "subap_model_rows", "subap_model_basis", "subap_model_free", "subap_profile_enable",
-           "subap_profile_reset", "subap_profile_entry", "subap_profile_count", "subap_status_string",
-           "subap_last_error")
+           "subap_profile_reset", "subap_profile_entry", "subap_plan_create", "subap_plan_execute",
+           "subap_plan_shape", "subap_plan_free", "subap_solve_multi", "subap_surrogate_create",
+           "subap_surrogate_weights", "subap_surrogate_gradient", "subap_surrogate_train",
+           "subap_surrogate_predict", "subap_surrogate_solve_batch", "subap_surrogate_free",
+           "subap_surrogate_nparams", "subap_profile_count", "subap_status_string", "subap_last_error")
+PLAN_GRAPH, PLAN_AUTOTUNE = 1, 2
 
 
 class ProblemDesc(C.Structure):
@@ -47,6 +51,11 @@ class OfflineOpts(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("contraction", C.c_int32), ("refine_steps", C.c_int32)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_double), ("lr_min", C.c_double),
+                ("seed", C.c_uint64)]
 
 
 class SubapError(RuntimeError):
@@ -81,7 +90,25 @@ def load(path: str = LIB_PATH):
     lib.subap_model_rows.argtypes = [vp, vp]
     lib.subap_model_basis.argtypes = [vp, vp]
     lib.subap_model_free.argtypes = [vp]
-    for name in EXPORTS[:11]:
+    pp = C.POINTER(vp)
+    lib.subap_plan_create.argtypes = [pp, i32, pp, C.POINTER(i64), pp, pp, pp, C.POINTER(SolveOpts), i32, vp,
+                                      C.POINTER(vp)]
+    lib.subap_plan_execute.argtypes = [vp, vp]
+    lib.subap_plan_shape.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
+    lib.subap_plan_free.argtypes = [vp]
+    lib.subap_solve_multi.argtypes = [pp, i32, pp, C.POINTER(i64), pp, pp, pp, C.POINTER(SolveOpts), vp]
+    dp = C.POINTER(C.c_double)
+    lib.subap_surrogate_create.argtypes = [i32, i32, i32, vp, C.POINTER(vp)]
+    lib.subap_surrogate_nparams.argtypes = [vp]
+    lib.subap_surrogate_nparams.restype = i64
+    lib.subap_surrogate_weights.argtypes = [vp, vp]
+    lib.subap_surrogate_gradient.argtypes = [vp, vp, vp, i64, vp, dp, vp]
+    lib.subap_surrogate_train.argtypes = [vp, vp, vp, i64, C.POINTER(TrainOpts), vp, vp]
+    lib.subap_surrogate_predict.argtypes = [vp, vp, i64, vp, vp]
+    lib.subap_surrogate_solve_batch.argtypes = [vp, vp, vp, i64, C.c_double, vp, vp, vp, C.POINTER(SolveOpts),
+                                                C.POINTER(i64), vp]
+    lib.subap_surrogate_free.argtypes = [vp]
+    for name in EXPORTS[:23]:
         getattr(lib, name).restype = C.c_int
     lib.subap_status_string.argtypes = [C.c_int]
     lib.subap_status_string.restype = C.c_char_p
@@ -199,6 +226,144 @@ def subap_profile_read():
         _check(lib.subap_profile_entry(i, C.byref(name), C.byref(calls), C.byref(ms)))
         out[name.value.decode()] = (calls.value, ms.value)
     return out
+
+
+def _ptr_array(items):
+    arr = (C.c_void_p * len(items))()
+    for i, t in enumerate(items):
+        arr[i] = None if t is None else t.data_ptr()
+    return arr
+
+
+def _multi_args(models, params, ys, rhos, statuses):
+    k = len(models)
+    for mdl, p, y in zip(models, params, ys):
+        _, r, _, d = subap_model_dims(mdl)
+        m = p.shape[0]
+        _expect(p, (m, d), "float64", "params")
+        _expect(y, (m, r), "float64", "y")
+    for lst, dt in ((rhos, "float64"), (statuses, "int32")):
+        if lst is not None:
+            for t, p in zip(lst, params):
+                if t is not None:
+                    _expect(t, (p.shape[0],), dt, "rho/status")
+    hm = (C.c_void_p * k)(*models)
+    mm = (C.c_int64 * k)(*[p.shape[0] for p in params])
+    return (hm, k, _ptr_array(params), mm, _ptr_array(ys),
+            _ptr_array(rhos) if rhos is not None else None,
+            _ptr_array(statuses) if statuses is not None else None)
+
+
+def subap_plan_create(models, params, ys, rhos=None, statuses=None, contraction=FP64, refine_steps=0,
+                      flags=0, stream=None):
+    """Plan over model handles with per-model (m, d) params and (m, r) outputs; returns the handle."""
+    lib = load()
+    a = _multi_args(models, params, ys, rhos, statuses)
+    opts = SolveOpts(int(contraction), int(refine_steps))
+    h = C.c_void_p()
+    _check(lib.subap_plan_create(*a, C.byref(opts), int(flags), _stream(stream), C.byref(h)))
+    return h.value
+
+
+def subap_plan_execute(plan, stream=None):
+    _check(load().subap_plan_execute(C.c_void_p(plan), _stream(stream)))
+
+
+def subap_plan_shape(plan):
+    t, b = C.c_int32(), C.c_int32()
+    _check(load().subap_plan_shape(C.c_void_p(plan), C.byref(t), C.byref(b)))
+    return t.value, b.value
+
+
+def subap_plan_free(plan):
+    _check(load().subap_plan_free(C.c_void_p(plan)))
+
+
+def subap_solve_multi(models, params, ys, rhos=None, statuses=None, contraction=FP64, refine_steps=0,
+                      stream=None):
+    lib = load()
+    a = _multi_args(models, params, ys, rhos, statuses)
+    opts = SolveOpts(int(contraction), int(refine_steps))
+    _check(lib.subap_solve_multi(*a, C.byref(opts), _stream(stream)))
+
+
+def flatten_mlp(params):
+    """[(W1, b1), (W2, b2), (W3, b3)] -> the library's flat FP64 weight vector."""
+    return np.concatenate([a.ravel() for W, b in params for a in (W, b)]).astype(np.float64)
+
+
+def unflatten_mlp(flat, widths):
+    out, o = [], 0
+    for fi, fo in zip(widths[:-1], widths[1:]):
+        W = flat[o:o + fo * fi].reshape(fo, fi)
+        o += fo * fi
+        b = flat[o:o + fo]
+        o += fo
+        out.append((W, b))
+    return out
+
+
+def subap_surrogate_create(d, r, hidden, weights):
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    if w.size != hidden * d + hidden + hidden * hidden + hidden + r * hidden + r:
+        raise ValueError("weights length does not match (d, hidden, r)")
+    h = C.c_void_p()
+    _check(load().subap_surrogate_create(d, r, hidden, w.ctypes.data, C.byref(h)))
+    return h.value
+
+
+def subap_surrogate_nparams(s):
+    return int(load().subap_surrogate_nparams(C.c_void_p(s)))
+
+
+def subap_surrogate_weights(s):
+    out = np.empty(subap_surrogate_nparams(s), dtype=np.float64)
+    _check(load().subap_surrogate_weights(C.c_void_p(s), out.ctypes.data))
+    return out
+
+
+def subap_surrogate_gradient(s, params, targets, stream=None):
+    """(grad (nparams,), loss) for standardised targets (m, r) on device."""
+    g = np.empty(subap_surrogate_nparams(s), dtype=np.float64)
+    loss = C.c_double()
+    _check(load().subap_surrogate_gradient(C.c_void_p(s), _ptr(params), _ptr(targets), params.shape[0],
+                                           g.ctypes.data, C.byref(loss), _stream(stream)))
+    return g, loss.value
+
+
+def subap_surrogate_train(s, params, y, epochs, batch=0, lr=0.0, lr_min=0.0, seed=0, stream=None):
+    losses = np.zeros(epochs)
+    o = TrainOpts(int(epochs), int(batch), float(lr), float(lr_min), int(seed))
+    _check(load().subap_surrogate_train(C.c_void_p(s), _ptr(params), _ptr(y), params.shape[0], C.byref(o),
+                                        losses.ctypes.data, _stream(stream)))
+    return losses
+
+
+def subap_surrogate_predict(s, params, y, stream=None):
+    _check(load().subap_surrogate_predict(C.c_void_p(s), _ptr(params), params.shape[0], _ptr(y), _stream(stream)))
+
+
+def subap_surrogate_solve_batch(model, s, params, accept_tol, y, accepted=None, status=None, contraction=FP64,
+                                refine_steps=0, stream=None):
+    """Returns the number of accepted predictions."""
+    _, r, _, d = subap_model_dims(model)
+    m = params.shape[0]
+    _expect(params, (m, d), "float64", "params")
+    _expect(y, (m, r), "float64", "y")
+    if accepted is not None:
+        _expect(accepted, (m,), "uint8", "accepted")
+    if status is not None:
+        _expect(status, (m,), "int32", "status")
+    opts = SolveOpts(int(contraction), int(refine_steps))
+    n = C.c_int64()
+    _check(load().subap_surrogate_solve_batch(C.c_void_p(model), C.c_void_p(s), _ptr(params), m, float(accept_tol),
+                                              _ptr(y), _ptr(accepted), _ptr(status), C.byref(opts), C.byref(n),
+                                              _stream(stream)))
+    return n.value
+
+
+def subap_surrogate_free(s):
+    _check(load().subap_surrogate_free(C.c_void_p(s)))
 
 
 def subap_model_dims(model):

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsubap.so")
 
-SOURCES = ["capi.hip", "offline.hip", "fd_solve.hip", "krr.hip", "lift.hip"]
+SOURCES = ["capi.hip", "offline.hip", "fd_solve.hip", "krr.hip", "lift.hip", "fd_multi.hip", "mlp.hip"]
 
 ARCH = "gfx950"
 # Packed FP32 VALU instructions are switched off for every device pass.

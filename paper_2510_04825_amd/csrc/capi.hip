@@ -113,7 +113,8 @@ namespace {
 void free_model(subap_model_s* M) {
   if (!M) return;
   void* bufs[] = {M->Q, M->rows_d, M->bS, M->QS, M->rhs, M->phi, M->delta64, M->delta32, M->points,
-                  M->Dt64, M->D32, M->Qrm, M->Q32, M->Qhi, M->Qlo, M->work};
+                  M->Dt64, M->D32, M->Qrm, M->Q32, M->Qhi, M->Qlo, M->Qh16, M->Ql16, M->colscale_inv,
+                  M->work};
   for (void* b : bufs) dfree(b);
   delete M;
 }
@@ -235,13 +236,13 @@ subap_status subap_solve_batch(subap_model M, const double* params, int64_t m, d
   if (!params || !y) return invalid("params and y must not be NULL");
   const int prec = opts ? opts->contraction : SUBAP_FP64;
   const int refine = opts ? opts->refine_steps : 0;
-  if (prec < SUBAP_FP64 || prec > SUBAP_BF16X3) return invalid("unknown contraction precision");
+  if (prec < SUBAP_FP64 || prec > SUBAP_FP16X3) return invalid("unknown contraction precision");
   if (refine < 0 || refine > 4) return invalid("refine_steps must be in [0, 4]");
   if (m > (int64_t(1) << 31) / 64) return invalid("m too large for one call");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   if (M->family == SUBAP_FAMILY_KRR) return krr_solve(M, params, m, y, rho, status, prec, refine, st);
-  if (prec == SUBAP_BF16X3) {
-    set_error("the split-bf16 contraction is implemented for the kernel family only");
+  if (prec == SUBAP_BF16X3 || prec == SUBAP_FP16X3) {
+    set_error("the split 16-bit contractions are implemented for the kernel family only");
     return SUBAP_E_UNSUPPORTED;
   }
   return fd_solve(M, params, m, y, rho, status, prec, refine, st);
@@ -294,6 +295,175 @@ subap_status subap_sketched_residual(subap_model M, const double* params, int64_
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   if (M->family == SUBAP_FAMILY_KRR) return krr_residual(M, params, m, y, res, norm, st);
   return fd_residual(M, params, m, y, res, norm, st);
+}
+
+static subap_status plan_args(const subap_model* models, int32_t k, const double* const* params, const int64_t* m,
+                              double* const* y, const subap_solve_opts* opts, int* prec, int* refine) {
+  if (!models || !params || !m || !y || k < 1) return invalid("models, params, m and y must be given and k >= 1");
+  *prec = opts ? opts->contraction : SUBAP_FP64;
+  *refine = opts ? opts->refine_steps : 0;
+  if (*prec != SUBAP_FP64 && *prec != SUBAP_FP32) return invalid("batched plans take FP64 or FP32 contractions");
+  if (*refine < 0 || *refine > 4) return invalid("refine_steps must be in [0, 4]");
+  int64_t total = 0;
+  for (int i = 0; i < k; ++i) {
+    if (!models[i]) return invalid("model must not be NULL");
+    if (models[i]->family != SUBAP_FAMILY_DIFF2D && models[i]->family != SUBAP_FAMILY_DIFF3D)
+      return invalid("batched plans take finite-difference models");
+    if (m[i] < 0) return invalid("m must be >= 0");
+    if (m[i] > 0 && (!params[i] || !y[i])) return invalid("params and y must not be NULL when m > 0");
+    total += m[i];
+  }
+  if (total > (int64_t(1) << 40)) return invalid("too many parameters in one plan");
+  return SUBAP_OK;
+}
+
+subap_status subap_plan_create(const subap_model* models, int32_t k, const double* const* params, const int64_t* m,
+                               double* const* y, double* const* rho, int32_t* const* status,
+                               const subap_solve_opts* opts, int32_t flags, void* hip_stream, subap_plan* out) {
+  clear_error();
+  if (!out) return invalid("out must not be NULL");
+  *out = nullptr;
+  int prec = 0, refine = 0;
+  SUBAP_TRY(plan_args(models, k, params, m, y, opts, &prec, &refine));
+  subap_plan_s* h = new (std::nothrow) subap_plan_s{nullptr};
+  if (!h) return SUBAP_E_NOMEM;
+  subap_status rc = plan_build(models, k, params, m, y, rho, status, prec, refine, flags,
+                               static_cast<hipStream_t>(hip_stream), &h->impl);
+  if (rc != SUBAP_OK) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return SUBAP_OK;
+}
+
+subap_status subap_plan_execute(subap_plan plan, void* hip_stream) {
+  clear_error();
+  if (!plan || !plan->impl) return invalid("plan must not be NULL");
+  return plan_execute(plan->impl, static_cast<hipStream_t>(hip_stream));
+}
+
+subap_status subap_plan_shape(subap_plan plan, int32_t* threads, int32_t* blocks) {
+  clear_error();
+  if (!plan || !plan->impl) return invalid("plan must not be NULL");
+  int t = 0, b = 0;
+  plan_shape(plan->impl, &t, &b);
+  if (threads) *threads = t;
+  if (blocks) *blocks = b;
+  return SUBAP_OK;
+}
+
+subap_status subap_plan_free(subap_plan plan) {
+  clear_error();
+  if (!plan) return SUBAP_OK;
+  (void)hipDeviceSynchronize();
+  plan_free(plan->impl);
+  delete plan;
+  return SUBAP_OK;
+}
+
+subap_status subap_solve_multi(const subap_model* models, int32_t k, const double* const* params, const int64_t* m,
+                               double* const* y, double* const* rho, int32_t* const* status,
+                               const subap_solve_opts* opts, void* hip_stream) {
+  subap_plan plan = nullptr;
+  SUBAP_TRY(subap_plan_create(models, k, params, m, y, rho, status, opts, 0, hip_stream, &plan));
+  subap_status rc = subap_plan_execute(plan, hip_stream);
+  if (rc == SUBAP_OK) rc = hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)) == hipSuccess
+                               ? SUBAP_OK : SUBAP_E_HIP;
+  subap_plan_free(plan);
+  return rc;
+}
+
+subap_status subap_surrogate_create(int32_t d, int32_t r, int32_t hidden, const double* w, subap_surrogate* out) {
+  clear_error();
+  if (!out || !w) return invalid("weights and out must not be NULL");
+  *out = nullptr;
+  if (d < 1 || d > 16 || r < 1 || r > kMaxR || hidden < 1 || hidden > 4096)
+    return invalid("need 1 <= d <= 16, 1 <= r <= 64, 1 <= hidden <= 4096");
+  const int64_t nw = int64_t(hidden) * d + hidden + int64_t(hidden) * hidden + hidden + int64_t(r) * hidden + r;
+  if (!all_finite(w, nw)) return invalid("weights have non-finite entries");
+  subap_surrogate_s* h = new (std::nothrow) subap_surrogate_s{nullptr};
+  if (!h) return SUBAP_E_NOMEM;
+  subap_status rc = surrogate_create(d, r, hidden, w, &h->impl);
+  if (rc != SUBAP_OK) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return SUBAP_OK;
+}
+
+int64_t subap_surrogate_nparams(subap_surrogate s) {
+  return (s && s->impl) ? surrogate_nparams(s->impl) : -1;
+}
+
+subap_status subap_surrogate_weights(subap_surrogate s, double* w) {
+  clear_error();
+  if (!s || !s->impl || !w) return invalid("surrogate and weights must not be NULL");
+  return surrogate_weights(s->impl, w);
+}
+
+subap_status subap_surrogate_gradient(subap_surrogate s, const double* P, const double* T, int64_t m, double* g,
+                                      double* loss, void* hip_stream) {
+  clear_error();
+  if (!s || !s->impl || !P || !T || !g || !loss) return invalid("arguments must not be NULL");
+  if (m < 1 || m > 65536) return invalid("m must be in [1, 65536]");
+  return surrogate_gradient(s->impl, P, T, m, g, loss, static_cast<hipStream_t>(hip_stream));
+}
+
+subap_status subap_surrogate_train(subap_surrogate s, const double* P, const double* Y, int64_t m,
+                                   const subap_train_opts* o, double* loss, void* hip_stream) {
+  clear_error();
+  if (!s || !s->impl || !P || !Y || !o) return invalid("arguments must not be NULL");
+  if (m < 1 || m > (int64_t(1) << 31) - 1) return invalid("m must be in [1, 2^31)");
+  if (o->epochs < 1) return invalid("epochs must be >= 1");
+  const int batch = o->batch == 0 ? 4096 : o->batch;
+  if (batch < 1 || batch > 65536) return invalid("batch must be in [1, 65536]");
+  const double lr = o->lr == 0.0 ? 1e-3 : o->lr;
+  if (!(lr > 0.0) || !(o->lr_min >= 0.0) || !std::isfinite(lr)) return invalid("learning rates must be finite, lr > 0");
+  return surrogate_train(s->impl, P, Y, m, o->epochs, batch, lr, o->lr_min, o->seed, loss,
+                         static_cast<hipStream_t>(hip_stream));
+}
+
+subap_status subap_surrogate_predict(subap_surrogate s, const double* P, int64_t m, double* y, void* hip_stream) {
+  clear_error();
+  if (!s || !s->impl) return invalid("surrogate must not be NULL");
+  if (m < 0) return invalid("m must be >= 0");
+  if (m == 0) return SUBAP_OK;
+  if (!P || !y) return invalid("params and y must not be NULL");
+  return surrogate_predict(s->impl, P, m, y, static_cast<hipStream_t>(hip_stream));
+}
+
+subap_status subap_surrogate_solve_batch(subap_model M, subap_surrogate s, const double* P, int64_t m, double tol,
+                                         double* y, uint8_t* accepted, int32_t* status,
+                                         const subap_solve_opts* fb, int64_t* n_acc, void* hip_stream) {
+  clear_error();
+  if (!M || !s || !s->impl || !n_acc) return invalid("model, surrogate and n_accepted must not be NULL");
+  if (m < 0) return invalid("m must be >= 0");
+  *n_acc = 0;
+  if (m == 0) return SUBAP_OK;
+  if (!P || !y) return invalid("params and y must not be NULL");
+  if (!(tol >= 0.0)) return invalid("accept_tol must be >= 0");
+  int sd_ = 0, sr_ = 0;
+  surrogate_shape(s->impl, &sd_, &sr_);
+  if (M->d != sd_ || M->r != sr_) return invalid("surrogate shape does not match the model");
+  const int prec = fb ? fb->contraction : SUBAP_FP64;
+  const int refine = fb ? fb->refine_steps : 0;
+  if (prec < SUBAP_FP64 || prec > SUBAP_FP16X3 || refine < 0 || refine > 4) return invalid("bad fallback options");
+  if (M->family != SUBAP_FAMILY_KRR && (prec == SUBAP_BF16X3 || prec == SUBAP_FP16X3))
+    return invalid("split 16-bit fallback is for the kernel family only");
+  if (m > (int64_t(1) << 31) / 64) return invalid("m too large for one call");
+  return surrogate_solve(M, s->impl, P, m, tol, y, accepted, status, prec, refine, n_acc,
+                         static_cast<hipStream_t>(hip_stream));
+}
+
+subap_status subap_surrogate_free(subap_surrogate s) {
+  clear_error();
+  if (!s) return SUBAP_OK;
+  (void)hipDeviceSynchronize();
+  surrogate_free(s->impl);
+  delete s;
+  return SUBAP_OK;
 }
 
 subap_status subap_profile_enable(int32_t on) {

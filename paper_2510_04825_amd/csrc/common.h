@@ -77,6 +77,9 @@ struct subap_model_s {
   float* Q32 = nullptr;               // n x r col-major FP32
   uint16_t* Qhi = nullptr;            // n x r col-major bf16 (round to nearest even)
   uint16_t* Qlo = nullptr;            // bf16(Q32 - hi)
+  uint16_t* Qh16 = nullptr;           // n x r col-major fp16 of Q[:, c] * 2^e_c
+  uint16_t* Ql16 = nullptr;           // fp16 of the remainder
+  double* colscale_inv = nullptr;     // r: 2^-e_c
 
   // online workspaces (grown on demand)
   void* work = nullptr;
@@ -104,4 +107,37 @@ subap_status krr_residual(subap_model_s* M, const double* params, int64_t m, con
 
 subap_status ensure_work(subap_model_s* M, size_t bytes);
 
+// ---- batched plans (fd_multi.hip) ----
+struct PlanImpl;
+subap_status plan_build(subap_model_s* const* models, int k, const double* const* params, const int64_t* m,
+                        double* const* y, double* const* rho, int32_t* const* status, int prec, int refine,
+                        int flags, hipStream_t st, PlanImpl** out);
+subap_status plan_execute(PlanImpl* P, hipStream_t st);
+void plan_free(PlanImpl* P);
+void plan_shape(const PlanImpl* P, int* threads, int* blocks);
+
+// ---- learned surrogate (mlp.hip) ----
+struct Surrogate;
+subap_status surrogate_create(int d, int r, int H, const double* weights, Surrogate** out);
+void surrogate_free(Surrogate* S);
+long surrogate_nparams(const Surrogate* S);
+void surrogate_shape(const Surrogate* S, int* d, int* r);
+subap_status surrogate_weights(Surrogate* S, double* host);
+subap_status surrogate_gradient(Surrogate* S, const double* P, const double* T, int64_t m, double* grad_host,
+                                double* loss, hipStream_t st);
+subap_status surrogate_train(Surrogate* S, const double* P, const double* Y, int64_t m, int epochs, int batch,
+                             double lr, double lr_min, uint64_t seed, double* loss_out, hipStream_t st);
+subap_status surrogate_predict(Surrogate* S, const double* P, int64_t m, double* y, hipStream_t st);
+subap_status surrogate_solve(subap_model_s* M, Surrogate* S, const double* P, int64_t m, double tol, double* y,
+                             uint8_t* accepted, int32_t* status, int prec, int refine, int64_t* n_acc,
+                             hipStream_t st);
+
 }  // namespace subap
+
+struct subap_surrogate_s {
+  subap::Surrogate* impl;
+};
+
+struct subap_plan_s {
+  subap::PlanImpl* impl;
+};

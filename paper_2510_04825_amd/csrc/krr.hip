@@ -8,7 +8,8 @@
 //   FP64      exp and products in FP64 (vector ALU);
 //   FP32      v_exp_f32 rows, FP32 MFMA 32x32x2, FP32 accumulation;
 //   BF16X3    v_exp_f32 rows split as bf16 hi + lo, Q split likewise, three
-//             MFMA 32x32x16 products hi*hi + hi*lo + lo*hi, FP32 accumulation.
+//             MFMA 32x32x16 products hi*hi + hi*lo + lo*hi, FP32 accumulation;
+//   FP16X3    the same with fp16 halves (Q columns scaled by powers of two).
 // Then the FP64 Householder least squares (team_qr.h), and optional FP64
 // refinement: r_S = K_S(p) (Q y) + lambda (Q y)_S - b_S with FP64-accurate
 // kernel entries, correction from the stored factorisation.
@@ -134,40 +135,80 @@ __global__ __launch_bounds__(256) void k_contract_f64_small(const double* params
 // (k0..k0+31) and PW parameters; per 16 points it loads its 32 x 16 distance
 // tile once and the 16 x 32 tile of Q per column block once, and reuses both
 // for all PW parameters.  MFMA 32x32 operand layout (64 lanes): lane l holds
-// row/column (l mod 32) and the 8 (bf16) or 1 (fp32) reduction indices of
+// row/column (l mod 32) and the 8 (16-bit) or 1 (fp32) reduction indices of
 // half (l / 32); A and B use the same reduction index for the same element.
 // Accumulator element i of lane l is (row 8 (i/4) + 4 (l/32) + i mod 4,
 // column l mod 32).
+//
+// The points are split into kSplit contiguous ranges (grid.z); each range is
+// accumulated in FP32 and written as its own partial, and the least-squares
+// kernel sums the partials in FP64, which keeps the FP32 accumulation error
+// to that of n / kSplit terms.
+//
+// 16-bit split forms: K = 2^(c D) from v_exp_f32 is split as hi = t16(K),
+// lo = t16(K - hi) and multiplied with the precomputed split of Q by three
+// MFMAs (hi*hi + hi*lo + lo*hi).  t16 is bf16 (BF16X3) or fp16 (FP16X3); the
+// fp16 split of Q is taken on the column scaled by a power of two so that its
+// largest entry is near 2^14, and the scale is undone in FP64 afterwards.
 // ---------------------------------------------------------------------------
+constexpr int kSplit = 4;
+
 struct MArgs {
   const double* params;
   int64_t m, n;
   int r, s;
   const float* D32;       // s x n
-  const uint16_t* Qhi;    // n x r col-major bf16
-  const uint16_t* Qlo;
+  const uint16_t* Qh;     // n x r col-major, bf16 or fp16 bits (scaled columns)
+  const uint16_t* Ql;
   const float* Q32;       // n x r col-major fp32
-  float* G;               // m x s x r
+  float* G;               // kSplit x m x s x r partials
 };
 
-__device__ __forceinline__ void load_dist8(const float* Drow, int64_t j, int64_t n, bool vec, float (&dv)[8]) {
-  if (vec && j + 8 <= n) {
+__device__ __forceinline__ void load_dist8(const float* Drow, int64_t j, int64_t jend, bool vec, float (&dv)[8]) {
+  if (vec && j + 8 <= jend) {
     const f32x4 a = *reinterpret_cast<const f32x4*>(Drow + j);
     const f32x4 b = *reinterpret_cast<const f32x4*>(Drow + j + 4);
     dv[0] = a[0]; dv[1] = a[1]; dv[2] = a[2]; dv[3] = a[3];
     dv[4] = b[0]; dv[5] = b[1]; dv[6] = b[2]; dv[7] = b[3];
   } else {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) dv[e] = (j + e < n) ? Drow[j + e] : __builtin_inff();
+    for (int e = 0; e < 8; ++e) dv[e] = (j + e < jend) ? Drow[j + e] : __builtin_inff();
   }
 }
 
-template <int PW, int NB>
-__global__ __launch_bounds__(256) void k_contract_bf16x3(MArgs A) {
+template <typename T16>
+struct Vec8;
+template <>
+struct Vec8<__bf16> {
+  typedef __bf16 type __attribute__((ext_vector_type(8)));
+  static __device__ __forceinline__ f32x16 mfma(type a, type b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Vec8<_Float16> {
+  typedef _Float16 type __attribute__((ext_vector_type(8)));
+  static __device__ __forceinline__ f32x16 mfma(type a, type b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+// (j range of split z)
+__device__ __forceinline__ void split_range(int64_t n, int z, int64_t* jb, int64_t* je) {
+  const int64_t per = ((n + kSplit - 1) / kSplit + 15) / 16 * 16;
+  *jb = z * per;
+  *je = n < (z + 1) * per ? n : (z + 1) * per;
+}
+
+template <typename T16, int PW, int NB>
+__global__ __launch_bounds__(256) void k_contract_x3(MArgs A) {
+  typedef typename Vec8<T16>::type v8;
   const int wave = threadIdx.x / 64, l = threadIdx.x % 64;
   const int k0 = (blockIdx.y * 4 + wave) * 32;
   if (k0 >= A.s) return;  // uniform per wave
   const int64_t p0 = static_cast<int64_t>(blockIdx.x) * PW;
+  int64_t jb, je;
+  split_range(A.n, blockIdx.z, &jb, &je);
   const int row = k0 + (l & 31);
   const bool row_ok = row < A.s;
   const float* Drow = A.D32 + static_cast<int64_t>(row_ok ? row : 0) * A.n;
@@ -187,49 +228,50 @@ __global__ __launch_bounds__(256) void k_contract_bf16x3(MArgs A) {
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[w][nb][i] = 0.0f;
-  for (int64_t j0 = 0; j0 < A.n; j0 += 16) {
+  for (int64_t j0 = jb; j0 < je; j0 += 16) {
     const int64_t j = j0 + jo;
     float dv[8];
-    load_dist8(Drow, j, A.n, vec, dv);
+    load_dist8(Drow, j, je, vec, dv);
     if (!row_ok)
 #pragma unroll
       for (int e = 0; e < 8; ++e) dv[e] = __builtin_inff();
-    bf16x8 qh[NB], ql[NB];
+    v8 qh[NB], ql[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
       const int c = nb * 32 + (l & 31);
-      if (c < A.r && vec && j + 8 <= A.n) {
-        qh[nb] = *reinterpret_cast<const bf16x8*>(A.Qhi + static_cast<int64_t>(c) * A.n + j);
-        ql[nb] = *reinterpret_cast<const bf16x8*>(A.Qlo + static_cast<int64_t>(c) * A.n + j);
+      if (c < A.r && vec && j + 8 <= je) {
+        qh[nb] = *reinterpret_cast<const v8*>(A.Qh + static_cast<int64_t>(c) * A.n + j);
+        ql[nb] = *reinterpret_cast<const v8*>(A.Ql + static_cast<int64_t>(c) * A.n + j);
       } else {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-          const bool ok = c < A.r && j + e < A.n;
-          const uint16_t hb = ok ? A.Qhi[static_cast<int64_t>(c) * A.n + j + e] : 0;
-          const uint16_t lb = ok ? A.Qlo[static_cast<int64_t>(c) * A.n + j + e] : 0;
-          qh[nb][e] = __builtin_bit_cast(__bf16, hb);
-          ql[nb][e] = __builtin_bit_cast(__bf16, lb);
+          const bool ok = c < A.r && j + e < je;
+          const uint16_t hb = ok ? A.Qh[static_cast<int64_t>(c) * A.n + j + e] : 0;
+          const uint16_t lb = ok ? A.Ql[static_cast<int64_t>(c) * A.n + j + e] : 0;
+          qh[nb][e] = __builtin_bit_cast(T16, hb);
+          ql[nb][e] = __builtin_bit_cast(T16, lb);
         }
       }
     }
 #pragma unroll
     for (int w = 0; w < PW; ++w) {
-      bf16x8 kh, kl;
+      v8 kh, kl;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const float kv = __builtin_amdgcn_exp2f(cexp[w] * dv[e]);
-        const __bf16 h = static_cast<__bf16>(kv);
+        const T16 h = static_cast<T16>(kv);
         kh[e] = h;
-        kl[e] = static_cast<__bf16>(kv - static_cast<float>(h));
+        kl[e] = static_cast<T16>(kv - static_cast<float>(h));
       }
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        acc[w][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kh, qh[nb], acc[w][nb], 0, 0, 0);
-        acc[w][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kh, ql[nb], acc[w][nb], 0, 0, 0);
-        acc[w][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(kl, qh[nb], acc[w][nb], 0, 0, 0);
+        acc[w][nb] = Vec8<T16>::mfma(kh, qh[nb], acc[w][nb]);
+        acc[w][nb] = Vec8<T16>::mfma(kh, ql[nb], acc[w][nb]);
+        acc[w][nb] = Vec8<T16>::mfma(kl, qh[nb], acc[w][nb]);
       }
     }
   }
+  float* Gz = A.G + static_cast<int64_t>(blockIdx.z) * A.m * A.s * A.r;
 #pragma unroll
   for (int w = 0; w < PW; ++w) {
     const int64_t p = p0 + w;
@@ -240,7 +282,7 @@ __global__ __launch_bounds__(256) void k_contract_bf16x3(MArgs A) {
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         const int rr = k0 + 8 * (i / 4) + 4 * (l >> 5) + (i & 3);
-        if (rr < A.s && c < A.r) A.G[(p * A.s + rr) * A.r + c] = acc[w][nb][i];
+        if (rr < A.s && c < A.r) Gz[(p * A.s + rr) * A.r + c] = acc[w][nb][i];
       }
     }
   }
@@ -252,6 +294,8 @@ __global__ __launch_bounds__(256) void k_contract_f32(MArgs A) {
   const int k0 = (blockIdx.y * 4 + wave) * 32;
   if (k0 >= A.s) return;
   const int64_t p0 = static_cast<int64_t>(blockIdx.x) * PW;
+  int64_t jb, je;
+  split_range(A.n, blockIdx.z, &jb, &je);
   const int row = k0 + (l & 31);
   const bool row_ok = row < A.s;
   const float* Drow = A.D32 + static_cast<int64_t>(row_ok ? row : 0) * A.n;
@@ -271,10 +315,10 @@ __global__ __launch_bounds__(256) void k_contract_f32(MArgs A) {
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[w][nb][i] = 0.0f;
-  for (int64_t j0 = 0; j0 < A.n; j0 += 16) {
+  for (int64_t j0 = jb; j0 < je; j0 += 16) {
     const int64_t j = j0 + jo;
     float dv[8];
-    load_dist8(Drow, j, A.n, vec, dv);
+    load_dist8(Drow, j, je, vec, dv);
     if (!row_ok)
 #pragma unroll
       for (int e = 0; e < 8; ++e) dv[e] = __builtin_inff();
@@ -284,9 +328,9 @@ __global__ __launch_bounds__(256) void k_contract_f32(MArgs A) {
       const int c = nb * 32 + (l & 31);
       const float* qc = A.Q32 + static_cast<int64_t>(c < A.r ? c : 0) * A.n;
       float tmp[8];
-      load_dist8(qc, j, A.n, vec, tmp);
+      load_dist8(qc, j, je, vec, tmp);
 #pragma unroll
-      for (int e = 0; e < 8; ++e) qv[nb][e] = (c < A.r && j + e < A.n) ? tmp[e] : 0.0f;
+      for (int e = 0; e < 8; ++e) qv[nb][e] = (c < A.r && j + e < je) ? tmp[e] : 0.0f;
     }
 #pragma unroll
     for (int w = 0; w < PW; ++w) {
@@ -299,6 +343,7 @@ __global__ __launch_bounds__(256) void k_contract_f32(MArgs A) {
       }
     }
   }
+  float* Gz = A.G + static_cast<int64_t>(blockIdx.z) * A.m * A.s * A.r;
 #pragma unroll
   for (int w = 0; w < PW; ++w) {
     const int64_t p = p0 + w;
@@ -309,7 +354,7 @@ __global__ __launch_bounds__(256) void k_contract_f32(MArgs A) {
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
         const int rr = k0 + 8 * (i / 4) + 4 * (l >> 5) + (i & 3);
-        if (rr < A.s && c < A.r) A.G[(p * A.s + rr) * A.r + c] = acc[w][nb][i];
+        if (rr < A.s && c < A.r) Gz[(p * A.s + rr) * A.r + c] = acc[w][nb][i];
       }
     }
   }
@@ -323,7 +368,9 @@ struct LArgs {
   const double* params;
   int64_t m;
   int r, s;
-  const void* G;          // float or double, m x s x r
+  const void* G;          // double m x s x r, or float nsplit x m x s x r partials
+  int nsplit;             // number of float partials to add (1 for double)
+  const double* colscale; // r: multiply column c of the sum by colscale[c] (or nullptr)
   const double* QS;       // s x r
   const double* bS;
   double lambda, bS_norm;
@@ -354,10 +401,16 @@ __global__ __launch_bounds__(256) void k_lsq(LArgs A) {
   for (int q = 0; q < R; ++q) {
     const int k = lane + TEAM * q;
 #pragma unroll
-    for (int c = 0; c < RM; ++c)
-      qr.a[q][c] = (k < s && c < r)
-                       ? static_cast<double>(G[(p * s + k) * r + c]) + A.lambda * A.QS[k * r + c]
-                       : 0.0;
+    for (int c = 0; c < RM; ++c) {
+      double g = 0.0;
+      if (k < s && c < r) {
+        for (int z = 0; z < A.nsplit; ++z)
+          g += static_cast<double>(G[((z * A.m + p) * s + k) * r + c]);
+        if (A.colscale) g *= A.colscale[c];
+        g += A.lambda * A.QS[k * r + c];
+      }
+      qr.a[q][c] = g;
+    }
     qr.b[q] = k < s ? A.bS[k] : 0.0;
   }
   qr.factor(r, lane, s_tau[team]);
@@ -599,7 +652,7 @@ subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double
     return SUBAP_E_UNSUPPORTED;
   }
   const int RM = rm_of(r);
-  const size_t gbytes = static_cast<size_t>(m) * s * r * (prec == SUBAP_FP64 ? 8 : 4);
+  const size_t gbytes = static_cast<size_t>(m) * s * r * (prec == SUBAP_FP64 ? 8 : 4 * kSplit);
   const int fac_stride = sh.team * sh.R * sh.RM + sh.RM;
   const size_t fbytes = refine > 0 ? static_cast<size_t>(m) * fac_stride * 8 : 0;
   const size_t pbytes = refine > 0 ? static_cast<size_t>(kRefSplit) * m * s * 8 : 0;
@@ -638,22 +691,32 @@ subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double
       }
     }
   } else {
-    MArgs a{params, m, n, r, s, M->D32, M->Qhi, M->Qlo, M->Q32, static_cast<float*>(G)};
+    const bool f16 = prec == SUBAP_FP16X3;
+    MArgs a{params, m, n, r, s, M->D32, f16 ? M->Qh16 : M->Qhi, f16 ? M->Ql16 : M->Qlo, M->Q32,
+            static_cast<float*>(G)};
     constexpr int PW = 8;
-    dim3 grid(static_cast<unsigned>((m + PW - 1) / PW), static_cast<unsigned>((s + 127) / 128));
+    const unsigned gy = static_cast<unsigned>((s + 127) / 128);
+    const dim3 g8(static_cast<unsigned>((m + PW - 1) / PW), gy, kSplit);
+    const dim3 g4(static_cast<unsigned>((m + 3) / 4), gy, kSplit);
     if (prec == SUBAP_BF16X3) {
       ProfScope prof("krr_contract_bf16x3", st);
-      if (r <= 32) hipLaunchKernelGGL((k_contract_bf16x3<PW, 1>), grid, dim3(256), 0, st, a);
-      else hipLaunchKernelGGL((k_contract_bf16x3<4, 2>), dim3((m + 3) / 4, grid.y), dim3(256), 0, st, a);
+      if (r <= 32) hipLaunchKernelGGL((k_contract_x3<__bf16, PW, 1>), g8, dim3(256), 0, st, a);
+      else hipLaunchKernelGGL((k_contract_x3<__bf16, 4, 2>), g4, dim3(256), 0, st, a);
+    } else if (prec == SUBAP_FP16X3) {
+      ProfScope prof("krr_contract_fp16x3", st);
+      if (r <= 32) hipLaunchKernelGGL((k_contract_x3<_Float16, PW, 1>), g8, dim3(256), 0, st, a);
+      else hipLaunchKernelGGL((k_contract_x3<_Float16, 4, 2>), g4, dim3(256), 0, st, a);
     } else {
       ProfScope prof("krr_contract_fp32", st);
-      if (r <= 32) hipLaunchKernelGGL((k_contract_f32<PW, 1>), grid, dim3(256), 0, st, a);
-      else hipLaunchKernelGGL((k_contract_f32<4, 2>), dim3((m + 3) / 4, grid.y), dim3(256), 0, st, a);
+      if (r <= 32) hipLaunchKernelGGL((k_contract_f32<PW, 1>), g8, dim3(256), 0, st, a);
+      else hipLaunchKernelGGL((k_contract_f32<4, 2>), g4, dim3(256), 0, st, a);
     }
   }
   SUBAP_HIP_TRY(hipGetLastError());
   // A3: least squares
-  LArgs la{params, m, r, s, G, M->QS, M->bS, M->lambda, M->bS_norm, y, rho, stat, fac, fac_stride};
+  LArgs la{params, m, r, s, G, prec == SUBAP_FP64 ? 1 : kSplit,
+           prec == SUBAP_FP16X3 ? M->colscale_inv : nullptr,
+           M->QS, M->bS, M->lambda, M->bS_norm, y, rho, stat, fac, fac_stride};
   {
     ProfScope prof("lsq_householder", st);
     if (prec == SUBAP_FP64) SUBAP_TRY(launch_lsq<double>(sh, la, st));

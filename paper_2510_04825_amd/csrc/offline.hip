@@ -637,6 +637,47 @@ __global__ void k_krr_tables(const double* Qm, const double* pts, int64_t n, int
   }
 }
 
+// Per-column power of two 2^e_c with max_j |Q[j, c]| 2^e_c in [2^13, 2^14).
+__global__ void k_colscale(const double* Qm, int64_t n, int r, double* scale, double* scale_inv) {
+  __shared__ double sh[kBlock];
+  const int c = blockIdx.x;
+  double mx = 0.0;
+  for (int64_t j = threadIdx.x; j < n; j += kBlock) mx = fmax(mx, fabs(Qm[static_cast<int64_t>(c) * n + j]));
+  sh[threadIdx.x] = mx;
+  __syncthreads();
+  for (int st = kBlock / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + st]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    int e = 0;
+    if (sh[0] > 0.0) {
+      int ex;
+      frexp(sh[0], &ex);  // sh[0] = f 2^ex, f in [0.5, 1)
+      e = 14 - ex;
+    }
+    scale[c] = ldexp(1.0, e);
+    scale_inv[c] = ldexp(1.0, -e);
+  }
+}
+
+__device__ __forceinline__ uint16_t f16_bits(float x) {
+  return __builtin_bit_cast(uint16_t, static_cast<_Float16>(x));
+}
+
+__global__ void k_fp16_split(const double* Qm, int64_t n, int r, const double* scale, uint16_t* Qh,
+                             uint16_t* Ql) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  for (int c = 0; c < r; ++c) {
+    const int64_t k = static_cast<int64_t>(c) * n + j;
+    const float v = static_cast<float>(Qm[k] * scale[c]);
+    const _Float16 hi = static_cast<_Float16>(v);
+    Qh[k] = __builtin_bit_cast(uint16_t, hi);
+    Ql[k] = f16_bits(v - static_cast<float>(hi));
+  }
+}
+
 __global__ void k_gather_rows(const double* Qm, int64_t n, int r, int s, const int* rows, const double* rhs,
                               double* bS, double* QS) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -670,6 +711,15 @@ subap_status build_tables(subap_model_s* M, hipStream_t st) {
                        M->Qlo);
     hipLaunchKernelGGL(k_gather_rows, dim3((s + 63) / 64), dim3(64), 0, st, M->Q, n, r, s, M->rows_d, M->rhs,
                        M->bS, M->QS);
+    DevVec scale;
+    SUBAP_TRY(dalloc(&scale.p, r));
+    SUBAP_TRY(dalloc(&M->colscale_inv, r));
+    SUBAP_TRY(dalloc(&M->Qh16, static_cast<size_t>(n) * r));
+    SUBAP_TRY(dalloc(&M->Ql16, static_cast<size_t>(n) * r));
+    hipLaunchKernelGGL(k_colscale, dim3(r), dim3(kBlock), 0, st, M->Q, n, r, scale.p, M->colscale_inv);
+    hipLaunchKernelGGL(k_fp16_split, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                       M->Q, n, r, scale.p, M->Qh16, M->Ql16);
+    SUBAP_HIP_TRY(hipStreamSynchronize(st));
   } else {
     const size_t tab = static_cast<size_t>(s) * M->F;
     SUBAP_TRY(dalloc(&M->phi, tab * M->d));

@@ -87,17 +87,18 @@ def krr(n: int = 16384, dim: int = 8, r: int = 32, s: int = 128, m: int = 4096,
     )
 
 
-def uneven(k: int = 64, seed: int = 404, max_m: int = 4096) -> list:
+def uneven(k: int = 64, seed: int = 404, max_m: int = 4096,
+           grids=(32, 64, 128, 256, 512)) -> list:
     """List of ``k`` independent 2-D diffusion instances of uneven size.
 
-    Instance i: grid side (32, 64, 128, 256, 512)[i % 5], r = (8, 16, 32, 64)[i % 4],
+    Instance i: grid side grids[i % len(grids)], r = (8, 16, 32, 64)[i % 4],
     s drawn uniformly in [2r, 4r], m = 2^j with j uniform in [4, 12] (capped at
     ``max_m``).  Each instance has its own snapshot and test points.
     """
     g_sizes, *g_inst = _streams(seed, 1 + 2 * k)
     out = []
     for i in range(k):
-        N = (32, 64, 128, 256, 512)[i % 5]
+        N = grids[i % len(grids)]
         r = (8, 16, 32, 64)[i % 4]
         s = int(g_sizes.integers(2 * r, 4 * r + 1))
         m = min(int(2 ** g_sizes.integers(4, 13)), max_m)

@@ -67,7 +67,7 @@ def test_krr_fp64_matches_oracle(krr_small, krr_model, krr_oracle_y):
     assert d.max() <= 1e-11, d.max()
 
 
-@pytest.mark.parametrize("prec", [B.FP32, B.BF16X3])
+@pytest.mark.parametrize("prec", [B.FP32, B.BF16X3, B.FP16X3])
 def test_krr_reduced_precision_with_refinement(krr_small, krr_model, krr_oracle_y, prec):
     w, off = krr_small
     header(f"krr precision {prec}")
@@ -147,8 +147,21 @@ def krr_full():
     return w, fam, Q, rows
 
 
-@pytest.mark.parametrize("prec,refine,tol", [(B.FP64, 0, 1e-11), (B.BF16X3, 1, 1e-6), (B.FP32, 1, 1e-6)])
-def test_krr_full_size_sampled(krr_full, prec, refine, tol):
+# First-order size of the contraction error relative to |S A Q|, per form:
+# generous upper bounds (2x or more over CPU emulation of each form).
+U_EFF = {B.BF16X3: 2.0 ** -15, B.FP16X3: 2.0 ** -18, B.FP32: 2.0 ** -18, B.FP64: 0.0}
+
+
+@pytest.mark.parametrize("prec,refine", [(B.FP64, 0), (B.BF16X3, 1), (B.FP16X3, 1), (B.FP32, 1)])
+def test_krr_full_size_sampled(krr_full, prec, refine):
+    """Full sizes, bench launch configuration (s = 128, m = 4096).
+
+    With s > r, simple refinement converges to the solution whose FP64
+    residual is orthogonal to the range of the computed S A Q, not of the
+    exact one: a bias of about u_eff kappa(S A Q) rho*, with rho* the sketched
+    relative residual.  The synthetic random basis used at full size makes
+    rho* of order one, so the bar is 1e-6 plus that bias (FP64: 1e-11).
+    """
     w, fam, Q, rows = krr_full
     header(f"krr full size prec={prec} refine={refine}")
     M = B.Model(w, basis=Q, rows=rows)
@@ -158,19 +171,43 @@ def test_krr_full_size_sampled(krr_full, prec, refine, tol):
         y, _, st = M.solve(to_dev(P), contraction=prec, refine_steps=refine)
         st = st.cpu().numpy()
         y = y.cpu().numpy()
-        bad = np.flatnonzero(st != B.OK)
-        print("status counts", {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))},
-              "first bad", bad[:8], "params", P[bad[:8], 0] if len(bad) else None,
-              "nan rows", int(np.isnan(y).any(axis=1).sum()))
         assert np.all(st == B.OK)
         idx = np.random.default_rng(7).choice(len(P), size=12, replace=False)
         idx = np.concatenate([idx, [0, len(P) - 1]])
         for i in idx:
             G = On.reduced_matrix(fam, Q, rows, P[i])
             bS = fam.rhs_rows(P[i], rows)
+            yo, _, rho = On.householder_lsq(G, bS)
+            sv = np.linalg.svd(G, compute_uv=False)
+            tol = 1e-11 if prec == B.FP64 else 1e-6 + U_EFF[prec] * sv[0] / sv[-1] * rho / np.linalg.norm(bS)
+            d = np.linalg.norm(G @ (y[i] - yo)) / np.linalg.norm(bS)
+            print(f"p[{i}]={P[i, 0]:.3f} sketched distance {d:.2e} (bar {tol:.1e})")
+            assert d <= tol, (i, d, tol)
+    finally:
+        M.free()
+
+
+@pytest.mark.parametrize("prec", [B.BF16X3, B.FP16X3, B.FP32])
+def test_krr_full_size_interpolation(krr_full, prec):
+    """s = r (interpolation, zero sketched residual): no refinement bias, so
+    reduced-precision forms plus one FP64 step are held to 1e-6 at full size."""
+    w, fam, Q, rows = krr_full
+    r = w["r"]
+    wi = dict(w, s=r)
+    rows_i = rows[:r]
+    header(f"krr full size interpolation prec={prec}")
+    M = B.Model(wi, basis=Q, rows=rows_i)
+    try:
+        P = w["test_params"]
+        y, _, st = M.solve(to_dev(P), contraction=prec, refine_steps=1)
+        assert np.all(st.cpu().numpy() == B.OK)
+        y = y.cpu().numpy()
+        for i in np.random.default_rng(8).choice(len(P), size=12, replace=False):
+            G = On.reduced_matrix(fam, Q, rows_i, P[i])
+            bS = fam.rhs_rows(P[i], rows_i)
             yo, _, _ = On.householder_lsq(G, bS)
             d = np.linalg.norm(G @ (y[i] - yo)) / np.linalg.norm(bS)
-            print(f"p[{i}]={P[i, 0]:.3f} sketched distance {d:.2e}")
-            assert d <= tol, (i, d)
+            print(f"p[{i}]={P[i, 0]:.3f} interpolation distance {d:.2e}")
+            assert d <= 1e-6, (i, d)
     finally:
         M.free()

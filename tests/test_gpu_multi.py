@@ -1,0 +1,110 @@
+"""GPU parity of the batched persistent solve (many uneven finite-difference
+instances in one launch) against the FP64 oracle, with and without hipGraph
+replay and autotuning.  Bars as for the single-model solve: delta_res
+<= 1e-12 (FP64), <= 1e-6 (FP32 contraction + one FP64 refinement)."""
+import numpy as np
+import pytest
+
+import subap_inputs as si
+from oracle import offline as O
+from oracle import online as On
+from paper_2510_04825_amd import binding as B
+from tests.gpu_util import device, header, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def uneven_small():
+    # every r of the uneven workload (8..64) and s in [2r, 4r], on grids the
+    # oracle solves in seconds; m capped to keep the oracle loop short
+    insts = si.uneven(k=8, grids=(16, 24, 20), max_m=64)
+    out = []
+    for w in insts:
+        off = O.offline(w)
+        yo = On.solve(off["family"], off["Q"], off["rows"], w["test_params"])
+        out.append((w, off, yo))
+    return out
+
+
+def _models(uneven_small):
+    device()
+    return [B.Model(w, basis=off["Q"], rows=off["rows"]) for w, off, _ in uneven_small]
+
+
+@pytest.mark.parametrize("prec,refine,tol,flags", [
+    (B.FP64, 0, 1e-12, 0),
+    (B.FP64, 0, 1e-12, B.PLAN_GRAPH | B.PLAN_AUTOTUNE),
+    (B.FP32, 1, 1e-6, B.PLAN_GRAPH),
+])
+def test_plan_matches_oracle(uneven_small, prec, refine, tol, flags, tmp_path, monkeypatch):
+    import torch
+    monkeypatch.setenv("SUBAP_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    header(f"plan prec={prec} refine={refine} flags={flags}")
+    models = _models(uneven_small)
+    try:
+        params = [to_dev(w["test_params"]) for w, _, _ in uneven_small]
+        ys = [torch.full((w["m"], w["r"]), -7.0, dtype=torch.float64, device=params[0].device)
+              for w, _, _ in uneven_small]
+        sts = [torch.full((w["m"],), -1, dtype=torch.int32, device=params[0].device) for w, _, _ in uneven_small]
+        plan = B.subap_plan_create([M.handle for M in models], params, ys, None, sts, prec, refine, flags)
+        try:
+            for rep in range(3):  # replays with eager work between them
+                for y in ys:
+                    y.fill_(-7.0)
+                B.subap_plan_execute(plan)
+                torch.cuda.synchronize()
+                for (w, off, yo), y, st in zip(uneven_small, ys, sts):
+                    assert np.all(st.cpu().numpy() == B.OK)
+                    yg = y.cpu().numpy()
+                    d = max(On.delta_res(off["family"], off["Q"], p, a, b)
+                            for p, a, b in zip(w["test_params"], yg, yo))
+                    assert d <= tol, (rep, w["r"], w["s"], d)
+            t, b = B.subap_plan_shape(plan)
+            assert t in (128, 256) and b > 0
+        finally:
+            B.subap_plan_free(plan)
+    finally:
+        for M in models:
+            M.free()
+
+
+def test_plan_equals_single_model_solves(uneven_small):
+    import torch
+    header("plan vs per-model batch solves")
+    models = _models(uneven_small)
+    try:
+        params = [to_dev(w["test_params"]) for w, _, _ in uneven_small]
+        ys = [torch.empty((w["m"], w["r"]), dtype=torch.float64, device=params[0].device)
+              for w, _, _ in uneven_small]
+        B.subap_solve_multi([M.handle for M in models], params, ys)
+        for (w, off, _), M, P, y in zip(uneven_small, models, params, ys):
+            y1, _, _ = M.solve(P)
+            assert np.abs(y1.cpu().numpy() - y.cpu().numpy()).max() <= 1e-9 * np.abs(y1.cpu().numpy()).max()
+    finally:
+        for M in models:
+            M.free()
+
+
+def test_autotune_cache_is_reused(uneven_small, tmp_path, monkeypatch):
+    import torch
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("SUBAP_AUTOTUNE_CACHE", str(cache))
+    header("autotune cache")
+    models = _models(uneven_small)
+    try:
+        params = [to_dev(w["test_params"]) for w, _, _ in uneven_small]
+        ys = [torch.empty((w["m"], w["r"]), dtype=torch.float64, device=params[0].device)
+              for w, _, _ in uneven_small]
+        p1 = B.subap_plan_create([M.handle for M in models], params, ys, flags=B.PLAN_AUTOTUNE)
+        shape1 = B.subap_plan_shape(p1)
+        B.subap_plan_free(p1)
+        lines = cache.read_text().strip().splitlines()
+        assert len(lines) == 1 and lines[0].startswith("fd_multi/")
+        p2 = B.subap_plan_create([M.handle for M in models], params, ys, flags=B.PLAN_AUTOTUNE)
+        assert B.subap_plan_shape(p2) == shape1
+        B.subap_plan_free(p2)
+        assert len(cache.read_text().strip().splitlines()) == 1  # looked up, not re-tuned
+    finally:
+        for M in models:
+            M.free()
