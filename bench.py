@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--plain-sample", type=int, default=256, help="parameters solved one per call")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle timing budget")
+    ap.add_argument("--workload", default="krr", choices=["krr", "diffusion3d", "uneven", "surrogate"],
+                    help="krr (default, the headline line) or one of the other configurations")
+    ap.add_argument("--grid", type=int, default=215, help="diffusion3d/surrogate: nodes per axis")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a device-to-device copy of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -120,6 +123,11 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+    if args.workload != "krr":
+        import bench_configs
+        out = getattr(bench_configs, args.workload)(args, B, si, torch, dev, stream, timed, PEAKS, TOL)
+        print(json.dumps(out), flush=True)
+        return
     w = si.krr()
     m, n, r, s = w["m"], w["n"], w["r"], w["s"]
 

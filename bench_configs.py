@@ -1,0 +1,223 @@
+"""Benchmark lines for the configurations other than the default kernel
+ridge regression line of bench.py (run as ``bench.py --workload NAME``).
+
+diffusion3d  3-D diffusion, 7-point stencil, N^3 nodes (N = 215: n = 9,938,375),
+             r = 40, s = 160, 65,536 parameters in one launch, FP64 and FP32 +
+             one FP64 refinement, and the lift x = Q y of 1,024 of them (FP32).
+uneven       64 independent 2-D diffusion instances (grids 32^2..512^2,
+             r in {8,16,32,64}, s in [2r, 4r], 16..4096 parameters each) in one
+             persistent, autotuned, hipGraph-replayed launch.
+surrogate    the learned p -> y surrogate on the 3-D model: training on 2^18
+             pairs from the batched solve, then 2^20 parameters with the
+             sketched-residual acceptance test and the plain batched fallback.
+
+Validity of a form: status OK and sketched distance |S A Q (y - y_fp64)| / |S b|
+<= 1e-6 to the FP64 batched solve of the same model (subap_sketched_residual).
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+
+def _validity(B, M, P, y, y64, st, tol):
+    import torch
+    res64, nrm64 = M.sketched_residual(P, y64, vector=True)
+    res, _ = M.sketched_residual(P, y, vector=True)
+    bn = torch.median(torch.linalg.norm(res64, dim=1) / nrm64)
+    dist = torch.linalg.norm(res - res64, dim=1) / bn
+    ok = (st == 0) & (dist <= tol)
+    return int(ok.sum()), float(dist.max())
+
+
+def _plain(B, M, P, r, k, stream, timed, torch, dev):
+    y1 = torch.empty((1, r), dtype=torch.float64, device=dev)
+    singles = [P[i:i + 1] for i in range(k)]
+
+    def run():
+        for pi in singles:
+            B.subap_solve_batch(M.handle, pi, y1, None, None, B.FP64, 0, stream)
+    run()
+    return timed(run, 1, stream) / k  # ms per solve
+
+
+def diffusion3d(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
+    N = args.grid
+    w = si.diffusion3d(N=N)
+    m, n, r, s = w["m"], w["n"], w["r"], w["s"]
+    t0 = time.perf_counter()
+    M = B.Model(w, snap_tol=1e-10)
+    torch.cuda.synchronize()
+    offline_s = time.perf_counter() - t0
+    P = torch.tensor(w["test_params"], dtype=torch.float64, device=dev)
+    y = torch.empty((m, r), dtype=torch.float64, device=dev)
+    y64 = torch.empty_like(y)
+    rho = torch.empty(m, dtype=torch.float64, device=dev)
+    st = torch.empty(m, dtype=torch.int32, device=dev)
+    B.subap_solve_batch(M.handle, P, y64, rho, st, B.FP64, 0, stream)
+    forms = {}
+    for name, prec, ref in (("fp64_batched", B.FP64, 0), ("fp32_refine1", B.FP32, 1)):
+        fn = lambda: B.subap_solve_batch(M.handle, P, y, rho, st, prec, ref, stream)
+        fn()
+        torch.cuda.synchronize()
+        valid, dmax = _validity(B, M, P, y, y64, st, TOL)
+        B.subap_profile_reset()
+        B.subap_profile_enable(True)
+        t = timed(fn, args.steps, stream)
+        B.subap_profile_enable(False)
+        prof = B.subap_profile_read()
+        forms[name] = {"ms_per_batch": t, "solves_per_s": m / (t / 1e3), "valid": valid,
+                       "max_sketched_distance": dmax,
+                       "kernels_ms": {k: v[1] / v[0] for k, v in prof.items()}}
+    tp = _plain(B, M, P, r, min(256, args.plain_sample), stream, timed, torch, dev)
+    forms["fp64_per_p_plain"] = {"solves_per_s": 1e3 / tp}
+    # lift of 1024 coefficient vectors to FP32 x (n x 1024, column-major)
+    k = w["n_lift"]
+    Y = y64[:k].contiguous()
+    x = torch.empty((k, n), dtype=torch.float32, device=dev)
+    B.subap_lift(M.handle, Y, x, B.FP32, stream)
+    tl = timed(lambda: B.subap_lift(M.handle, Y, x, B.FP32, stream), 3, stream)
+    lift_bytes = 8.0 * n * r + 4.0 * n * k + 8.0 * k * r
+    del x
+    # dominant solve kernel: FP64 ALU (Householder 2 s r^2 - 2/3 r^3 + face contraction 2 s F r per p)
+    flops = m * (2.0 * s * r * r - 2.0 / 3.0 * r ** 3 + 2.0 * s * 6 * r)
+    kms = forms["fp64_batched"]["kernels_ms"].get("fd_solve", forms["fp64_batched"]["ms_per_batch"])
+    best = max(("fp64_batched", "fp32_refine1"), key=lambda f: forms[f]["valid"] / forms[f]["ms_per_batch"])
+    ms = forms[best]["ms_per_batch"]
+    M.free()
+    return {
+        "metric": "online solves/s at rel. residual <=1e-6: batched/learned vs plain, 1 MI355X",
+        "value": forms[best]["valid"] / (ms / 1e3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if best == "fp64_batched" else "f32+f64", "data": "synthetic",
+        "config": {"workload": f"diffusion3d_n{N}^3_r{r}_s{s}_m{m}", "n": n, "form": best},
+        "forms": forms,
+        "roofline": {"bound": "alu", "kernel": "fd_solve", "achieved": flops / (kms * 1e-3) / 1e12,
+                     "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s",
+                     "frac": flops / (kms * 1e-3) / 1e12 / PEAKS["fp64_tflops"], "traffic": None},
+        "lift": {"k": k, "ms": tl, "GB_per_s": lift_bytes / (tl * 1e-3) / 1e9,
+                 "frac_hbm": lift_bytes / (tl * 1e-3) / 1e9 / PEAKS["hbm_gbs"]},
+        "offline_s": offline_s,
+    }
+
+
+def uneven(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
+    insts = si.uneven()
+    t0 = time.perf_counter()
+    models = [B.Model(w, snap_tol=1e-10) for w in insts]
+    torch.cuda.synchronize()
+    offline_s = time.perf_counter() - t0
+    Ps = [torch.tensor(w["test_params"], dtype=torch.float64, device=dev) for w in insts]
+    ys = [torch.empty((w["m"], w["r"]), dtype=torch.float64, device=dev) for w in insts]
+    y64 = [torch.empty_like(y) for y in ys]
+    sts = [torch.empty(w["m"], dtype=torch.int32, device=dev) for w in insts]
+    total = sum(w["m"] for w in insts)
+    for M, P, y in zip(models, Ps, y64):
+        B.subap_solve_batch(M.handle, P, y, None, None, B.FP64, 0, stream)
+    t0 = time.perf_counter()
+    plan = B.subap_plan_create([M.handle for M in models], Ps, ys, None, sts, B.FP32, 1,
+                               B.PLAN_GRAPH | B.PLAN_AUTOTUNE, stream)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    B.subap_plan_execute(plan, stream)
+    torch.cuda.synchronize()
+    valid, dmax = 0, 0.0
+    for M, P, y, y6, st in zip(models, Ps, ys, y64, sts):
+        v, d = _validity(B, M, P, y, y6, st, TOL)
+        valid += v
+        dmax = max(dmax, d)
+    t_plan = timed(lambda: B.subap_plan_execute(plan, stream), args.steps, stream)
+    threads, blocks = B.subap_plan_shape(plan)
+
+    def per_instance():
+        for M, P, y, st in zip(models, Ps, ys, sts):
+            B.subap_solve_batch(M.handle, P, y, None, st, B.FP32, 1, stream)
+    per_instance()
+    t_inst = timed(per_instance, 3, stream)
+    # plain per-p FP64 on a sample spread over the instances
+    k_each = 4
+    tp = 0.0
+    for M, P, w in zip(models, Ps, insts):
+        tp += _plain(B, M, P, w["r"], min(k_each, w["m"]), stream, timed, torch, dev) * min(k_each, w["m"])
+    plain_rate = sum(min(k_each, w["m"]) for w in insts) / (tp / 1e3)
+    flops = sum(w["m"] * (2.0 * w["s"] * w["r"] ** 2 - 2.0 / 3.0 * w["r"] ** 3) for w in insts)
+    B.subap_plan_free(plan)
+    for M in models:
+        M.free()
+    return {
+        "metric": "online solves/s at rel. residual <=1e-6: batched/learned vs plain, 1 MI355X",
+        "value": valid / (t_plan / 1e3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": t_plan, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "uneven_64_instances_diffusion2d", "parameters": total,
+                   "form": "one persistent hipGraph launch, FP32 contraction + FP64 LSQ + 1 refinement",
+                   "autotuned_shape": {"threads": threads, "blocks": blocks}},
+        "valid": {"count": valid, "of": total, "max_sketched_distance": dmax},
+        "forms": {"plan_graph": {"ms": t_plan, "solves_per_s": total / (t_plan / 1e3)},
+                  "per_instance_calls": {"ms": t_inst, "solves_per_s": total / (t_inst / 1e3)},
+                  "fp64_per_p_plain": {"solves_per_s": plain_rate}},
+        "roofline": {"bound": "alu", "kernel": "fd_multi_persistent",
+                     "achieved": flops / (t_plan * 1e-3) / 1e12, "peak": PEAKS["fp64_tflops"],
+                     "unit": "TFLOP/s", "frac": flops / (t_plan * 1e-3) / 1e12 / PEAKS["fp64_tflops"],
+                     "traffic": None},
+        "offline_s": offline_s, "plan_create_s": plan_s,
+    }
+
+
+def surrogate(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
+    N = args.grid
+    w = si.diffusion3d(N=N, m=16)
+    sg = si.surrogate()
+    M = B.Model(w, snap_tol=1e-10)
+    r = w["r"]
+    Ptr = torch.tensor(sg["train_params"], dtype=torch.float64, device=dev)
+    ytr = torch.empty((Ptr.shape[0], r), dtype=torch.float64, device=dev)
+    t0 = time.perf_counter()
+    B.subap_solve_batch(M.handle, Ptr, ytr, None, None, B.FP64, 0, stream)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    widths = (4, 256, 256, r)
+    S = B.subap_surrogate_create(4, r, 256, B.flatten_mlp(si.mlp_init(widths)))
+    t0 = time.perf_counter()
+    losses = B.subap_surrogate_train(S, Ptr, ytr, epochs=30, batch=4096, lr=2e-3, lr_min=1e-5, seed=7)
+    train_s = time.perf_counter() - t0
+    Pin = torch.tensor(sg["infer_params"], dtype=torch.float64, device=dev)
+    mi = Pin.shape[0]
+    y = torch.empty((mi, r), dtype=torch.float64, device=dev)
+    y64 = torch.empty_like(y)
+    st = torch.empty(mi, dtype=torch.int32, device=dev)
+    acc = torch.empty(mi, dtype=torch.uint8, device=dev)
+    B.subap_solve_batch(M.handle, Pin, y64, None, st, B.FP64, 0, stream)
+    t_plain = timed(lambda: B.subap_solve_batch(M.handle, Pin, y64, None, st, B.FP64, 0, stream), 3, stream)
+    out = {}
+    for name, tol in (("literal_1e-5", 1e-5),):
+        t0 = time.perf_counter()
+        n_acc = B.subap_surrogate_solve_batch(M.handle, S, Pin, tol, y, acc, st)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) * 1e3
+        valid, dmax = _validity(B, M, Pin, y, y64, st, TOL)
+        out[name] = {"accepted": n_acc, "ms": t, "solves_per_s": mi / (t / 1e3), "valid": valid,
+                     "max_sketched_distance": dmax}
+    # prediction quality and the predicted residual floor
+    yh = torch.empty_like(y)
+    B.subap_surrogate_predict(S, Pin, yh)
+    t_pred = timed(lambda: B.subap_surrogate_predict(S, Pin, yh), 3, stream)
+    _, rho_h = M.sketched_residual(Pin, yh)
+    _, rho_s = M.sketched_residual(Pin, y64)
+    rel = float(torch.linalg.norm(yh - y64) / torch.linalg.norm(y64))
+    B.subap_surrogate_free(S)
+    M.free()
+    return {
+        "metric": "online solves/s at rel. residual <=1e-6: batched/learned vs plain, 1 MI355X",
+        "value": out["literal_1e-5"]["valid"] / (out["literal_1e-5"]["ms"] / 1e3), "unit": "solves/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": out["literal_1e-5"]["ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16 mlp + f64", "data": "synthetic",
+        "config": {"workload": f"surrogate_diffusion3d_n{N}^3_r{r}", "train_pairs": int(Ptr.shape[0]),
+                   "infer": mi, "widths": widths},
+        "surrogate": out, "plain_batched_fp64": {"ms": t_plain, "solves_per_s": mi / (t_plain / 1e3)},
+        "predict_ms": t_pred, "prediction_rel_error": rel,
+        "sketched_residual_median": {"prediction": float(torch.median(rho_h)), "subapsnap": float(torch.median(rho_s))},
+        "train": {"pairs_generation_s": gen_s, "train_s": train_s, "loss_first": float(losses[0]),
+                  "loss_last": float(losses[-1])},
+    }

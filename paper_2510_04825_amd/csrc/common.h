@@ -84,6 +84,8 @@ struct subap_model_s {
   // online workspaces (grown on demand)
   void* work = nullptr;
   size_t work_bytes = 0;
+  void* lds_inst = nullptr;      // one-entry instance table of the LDS solve kernel
+  void* lds_counter = nullptr;
 };
 
 namespace subap {
@@ -115,6 +117,8 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
 subap_status plan_execute(PlanImpl* P, hipStream_t st);
 void plan_free(PlanImpl* P);
 void plan_shape(const PlanImpl* P, int* threads, int* blocks);
+subap_status fd_solve_lds(subap_model_s* M, const double* params, int64_t m, double* y, double* rho,
+                          int32_t* status, int prec, int refine, hipStream_t st);
 
 // ---- learned surrogate (mlp.hip) ----
 struct Surrogate;

@@ -466,6 +466,36 @@ void plan_free(PlanImpl* P) {
   delete P;
 }
 
+// Single-model solve through the LDS kernel, for (s, r) shapes the register
+// kernel is not instantiated for.  The one-entry instance table and the work
+// counter are allocated once per model.
+subap_status fd_solve_lds(subap_model_s* M, const double* params, int64_t m, double* y, double* rho,
+                          int32_t* status, int prec, int refine, hipStream_t st) {
+  if (!M->lds_inst) {
+    SUBAP_TRY(dalloc(reinterpret_cast<MultiInst**>(&M->lds_inst), 1));
+    SUBAP_TRY(dalloc(reinterpret_cast<unsigned long long**>(&M->lds_counter), 1));
+  }
+  MultiInst I{M->r, M->s, M->F, M->d, M->phi, M->delta64, M->delta32, M->bS, M->inv_h2, M->bS_norm,
+              params, m, y, rho, status, 0};
+  // pageable source: the copy is staged before hipMemcpyAsync returns
+  SUBAP_HIP_TRY(hipMemcpyAsync(M->lds_inst, &I, sizeof(I), hipMemcpyHostToDevice, st));
+  const size_t lds = lds_bytes(M->s, M->r);
+  SUBAP_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(k_fd_multi),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int per_cu = std::max(1, std::min(4, static_cast<int>((160 * 1024) / lds)));
+  const int64_t blocks = std::min<int64_t>(m, static_cast<int64_t>(cus) * per_cu);
+  MultiArgs a{static_cast<const MultiInst*>(M->lds_inst), 1, m,
+              static_cast<unsigned long long*>(M->lds_counter), prec, refine, M->r + 1, M->s};
+  ProfScope prof("fd_solve_lds", st);
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, st, static_cast<unsigned long long*>(M->lds_counter));
+  hipLaunchKernelGGL(k_fd_multi, dim3(static_cast<unsigned>(blocks)), dim3(256), lds, st, a);
+  SUBAP_HIP_TRY(hipGetLastError());
+  return SUBAP_OK;
+}
+
 void plan_shape(const PlanImpl* P, int* threads, int* blocks) {
   *threads = P->threads;
   *blocks = P->blocks;

@@ -226,8 +226,7 @@ subap_status dispatch(const FDArgs& a, hipStream_t st) {
   SUBAP_FD(16, 1, 8) SUBAP_FD(32, 1, 8) SUBAP_FD(32, 1, 16)
   SUBAP_FD(64, 1, 16) SUBAP_FD(64, 2, 32) SUBAP_FD(64, 3, 40)
 #undef SUBAP_FD
-  set_error("no finite-difference solve kernel for this (s, r)");
-  return SUBAP_E_UNSUPPORTED;
+  return SUBAP_E_UNSUPPORTED;  // the caller falls back to the LDS kernel
 }
 
 }  // namespace
@@ -236,8 +235,10 @@ subap_status fd_solve(subap_model_s* M, const double* params, int64_t m, double*
                       int32_t* status, int prec, int refine, hipStream_t st) {
   FDArgs a{params, m, M->r, M->s, M->phi, M->delta64, M->delta32, M->bS, M->inv_h2, M->bS_norm,
            y, rho, status, prec, refine};
-  if (M->dimx == 2) return dispatch<4, 2>(a, st);
-  return dispatch<6, 4>(a, st);
+  const subap_status rc = M->dimx == 2 ? dispatch<4, 2>(a, st) : dispatch<6, 4>(a, st);
+  if (rc != SUBAP_E_UNSUPPORTED) return rc;
+  // shapes without a register-resident instantiation: Householder in LDS
+  return fd_solve_lds(M, params, m, y, rho, status, prec, refine, st);
 }
 
 subap_status fd_residual(subap_model_s* M, const double* params, int64_t m, const double* y, double* res,

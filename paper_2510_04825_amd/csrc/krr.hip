@@ -360,6 +360,18 @@ __global__ __launch_bounds__(256) void k_contract_f32(MArgs A) {
   }
 }
 
+// Sum of the kSplit FP32 partials in FP64, with the column scale undone:
+// G64[e] = colscale[c] * sum_z G32[z][e], e = (p s + k) r + c.  Coalesced.
+__global__ void k_reduce_partials(const float* G32, int64_t len, int r, const double* colscale, double* G64) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= len) return;
+  double g = 0.0;
+#pragma unroll
+  for (int z = 0; z < kSplit; ++z) g += static_cast<double>(G32[z * len + e]);
+  if (colscale) g *= colscale[e % r];
+  G64[e] = g;
+}
+
 // ---------------------------------------------------------------------------
 // Least squares from a contraction in global memory: one team per p.
 // G_full = G + lambda Q_S.  Stores the factorisation for refinement.
@@ -447,8 +459,8 @@ __global__ __launch_bounds__(256) void k_lsq(LArgs A) {
 // points, with FP64-accurate kernel entries.  Block: PB parameters x one
 // point range; thread = selected row k.
 // ---------------------------------------------------------------------------
-constexpr int kRefPB = 8;      // parameters per block
-constexpr int kRefNJ = 256;    // points per LDS chunk
+constexpr int kRefPB = 16;     // parameters per block
+constexpr int kRefNJ = 128;    // points per LDS chunk
 constexpr int kRefSplit = 8;   // point ranges (grid.y)
 
 template <int RM>
@@ -465,11 +477,13 @@ __global__ __launch_bounds__(256) void k_refine_partial(const double* params, in
     const int w = idx / RM, c = idx % RM;
     s_y[w][c] = (p0 + w < m && c < r) ? y[(p0 + w) * r + c] : 0.0;
   }
-  double cexp[kRefPB];
+  // per-parameter factor of exp_tab_v: v = 64 log2(e) (-1 / (2 p^2)) D
+  constexpr double k64log2e = 92.332482616893656877;
+  double cv[kRefPB];
 #pragma unroll
   for (int w = 0; w < kRefPB; ++w) {
     const double sig = p0 + w < m ? params[p0 + w] : 1.0;
-    cexp[w] = krr_param_ok(sig) ? -0.5 / (sig * sig) : 0.0;
+    cv[w] = krr_param_ok(sig) ? -0.5 * k64log2e / (sig * sig) : 0.0;
   }
   double acc[kRefPB];
 #pragma unroll
@@ -489,10 +503,13 @@ __global__ __launch_bounds__(256) void k_refine_partial(const double* params, in
     __syncthreads();
     if (t < s) {
       const int cnt = static_cast<int>(std::min<int64_t>(kRefNJ, je - j0));
+      const double* Dp = Dt64 + j0 * s + t;
+      double dn = cnt > 0 ? Dp[0] : 0.0;
       for (int jj = 0; jj < cnt; ++jj) {
-        const double d = Dt64[(j0 + jj) * s + t];
+        const double d = dn;
+        if (jj + 1 < cnt) dn = Dp[(jj + 1) * s];  // prefetch the next distance
 #pragma unroll
-        for (int w = 0; w < kRefPB; ++w) acc[w] = fma(exp_tab(cexp[w] * d, s_tab), s_z[jj][w], acc[w]);
+        for (int w = 0; w < kRefPB; ++w) acc[w] = fma(exp_tab_v(cv[w] * d, s_tab), s_z[jj][w], acc[w]);
       }
     }
   }
@@ -652,7 +669,8 @@ subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double
     return SUBAP_E_UNSUPPORTED;
   }
   const int RM = rm_of(r);
-  const size_t gbytes = static_cast<size_t>(m) * s * r * (prec == SUBAP_FP64 ? 8 : 4 * kSplit);
+  // FP64 G, plus the FP32 split partials for the MFMA forms
+  const size_t gbytes = static_cast<size_t>(m) * s * r * (prec == SUBAP_FP64 ? 8 : 8 + 4 * kSplit);
   const int fac_stride = sh.team * sh.R * sh.RM + sh.RM;
   const size_t fbytes = refine > 0 ? static_cast<size_t>(m) * fac_stride * 8 : 0;
   const size_t pbytes = refine > 0 ? static_cast<size_t>(kRefSplit) * m * s * 8 : 0;
@@ -692,8 +710,8 @@ subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double
     }
   } else {
     const bool f16 = prec == SUBAP_FP16X3;
-    MArgs a{params, m, n, r, s, M->D32, f16 ? M->Qh16 : M->Qhi, f16 ? M->Ql16 : M->Qlo, M->Q32,
-            static_cast<float*>(G)};
+    float* G32 = reinterpret_cast<float*>(static_cast<double*>(G) + static_cast<size_t>(m) * s * r);
+    MArgs a{params, m, n, r, s, M->D32, f16 ? M->Qh16 : M->Qhi, f16 ? M->Ql16 : M->Qlo, M->Q32, G32};
     constexpr int PW = 8;
     const unsigned gy = static_cast<unsigned>((s + 127) / 128);
     const dim3 g8(static_cast<unsigned>((m + PW - 1) / PW), gy, kSplit);
@@ -711,16 +729,17 @@ subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double
       if (r <= 32) hipLaunchKernelGGL((k_contract_f32<PW, 1>), g8, dim3(256), 0, st, a);
       else hipLaunchKernelGGL((k_contract_f32<4, 2>), g4, dim3(256), 0, st, a);
     }
+    const int64_t len = m * s * r;
+    ProfScope prof("reduce_partials", st);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(static_cast<unsigned>((len + 255) / 256)), dim3(256), 0, st, G32,
+                       len, r, f16 ? M->colscale_inv : nullptr, static_cast<double*>(G));
   }
   SUBAP_HIP_TRY(hipGetLastError());
   // A3: least squares
-  LArgs la{params, m, r, s, G, prec == SUBAP_FP64 ? 1 : kSplit,
-           prec == SUBAP_FP16X3 ? M->colscale_inv : nullptr,
-           M->QS, M->bS, M->lambda, M->bS_norm, y, rho, stat, fac, fac_stride};
+  LArgs la{params, m, r, s, G, 1, nullptr, M->QS, M->bS, M->lambda, M->bS_norm, y, rho, stat, fac, fac_stride};
   {
     ProfScope prof("lsq_householder", st);
-    if (prec == SUBAP_FP64) SUBAP_TRY(launch_lsq<double>(sh, la, st));
-    else SUBAP_TRY(launch_lsq<float>(sh, la, st));
+    SUBAP_TRY(launch_lsq<double>(sh, la, st));
   }
   // A4: refinement
   for (int it = 0; it < refine; ++it) {

@@ -184,3 +184,48 @@ def test_lift_matches_q_times_y(c1):
         assert np.all(np.abs(x32 - ref) <= bound + 1e-30)
     finally:
         M.free()
+
+
+@pytest.fixture(scope="module")
+def d3_full():
+    """Full 3-D configuration size (215^3 nodes, r = 40, s = 160) with an
+    oracle-made orthonormal basis and seeded rows: the online solve does not
+    depend on where they came from, and every oracle input stays independent
+    of the GPU path."""
+    from oracle import families as F
+    w = si.diffusion3d()
+    fam = F.from_workload(w)
+    rng = np.random.default_rng(2025)
+    Q, _ = O.orthonormalise(rng.standard_normal((w["n"], w["r"])))
+    rows = np.sort(rng.choice(w["n"], size=w["s"], replace=False))
+    return w, fam, Q, rows
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec,refine", [(B.FP64, 0), (B.FP32, 1)])
+def test_diffusion3d_full_size_sampled(d3_full, prec, refine):
+    """All 65,536 parameters in one launch (the benchmark's configuration);
+    the oracle recomputes sampled parameters one by one.  FP64: sketched
+    distance <= 1e-11.  FP32 + one refinement: 1e-6 plus the simple-refinement
+    bias bound 2^-20 kappa(S A Q) rho* (rho* is of order one for a random basis)."""
+    w, fam, Q, rows = d3_full
+    header(f"3-D full size prec={prec}")
+    M = B.Model(w, basis=Q, rows=rows)
+    try:
+        P = w["test_params"]
+        y, _, st = M.solve(to_dev(P), contraction=prec, refine_steps=refine)
+        st = st.cpu().numpy()
+        y = y.cpu().numpy()
+        assert np.all(st == B.OK)
+        idx = np.concatenate([np.random.default_rng(9).choice(len(P), size=10, replace=False), [0, len(P) - 1]])
+        for i in idx:
+            G = On.reduced_matrix(fam, Q, rows, P[i])
+            bS = fam.rhs_rows(P[i], rows)
+            yo, _, rho = On.householder_lsq(G, bS)
+            sv = np.linalg.svd(G, compute_uv=False)
+            tol = 1e-11 if prec == B.FP64 else 1e-6 + 2.0 ** -20 * sv[0] / sv[-1] * rho / np.linalg.norm(bS)
+            d = np.linalg.norm(G @ (y[i] - yo)) / np.linalg.norm(bS)
+            print(f"p[{i}] sketched distance {d:.2e} (bar {tol:.1e})")
+            assert d <= tol, (i, d, tol)
+    finally:
+        M.free()
