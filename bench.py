@@ -55,6 +55,11 @@ def parse():
     ap.add_argument("--grid", type=int, default=215, help="diffusion3d/surrogate: nodes per axis")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a device-to-device copy of MIB MiB (HBM counter calibration)")
+    ap.add_argument("--given-basis", action="store_true",
+                    help="krr: seeded random orthonormal basis instead of snapshot solves (profiling runs; "
+                         "the online kernels do the same work for any basis)")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="krr: time the headline form only (no validity check, other forms or CPU baseline)")
     return ap.parse_args()
 
 
@@ -69,6 +74,75 @@ def timed(fn, steps, stream):
     end.record(stream)
     torch.cuda.synchronize()
     return start.elapsed_time(end) / steps
+
+
+# FP64 flops of one refinement entry 2^(c D) z: the reduction (two FMAs and a
+# subtraction), the degree-9 Horner polynomial (9 FMAs), ldexp and the
+# accumulating FMA; FMAs count 2.
+REFINE_FLOPS_PER_ENTRY = 2 * 2 + 1 + 9 * 2 + 1 + 2
+
+
+# HBM traffic of the dominant kernel from two rocprofv3 counter runs (FETCH_SIZE,
+# then WRITE_SIZE, KiB per dispatch of k_refine_partial<32, 9> on this workload),
+# scaled by the factors a 1 GiB device copy gives (FETCH 2.0, WRITE 1.0).  Valid
+# only for the kernel sources they were taken with: the hash below covers them,
+# and a changed source reports traffic null.
+TRAFFIC_SOURCES = ("krr.hip", "family.h", "exp2_poly.h", "common.h", "team_qr.h")
+TRAFFIC = {"kernel": "krr_refine_partial", "sources_sha256_16": "7f149a3035f248b1",
+           "fetch_kib": 21413.9, "write_kib": 40960.0, "fetch_factor": 2.0, "write_factor": 1.0}
+
+
+def traffic_bytes(kernel):
+    import hashlib
+    if kernel != TRAFFIC["kernel"]:
+        return None
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2510_04825_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != TRAFFIC["sources_sha256_16"]:
+        return None
+    return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_factor"] + TRAFFIC["write_kib"] * TRAFFIC["write_factor"])
+
+
+def roofline(prof, m, n, r, s):
+    """Roofline of the dominant kernel of the timed step (per-launch averages)."""
+    avg = {k: v[1] / max(v[0], 1) for k, v in prof.items()}
+    dname = max(prof.items(), key=lambda kv: kv[1][1])[0]
+    mfma_flops = 3 * 2.0 * m * s * n * r          # three split products per entry and column
+    contract = None
+    for k in ("krr_contract_fp16x3", "krr_contract_bf16x3"):
+        if k in avg:
+            contract = {"kernel": k, "avg_ms": avg[k], "bound": "mfma",
+                        "achieved": mfma_flops / (avg[k] * 1e-3) / 1e12, "peak": PEAKS["bf16_mfma_tflops"],
+                        "unit": "TFLOP/s"}
+            contract["frac"] = contract["achieved"] / contract["peak"]
+    if dname == "krr_refine_partial":
+        flops = m * (REFINE_FLOPS_PER_ENTRY * s * n + 2.0 * n * r)
+        roof = {"bound": "alu", "achieved": flops / (avg[dname] * 1e-3) / 1e12,
+                "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s"}
+    elif contract is not None and dname == contract["kernel"]:
+        roof = {k: contract[k] for k in ("bound", "achieved", "peak", "unit")}
+    else:
+        roof = {"bound": "alu", "achieved": None, "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"] if roof["achieved"] is not None else None
+    roof.update({"kernel": dname, "avg_ms": avg[dname], "traffic": traffic_bytes(dname)})
+    if contract is not None and contract["kernel"] != dname:
+        roof["contraction"] = contract
+    return roof
+
+
+def calibrate_copy(args, torch, dev):
+    """Known-size device copies (3 x MIB MiB read and written) for scaling HBM counters."""
+    if args.calibrate_copy <= 0:
+        return 0
+    nb = args.calibrate_copy << 20
+    a = torch.empty(nb // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return nb
 
 
 def cpu_baseline(w, budget_s):
@@ -132,7 +206,11 @@ def main():
     m, n, r, s = w["m"], w["n"], w["r"], w["s"]
 
     t0 = time.perf_counter()
-    M = B.Model(w, snap_tol=1e-10)
+    if args.given_basis:
+        Q0, _ = np.linalg.qr(np.random.default_rng(7).standard_normal((n, r)))
+        M = B.Model(w, basis=Q0)
+    else:
+        M = B.Model(w, snap_tol=1e-10)
     torch.cuda.synchronize()
     offline_s = time.perf_counter() - t0
 
@@ -158,6 +236,21 @@ def main():
         dist = torch.linalg.norm(res - res64, dim=1) / bS_norm
         ok = (st == 0) & (dist <= TOL)
         return {"valid": int(ok.sum()), "max_sketched_distance": float(dist.max())}
+
+    if args.profile_only:
+        for _ in range(args.warmup):
+            solve(*HEADLINE)
+        B.subap_profile_reset()
+        B.subap_profile_enable(True)
+        ms = timed(lambda: solve(*HEADLINE), args.steps, stream)
+        B.subap_profile_enable(False)
+        prof = B.subap_profile_read()
+        calibrate_copy(args, torch, dev)
+        print(json.dumps({"profile_only": True, "ms_per_step": ms, "steps": args.steps,
+                          "kernels_ms_per_step": {k2: v[1] / max(args.steps, 1) for k2, v in prof.items()},
+                          "kernels_avg_ms": {k2: v[1] / max(v[0], 1) for k2, v in prof.items()}}), flush=True)
+        M.free()
+        return
 
     head_valid = validity(*HEADLINE)
     n_valid = head_valid["valid"]
@@ -194,25 +287,8 @@ def main():
     forms["fp64_per_p_plain"] = {"ms_per_batch": tp * m / k, "solves_per_s": k / (tp / 1e3),
                                  "sample": k}
 
-    # roofline of the dominant kernel of the timed step
-    dom = max(prof.items(), key=lambda kv: kv[1][1])
-    dname, (calls, tot_ms) = dom
-    avg_ms = tot_ms / max(calls, 1)
-    flops_contract = 2.0 * m * s * n * r
-    if dname in ("krr_contract_bf16x3", "krr_contract_fp16x3"):
-        roof = {"bound": "mfma", "achieved": flops_contract / (avg_ms * 1e-3) / 1e12,
-                "peak": PEAKS["bf16_mfma_tflops"], "unit": "TFLOP/s"}
-    elif dname == "krr_refine_partial":
-        # one FP64 kernel entry and one fused multiply-add per (p, selected row, point)
-        flops = m * (2.0 * s * n + 2.0 * n * r)
-        roof = {"bound": "alu", "achieved": flops / (avg_ms * 1e-3) / 1e12,
-                "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s"}
-    else:
-        roof = {"bound": "alu", "achieved": None, "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s"}
-    if roof["achieved"] is not None:
-        roof["frac"] = roof["achieved"] / roof["peak"]
-    roof.update({"kernel": dname, "avg_ms": avg_ms, "traffic": None})
-
+    # roofline of the dominant kernel of the timed step, plus the contraction's
+    roof = roofline(prof, m, n, r, s)
     out = {
         "metric": "online solves/s at rel. residual <=1e-6: batched/learned vs plain, 1 MI355X",
         "value": n_valid / (ms / 1e3),
@@ -237,13 +313,7 @@ def main():
         "offline_s": offline_s,
     }
     if args.calibrate_copy > 0:
-        nb = args.calibrate_copy << 20
-        a = torch.empty(nb // 4, dtype=torch.float32, device=dev).fill_(1.0)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        out["calibration_copy_bytes"] = nb
+        out["calibration_copy_bytes"] = calibrate_copy(args, torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     M.free()

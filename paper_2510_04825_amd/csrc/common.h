@@ -55,6 +55,7 @@ struct subap_model_s {
   double h = 0.0, inv_h2 = 0.0;
   double lambda = 0.0;
   double bS_norm = 0.0;               // |S b|_2 (b is p-independent in every family)
+  double dmax = 0.0;                  // KRR: upper bound on every squared distance D[k, j]
   std::vector<int64_t> rows;          // host copy, selection order
 
   // basis and selection (device)

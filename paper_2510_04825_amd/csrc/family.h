@@ -1,8 +1,11 @@
 // Row generators shared by the offline and online kernels: the coefficient
-// modes of the diffusion families and an FP64 exponential.
+// modes of the diffusion families and FP64 powers of two for the Gaussian
+// kernel rows.
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include "exp2_poly.h"
 
 namespace subap {
 
@@ -24,38 +27,44 @@ __device__ __forceinline__ void modes3d(double x, double y, double z, double* ph
   phi[3] = cx * cy * cz;
 }
 
-// Table-driven FP64 exponential (Tang's method): exp(t) = 2^k 2^(j/64) 2^(f/64),
-// with 64 t log2(e) = 64 k + j + f, |f| <= 1/2, and 2^(f/64) from its Taylor
-// series to degree 4 (truncation error < 4e-14 relative).  tab[j] = 2^(j/64)
-// must be visible to the calling lanes (LDS or constant memory).
-//
-// exp_tab_v takes v = 64 t log2(e) directly (callers fold the factor into a
-// per-parameter constant).  Only full-rate operations are used: the nearest
-// integer comes from adding and subtracting 1.5 * 2^52 (round to nearest
-// even in the add) and its two's-complement value is the low word of the
-// sum; 2^k is applied by adding k to the exponent field of the (normal)
-// product tab[j] * poly in [1, 2).  v is clamped at -64 * 1020, so results
-// below 2^-1020 (far below any term the solves keep) stay normal instead of
-// flushing to zero.
-__device__ __forceinline__ double exp_tab_v(double v, const double* tab) {
-  constexpr double c1 = 0.010830424696249145;                // ln2 / 64
-  constexpr double c2 = c1 * c1 / 2.0;
-  constexpr double c3 = c2 * c1 / 3.0;
-  constexpr double c4 = c3 * c1 / 4.0;
-  constexpr double kShift = 6755399441055744.0;               // 1.5 * 2^52
-  v = fmax(v, -65280.0);
-  const double sh = v + kShift;
-  const double nr = sh - kShift;
-  const double f = v - nr;
-  const int ni = static_cast<int>(__double2loint(sh));
-  const double poly = fma(fma(fma(fma(c4, f, c3), f, c2), f, c1), f, 1.0);
-  const double e = tab[ni & 63] * poly;
-  return __hiloint2double(__double2hiint(e) + ((ni >> 6) << 20), __double2loint(e));
+// FP64 powers of two without tables.  2^v = 2^k 2^f with k the integer
+// nearest to v and |f| <= 1/2; 2^f from the near-minimax polynomial of degree
+// DEG in exp2_poly.h (relative error 5.5e-11, 1.9e-14 and 2.2e-16 for DEG = 7,
+// 9, 11, Horner evaluation included) and 2^k from ldexp.  k comes from adding
+// 1.5 * 2^52, which rounds to the nearest integer and leaves k in
+// two's complement in the low word of the sum.
+
+template <int DEG>
+__device__ __forceinline__ double exp2_reduced(double f) {
+  double p = Exp2Poly<DEG>::c[DEG];
+#pragma unroll
+  for (int i = DEG - 1; i >= 0; --i) p = fma(p, f, Exp2Poly<DEG>::c[i]);
+  return p;
 }
 
-__device__ __forceinline__ double exp_tab(double t, const double* tab) {
-  constexpr double k64log2e = 92.332482616893656877;        // 64 / ln 2
-  return exp_tab_v(t * k64log2e, tab);
+constexpr double kRoundShift = 6755399441055744.0;  // 1.5 * 2^52
+constexpr double kExp2Range = 1073741824.0;          // 2^30
+
+// 2^(c d).  The product is not rounded before the reduction: f = c d - k comes
+// from one fused multiply-add.  Requires |c d| < 2^30 (callers check a bound
+// once per block); then k fits the low word and ldexp returns 0 or inf where
+// the power leaves the FP64 range.
+template <int DEG>
+__device__ __forceinline__ double exp2_mul(double c, double d) {
+  const double sh = fma(c, d, kRoundShift);
+  const double k = sh - kRoundShift;
+  const double f = fma(c, d, -k);
+  return ldexp(exp2_reduced<DEG>(f), static_cast<int>(__double2loint(sh)));
+}
+
+// 2^v for any v: v is clamped to [-2^30, 2^30] first, which changes no
+// finite result (2^-2^30 is 0 and 2^2^30 is inf in FP64); NaN gives 0.
+template <int DEG>
+__device__ __forceinline__ double exp2_any(double v) {
+  v = fmin(fmax(v, -kExp2Range), kExp2Range);
+  const double sh = v + kRoundShift;
+  const double k = sh - kRoundShift;
+  return ldexp(exp2_reduced<DEG>(v - k), static_cast<int>(__double2loint(sh)));
 }
 
 }  // namespace subap

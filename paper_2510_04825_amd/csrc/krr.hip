@@ -33,9 +33,6 @@ constexpr double kLog2e = 1.4426950408889634074;
 
 __device__ __forceinline__ bool krr_param_ok(double sig) { return isfinite(sig) && sig > 0.0; }
 
-__device__ __forceinline__ void load_exp_table(double* tab) {
-  for (int j = threadIdx.x; j < 64; j += blockDim.x) tab[j] = exp2(static_cast<double>(j) / 64.0);
-}
 
 // ---------------------------------------------------------------------------
 // FP64 contraction, many parameters: lanes = parameters, one wave per KR rows.
@@ -47,15 +44,13 @@ template <int KR, int RM>
 __global__ __launch_bounds__(256) void k_contract_f64(const double* params, int64_t m, int64_t n, int r,
                                                        int s, const double* Dt64, const double* Qrm,
                                                        double* G) {
-  __shared__ double s_tab[64];
   __shared__ double s_q[kJC][RM];
   __shared__ double s_d[kJC][4 * KR];
   const int wave = threadIdx.x / 64, l = threadIdx.x % 64;
   const int64_t p = static_cast<int64_t>(blockIdx.x) * 64 + l;
   const int kbase = blockIdx.y * 4 * KR;
-  load_exp_table(s_tab);
   const double sig = p < m ? params[p] : 1.0;
-  const double cexp = krr_param_ok(sig) ? -0.5 / (sig * sig) : 0.0;
+  const double cexp = krr_param_ok(sig) ? -0.5 * kLog2e / (sig * sig) : 0.0;
   double acc[KR][RM];
 #pragma unroll
   for (int kr = 0; kr < KR; ++kr)
@@ -79,7 +74,7 @@ __global__ __launch_bounds__(256) void k_contract_f64(const double* params, int6
     for (int jj = 0; jj < cnt; ++jj) {
 #pragma unroll
       for (int kr = 0; kr < KR; ++kr) {
-        const double e = exp_tab(cexp * s_d[jj][wave * KR + kr], s_tab);
+        const double e = exp2_any<11>(cexp * s_d[jj][wave * KR + kr]);
 #pragma unroll
         for (int c = 0; c < RM; ++c) acc[kr][c] = fma(e, s_q[jj][c], acc[kr][c]);
       }
@@ -102,19 +97,16 @@ __global__ __launch_bounds__(256) void k_contract_f64(const double* params, int6
 template <int RM>
 __global__ __launch_bounds__(256) void k_contract_f64_small(const double* params, int64_t n, int r, int s,
                                                              const double* Dt64, const double* Qrm, double* G) {
-  __shared__ double s_tab[64];
   __shared__ double s_red[4][RM];
   const int64_t p = blockIdx.x;
   const int k = blockIdx.y;
-  load_exp_table(s_tab);
-  __syncthreads();
   const double sig = params[p];
-  const double cexp = krr_param_ok(sig) ? -0.5 / (sig * sig) : 0.0;
+  const double cexp = krr_param_ok(sig) ? -0.5 * kLog2e / (sig * sig) : 0.0;
   double acc[RM];
 #pragma unroll
   for (int c = 0; c < RM; ++c) acc[c] = 0.0;
   for (int64_t j = threadIdx.x; j < n; j += 256) {
-    const double e = exp_tab(cexp * Dt64[j * s + k], s_tab);
+    const double e = exp2_any<11>(cexp * Dt64[j * s + k]);
 #pragma unroll
     for (int c = 0; c < RM; ++c)
       if (c < r) acc[c] = fma(e, Qrm[j * r + c], acc[c]);
@@ -184,12 +176,26 @@ struct Vec8<__bf16> {
   static __device__ __forceinline__ f32x16 mfma(type a, type b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
   }
+  // hi = nearest bf16 of v, lo = nearest bf16 of v - hi
+  static __device__ __forceinline__ void split(float v, __bf16* h, __bf16* l) {
+    const __bf16 hh = static_cast<__bf16>(v);
+    *h = hh;
+    *l = static_cast<__bf16>(v - static_cast<float>(hh));
+  }
 };
 template <>
 struct Vec8<_Float16> {
   typedef _Float16 type __attribute__((ext_vector_type(8)));
   static __device__ __forceinline__ f32x16 mfma(type a, type b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+  }
+  // hi = v with its mantissa cut to fp16's 10 bits (a mask, exact in fp16 for
+  // v >= 2^-14; below that the conversion rounds to the subnormal grid),
+  // lo = nearest fp16 of v - hi, which is exact in FP32.
+  static __device__ __forceinline__ void split(float v, _Float16* h, _Float16* l) {
+    const float hf = __uint_as_float(__float_as_uint(v) & 0xFFFFE000u);
+    *h = static_cast<_Float16>(hf);
+    *l = static_cast<_Float16>(v - hf);
   }
 };
 
@@ -200,15 +206,38 @@ __device__ __forceinline__ void split_range(int64_t n, int z, int64_t* jb, int64
   *je = n < (z + 1) * per ? n : (z + 1) * per;
 }
 
+// Block -> (parameter block, point range).  Consecutive block indices go
+// round-robin over the 8 XCDs; each point range is given to kXcd / kSplit
+// XCDs so that every XCD's L2 holds one range of D and Q instead of all of
+// them.  The grid has ceil(parameter blocks / (kXcd / kSplit)) * kXcd blocks
+// along x; blocks past the last parameter block return at once.
+constexpr int kXcd = 8;
+static_assert(kXcd % kSplit == 0, "point ranges must divide the XCD count");
+
+__device__ __forceinline__ void xcd_block(int64_t* pb, int* z) {
+  constexpr unsigned per = kXcd / kSplit;
+  const unsigned id = blockIdx.x, x = id % kXcd;
+  *z = static_cast<int>(x / per);
+  *pb = static_cast<int64_t>(id / kXcd) * per + x % per;
+}
+
+inline unsigned xcd_grid(int64_t blocks) {
+  constexpr int64_t per = kXcd / kSplit;
+  return static_cast<unsigned>((blocks + per - 1) / per * kXcd);
+}
+
 template <typename T16, int PW, int NB>
 __global__ __launch_bounds__(256) void k_contract_x3(MArgs A) {
   typedef typename Vec8<T16>::type v8;
   const int wave = threadIdx.x / 64, l = threadIdx.x % 64;
   const int k0 = (blockIdx.y * 4 + wave) * 32;
-  if (k0 >= A.s) return;  // uniform per wave
-  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * PW;
+  int64_t pb;
+  int z;
+  xcd_block(&pb, &z);
+  const int64_t p0 = pb * PW;
+  if (k0 >= A.s || p0 >= A.m) return;  // uniform per wave
   int64_t jb, je;
-  split_range(A.n, blockIdx.z, &jb, &je);
+  split_range(A.n, z, &jb, &je);
   const int row = k0 + (l & 31);
   const bool row_ok = row < A.s;
   const float* Drow = A.D32 + static_cast<int64_t>(row_ok ? row : 0) * A.n;
@@ -258,10 +287,10 @@ __global__ __launch_bounds__(256) void k_contract_x3(MArgs A) {
       v8 kh, kl;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const float kv = __builtin_amdgcn_exp2f(cexp[w] * dv[e]);
-        const T16 h = static_cast<T16>(kv);
+        T16 h, lo;
+        Vec8<T16>::split(__builtin_amdgcn_exp2f(cexp[w] * dv[e]), &h, &lo);
         kh[e] = h;
-        kl[e] = static_cast<T16>(kv - static_cast<float>(h));
+        kl[e] = lo;
       }
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
@@ -271,7 +300,7 @@ __global__ __launch_bounds__(256) void k_contract_x3(MArgs A) {
       }
     }
   }
-  float* Gz = A.G + static_cast<int64_t>(blockIdx.z) * A.m * A.s * A.r;
+  float* Gz = A.G + static_cast<int64_t>(z) * A.m * A.s * A.r;
 #pragma unroll
   for (int w = 0; w < PW; ++w) {
     const int64_t p = p0 + w;
@@ -292,10 +321,13 @@ template <int PW, int NB>
 __global__ __launch_bounds__(256) void k_contract_f32(MArgs A) {
   const int wave = threadIdx.x / 64, l = threadIdx.x % 64;
   const int k0 = (blockIdx.y * 4 + wave) * 32;
-  if (k0 >= A.s) return;
-  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * PW;
+  int64_t pb;
+  int z;
+  xcd_block(&pb, &z);
+  const int64_t p0 = pb * PW;
+  if (k0 >= A.s || p0 >= A.m) return;  // uniform per wave
   int64_t jb, je;
-  split_range(A.n, blockIdx.z, &jb, &je);
+  split_range(A.n, z, &jb, &je);
   const int row = k0 + (l & 31);
   const bool row_ok = row < A.s;
   const float* Drow = A.D32 + static_cast<int64_t>(row_ok ? row : 0) * A.n;
@@ -343,7 +375,7 @@ __global__ __launch_bounds__(256) void k_contract_f32(MArgs A) {
       }
     }
   }
-  float* Gz = A.G + static_cast<int64_t>(blockIdx.z) * A.m * A.s * A.r;
+  float* Gz = A.G + static_cast<int64_t>(z) * A.m * A.s * A.r;
 #pragma unroll
   for (int w = 0; w < PW; ++w) {
     const int64_t p = p0 + w;
@@ -456,67 +488,88 @@ __global__ __launch_bounds__(256) void k_lsq(LArgs A) {
 
 // ---------------------------------------------------------------------------
 // Refinement, part 1: partial sums of K_S(p) z, z = Q y, over a range of
-// points, with FP64-accurate kernel entries.  Block: PB parameters x one
-// point range; thread = selected row k.
+// points.  Block: PB parameters x one point range; thread = selected row k.
+// Kernel entries 2^(c_p D) with the degree-DEG polynomial: DEG = 9 (relative
+// error 2e-14) in the refinement, DEG = 11 (FP64 rounding) in the sketched
+// residual.  The range index is the block index mod 8, so with round-robin
+// dispatch over the 8 XCDs each XCD reads one eighth of D through its L2.
 // ---------------------------------------------------------------------------
 constexpr int kRefPB = 16;     // parameters per block
 constexpr int kRefNJ = 128;    // points per LDS chunk
-constexpr int kRefSplit = 8;   // point ranges (grid.y)
+constexpr int kRefSplit = 8;   // point ranges
 
-template <int RM>
-__global__ __launch_bounds__(256) void k_refine_partial(const double* params, int64_t m, int64_t n, int r,
-                                                         int s, const double* Dt64, const double* Qrm,
-                                                         const double* y, double* part) {
-  __shared__ double s_tab[64];
-  __shared__ double s_y[kRefPB][RM];
+template <int RM, int DEG>
+__global__ __launch_bounds__(256, 4) void k_refine_partial(const double* params, int64_t m, int64_t n, int r,
+                                                         int s, double dmax, const double* Dt64,
+                                                         const double* Qrm, const double* y, double* part) {
+  __shared__ double s_y[RM][kRefPB];
   __shared__ double s_z[kRefNJ][kRefPB];
   const int t = threadIdx.x;
-  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * kRefPB;
-  load_exp_table(s_tab);
+  const int split = blockIdx.x % kRefSplit;
+  const int64_t p0 = static_cast<int64_t>(blockIdx.x / kRefSplit) * kRefPB;
   for (int idx = t; idx < kRefPB * RM; idx += blockDim.x) {
     const int w = idx / RM, c = idx % RM;
-    s_y[w][c] = (p0 + w < m && c < r) ? y[(p0 + w) * r + c] : 0.0;
+    s_y[c][w] = (p0 + w < m && c < r) ? y[(p0 + w) * r + c] : 0.0;
   }
-  // per-parameter factor of exp_tab_v: v = 64 log2(e) (-1 / (2 p^2)) D
-  constexpr double k64log2e = 92.332482616893656877;
+  // per-parameter factor: entry = 2^(cv D), cv = -log2(e) / (2 p^2)
   double cv[kRefPB];
+  double cmax = 0.0;
 #pragma unroll
   for (int w = 0; w < kRefPB; ++w) {
     const double sig = p0 + w < m ? params[p0 + w] : 1.0;
-    cv[w] = krr_param_ok(sig) ? -0.5 * k64log2e / (sig * sig) : 0.0;
+    cv[w] = krr_param_ok(sig) ? -0.5 * kLog2e / (sig * sig) : 0.0;
+    cmax = fmax(cmax, -cv[w]);
   }
+  // every |cv D| of the block below 2^30: unclamped reduction (uniform branch)
+  const bool direct = cmax * dmax < kExp2Range;
   double acc[kRefPB];
 #pragma unroll
   for (int w = 0; w < kRefPB; ++w) acc[w] = 0.0;
   const int64_t per = (n + kRefSplit - 1) / kRefSplit;
-  const int64_t jb = blockIdx.y * per, je = std::min<int64_t>(n, jb + per);
+  const int64_t jb = split * per, je = std::min<int64_t>(n, jb + per);
   for (int64_t j0 = jb; j0 < je; j0 += kRefNJ) {
     __syncthreads();
-    for (int idx = t; idx < kRefNJ * kRefPB; idx += blockDim.x) {
-      const int jj = idx / kRefPB, w = idx % kRefPB;
+    // z for this chunk: thread = point, all PB parameters
+    for (int jj = t; jj < kRefNJ; jj += blockDim.x) {
       const int64_t j = j0 + jj;
-      double z = 0.0;
+      double z[kRefPB];
+#pragma unroll
+      for (int w = 0; w < kRefPB; ++w) z[w] = 0.0;
       if (j < je)
-        for (int c = 0; c < r; ++c) z = fma(Qrm[j * r + c], s_y[w][c], z);
-      s_z[jj][w] = z;
+        for (int c = 0; c < r; ++c) {
+          const double q = Qrm[j * r + c];
+#pragma unroll
+          for (int w = 0; w < kRefPB; ++w) z[w] = fma(q, s_y[c][w], z[w]);
+        }
+#pragma unroll
+      for (int w = 0; w < kRefPB; ++w) s_z[jj][w] = z[w];
     }
     __syncthreads();
     if (t < s) {
       const int cnt = static_cast<int>(std::min<int64_t>(kRefNJ, je - j0));
       const double* Dp = Dt64 + j0 * s + t;
       double dn = cnt > 0 ? Dp[0] : 0.0;
-      for (int jj = 0; jj < cnt; ++jj) {
-        const double d = dn;
-        if (jj + 1 < cnt) dn = Dp[(jj + 1) * s];  // prefetch the next distance
+      if (direct) {
+        for (int jj = 0; jj < cnt; ++jj) {
+          const double d = dn;
+          if (jj + 1 < cnt) dn = Dp[(jj + 1) * s];  // prefetch the next distance
 #pragma unroll
-        for (int w = 0; w < kRefPB; ++w) acc[w] = fma(exp_tab_v(cv[w] * d, s_tab), s_z[jj][w], acc[w]);
+          for (int w = 0; w < kRefPB; ++w) acc[w] = fma(exp2_mul<DEG>(cv[w], d), s_z[jj][w], acc[w]);
+        }
+      } else {
+        for (int jj = 0; jj < cnt; ++jj) {
+          const double d = dn;
+          if (jj + 1 < cnt) dn = Dp[(jj + 1) * s];
+#pragma unroll
+          for (int w = 0; w < kRefPB; ++w) acc[w] = fma(exp2_any<DEG>(cv[w] * d), s_z[jj][w], acc[w]);
+        }
       }
     }
   }
   if (t < s)
 #pragma unroll
     for (int w = 0; w < kRefPB; ++w)
-      if (p0 + w < m) part[(static_cast<int64_t>(blockIdx.y) * m + p0 + w) * s + t] = acc[w];
+      if (p0 + w < m) part[(static_cast<int64_t>(split) * m + p0 + w) * s + t] = acc[w];
 }
 
 // Refinement, part 2: r_S = sum of partials + lambda Q_S y - b_S; y -= R^{-1} Q^T r_S.
@@ -657,7 +710,7 @@ int rm_of(int r) { return r <= 8 ? 8 : r <= 16 ? 16 : r <= 32 ? 32 : r <= 40 ? 4
 }  // namespace
 
 subap_status launch_refine_partial(subap_model_s* M, const double* params, int64_t m, const double* y,
-                                   double* part, hipStream_t st);
+                                   double* part, bool exact, hipStream_t st);
 
 subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double* y, double* rho,
                        int32_t* status, int prec, int refine, hipStream_t st) {
@@ -714,8 +767,8 @@ subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double
     MArgs a{params, m, n, r, s, M->D32, f16 ? M->Qh16 : M->Qhi, f16 ? M->Ql16 : M->Qlo, M->Q32, G32};
     constexpr int PW = 8;
     const unsigned gy = static_cast<unsigned>((s + 127) / 128);
-    const dim3 g8(static_cast<unsigned>((m + PW - 1) / PW), gy, kSplit);
-    const dim3 g4(static_cast<unsigned>((m + 3) / 4), gy, kSplit);
+    const dim3 g8(xcd_grid((m + PW - 1) / PW), gy);
+    const dim3 g4(xcd_grid((m + 3) / 4), gy);
     if (prec == SUBAP_BF16X3) {
       ProfScope prof("krr_contract_bf16x3", st);
       if (r <= 32) hipLaunchKernelGGL((k_contract_x3<__bf16, PW, 1>), g8, dim3(256), 0, st, a);
@@ -743,7 +796,7 @@ subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double
   }
   // A4: refinement
   for (int it = 0; it < refine; ++it) {
-    SUBAP_TRY(launch_refine_partial(M, params, m, y, part, st));
+    SUBAP_TRY(launch_refine_partial(M, params, m, y, part, false, st));
     CArgs ca{m, r, s, part, M->QS, M->bS, M->lambda, M->bS_norm, fac, fac_stride, y, rho, stat};
     ProfScope prof("lsq_correct", st);
     SUBAP_TRY(launch_correct(sh, ca, st));
@@ -756,7 +809,7 @@ subap_status krr_residual(subap_model_s* M, const double* params, int64_t m, con
   const int s = M->s;
   SUBAP_TRY(ensure_work(M, static_cast<size_t>(kRefSplit) * m * s * 8));
   double* part = static_cast<double*>(M->work);
-  SUBAP_TRY(launch_refine_partial(M, params, m, y, part, st));
+  SUBAP_TRY(launch_refine_partial(M, params, m, y, part, true, st));
   ProfScope prof("krr_resid_finish", st);
   hipLaunchKernelGGL(k_resid_finish, dim3(static_cast<unsigned>((m + 3) / 4)), dim3(256), 0, st, params, m,
                      M->r, s, part, M->QS, M->bS, M->lambda, M->bS_norm, y, res, norm);
@@ -764,23 +817,33 @@ subap_status krr_residual(subap_model_s* M, const double* params, int64_t m, con
   return SUBAP_OK;
 }
 
-// (refinement partial-sum launcher, shared by the solve and the residual)
-subap_status launch_refine_partial(subap_model_s* M, const double* params, int64_t m, const double* y,
-                                   double* part, hipStream_t st) {
+// (refinement partial-sum launcher, shared by the solve and the residual;
+// exact selects the FP64-rounding polynomial)
+template <int DEG>
+static void launch_refine_deg(subap_model_s* M, const double* params, int64_t m, const double* y, double* part,
+                              hipStream_t st) {
   const int r = M->r, s = M->s;
   const int64_t n = M->n;
-  const int RM = rm_of(r);
+  const dim3 grid(static_cast<unsigned>((m + kRefPB - 1) / kRefPB * kRefSplit));
+  const dim3 block(static_cast<unsigned>(std::max(64, (s + 63) / 64 * 64)));
+  const double dmax = M->dmax;
+  switch (rm_of(r)) {
+    case 8: hipLaunchKernelGGL((k_refine_partial<8, DEG>), grid, block, 0, st, params, m, n, r, s, dmax, M->Dt64, M->Qrm, y, part); break;
+    case 16: hipLaunchKernelGGL((k_refine_partial<16, DEG>), grid, block, 0, st, params, m, n, r, s, dmax, M->Dt64, M->Qrm, y, part); break;
+    case 32: hipLaunchKernelGGL((k_refine_partial<32, DEG>), grid, block, 0, st, params, m, n, r, s, dmax, M->Dt64, M->Qrm, y, part); break;
+    case 40: hipLaunchKernelGGL((k_refine_partial<40, DEG>), grid, block, 0, st, params, m, n, r, s, dmax, M->Dt64, M->Qrm, y, part); break;
+    default: hipLaunchKernelGGL((k_refine_partial<64, DEG>), grid, block, 0, st, params, m, n, r, s, dmax, M->Dt64, M->Qrm, y, part); break;
+  }
+}
+
+subap_status launch_refine_partial(subap_model_s* M, const double* params, int64_t m, const double* y,
+                                   double* part, bool exact, hipStream_t st) {
   {
-    ProfScope prof("krr_refine_partial", st);
-    dim3 grid(static_cast<unsigned>((m + kRefPB - 1) / kRefPB), kRefSplit);
-    const int threads = std::max(64, (s + 63) / 64 * 64);
-    switch (RM) {
-      case 8: hipLaunchKernelGGL((k_refine_partial<8>), grid, dim3(threads), 0, st, params, m, n, r, s, M->Dt64, M->Qrm, y, part); break;
-      case 16: hipLaunchKernelGGL((k_refine_partial<16>), grid, dim3(threads), 0, st, params, m, n, r, s, M->Dt64, M->Qrm, y, part); break;
-      case 32: hipLaunchKernelGGL((k_refine_partial<32>), grid, dim3(threads), 0, st, params, m, n, r, s, M->Dt64, M->Qrm, y, part); break;
-      case 40: hipLaunchKernelGGL((k_refine_partial<40>), grid, dim3(threads), 0, st, params, m, n, r, s, M->Dt64, M->Qrm, y, part); break;
-      default: hipLaunchKernelGGL((k_refine_partial<64>), grid, dim3(threads), 0, st, params, m, n, r, s, M->Dt64, M->Qrm, y, part); break;
-    }
+    ProfScope prof(exact ? "krr_resid_partial" : "krr_refine_partial", st);
+    if (exact)
+      launch_refine_deg<11>(M, params, m, y, part, st);
+    else
+      launch_refine_deg<9>(M, params, m, y, part, st);
   }
   SUBAP_HIP_TRY(hipGetLastError());
   return SUBAP_OK;

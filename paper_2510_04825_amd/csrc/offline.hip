@@ -754,6 +754,14 @@ subap_status offline_build(const subap_problem_desc* pd, const subap_offline_opt
   if (M->family == SUBAP_FAMILY_KRR) {
     SUBAP_TRY(dalloc(&M->points, static_cast<size_t>(n) * M->dimx));
     SUBAP_HIP_TRY(hipMemcpyAsync(M->points, pd->points, sizeof(double) * n * M->dimx, hipMemcpyHostToDevice, st));
+    // |t_i - t_j|^2 <= (2 max_i |t_i|)^2; infinite if any coordinate is not finite
+    double rmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      double t2 = 0.0;
+      for (int q = 0; q < M->dimx; ++q) t2 += pd->points[i * M->dimx + q] * pd->points[i * M->dimx + q];
+      rmax = std::isfinite(t2) ? std::max(rmax, t2) : HUGE_VAL;
+    }
+    M->dmax = 4.0 * rmax;
   }
   OpArgs A{M->family, M->N, M->dimx, n, d, M->h, M->inv_h2, M->lambda, M->points};
 

@@ -167,6 +167,22 @@ def test_diffusion3d_given_basis(N, r, s):
         M.free()
 
 
+def _check_lift32(x32, ref, Q, Y):
+    """FP32 lift bar.  Q and y are rounded to FP32 and split exactly into three
+    bf16 parts; the kernel accumulates 6 r part products in FP32 and drops
+    terms below 2^-24 |q||y|.  The worst case is therefore
+    |x - Q y| <= (6 r + 3) u32 (|Q| |y|) elementwise (u32 = 2^-24); the typical
+    error is a few u32."""
+    u = 2.0 ** -24
+    r = Q.shape[1]
+    mag = (np.abs(Q) @ np.abs(Y.T)).T
+    err = np.abs(x32 - ref)
+    assert np.all(err <= (6 * r + 3) * u * mag + 1e-300)
+    rel = err / np.maximum(mag, 1e-300)
+    print(f"lift fp32: median {np.median(rel) / u:.2f} u32, max {rel.max() / u:.2f} u32")
+    assert np.median(rel) <= 2 * u
+
+
 def test_lift_matches_q_times_y(c1):
     import torch
     w, off = c1
@@ -180,8 +196,26 @@ def test_lift_matches_q_times_y(c1):
         ref = (Qg @ Y.T).T
         assert np.abs(x64 - ref).max() <= 1e-14 * np.abs(ref).max()
         x32 = M.lift(to_dev(Y), precision=B.FP32).cpu().numpy()
-        bound = 4 * 2.0 ** -24 * (np.abs(Qg) @ np.abs(Y.T)).T
-        assert np.all(np.abs(x32 - ref) <= bound + 1e-30)
+        _check_lift32(x32, ref, Qg, Y)
+    finally:
+        M.free()
+
+
+@pytest.mark.parametrize("k", [1, 33, 130])
+def test_lift_3d_many_vectors(k):
+    """FP32 lift on a 3-D basis (N = 40, n = 64000, r = 40) with a vector
+    count that leaves a ragged tile; checked against FP64 Q y on the host."""
+    header(f"lift 3-D k={k}")
+    device()
+    w = si.diffusion3d(N=40, r=40, s=160, m=8)
+    rng = np.random.default_rng(11)
+    Q0, _ = np.linalg.qr(rng.standard_normal((w["n"], w["r"])))
+    M = B.Model(w, basis=Q0)
+    try:
+        Y = rng.standard_normal((k, w["r"])) * np.logspace(0, -6, w["r"])
+        x32 = M.lift(to_dev(Y), precision=B.FP32).cpu().numpy()
+        Qg = M.basis()
+        _check_lift32(x32, (Qg @ Y.T).T, Qg, Y)
     finally:
         M.free()
 

@@ -1,8 +1,8 @@
 """GPU parity for kernel ridge regression against the FP64 oracle.
 
 Bars: row indices bit-exact (given basis); FP64 contraction within
-delta_res <= 1e-11 of the oracle (the GPU's table-driven exp is accurate to
-~4e-14 per kernel entry); FP32 and split-bf16 contractions followed by one
+delta_res <= 1e-11 of the oracle (the GPU's polynomial exp2 is accurate to
+FP64 rounding there, and to 2e-14 per kernel entry in the refinement); FP32 and split-bf16 contractions followed by one
 FP64 refinement step within delta_res <= 1e-6, the tolerance the method's
 reduced-precision forms are held to.  At the full configuration size the
 oracle checks sampled parameters through the sketched distance
@@ -112,6 +112,27 @@ def test_krr_nonpositive_length_scale(krr_model):
     assert list(st) == [B.OK, B.E_NONFINITE, B.E_NONFINITE, B.E_NONFINITE, B.OK]
     y = y.cpu().numpy()
     assert np.all(np.isnan(y[1:4])) and np.all(np.isfinite(y[[0, 4]]))
+
+
+@pytest.mark.parametrize("prec,refine", [(B.FP64, 0), (B.FP16X3, 1)])
+def test_krr_extreme_length_scales(krr_small, krr_model, prec, refine):
+    """Length scales far outside the snapshot range: tiny p makes every
+    off-point entry underflow (the refinement takes its clamped reduction for
+    those parameter blocks), huge p makes K_p nearly the all-ones matrix.
+    The first 16 parameters are ordinary, so one block of the refinement
+    takes the unclamped reduction in the same launch.  p = 1e4 is checked in
+    FP64 only: S A(p) Q then has a condition number near n / lambda, and one
+    refinement step from a contraction accurate to 2^-18 cannot reach 1e-6."""
+    w, off = krr_small
+    header(f"krr extreme length scales prec {prec} refine {refine}")
+    extra = [[1e-5], [1.0], [3e-6], [1e-3], [0.05]] + ([[1e4]] if prec == B.FP64 else [])
+    P = np.concatenate([w["test_params"][:16], extra])
+    y, _, st = krr_model.solve(to_dev(P), contraction=prec, refine_steps=refine)
+    assert np.all(st.cpu().numpy() == B.OK)
+    yo = On.solve(off["family"], off["Q"], off["rows"], P)
+    d = _dres(off["family"], off["Q"], P, y.cpu().numpy(), yo)
+    print("delta_res", d)
+    assert d.max() <= (1e-11 if prec == B.FP64 else 1e-6), d.max()
 
 
 def test_krr_full_chain_on_gpu(krr_small):
