@@ -72,14 +72,20 @@ def diffusion3d(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
                        "kernels_ms": {k: v[1] / v[0] for k, v in prof.items()}}
     tp = _plain(B, M, P, r, min(256, args.plain_sample), stream, timed, torch, dev)
     forms["fp64_per_p_plain"] = {"solves_per_s": 1e3 / tp}
-    # lift of 1024 coefficient vectors to FP32 x (n x 1024, column-major)
+    # lift of 1024 coefficient vectors to FP32 x (column-major, n rows per column):
+    # leading dimension n (odd for this grid) and n rounded up to 32 (line-aligned
+    # columns); bytes = Q read once (FP64) + x written once + y
     k = w["n_lift"]
     Y = y64[:k].contiguous()
-    x = torch.empty((k, n), dtype=torch.float32, device=dev)
-    B.subap_lift(M.handle, Y, x, B.FP32, stream)
-    tl = timed(lambda: B.subap_lift(M.handle, Y, x, B.FP32, stream), 3, stream)
     lift_bytes = 8.0 * n * r + 4.0 * n * k + 8.0 * k * r
-    del x
+    lift = {"k": k, "bytes": lift_bytes}
+    for tag, ld in (("ld_n", n), ("ld_aligned", (n + 31) // 32 * 32)):
+        x = torch.empty((k, ld), dtype=torch.float32, device=dev)
+        B.subap_lift(M.handle, Y, x, B.FP32, stream)
+        tl = timed(lambda: B.subap_lift(M.handle, Y, x, B.FP32, stream), 3, stream)
+        lift[tag] = {"ldx": ld, "ms": tl, "GB_per_s": lift_bytes / (tl * 1e-3) / 1e9,
+                     "frac_hbm": lift_bytes / (tl * 1e-3) / 1e9 / PEAKS["hbm_gbs"]}
+        del x
     # dominant solve kernel: FP64 ALU (Householder 2 s r^2 - 2/3 r^3 + face contraction 2 s F r per p)
     flops = m * (2.0 * s * r * r - 2.0 / 3.0 * r ** 3 + 2.0 * s * 6 * r)
     kms = forms["fp64_batched"]["kernels_ms"].get("fd_solve", forms["fp64_batched"]["ms_per_batch"])
@@ -96,8 +102,7 @@ def diffusion3d(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
         "roofline": {"bound": "alu", "kernel": "fd_solve", "achieved": flops / (kms * 1e-3) / 1e12,
                      "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s",
                      "frac": flops / (kms * 1e-3) / 1e12 / PEAKS["fp64_tflops"], "traffic": None},
-        "lift": {"k": k, "ms": tl, "GB_per_s": lift_bytes / (tl * 1e-3) / 1e9,
-                 "frac_hbm": lift_bytes / (tl * 1e-3) / 1e9 / PEAKS["hbm_gbs"]},
+        "lift": lift,
         "offline_s": offline_s,
     }
 
@@ -190,21 +195,25 @@ def surrogate(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
     acc = torch.empty(mi, dtype=torch.uint8, device=dev)
     B.subap_solve_batch(M.handle, Pin, y64, None, st, B.FP64, 0, stream)
     t_plain = timed(lambda: B.subap_solve_batch(M.handle, Pin, y64, None, st, B.FP64, 0, stream), 3, stream)
+    # the method's own sketched-residual floor on these parameters
+    _, rho_s = M.sketched_residual(Pin, y64)
+    floor = float(torch.median(rho_s))
     out = {}
-    for name, tol in (("literal_1e-5", 1e-5),):
+    # literal threshold of the configuration, and one just above the method's floor
+    # (its accepted solves are not counted toward the 1e-6 metric)
+    for name, tol in (("literal_1e-5", 1e-5), ("above_floor_1.5x_median", 1.5 * floor)):
         t0 = time.perf_counter()
         n_acc = B.subap_surrogate_solve_batch(M.handle, S, Pin, tol, y, acc, st)
         torch.cuda.synchronize()
         t = (time.perf_counter() - t0) * 1e3
         valid, dmax = _validity(B, M, Pin, y, y64, st, TOL)
-        out[name] = {"accepted": n_acc, "ms": t, "solves_per_s": mi / (t / 1e3), "valid": valid,
-                     "max_sketched_distance": dmax}
+        out[name] = {"tolerance": tol, "accepted": n_acc, "ms": t, "solves_per_s": mi / (t / 1e3),
+                     "valid": valid, "max_sketched_distance": dmax}
     # prediction quality and the predicted residual floor
     yh = torch.empty_like(y)
     B.subap_surrogate_predict(S, Pin, yh)
     t_pred = timed(lambda: B.subap_surrogate_predict(S, Pin, yh), 3, stream)
     _, rho_h = M.sketched_residual(Pin, yh)
-    _, rho_s = M.sketched_residual(Pin, y64)
     rel = float(torch.linalg.norm(yh - y64) / torch.linalg.norm(y64))
     B.subap_surrogate_free(S)
     M.free()
@@ -217,7 +226,7 @@ def surrogate(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
                    "infer": mi, "widths": widths},
         "surrogate": out, "plain_batched_fp64": {"ms": t_plain, "solves_per_s": mi / (t_plain / 1e3)},
         "predict_ms": t_pred, "prediction_rel_error": rel,
-        "sketched_residual_median": {"prediction": float(torch.median(rho_h)), "subapsnap": float(torch.median(rho_s))},
+        "sketched_residual_median": {"prediction": float(torch.median(rho_h)), "subapsnap": floor},
         "train": {"pairs_generation_s": gen_s, "train_s": train_s, "loss_first": float(losses[0]),
                   "loss_last": float(losses[-1])},
     }

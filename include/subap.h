@@ -154,11 +154,20 @@ SUBAP_API subap_status subap_solve_batch(subap_model model, const double* params
 
 /*
  * subap_lift -- x = Q y (Algorithm 3.1 step 4, output X c) for k coefficient
- * vectors.  y_dev: device k x r row-major FP64.  x_dev: device n x k
- * col-major, FP64 (precision = SUBAP_FP64) or FP32 (SUBAP_FP32).
+ * vectors.
+ *   y_dev      device k x r row-major FP64.
+ *   x_dev      device, column i (i < k) at x_dev + i * ldx, rows 0..n-1 written,
+ *              rows n..ldx-1 untouched; FP64 (precision = SUBAP_FP64) or FP32
+ *              (SUBAP_FP32, split-bf16 MFMA with FP32-level error).
+ *   ldx        leading dimension in elements, 0 (= n) or >= n.  For FP32 output
+ *              an ldx that is a multiple of 32 with x_dev 128-byte aligned lets
+ *              every column start on a cache line (full-line stores; about twice
+ *              the write bandwidth of an odd n).
+ * k = 0 is a no-op.  SUBAP_E_INVALID for k < 0, 0 < ldx < n, NULL pointers or
+ * another precision.  Asynchronous on hip_stream.
  */
 SUBAP_API subap_status subap_lift(subap_model model, const double* y_dev, int64_t k,
-                        void* x_dev, int32_t precision, void* hip_stream);
+                        void* x_dev, int64_t ldx, int32_t precision, void* hip_stream);
 
 /*
  * subap_sketched_residual -- FP64 sketched residual of given coefficients,

@@ -79,7 +79,7 @@ def load(path: str = LIB_PATH):
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     lib.subap_offline.argtypes = [C.POINTER(ProblemDesc), C.POINTER(OfflineOpts), vp, C.POINTER(vp)]
     lib.subap_solve_batch.argtypes = [vp, vp, i64, vp, vp, vp, C.POINTER(SolveOpts), vp]
-    lib.subap_lift.argtypes = [vp, vp, i64, vp, i32, vp]
+    lib.subap_lift.argtypes = [vp, vp, i64, vp, i64, i32, vp]
     lib.subap_sketched_residual.argtypes = [vp, vp, i64, vp, vp, vp, vp]
     lib.subap_profile_enable.argtypes = [i32]
     lib.subap_profile_reset.argtypes = []
@@ -185,13 +185,18 @@ def subap_solve_batch(model, params, y, rho=None, status=None, contraction=FP64,
 
 
 def subap_lift(model, y, x, precision=FP64, stream=None):
-    """y: (k, r) float64 cuda tensor; x: (k, n) tensor (column i of x is row i), float64 or float32."""
+    """y: (k, r) float64 cuda tensor; x: (k, ldx) tensor with ldx >= n, float64 or
+    float32 (row i of x holds column i of the lift in its first n entries)."""
     lib = load()
     n, r, _, _ = subap_model_dims(model)
     k = y.shape[0]
     _expect(y, (k, r), "float64", "y")
-    _expect(x, (k, n), "float64" if precision == FP64 else "float32", "x")
-    _check(lib.subap_lift(C.c_void_p(model), _ptr(y), k, _ptr(x), int(precision), _stream(stream)))
+    dt = "float64" if precision == FP64 else "float32"
+    if x.dim() != 2 or x.shape[0] != k or x.shape[1] < n or not x.is_contiguous() or str(x.dtype) != "torch." + dt \
+            or not x.is_cuda:
+        raise ValueError(f"x must be a contiguous {dt} cuda tensor of shape ({k}, >= {n}), got "
+                         f"{tuple(x.shape)} {x.dtype}")
+    _check(lib.subap_lift(C.c_void_p(model), _ptr(y), k, _ptr(x), int(x.shape[1]), int(precision), _stream(stream)))
 
 
 def subap_sketched_residual(model, params, y, res=None, norm=None, stream=None):
@@ -438,12 +443,13 @@ class Model:
         subap_sketched_residual(self.handle, params, y, res, norm, stream)
         return res, norm
 
-    def lift(self, y, precision=FP64, stream=None):
+    def lift(self, y, precision=FP64, stream=None, ldx=None):
+        """x = Q y for the rows of y; returns a (k, n) view of a (k, ldx) tensor."""
         import torch
         dt = torch.float64 if precision == FP64 else torch.float32
-        x = torch.empty((y.shape[0], self.n), dtype=dt, device=y.device)
+        x = torch.empty((y.shape[0], ldx or self.n), dtype=dt, device=y.device)
         subap_lift(self.handle, y, x, precision, stream)
-        return x
+        return x[:, :self.n]
 
     def free(self):
         if getattr(self, "handle", None):

@@ -112,7 +112,7 @@ namespace {
 
 void free_model(subap_model_s* M) {
   if (!M) return;
-  void* bufs[] = {M->Q, M->rows_d, M->bS, M->QS, M->rhs, M->phi, M->delta64, M->delta32, M->points,
+  void* bufs[] = {M->Q, M->rows_d, M->bS, M->QS, M->rhs, M->phi, M->delta64, M->delta32, M->delta64T, M->points,
                   M->Dt64, M->D32, M->Qrm, M->Q32, M->Qhi, M->Qlo, M->Qh16, M->Ql16, M->colscale_inv,
                   M->work, M->lds_inst, M->lds_counter};
   for (void* b : bufs) dfree(b);
@@ -248,14 +248,16 @@ subap_status subap_solve_batch(subap_model M, const double* params, int64_t m, d
   return fd_solve(M, params, m, y, rho, status, prec, refine, st);
 }
 
-subap_status subap_lift(subap_model M, const double* y, int64_t k, void* x, int32_t precision, void* hip_stream) {
+subap_status subap_lift(subap_model M, const double* y, int64_t k, void* x, int64_t ldx, int32_t precision,
+                        void* hip_stream) {
   clear_error();
   if (!M) return invalid("model must not be NULL");
   if (k < 0) return invalid("k must be >= 0");
+  if (ldx != 0 && ldx < M->n) return invalid("ldx must be 0 or >= n");
   if (k == 0) return SUBAP_OK;
   if (!y || !x) return invalid("y and x must not be NULL");
   if (precision != SUBAP_FP64 && precision != SUBAP_FP32) return invalid("lift precision must be FP64 or FP32");
-  return lift(M, y, k, x, precision, static_cast<hipStream_t>(hip_stream));
+  return lift(M, y, k, x, ldx == 0 ? M->n : ldx, precision, static_cast<hipStream_t>(hip_stream));
 }
 
 subap_status subap_model_dims(subap_model M, int64_t* n, int32_t* r, int32_t* s, int32_t* d) {

@@ -69,6 +69,7 @@ struct subap_model_s {
   double* phi = nullptr;              // s x F x d  mode values at face midpoints
   double* delta64 = nullptr;          // s x F x r  Q[i_k] - Q[nb_f(i_k)] (0 outside)
   float* delta32 = nullptr;
+  double* delta64T = nullptr;         // the same at [(f * s + k) * r + c] (lanes = columns)
 
   // kernel ridge regression tables
   double* points = nullptr;           // n x dimx row-major
@@ -101,7 +102,7 @@ subap_status fd_solve(subap_model_s* M, const double* params, int64_t m, double*
                       double* rho, int32_t* status, int prec, int refine, hipStream_t st);
 subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double* y,
                        double* rho, int32_t* status, int prec, int refine, hipStream_t st);
-subap_status lift(subap_model_s* M, const double* y, int64_t k, void* x, int prec,
+subap_status lift(subap_model_s* M, const double* y, int64_t k, void* x, int64_t ldx, int prec,
                   hipStream_t st);
 subap_status fd_residual(subap_model_s* M, const double* params, int64_t m, const double* y, double* res,
                          double* norm, hipStream_t st);

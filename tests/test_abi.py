@@ -98,6 +98,6 @@ def test_null_model_calls(lib):
     assert lib.subap_offline(None, None, None, None) == B.E_INVALID
     opts = B.SolveOpts(0, 0)
     assert lib.subap_solve_batch(None, None, 4, None, None, None, C.byref(opts), None) == B.E_INVALID
-    assert lib.subap_lift(None, None, 1, None, 0, None) == B.E_INVALID
+    assert lib.subap_lift(None, None, 1, None, 0, 0, None) == B.E_INVALID
     assert lib.subap_model_rows(None, None) == B.E_INVALID
     assert lib.subap_model_free(None) == B.OK

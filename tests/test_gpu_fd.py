@@ -149,6 +149,51 @@ def test_rank_deficient_rows_report_rank_status():
         M.free()
 
 
+@pytest.mark.parametrize("dim,N,r,s,m", [(2, 32, 16, 100, 37), (2, 40, 32, 131, 21), (3, 16, 40, 96, 9),
+                                         (3, 20, 40, 191, 15)])
+def test_fd_tall_fp64_shapes(dim, N, r, s, m):
+    """FP64 solves of tall problems (s >= 96, the column-per-lane kernel) with
+    ragged row blocks, an odd batch and a non-finite parameter; y within
+    delta_res 1e-12 of the oracle and rho equal to the oracle's sketched
+    residual."""
+    w = si.diffusion2d(N=N, r=r, s=s, m=m) if dim == 2 else si.diffusion3d(N=N, r=r, s=s, m=m)
+    off = O.offline(w)
+    fam, Q, rows = off["family"], off["Q"], off["rows"]
+    header(f"tall fp64 dim={dim} N={N} r={r} s={s} m={m}")
+    M = B.Model(w, basis=Q, rows=rows)
+    try:
+        P = np.array(w["test_params"])
+        P[3, 0] = np.nan
+        y, rho, st = M.solve(to_dev(P))
+        st, y, rho = st.cpu().numpy(), y.cpu().numpy(), rho.cpu().numpy()
+        assert st[3] == B.E_NONFINITE and np.all(np.isnan(y[3]))
+        ok = np.arange(m) != 3
+        assert np.all(st[ok] == B.OK)
+        Yo = On.solve(fam, Q, rows, P[ok])
+        assert _dres(fam, Q, P[ok], y[ok], Yo).max() <= 1e-12
+        ro = np.array([On.sketched_residual(fam, Q, rows, p, yo) for p, yo in zip(P[ok], Yo)])
+        assert np.allclose(rho[ok], ro, rtol=1e-6, atol=1e-10), np.abs(rho[ok] - ro).max()
+    finally:
+        M.free()
+
+
+def test_rank_deficient_tall_problem():
+    # unit-vector basis at nodes 13 or more grid lines away from the 96 selected
+    # rows (the first three lines): S A(p) Q = 0
+    w = si.diffusion2d(N=32, r=16, s=96, m=5)
+    Q = np.zeros((1024, 16))
+    for c in range(16):
+        Q[512 + 32 * c, c] = 1.0
+    header("rank-deficient tall S A Q")
+    M = B.Model(w, basis=Q, rows=np.arange(96))
+    try:
+        y, _, st = M.solve(to_dev(w["test_params"]))
+        assert np.all(st.cpu().numpy() == B.E_RANK)
+        assert np.all(np.isnan(y.cpu().numpy()))
+    finally:
+        M.free()
+
+
 @pytest.mark.parametrize("N,r,s", [(16, 8, 32), (24, 40, 160)])
 def test_diffusion3d_given_basis(N, r, s):
     w = si.diffusion3d(N=N, r=r, s=s, m=50)
@@ -201,21 +246,29 @@ def test_lift_matches_q_times_y(c1):
         M.free()
 
 
-@pytest.mark.parametrize("k", [1, 33, 130])
-def test_lift_3d_many_vectors(k):
-    """FP32 lift on a 3-D basis (N = 40, n = 64000, r = 40) with a vector
-    count that leaves a ragged tile; checked against FP64 Q y on the host."""
-    header(f"lift 3-D k={k}")
-    device()
-    w = si.diffusion3d(N=40, r=40, s=160, m=8)
+@pytest.mark.parametrize("k,pad", [(1, 0), (33, 0), (130, 0), (70, 32), (70, 5), (45, 4), (1, 32)])
+def test_lift_3d_many_vectors(k, pad):
+    """FP32 lift on a 3-D basis (N = 41, n = 68921, odd, r = 40) with a vector
+    count that leaves a ragged tile, with ld = n and with padded leading
+    dimensions (aligned to 32 and not); checked against FP64 Q y on the host,
+    padding rows must keep their contents."""
+    import torch
+    header(f"lift 3-D k={k} pad={pad}")
+    dev = device()
+    w = si.diffusion3d(N=41, r=40, s=160, m=8)
+    n = w["n"]
     rng = np.random.default_rng(11)
-    Q0, _ = np.linalg.qr(rng.standard_normal((w["n"], w["r"])))
+    Q0, _ = np.linalg.qr(rng.standard_normal((n, w["r"])))
     M = B.Model(w, basis=Q0)
     try:
         Y = rng.standard_normal((k, w["r"])) * np.logspace(0, -6, w["r"])
-        x32 = M.lift(to_dev(Y), precision=B.FP32).cpu().numpy()
+        ld = n if pad == 0 else (n + 31) // 32 * 32 + (0 if pad == 32 else pad)
+        x = torch.full((k, ld), 7.5, dtype=torch.float32, device=dev)
+        B.subap_lift(M.handle, to_dev(Y), x, B.FP32)
+        xh = x.cpu().numpy()
+        assert np.all(xh[:, n:] == 7.5)
         Qg = M.basis()
-        _check_lift32(x32, (Qg @ Y.T).T, Qg, Y)
+        _check_lift32(xh[:, :n], (Qg @ Y.T).T, Qg, Y)
     finally:
         M.free()
 

@@ -114,6 +114,9 @@ def test_training_prediction_and_fallback(small3d):
         _, rho_acc = M.sketched_residual(Pin, y)
         assert np.all(rho_acc.cpu().numpy()[a] <= tol * (1 + 1e-12))
         print(f"accepted {n} of 1024 at tolerance {tol:.2e}; prediction error {rel:.2e}")
+        # what the network gains over the method alone: at a threshold just above the
+        # method's own sketched-residual floor most parameters skip the solve
+        assert n >= 512, n
     finally:
         B.subap_surrogate_free(s)
         M.free()
