@@ -76,20 +76,20 @@ def timed(fn, steps, stream):
     return start.elapsed_time(end) / steps
 
 
-# FP64 flops of one refinement entry 2^(c D) z: the reduction (two FMAs and a
-# subtraction), the degree-9 Horner polynomial (9 FMAs), ldexp and the
-# accumulating FMA; FMAs count 2.
-REFINE_FLOPS_PER_ENTRY = 2 * 2 + 1 + 9 * 2 + 1 + 2
+# FP64 flops of one entry 2^(c D) z of the first refinement step: the reduction
+# (two FMAs and a subtraction), the degree-7 Horner polynomial (7 FMAs), ldexp
+# and the accumulating FMA; FMAs count 2.
+REFINE_FLOPS_PER_ENTRY = 2 * 2 + 1 + 7 * 2 + 1 + 2
 
 
 # HBM traffic of the dominant kernel from two rocprofv3 counter runs (FETCH_SIZE,
-# then WRITE_SIZE, KiB per dispatch of k_refine_partial<32, 9> on this workload),
+# then WRITE_SIZE, KiB per dispatch of k_refine_partial<32, 7> on this workload),
 # scaled by the factors a 1 GiB device copy gives (FETCH 2.0, WRITE 1.0).  Valid
 # only for the kernel sources they were taken with: the hash below covers them,
 # and a changed source reports traffic null.
 TRAFFIC_SOURCES = ("krr.hip", "family.h", "exp2_poly.h")
-TRAFFIC = {"kernel": "krr_refine_partial", "sources_sha256_16": "551139d9fdb4c639",
-           "fetch_kib": 21413.9, "write_kib": 40960.0, "fetch_factor": 2.0, "write_factor": 1.0}
+TRAFFIC = {"kernel": "krr_refine_partial", "sources_sha256_16": "b0a6237da0417ebe",
+           "fetch_kib": 21395.5, "write_kib": 43326.7, "fetch_factor": 2.0, "write_factor": 1.0}
 
 
 def traffic_bytes(kernel):

@@ -489,10 +489,11 @@ __global__ __launch_bounds__(256) void k_lsq(LArgs A) {
 // ---------------------------------------------------------------------------
 // Refinement, part 1: partial sums of K_S(p) z, z = Q y, over a range of
 // points.  Block: PB parameters x one point range; thread = selected row k.
-// Kernel entries 2^(c_p D) with the degree-DEG polynomial: DEG = 9 (relative
-// error 2e-14) in the refinement, DEG = 11 (FP64 rounding) in the sketched
-// residual.  The range index is the block index mod 8, so with round-robin
-// dispatch over the 8 XCDs each XCD reads one eighth of D through its L2.
+// Kernel entries 2^(c_p D) with the degree-DEG polynomial of exp2_poly.h:
+// DEG = 7 (relative error 5.5e-11) in the first refinement step, DEG = 11
+// (FP64 rounding) in later steps and in the sketched residual.  The range
+// index is the block index mod 8, so with round-robin dispatch over the 8
+// XCDs each XCD reads one eighth of D through its L2.
 // ---------------------------------------------------------------------------
 constexpr int kRefPB = 16;     // parameters per block
 constexpr int kRefNJ = 128;    // points per LDS chunk
@@ -796,7 +797,7 @@ subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double
   }
   // A4: refinement
   for (int it = 0; it < refine; ++it) {
-    SUBAP_TRY(launch_refine_partial(M, params, m, y, part, false, st));
+    SUBAP_TRY(launch_refine_partial(M, params, m, y, part, it > 0, st));
     CArgs ca{m, r, s, part, M->QS, M->bS, M->lambda, M->bS_norm, fac, fac_stride, y, rho, stat};
     ProfScope prof("lsq_correct", st);
     SUBAP_TRY(launch_correct(sh, ca, st));
@@ -817,8 +818,13 @@ subap_status krr_residual(subap_model_s* M, const double* params, int64_t m, con
   return SUBAP_OK;
 }
 
-// (refinement partial-sum launcher, shared by the solve and the residual;
-// exact selects the FP64-rounding polynomial)
+// (refinement partial-sum launcher, shared by the solve and the residual.
+// exact selects the FP64-rounding polynomial (degree 11): the sketched
+// residual and every refinement step after the first.  The first step uses
+// degree 7 (relative error 5.5e-11 per entry): its result is limited by the
+// contraction it corrects (errors near 1e-7), so the entries' share of its
+// error stays four orders below that while the evaluation takes 12 VALU
+// instructions instead of 16.)
 template <int DEG>
 static void launch_refine_deg(subap_model_s* M, const double* params, int64_t m, const double* y, double* part,
                               hipStream_t st) {
@@ -839,11 +845,11 @@ static void launch_refine_deg(subap_model_s* M, const double* params, int64_t m,
 subap_status launch_refine_partial(subap_model_s* M, const double* params, int64_t m, const double* y,
                                    double* part, bool exact, hipStream_t st) {
   {
-    ProfScope prof(exact ? "krr_resid_partial" : "krr_refine_partial", st);
+    ProfScope prof(exact ? "krr_refine_partial_exact" : "krr_refine_partial", st);
     if (exact)
       launch_refine_deg<11>(M, params, m, y, part, st);
     else
-      launch_refine_deg<9>(M, params, m, y, part, st);
+      launch_refine_deg<7>(M, params, m, y, part, st);
   }
   SUBAP_HIP_TRY(hipGetLastError());
   return SUBAP_OK;
