@@ -177,9 +177,10 @@ __global__ __launch_bounds__(256) void k_fd_solve(FDArgs A) {
 // Householder QR of S A(p) Q applied in block order, the same R up to
 // rounding.  R (with Q^T b as column r) lives in wave-private LDS, packed by
 // rows, so that step j reads row j across the lanes without bank conflicts
-// and the registers hold only the block.  The reflector of column j is
-// broadcast through LDS; the squared norm each column needs for its own
-// reflector is accumulated while the previous reflector is applied.  After a
+// and the registers hold only the block.  The pivot lane's block column is
+// broadcast into scalar registers by v_readlane (no LDS round trip in the
+// step); the squared norm each column needs for its own reflector is
+// accumulated while the previous reflector is applied.  After a
 // block, the block part of the b column is orthogonal to the range of the
 // first r columns, so its squared norm adds to the sketched residual.  No
 // block-level barrier is used: the waves of a block are independent.
@@ -194,7 +195,6 @@ __global__ __launch_bounds__(128) void k_fd_cols(FDArgs A) {
   constexpr int RP = (RM + 1) * (RM + 2) / 2;
   struct Smem {
     double R[RP];      // packed rows of [R | Q^T b]
-    double v[RB];      // reflector of the current column (block part)
     double a[RB][F];   // face coefficients / h^2 of the current rows
     double y[RM];
   };
@@ -261,40 +261,35 @@ __global__ __launch_bounds__(128) void k_fd_cols(FDArgs A) {
         tau = -d / beta;
         scale = 1.0 / d;
       }
-      // lane j publishes its unscaled block column (the reflector's block part
-      // is that column times scale, folded into the products below)
-      if (lane == j) {
-#pragma unroll
-        for (int i = 0; i < RB; ++i) sm.v[i] = B[i];
-        sm.R[rowj] = beta;
-      }
+      if (lane == j) sm.R[rowj] = beta;
       const double tauj = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(tau), j),
                                            __builtin_amdgcn_readlane(__double2loint(tau), j));
       const double betaj = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(beta), j),
                                             __builtin_amdgcn_readlane(__double2loint(beta), j));
       const double scalej = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(scale), j),
                                              __builtin_amdgcn_readlane(__double2loint(scale), j));
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // lane j's block column, broadcast into scalar registers
+      double vj[RB];
+#pragma unroll
+      for (int i = 0; i < RB; ++i)
+        vj[i] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(B[i]), j),
+                                 __builtin_amdgcn_readlane(__double2loint(B[i]), j));
       if (lane > j && col) {
         double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
 #pragma unroll
         for (int i = 0; i < RB; i += 4) {
-          w0 = fma(sm.v[i], B[i], w0);
-          if (i + 1 < RB) w1 = fma(sm.v[i + 1], B[i + 1], w1);
-          if (i + 2 < RB) w2 = fma(sm.v[i + 2], B[i + 2], w2);
-          if (i + 3 < RB) w3 = fma(sm.v[i + 3], B[i + 3], w3);
+          w0 = fma(vj[i], B[i], w0);
+          if (i + 1 < RB) w1 = fma(vj[i + 1], B[i + 1], w1);
+          if (i + 2 < RB) w2 = fma(vj[i + 2], B[i + 2], w2);
+          if (i + 3 < RB) w3 = fma(vj[i + 3], B[i + 3], w3);
         }
-        // w = tau (alpha + v^T B) with v = scale * (lane j's column)
         const double w = tauj * fma(scalej, (w0 + w1) + (w2 + w3), alpha);
         sm.R[rowj + (lane - j)] = alpha - w;
         const double ws = w * scalej;
-        asm volatile("" ::: "memory");  // re-read v rather than keep RB values live
         double s0 = 0.0, s1 = 0.0;
 #pragma unroll
         for (int i = 0; i < RB; ++i) {
-          B[i] = fma(-ws, sm.v[i], B[i]);
+          B[i] = fma(-ws, vj[i], B[i]);
           if (i % 2 == 0) s0 = fma(B[i], B[i], s0);
           else s1 = fma(B[i], B[i], s1);
         }
@@ -305,7 +300,6 @@ __global__ __launch_bounds__(128) void k_fd_cols(FDArgs A) {
         if (j == 0) r00 = ab;
         if (!(ab > kRankTol * r00)) full_rank = false;
       }
-      __builtin_amdgcn_wave_barrier();  // reads of v before the next column writes it
     }
     if (lane == r) rho2 += ss;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
