@@ -112,9 +112,9 @@ namespace {
 
 void free_model(subap_model_s* M) {
   if (!M) return;
-  void* bufs[] = {M->Q, M->rows_d, M->bS, M->QS, M->rhs, M->phi, M->delta64, M->delta32, M->delta64T, M->points,
+  void* bufs[] = {M->Q, M->rows_d, M->bS, M->QS, M->rhs, M->phi, M->delta64, M->delta32, M->delta64T, M->delta32T, M->points,
                   M->Dt64, M->D32, M->Qrm, M->Q32, M->Qhi, M->Qlo, M->Qh16, M->Ql16, M->colscale_inv,
-                  M->work, M->lds_inst, M->lds_counter};
+                  M->work};
   for (void* b : bufs) dfree(b);
   delete M;
 }

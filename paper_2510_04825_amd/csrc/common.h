@@ -70,6 +70,7 @@ struct subap_model_s {
   double* delta64 = nullptr;          // s x F x r  Q[i_k] - Q[nb_f(i_k)] (0 outside)
   float* delta32 = nullptr;
   double* delta64T = nullptr;         // the same at [(f * s + k) * r + c] (lanes = columns)
+  float* delta32T = nullptr;
 
   // kernel ridge regression tables
   double* points = nullptr;           // n x dimx row-major
@@ -86,8 +87,6 @@ struct subap_model_s {
   // online workspaces (grown on demand)
   void* work = nullptr;
   size_t work_bytes = 0;
-  void* lds_inst = nullptr;      // one-entry instance table of the LDS solve kernel
-  void* lds_counter = nullptr;
 };
 
 namespace subap {
@@ -119,9 +118,6 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
 subap_status plan_execute(PlanImpl* P, hipStream_t st);
 void plan_free(PlanImpl* P);
 void plan_shape(const PlanImpl* P, int* threads, int* blocks);
-subap_status fd_solve_lds(subap_model_s* M, const double* params, int64_t m, double* y, double* rho,
-                          int32_t* status, int prec, int refine, hipStream_t st);
-
 // ---- learned surrogate (mlp.hip) ----
 struct Surrogate;
 subap_status surrogate_create(int d, int r, int H, const double* weights, Surrogate** out);

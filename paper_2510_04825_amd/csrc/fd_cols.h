@@ -1,0 +1,323 @@
+// Column-per-lane Householder solve of one finite-difference parameter
+// (Section 3.1 rows, eq. (3.4) contraction, eq. (3.3) least squares) by one
+// wavefront.
+//
+// Lane c < r owns column c of G = S A(p) Q; S b is owned by lane r when
+// r < 64 and carried identically by every lane when r = 64.  No dot product
+// needs a cross-lane reduction.  The s rows arrive in blocks of kColsRB held
+// in registers; each block is merged into the running triangular factor by
+// Householder reflections of the stacked matrix [R; block] (reflector j acts
+// on row j of R and on all block rows).  This is Householder QR of G applied
+// in block order: the same R up to rounding.  R, with Q^T b as its last
+// column, lives in wave-private LDS packed by rows, so that step j reads row
+// j across the lanes without bank conflicts.  The pivot lane's block column
+// is broadcast into scalar registers by v_readlane, and the squared norm each
+// column needs for its own reflector is accumulated while the previous
+// reflector is applied.  After a block, the block part of the b column is
+// orthogonal to the range of the first r columns, so its squared norm adds to
+// the sketched residual.
+//
+// Refinement (FP64) does not need the reflectors: with r_S = S(A(p) Q y - b)
+// from the FP64 difference table, the correction solves R^T R dy = G^T r_S
+// with the G that was factorised (recomputed in the same arithmetic), which
+// equals R^{-1} Q^T r_S.
+//
+// The caller gives each wavefront cols_lds_doubles(rmax, smax) doubles of LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace subap {
+
+constexpr int kColsRB = 32;  // rows per block
+
+struct ColsModel {
+  int r, s;
+  const double* phi;    // [(f * DP + q) * s + k]
+  const double* d64T;   // [(f * s + k) * r + c]
+  const float* d32T;    // [(f * s + k) * r + c]
+  const double* bS;
+  double inv_h2, bS_norm;
+};
+
+__host__ __device__ inline int cols_lds_doubles(int rmax, int smax) {
+  return (rmax + 1) * (rmax + 2) / 2  // packed [R | Q^T b]
+         + kColsRB * 6                // face coefficients of a block
+         + 2 * kMaxR                  // y, and the correction
+         + smax;                      // residual vector
+}
+
+// start of packed row j (columns j..r1-1) for r1 = r + 1 columns
+__device__ __forceinline__ int cols_row(int j, int r1) { return j * r1 - j * (j - 1) / 2; }
+
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), src),
+                          __builtin_amdgcn_readlane(__double2loint(v), src));
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// face coefficients / h^2 of rows k0 .. k0 + kColsRB - 1 into a[i * F + f]
+template <int F, int DP>
+__device__ __forceinline__ void cols_faces(const ColsModel& M, const double* pv, int k0, double* a, int lane) {
+  for (int idx = lane; idx < kColsRB * F; idx += 64) {
+    const int i = idx / F, f = idx % F;
+    const int k = k0 + i;
+    double t = 0.0;
+    if (k < M.s) {
+#pragma unroll
+      for (int q = 0; q < DP; ++q) t += pv[q] * M.phi[(f * DP + q) * M.s + k];
+    }
+    a[idx] = (k < M.s) ? exp(t) * M.inv_h2 : 0.0;
+  }
+  wave_sync_lds();
+}
+
+// this block's rows of column `lane` of G in the contraction precision
+template <int F>
+__device__ __forceinline__ void cols_block(const ColsModel& M, int prec, int k0, const double* a, int lane,
+                                           double (&B)[kColsRB]) {
+#pragma unroll
+  for (int i = 0; i < kColsRB; ++i) {
+    const int k = k0 + i;
+    double t = 0.0;
+    if (k < M.s && lane < M.r) {
+      if (prec == SUBAP_FP64) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) t = fma(a[i * F + f], M.d64T[(static_cast<int64_t>(f) * M.s + k) * M.r + lane], t);
+      } else {
+        float t32 = 0.0f;
+#pragma unroll
+        for (int f = 0; f < F; ++f)
+          t32 = fmaf(static_cast<float>(a[i * F + f]), M.d32T[(static_cast<int64_t>(f) * M.s + k) * M.r + lane], t32);
+        t = t32;
+      }
+    }
+    B[i] = t;
+  }
+}
+
+// FP64 residual r_k = (S A(p) Q y - b)_k for all k < s (lanes over rows); y in LDS
+template <int F, int DP>
+__device__ __forceinline__ void cols_residual(const ColsModel& M, const double* pv, const double* y, double* res,
+                                              int lane) {
+  const int r = M.r, s = M.s;
+  for (int k = lane; k < s; k += 64) {
+    double t = 0.0;
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      double arg = 0.0;
+#pragma unroll
+      for (int q = 0; q < DP; ++q) arg += pv[q] * M.phi[(f * DP + q) * s + k];
+      const double* d = M.d64T + (static_cast<int64_t>(f) * s + k) * r;
+      double u0 = 0.0, u1 = 0.0;
+      int c = 0;
+      for (; c + 1 < r; c += 2) {
+        u0 = fma(d[c], y[c], u0);
+        u1 = fma(d[c + 1], y[c + 1], u1);
+      }
+      if (c < r) u0 = fma(d[c], y[c], u0);
+      t = fma(exp(arg) * M.inv_h2, u0 + u1, t);
+    }
+    res[k] = t - M.bS[k];
+  }
+  wave_sync_lds();
+}
+
+// y <- R^{-1} v in place (v in LDS, every lane computes the same values)
+__device__ __forceinline__ void cols_back_solve(const double* R, int r1, int r, double* v) {
+  for (int j = r - 1; j >= 0; --j) {
+    const int rowj = cols_row(j, r1);
+    double t = v[j];
+    for (int c = j + 1; c < r; ++c) t = fma(-R[rowj + (c - j)], v[c], t);
+    t /= R[rowj];
+    wave_sync_lds();
+    v[j] = t;  // identical in every lane
+    wave_sync_lds();
+  }
+}
+
+// v <- R^{-T} v in place
+__device__ __forceinline__ void cols_forward_solve(const double* R, int r1, int r, double* v) {
+  for (int j = 0; j < r; ++j) {
+    double t = v[j];
+    for (int i = 0; i < j; ++i) t = fma(-R[cols_row(i, r1) + (j - i)], v[i], t);
+    t /= R[cols_row(j, r1)];
+    wave_sync_lds();
+    v[j] = t;
+    wave_sync_lds();
+  }
+}
+
+// One parameter.  BRED: r == 64 (S b carried by every lane).  REF: an FP32
+// contraction or refinement steps (FP64 residuals); without it prec must be
+// FP64 and refine 0.  Writes y (r values), rho and status when the pointers
+// are not NULL.
+template <int F, int DP, bool BRED, bool REF>
+__device__ void cols_solve(const ColsModel& M, const double* params, int prec, int refine, double* lds, int smax,
+                           int lane, double* y_out, double* rho_out, int32_t* status_out) {
+  constexpr int RB = kColsRB;
+  const int r = M.r, s = M.s, r1 = r + 1;
+  double* R = lds;                     // r1 (r1 + 1) / 2 doubles
+  double* a = R + r1 * (r1 + 1) / 2;
+  double* yv = a + RB * 6;
+  double* cv = yv + kMaxR;
+  double* res = cv + kMaxR;
+  (void)smax;
+  const bool col = lane < r || (!BRED && lane == r);
+  double pv[DP];
+  bool finite = true;
+#pragma unroll
+  for (int q = 0; q < DP; ++q) {
+    pv[q] = params[q];
+    finite = finite && isfinite(pv[q]);
+  }
+  for (int idx = lane; idx < r1 * (r1 + 1) / 2; idx += 64) R[idx] = 0.0;
+  wave_sync_lds();
+  double rho2 = 0.0, r00 = 0.0;
+  bool full_rank = true;
+  for (int k0 = 0; k0 < s; k0 += RB) {
+    cols_faces<F, DP>(M, pv, k0, a, lane);
+    double B[RB];
+    cols_block<F>(M, REF ? prec : SUBAP_FP64, k0, a, lane, B);
+    double Bb[BRED ? RB : 1];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const double bk = (k0 + i < s) ? M.bS[k0 + i] : 0.0;
+      if constexpr (BRED) Bb[i] = bk;
+      else if (lane == r) B[i] = bk;
+    }
+    double ss = 0.0;
+#pragma unroll
+    for (int i = 0; i < RB; ++i) ss = fma(B[i], B[i], ss);
+    const bool last = k0 + RB >= s;  // the pivots of the last block are final
+    for (int j = 0; j < r; ++j) {
+      const int rowj = cols_row(j, r1);
+      const double alpha = (col && lane >= j) ? R[rowj + (lane - j)] : 0.0;
+      // reflector of column j from (R[j][j], block column j): lane j's values count
+      double tau = 0.0, scale = 0.0, beta = alpha;
+      if (ss > 0.0) {
+        const double nrm = sqrt(alpha * alpha + ss);
+        beta = (alpha >= 0.0) ? -nrm : nrm;
+        const double d = alpha - beta;
+        tau = -d / beta;
+        scale = 1.0 / d;
+      }
+      if (lane == j) R[rowj] = beta;
+      const double tauj = lane_bcast(tau, j);
+      const double betaj = lane_bcast(beta, j);
+      const double scalej = lane_bcast(scale, j);
+      double vj[RB];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) vj[i] = lane_bcast(B[i], j);
+      if (lane > j && col) {
+        double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+#pragma unroll
+        for (int i = 0; i < RB; i += 4) {
+          w0 = fma(vj[i], B[i], w0);
+          w1 = fma(vj[i + 1], B[i + 1], w1);
+          w2 = fma(vj[i + 2], B[i + 2], w2);
+          w3 = fma(vj[i + 3], B[i + 3], w3);
+        }
+        // w = tau (alpha + v^T B), v = scale * (lane j's column)
+        const double w = tauj * fma(scalej, (w0 + w1) + (w2 + w3), alpha);
+        R[rowj + (lane - j)] = alpha - w;
+        const double ws = w * scalej;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          B[i] = fma(-ws, vj[i], B[i]);
+          if (i % 2 == 0) s0 = fma(B[i], B[i], s0);
+          else s1 = fma(B[i], B[i], s1);
+        }
+        ss = s0 + s1;
+      }
+      if constexpr (BRED) {
+        const double alpha_b = R[rowj + (r - j)];
+        double w0 = 0.0, w1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < RB; i += 2) {
+          w0 = fma(vj[i], Bb[i], w0);
+          w1 = fma(vj[i + 1], Bb[i + 1], w1);
+        }
+        const double wb = tauj * fma(scalej, w0 + w1, alpha_b);
+        wave_sync_lds();  // every lane has read R[j][r] before lane 0 overwrites it
+        if (lane == 0) R[rowj + (r - j)] = alpha_b - wb;
+        const double wsb = wb * scalej;
+#pragma unroll
+        for (int i = 0; i < RB; ++i) Bb[i] = fma(-wsb, vj[i], Bb[i]);
+      }
+      if (last) {
+        const double ab = fabs(betaj);
+        if (j == 0) r00 = ab;
+        if (!(ab > kRankTol * r00)) full_rank = false;
+      }
+    }
+    if constexpr (BRED) {
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < RB; ++i) t = fma(Bb[i], Bb[i], t);
+      rho2 += t;
+    } else {
+      rho2 += lane_bcast(ss, r);
+    }
+    wave_sync_lds();
+  }
+  // y = R^{-1} (Q^T b)[0..r-1]
+  for (int j = lane; j < r; j += 64) yv[j] = R[cols_row(j, r1) + (r - j)];
+  wave_sync_lds();
+  cols_back_solve(R, r1, r, yv);
+  // FP64 refinement: R^T R dy = G^T r_S with the factorised G
+  for (int it = 0; it < (REF ? refine : 0); ++it) {
+    cols_residual<F, DP>(M, pv, yv, res, lane);
+    double g = 0.0;
+    for (int k0 = 0; k0 < s; k0 += RB) {
+      cols_faces<F, DP>(M, pv, k0, a, lane);
+      double B[RB];
+      cols_block<F>(M, prec, k0, a, lane, B);
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        const double rk = (k0 + i < s) ? res[k0 + i] : 0.0;
+        g = fma(B[i], rk, g);
+      }
+      wave_sync_lds();  // the next block's face coefficients overwrite a
+    }
+    if (lane < r) cv[lane] = g;
+    wave_sync_lds();
+    cols_forward_solve(R, r1, r, cv);
+    cols_back_solve(R, r1, r, cv);
+    for (int j = lane; j < r; j += 64) yv[j] -= cv[j];
+    wave_sync_lds();
+  }
+  double rho;
+  if (REF && (refine > 0 || prec != SUBAP_FP64)) {
+    cols_residual<F, DP>(M, pv, yv, res, lane);
+    double t = 0.0;
+    for (int k = lane; k < s; k += 64) t = fma(res[k], res[k], t);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+    rho = sqrt(t);
+  } else {
+    rho = sqrt(rho2);
+  }
+  const double yc = lane < r ? yv[lane] : 0.0;
+  const bool yfin = __all(lane >= r || isfinite(yc));
+  int32_t code = SUBAP_OK;
+  if (!finite) code = SUBAP_E_NONFINITE;
+  else if (!full_rank) code = SUBAP_E_RANK;
+  else if (!yfin) code = SUBAP_E_NONFINITE;
+  if (lane < r) y_out[lane] = (code == SUBAP_OK) ? yc : __longlong_as_double(0x7ff8000000000000LL);
+  if (lane == 0) {
+    if (rho_out) *rho_out = rho / M.bS_norm;
+    if (status_out) *status_out = code;
+  }
+  wave_sync_lds();  // the region is reused by the next item
+}
+
+}  // namespace subap

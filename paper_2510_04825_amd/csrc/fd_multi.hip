@@ -1,11 +1,12 @@
 // Batched online solve over many finite-difference models of uneven size in
-// one persistent launch.  Each block repeatedly takes the next work item (one
-// parameter of one instance) from a global counter, generates its s rows
-// (face coefficients), forms S A(p) Q (eq. (3.4)) in LDS, solves the least
-// squares problem (eq. (3.3)) by Householder QR in LDS, optionally refines in
-// FP64, and writes y.  The LDS formulation handles any s <= 256, r <= 64, so
-// instances of every shape share one kernel; items are ordered largest
-// instance first so the long solves start early.
+// one persistent launch.  Each wavefront repeatedly takes the next work item
+// (one parameter of one instance) from a global counter and solves it with
+// the column-per-lane Householder routine of fd_cols.h (rows generated on the
+// fly, eq. (3.4) contraction in FP64 or FP32, eq. (3.3) least squares,
+// optional FP64 refinement).  Every instance with r <= 64 and s <= 256 shares
+// the kernel; items are ordered largest instance first so the long solves
+// start early, and every wavefront leaves once the counter passes the last
+// item.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -20,6 +21,7 @@
 #include <vector>
 
 #include "common.h"
+#include "fd_cols.h"
 #include "profile.h"
 
 namespace subap {
@@ -27,8 +29,8 @@ namespace subap {
 struct MultiInst {
   int r, s, F, DP;
   const double* phi;
-  const double* delta64;
-  const float* delta32;
+  const double* delta64T;
+  const float* delta32T;
   const double* bS;
   double inv_h2, bS_norm;
   const double* params;
@@ -50,212 +52,46 @@ struct MultiArgs {
   unsigned long long* counter;
   int prec;
   int refine;
-  int lds_r;  // leading dimension of G in LDS (max r + 1)
-  int lds_s;  // rows of G in LDS (max s)
+  int ldsw;  // LDS doubles per wavefront
 };
-
-// block-wide sum; every thread returns the same value (fixed order)
-__device__ double block_sum(double v, double* red) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  const int w = threadIdx.x / 64;
-  __syncthreads();
-  if (threadIdx.x % 64 == 0) red[w] = v;
-  __syncthreads();
-  double t = 0.0;
-  const int nw = blockDim.x / 64;
-  for (int i = 0; i < nw; ++i) t += red[i];
-  return t;
-}
 
 __global__ void k_reset(unsigned long long* c) { *c = 0ull; }
 
-__global__ __launch_bounds__(kMT) void k_fd_multi(MultiArgs A) {
-  extern __shared__ double lds[];
-  const int LD = A.lds_r;
-  double* G = lds;                              // lds_s x LD
-  double* bv = G + A.lds_s * LD;                // lds_s
-  double* b0 = bv + A.lds_s;                    // lds_s
-  double* af = b0 + A.lds_s;                    // lds_s x 6
-  double* tau = af + A.lds_s * 6;               // 64
-  double* yv = tau + kMaxR;                     // 64
-  double* wv = yv + kMaxR;                      // 65
-  double* red = wv + kMaxR + 1;                 // 4
-  long long* item_s = reinterpret_cast<long long*>(red + 4);
-  const int tid = threadIdx.x, nt = blockDim.x;
-
-  while (true) {
-    __syncthreads();
-    if (tid == 0) {
-      const long long it = static_cast<long long>(atomicAdd(A.counter, 1ull));
-      int lo = 0, hi = A.k - 1;  // instance with begin <= it (begins are increasing)
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) / 2;
-        if (A.inst[mid].begin <= it) lo = mid;
-        else hi = mid - 1;
-      }
-      item_s[0] = it;
-      item_s[1] = lo;
-    }
-    __syncthreads();
-    const long long item = item_s[0];
-    if (item >= A.total) return;  // uniform: every wave leaves the loop
-    const MultiInst I = A.inst[item_s[1]];
-    const int64_t p = item - I.begin;
-    const int r = I.r, s = I.s, F = I.F, DP = I.DP;
-    double pv[4] = {0.0, 0.0, 0.0, 0.0};
-    bool finite = true;
-    for (int q = 0; q < DP; ++q) {
-      pv[q] = I.params[p * DP + q];
-      finite = finite && isfinite(pv[q]);
-    }
-    // A1: face coefficients
-    for (int idx = tid; idx < s * F; idx += nt) {
-      const int k = idx / F, f = idx % F;
-      double t = 0.0;
-      for (int q = 0; q < DP; ++q) t += pv[q] * I.phi[(f * DP + q) * s + k];
-      af[k * 6 + f] = exp(t) * I.inv_h2;
-    }
-    __syncthreads();
-    // A2: S A(p) Q into LDS (threads walk k fastest: coalesced table reads)
-    for (int idx = tid; idx < s * r; idx += nt) {
-      const int c = idx / s, k = idx % s;
-      double g;
-      if (A.prec == SUBAP_FP64) {
-        g = 0.0;
-        for (int f = 0; f < F; ++f) g += af[k * 6 + f] * I.delta64[(f * r + c) * s + k];
-      } else {
-        float g32 = 0.0f;
-        for (int f = 0; f < F; ++f)
-          g32 = fmaf(static_cast<float>(af[k * 6 + f]), I.delta32[(f * r + c) * s + k], g32);
-        g = g32;
-      }
-      G[k * LD + c] = g;
-    }
-    for (int k = tid; k < s; k += nt) {
-      b0[k] = I.bS[k];
-      bv[k] = I.bS[k];
-    }
-    __syncthreads();
-    // A3: Householder QR in LDS, applied to bv as well
-    bool full_rank = true;
-    double r00 = 0.0;
-    for (int j = 0; j < r; ++j) {
-      double ss = 0.0;
-      for (int i = j + 1 + tid; i < s; i += nt) ss += G[i * LD + j] * G[i * LD + j];
-      ss = block_sum(ss, red);
-      const double alpha = G[j * LD + j];
-      double tj = 0.0, scale = 0.0, beta = alpha;
-      if (ss > 0.0) {
-        const double norm = sqrt(alpha * alpha + ss);
-        beta = alpha >= 0.0 ? -norm : norm;
-        tj = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-      }
-      __syncthreads();
-      for (int i = j + 1 + tid; i < s; i += nt) G[i * LD + j] *= scale;
-      __syncthreads();
-      // w_c = v^T G[:, c] for c in (j, r) and for b (c == r); 4 lanes per column
-      const int ncol = r - j;  // columns j+1..r-1 plus b
-      for (int cc = tid / 4; cc < ncol; cc += nt / 4) {
-        const int c = j + 1 + cc;  // c == r means b
-        double t = 0.0;
-        for (int i = j + (tid & 3); i < s; i += 4) {
-          const double v = (i == j) ? 1.0 : G[i * LD + j];
-          t += v * (c < r ? G[i * LD + c] : bv[i]);
-        }
-        t += __shfl_xor(t, 1, 64);
-        t += __shfl_xor(t, 2, 64);
-        if ((tid & 3) == 0) wv[cc] = t;
-      }
-      __syncthreads();
-      for (int idx = tid; idx < (s - j) * ncol; idx += nt) {
-        const int i = j + idx / ncol, cc = idx % ncol, c = j + 1 + cc;
-        const double v = (i == j) ? 1.0 : G[i * LD + j];
-        const double d = tj * wv[cc] * v;
-        if (c < r) G[i * LD + c] -= d;
-        else bv[i] -= d;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        G[j * LD + j] = beta;
-        tau[j] = tj;
-      }
-      const double ab = fabs(beta);
-      if (j == 0) r00 = ab;
-      if (!(ab > kRankTol * r00)) full_rank = false;
-    }
-    __syncthreads();
-    double tail = 0.0;
-    {
-      double t = 0.0;
-      for (int i = r + tid; i < s; i += nt) t += bv[i] * bv[i];
-      tail = sqrt(block_sum(t, red));
-    }
-    // back substitution R y = (Q^T b)[0:r], overwriting bv
-    for (int c = r - 1; c >= 0; --c) {
-      const double yc = bv[c] / G[c * LD + c];
-      __syncthreads();
-      for (int i = tid; i < c; i += nt) bv[i] -= G[i * LD + c] * yc;
-      if (tid == 0) yv[c] = yc;
-      __syncthreads();
-    }
-    // A4: FP64 refinement with the same factorisation; residual in bv
-    auto residual = [&]() {
-      for (int k = tid; k < s; k += nt) {
-        double t = 0.0;
-        for (int f = 0; f < F; ++f) {
-          double u = 0.0;
-          for (int c = 0; c < r; ++c) u += I.delta64[(f * r + c) * s + k] * yv[c];
-          t += af[k * 6 + f] * u;
-        }
-        bv[k] = t - b0[k];
-      }
-      __syncthreads();
-    };
-    for (int it = 0; it < A.refine; ++it) {
-      residual();
-      for (int j = 0; j < r; ++j) {
-        double t = 0.0;
-        for (int i = j + tid; i < s; i += nt) t += ((i == j) ? 1.0 : G[i * LD + j]) * bv[i];
-        t = block_sum(t, red) * tau[j];
-        for (int i = j + tid; i < s; i += nt) bv[i] -= t * ((i == j) ? 1.0 : G[i * LD + j]);
-        __syncthreads();
-      }
-      for (int c = r - 1; c >= 0; --c) {
-        const double dc = bv[c] / G[c * LD + c];
-        __syncthreads();
-        for (int i = tid; i < c; i += nt) bv[i] -= G[i * LD + c] * dc;
-        if (tid == 0) yv[c] -= dc;
-        __syncthreads();
-      }
-    }
-    double rho = tail;
-    if (A.refine > 0 || A.prec != SUBAP_FP64) {
-      residual();
-      double t = 0.0;
-      for (int k = tid; k < s; k += nt) t += bv[k] * bv[k];
-      rho = sqrt(block_sum(t, red));
-    }
-    __syncthreads();
-    bool yfin = true;
-    for (int c = 0; c < r; ++c) yfin = yfin && isfinite(yv[c]);
-    int32_t code = SUBAP_OK;
-    if (!finite) code = SUBAP_E_NONFINITE;
-    else if (!full_rank) code = SUBAP_E_RANK;
-    else if (!yfin) code = SUBAP_E_NONFINITE;
-    for (int c = tid; c < r; c += nt)
-      I.y[p * r + c] = code == SUBAP_OK ? yv[c] : __longlong_as_double(0x7ff8000000000000LL);
-    if (tid == 0) {
-      if (I.rho) I.rho[p] = rho / I.bS_norm;
-      if (I.status) I.status[p] = code;
-    }
-  }
+template <int F, int DP, bool REF>
+__device__ __forceinline__ void multi_item(const MultiInst& I, int64_t p, int prec, int refine, double* lds,
+                                           int lane) {
+  const ColsModel M{I.r, I.s, I.phi, I.delta64T, I.delta32T, I.bS, I.inv_h2, I.bS_norm};
+  double* yo = I.y + p * I.r;
+  double* ro = I.rho ? I.rho + p : nullptr;
+  int32_t* so = I.status ? I.status + p : nullptr;
+  if (I.r == 64) cols_solve<F, DP, true, REF>(M, I.params + p * DP, prec, refine, lds, I.s, lane, yo, ro, so);
+  else cols_solve<F, DP, false, REF>(M, I.params + p * DP, prec, refine, lds, I.s, lane, yo, ro, so);
 }
 
-size_t lds_bytes(int max_s, int max_r) {
-  const int LD = max_r + 1;
-  return sizeof(double) * (static_cast<size_t>(max_s) * LD + 2 * max_s + 6 * max_s + kMaxR + kMaxR +
-                           (kMaxR + 1) + 4) + 2 * sizeof(long long);
+// REF: FP32 contraction or refinement steps (uniform over the launch)
+template <bool REF>
+__global__ __launch_bounds__(kMT) void k_fd_multi(MultiArgs A) {
+  extern __shared__ double lds[];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  double* mine = lds + static_cast<int64_t>(wave) * A.ldsw;
+  while (true) {
+    unsigned long long it = 0;
+    if (lane == 0) it = atomicAdd(A.counter, 1ull);
+    it = (static_cast<unsigned long long>(static_cast<unsigned>(__builtin_amdgcn_readfirstlane(static_cast<int>(it >> 32))))
+          << 32) |
+         static_cast<unsigned>(__builtin_amdgcn_readfirstlane(static_cast<int>(it & 0xffffffffull)));
+    if (it >= static_cast<unsigned long long>(A.total)) return;  // uniform per wavefront
+    int lo = 0, hi = A.k - 1;  // instance with begin <= it (begins are increasing)
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (A.inst[mid].begin <= static_cast<int64_t>(it)) lo = mid;
+      else hi = mid - 1;
+    }
+    const MultiInst I = A.inst[lo];
+    const int64_t p = static_cast<int64_t>(it) - I.begin;
+    if (I.F == 4) multi_item<4, 2, REF>(I, p, A.prec, A.refine, mine, lane);
+    else multi_item<6, 4, REF>(I, p, A.prec, A.refine, mine, lane);
+  }
 }
 
 }  // namespace
@@ -278,12 +114,19 @@ struct PlanImpl {
 
 namespace {
 
+size_t plan_lds(const PlanImpl* P, int threads) {
+  return sizeof(double) * static_cast<size_t>(threads / 64) * cols_lds_doubles(P->max_r, P->max_s);
+}
+
 subap_status launch_plan(PlanImpl* P, hipStream_t st) {
   MultiArgs a{P->inst_d, static_cast<int>(P->inst.size()), P->total, P->counter, P->prec, P->refine,
-              P->max_r + 1, P->max_s};
+              cols_lds_doubles(P->max_r, P->max_s)};
   ProfScope prof("fd_multi_persistent", st);
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, st, P->counter);
-  hipLaunchKernelGGL(k_fd_multi, dim3(P->blocks), dim3(P->threads), lds_bytes(P->max_s, P->max_r), st, a);
+  if (P->refine > 0 || P->prec != SUBAP_FP64)
+    hipLaunchKernelGGL(k_fd_multi<true>, dim3(P->blocks), dim3(P->threads), plan_lds(P, P->threads), st, a);
+  else
+    hipLaunchKernelGGL(k_fd_multi<false>, dim3(P->blocks), dim3(P->threads), plan_lds(P, P->threads), st, a);
   SUBAP_HIP_TRY(hipGetLastError());
   return SUBAP_OK;
 }
@@ -345,7 +188,7 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
   int64_t begin = 0;
   for (int oi : order) {
     const subap_model_s* M = models[oi];
-    MultiInst I{M->r, M->s, M->F, M->d, M->phi, M->delta64, M->delta32, M->bS, M->inv_h2, M->bS_norm,
+    MultiInst I{M->r, M->s, M->F, M->d, M->phi, M->delta64T, M->delta32T, M->bS, M->inv_h2, M->bS_norm,
                 params[oi], m[oi], y[oi], rho ? rho[oi] : nullptr, status ? status[oi] : nullptr, begin};
     P->inst.push_back(I);
     begin += m[oi];
@@ -367,16 +210,18 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
     set_error("copying the instance table failed");
     return fail(SUBAP_E_HIP);
   }
-  const size_t lds = lds_bytes(P->max_s, P->max_r);
-  if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_fd_multi), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          static_cast<int>(lds)) != hipSuccess) {
+  const size_t lds_max = plan_lds(P, kMT);
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_fd_multi<true>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_max)) != hipSuccess ||
+      hipFuncSetAttribute(reinterpret_cast<const void*>(k_fd_multi<false>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_max)) != hipSuccess) {
     set_error("cannot reserve LDS for the persistent kernel");
     return fail(SUBAP_E_HIP);
   }
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const int per_cu = std::max(1, static_cast<int>((160 * 1024) / std::max<size_t>(lds, 1)));
+  const int per_cu = std::max(1, static_cast<int>((160 * 1024) / std::max<size_t>(lds_max, 1)));
   P->threads = 256;
   P->blocks = cus * std::min(per_cu, 4);
   const bool tune = flags & SUBAP_PLAN_AUTOTUNE;
@@ -429,9 +274,12 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
     bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
       MultiArgs a{P->inst_d, static_cast<int>(P->inst.size()), P->total, P->counter, P->prec, P->refine,
-                  P->max_r + 1, P->max_s};
+                  cols_lds_doubles(P->max_r, P->max_s)};
       hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, cs, P->counter);
-      hipLaunchKernelGGL(k_fd_multi, dim3(P->blocks), dim3(P->threads), lds, cs, a);
+      if (P->refine > 0 || P->prec != SUBAP_FP64)
+        hipLaunchKernelGGL(k_fd_multi<true>, dim3(P->blocks), dim3(P->threads), plan_lds(P, P->threads), cs, a);
+      else
+        hipLaunchKernelGGL(k_fd_multi<false>, dim3(P->blocks), dim3(P->threads), plan_lds(P, P->threads), cs, a);
       ok = hipStreamEndCapture(cs, &P->graph) == hipSuccess;
     }
     ok = ok && hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0) == hipSuccess;
@@ -464,36 +312,6 @@ void plan_free(PlanImpl* P) {
   dfree(P->inst_d);
   dfree(P->counter);
   delete P;
-}
-
-// Single-model solve through the LDS kernel, for (s, r) shapes the register
-// kernel is not instantiated for.  The one-entry instance table and the work
-// counter are allocated once per model.
-subap_status fd_solve_lds(subap_model_s* M, const double* params, int64_t m, double* y, double* rho,
-                          int32_t* status, int prec, int refine, hipStream_t st) {
-  if (!M->lds_inst) {
-    SUBAP_TRY(dalloc(reinterpret_cast<MultiInst**>(&M->lds_inst), 1));
-    SUBAP_TRY(dalloc(reinterpret_cast<unsigned long long**>(&M->lds_counter), 1));
-  }
-  MultiInst I{M->r, M->s, M->F, M->d, M->phi, M->delta64, M->delta32, M->bS, M->inv_h2, M->bS_norm,
-              params, m, y, rho, status, 0};
-  // pageable source: the copy is staged before hipMemcpyAsync returns
-  SUBAP_HIP_TRY(hipMemcpyAsync(M->lds_inst, &I, sizeof(I), hipMemcpyHostToDevice, st));
-  const size_t lds = lds_bytes(M->s, M->r);
-  SUBAP_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(k_fd_multi),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-  int dev = 0, cus = 256;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const int per_cu = std::max(1, std::min(4, static_cast<int>((160 * 1024) / lds)));
-  const int64_t blocks = std::min<int64_t>(m, static_cast<int64_t>(cus) * per_cu);
-  MultiArgs a{static_cast<const MultiInst*>(M->lds_inst), 1, m,
-              static_cast<unsigned long long*>(M->lds_counter), prec, refine, M->r + 1, M->s};
-  ProfScope prof("fd_solve_lds", st);
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, st, static_cast<unsigned long long*>(M->lds_counter));
-  hipLaunchKernelGGL(k_fd_multi, dim3(static_cast<unsigned>(blocks)), dim3(256), lds, st, a);
-  SUBAP_HIP_TRY(hipGetLastError());
-  return SUBAP_OK;
 }
 
 void plan_shape(const PlanImpl* P, int* threads, int* blocks) {

@@ -569,7 +569,7 @@ subap_status select_rows_gpu(const double* W0, int64_t n, int r, int s, int64_t*
 // ----------------------------------------------------------------------------
 __global__ void k_fd_tables(const double* Qm, int64_t n, int r, int s, int N, int dimx, int d, double h,
                             const int* rows, const double* rhs, double* phi, double* delta64,
-                            float* delta32, double* delta64T, double* bS, double* QS) {
+                            float* delta32, double* delta64T, float* delta32T, double* bS, double* QS) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= s) return;
   const int64_t i = rows[k];
@@ -598,6 +598,7 @@ __global__ void k_fd_tables(const double* Qm, int64_t n, int r, int s, int N, in
       delta64[(static_cast<int64_t>(f) * r + cc) * s + k] = dv;
       delta32[(static_cast<int64_t>(f) * r + cc) * s + k] = static_cast<float>(dv);
       delta64T[(static_cast<int64_t>(f) * s + k) * r + cc] = dv;
+      delta32T[(static_cast<int64_t>(f) * s + k) * r + cc] = static_cast<float>(dv);
     }
   }
   bS[k] = rhs[i];
@@ -727,8 +728,9 @@ subap_status build_tables(subap_model_s* M, hipStream_t st) {
     SUBAP_TRY(dalloc(&M->delta64, tab * r));
     SUBAP_TRY(dalloc(&M->delta32, tab * r));
     SUBAP_TRY(dalloc(&M->delta64T, tab * r));
+    SUBAP_TRY(dalloc(&M->delta32T, tab * r));
     hipLaunchKernelGGL(k_fd_tables, dim3((s + 63) / 64), dim3(64), 0, st, M->Q, n, r, s, M->N, M->dimx, M->d, M->h,
-                       M->rows_d, M->rhs, M->phi, M->delta64, M->delta32, M->delta64T, M->bS, M->QS);
+                       M->rows_d, M->rhs, M->phi, M->delta64, M->delta32, M->delta64T, M->delta32T, M->bS, M->QS);
   }
   SUBAP_HIP_TRY(hipGetLastError());
   std::vector<double> hb(s);

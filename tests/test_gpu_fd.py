@@ -177,6 +177,43 @@ def test_fd_tall_fp64_shapes(dim, N, r, s, m):
         M.free()
 
 
+@pytest.mark.parametrize("dim,N,r,s,m", [(2, 40, 64, 128, 9), (2, 32, 32, 100, 11), (3, 16, 40, 160, 7),
+                                         (2, 40, 64, 70, 5)])
+def test_fd_column_kernel_forms(dim, N, r, s, m):
+    """Column-per-lane kernel in every form: r = 64 (S b carried by every
+    lane), FP32 contraction with one and two FP64 refinement steps
+    (corrections from R^T R dy = G^T r_S), and a shape the register team
+    kernel has no instantiation for (r = 64, s = 70)."""
+    w = si.diffusion2d(N=N, r=r, s=s, m=m) if dim == 2 else si.diffusion3d(N=N, r=r, s=s, m=m)
+    off = O.offline(w)
+    fam, Q, rows = off["family"], off["Q"], off["rows"]
+    header(f"column kernel forms dim={dim} N={N} r={r} s={s} m={m}")
+    M = B.Model(w, basis=Q, rows=rows)
+    try:
+        P = w["test_params"]
+        Yo = On.solve(fam, Q, rows, P)
+        y64, rho64, st = M.solve(to_dev(P))
+        assert np.all(st.cpu().numpy() == B.OK)
+        assert _dres(fam, Q, P, y64.cpu().numpy(), Yo).max() <= 1e-12
+        ro = np.array([On.sketched_residual(fam, Q, rows, p, yo) for p, yo in zip(P, Yo)])
+        assert np.allclose(rho64.cpu().numpy(), ro, rtol=1e-6, atol=1e-10)
+        y0, _, _ = M.solve(to_dev(P), contraction=B.FP32, refine_steps=0)
+        y1, rho1, st1 = M.solve(to_dev(P), contraction=B.FP32, refine_steps=1)
+        y2, _, st2 = M.solve(to_dev(P), contraction=B.FP32, refine_steps=2)
+        assert np.all(st1.cpu().numpy() == B.OK) and np.all(st2.cpu().numpy() == B.OK)
+        d0 = _dres(fam, Q, P, y0.cpu().numpy(), Yo)
+        d1 = _dres(fam, Q, P, y1.cpu().numpy(), Yo)
+        d2 = _dres(fam, Q, P, y2.cpu().numpy(), Yo)
+        print(f"fp32: before {d0.max():.2e}, 1 step {d1.max():.2e}, 2 steps {d2.max():.2e}")
+        assert d1.max() <= 1e-6 and d1.max() < d0.max()
+        assert d2.max() <= max(d1.max(), 1e-12)
+        # rho after refinement is the FP64 sketched residual of the refined y
+        rg = np.array([On.sketched_residual(fam, Q, rows, p, yg) for p, yg in zip(P, y1.cpu().numpy())])
+        assert np.allclose(rho1.cpu().numpy(), rg, rtol=1e-9, atol=1e-13)
+    finally:
+        M.free()
+
+
 def test_rank_deficient_tall_problem():
     # unit-vector basis at nodes 13 or more grid lines away from the 96 selected
     # rows (the first three lines): S A(p) Q = 0
