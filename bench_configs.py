@@ -230,3 +230,35 @@ def surrogate(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
         "train": {"pairs_generation_s": gen_s, "train_s": train_s, "loss_first": float(losses[0]),
                   "loss_last": float(losses[-1])},
     }
+
+
+def lift(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
+    """FP32 lift of 1024 coefficient vectors on a 3-D basis (N^3 nodes, r = 40, seeded
+    basis; the lift does not depend on how the basis was made), for the leading
+    dimensions n, n rounded up to 4 and n rounded up to 32."""
+    import numpy as np
+    N = args.grid
+    w = si.diffusion3d(N=N, r=40, s=160, m=16)
+    n, r = w["n"], w["r"]
+    rng = np.random.default_rng(3)
+    M = B.Model(w, basis=rng.standard_normal((n, r)))
+    k = 1024
+    Y = torch.tensor(rng.standard_normal((k, r)), dtype=torch.float64, device=dev)
+    byt = 8.0 * n * r + 4.0 * n * k + 8.0 * k * r
+    out = {}
+    for tag, ld in (("ld_n", n), ("ld_round4", (n + 3) // 4 * 4), ("ld_round32", (n + 31) // 32 * 32)):
+        x = torch.empty((k, ld), dtype=torch.float32, device=dev)
+        B.subap_lift(M.handle, Y, x, B.FP32, stream)
+        t = timed(lambda: B.subap_lift(M.handle, Y, x, B.FP32, stream), args.steps, stream)
+        out[tag] = {"ldx": ld, "ms": t, "GB_per_s": byt / (t * 1e-3) / 1e9,
+                    "frac_hbm": byt / (t * 1e-3) / 1e9 / PEAKS["hbm_gbs"]}
+        del x
+    M.free()
+    best = min(out.values(), key=lambda v: v["ms"])
+    return {"metric": "FP32 lift bandwidth (x = Q y, 1024 vectors)", "value": best["GB_per_s"], "unit": "GB/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": best["ms"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16x6 mfma, f32 out", "data": "synthetic",
+            "config": {"workload": f"lift_diffusion3d_n{N}^3_r{r}_k{k}", "n": n, "bytes": byt},
+            "forms": out,
+            "roofline": {"bound": "hbm", "kernel": "lift", "achieved": best["GB_per_s"], "peak": PEAKS["hbm_gbs"],
+                         "unit": "GB/s", "frac": best["frac_hbm"], "traffic": None}}
