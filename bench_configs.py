@@ -21,6 +21,30 @@ import time
 import numpy as np
 
 
+def _oracle_rate(jobs, budget_s, sample_text):
+    """The FP64 oracle's online solve timed on this host: jobs = [(family, Q, rows, params)],
+    solved in turn, parameter chunks growing until about budget_s seconds are spent."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import online as On
+    done, spent = 0, 0.0
+    for fam, Q, rows, P in jobs:
+        On.solve(fam, Q, rows, P[:1])  # warm caches
+        i, chunk = 0, 4
+        while i < len(P) and spent < budget_s:
+            t0 = time.perf_counter()
+            On.solve(fam, Q, rows, P[i:i + chunk])
+            spent += time.perf_counter() - t0
+            done += len(P[i:i + chunk])
+            i += chunk
+            chunk *= 2
+        if spent >= budget_s:
+            break
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    return {"value": done / spent, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{done} parameters: {sample_text}", "seconds": spent}
+
+
 def _validity(B, M, P, y, y64, st, tol):
     import torch
     res64, nrm64 = M.sketched_residual(P, y64, vector=True)
@@ -91,8 +115,14 @@ def diffusion3d(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
     kms = forms["fp64_batched"]["kernels_ms"].get("fd_solve", forms["fp64_batched"]["ms_per_batch"])
     best = max(("fp64_batched", "fp32_refine1"), key=lambda f: forms[f]["valid"] / forms[f]["ms_per_batch"])
     ms = forms[best]["ms_per_batch"]
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import families as F
+        cpu = _oracle_rate([(F.from_workload(w), M.basis(), M.rows(), w["test_params"])], 0.5 * args.cpu_seconds,
+                           "FP64 NumPy/SciPy rows, S A(p) Q and Householder least squares per parameter on the "
+                           "full 215^3 model (the GPU's basis and rows passed in)")
     M.free()
-    return {
+    out = {
         "metric": "online solves/s at rel. residual <=1e-6: batched/learned vs plain, 1 MI355X",
         "value": forms[best]["valid"] / (ms / 1e3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": 1, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -105,6 +135,9 @@ def diffusion3d(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
         "lift": lift,
         "offline_s": offline_s,
     }
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    return out
 
 
 def uneven(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
@@ -148,9 +181,17 @@ def uneven(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
     plain_rate = sum(min(k_each, w["m"]) for w in insts) / (tp / 1e3)
     flops = sum(w["m"] * (2.0 * w["s"] * w["r"] ** 2 - 2.0 / 3.0 * w["r"] ** 3) for w in insts)
     B.subap_plan_free(plan)
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import families as F
+        small = sorted(range(len(insts)), key=lambda i: insts[i]["n"] * insts[i]["r"])[:16]
+        cpu = _oracle_rate([(F.from_workload(insts[i]), models[i].basis(), models[i].rows(), insts[i]["test_params"])
+                            for i in small], 0.5 * args.cpu_seconds,
+                           "FP64 oracle solves of the 16 smallest instances in turn (the GPU's bases and rows "
+                           "passed in)")
     for M in models:
         M.free()
-    return {
+    out = {
         "metric": "online solves/s at rel. residual <=1e-6: batched/learned vs plain, 1 MI355X",
         "value": valid / (t_plan / 1e3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
         "ms_per_step": t_plan, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -168,6 +209,9 @@ def uneven(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
                      "traffic": None},
         "offline_s": offline_s, "plan_create_s": plan_s,
     }
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    return out
 
 
 def surrogate(args, B, si, torch, dev, stream, timed, PEAKS, TOL):

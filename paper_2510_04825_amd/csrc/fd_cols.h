@@ -22,7 +22,7 @@
 // with the G that was factorised (recomputed in the same arithmetic), which
 // equals R^{-1} Q^T r_S.
 //
-// The caller gives each wavefront cols_lds_doubles(rmax, smax) doubles of LDS.
+// The caller gives each wavefront cols_lds_doubles(rmax, smax, REF) doubles of LDS.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -42,11 +42,11 @@ struct ColsModel {
   double inv_h2, bS_norm;
 };
 
-__host__ __device__ inline int cols_lds_doubles(int rmax, int smax) {
-  return (rmax + 1) * (rmax + 2) / 2  // packed [R | Q^T b]
-         + kColsRB * 6                // face coefficients of a block
-         + 2 * kMaxR                  // y, and the correction
-         + smax;                      // residual vector
+__host__ __device__ inline int cols_lds_doubles(int rmax, int smax, bool ref) {
+  return (rmax + 1) * (rmax + 2) / 2         // packed [R | Q^T b]
+         + kColsRB * 6                       // face coefficients of a block
+         + kMaxR                             // y
+         + (ref ? kMaxR + smax : 0);         // correction and residual vector (refinement)
 }
 
 // start of packed row j (columns j..r1-1) for r1 = r + 1 columns

@@ -115,12 +115,12 @@ struct PlanImpl {
 namespace {
 
 size_t plan_lds(const PlanImpl* P, int threads) {
-  return sizeof(double) * static_cast<size_t>(threads / 64) * cols_lds_doubles(P->max_r, P->max_s);
+  return sizeof(double) * static_cast<size_t>(threads / 64) * cols_lds_doubles(P->max_r, P->max_s, P->refine > 0 || P->prec != SUBAP_FP64);
 }
 
 subap_status launch_plan(PlanImpl* P, hipStream_t st) {
   MultiArgs a{P->inst_d, static_cast<int>(P->inst.size()), P->total, P->counter, P->prec, P->refine,
-              cols_lds_doubles(P->max_r, P->max_s)};
+              cols_lds_doubles(P->max_r, P->max_s, P->refine > 0 || P->prec != SUBAP_FP64)};
   ProfScope prof("fd_multi_persistent", st);
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, st, P->counter);
   if (P->refine > 0 || P->prec != SUBAP_FP64)
@@ -274,7 +274,7 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
     bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
       MultiArgs a{P->inst_d, static_cast<int>(P->inst.size()), P->total, P->counter, P->prec, P->refine,
-                  cols_lds_doubles(P->max_r, P->max_s)};
+                  cols_lds_doubles(P->max_r, P->max_s, P->refine > 0 || P->prec != SUBAP_FP64)};
       hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, cs, P->counter);
       if (P->refine > 0 || P->prec != SUBAP_FP64)
         hipLaunchKernelGGL(k_fd_multi<true>, dim3(P->blocks), dim3(P->threads), plan_lds(P, P->threads), cs, a);

@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256) void k_fd_solve(FDArgs A) {
 
 // Column-per-lane solve (fd_cols.h): one wavefront per parameter, two per block.
 template <int F, int DP, bool BRED, bool REF>
-__global__ __launch_bounds__(128) void k_fd_cols(FDArgs A, int ldsw) {
+__global__ __launch_bounds__(128, REF ? 1 : 4) void k_fd_cols(FDArgs A, int ldsw) {
   extern __shared__ double lds_cols[];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int64_t p = static_cast<int64_t>(blockIdx.x) * 2 + wave;
@@ -239,11 +239,11 @@ subap_status launch_cols(const FDArgs& a, hipStream_t st) {
     set_error("batch too large");
     return SUBAP_E_INVALID;
   }
-  const int ldsw = cols_lds_doubles(a.r, a.s);
+  const bool ref = a.refine > 0 || a.prec != SUBAP_FP64;
+  const int ldsw = cols_lds_doubles(a.r, a.s, ref);
   const size_t lds = sizeof(double) * 2 * static_cast<size_t>(ldsw);
   ProfScope prof("fd_solve", st);
   const dim3 grid(static_cast<unsigned>(nb)), block(128);
-  const bool ref = a.refine > 0 || a.prec != SUBAP_FP64;
   if (a.r == 64) {
     if (ref) hipLaunchKernelGGL((k_fd_cols<F, DP, true, true>), grid, block, lds, st, a, ldsw);
     else hipLaunchKernelGGL((k_fd_cols<F, DP, true, false>), grid, block, lds, st, a, ldsw);
