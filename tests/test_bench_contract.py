@@ -1,0 +1,21 @@
+"""Host-side checks of the benchmark's command-line contract (no GPU needed)."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode == 2
+    assert "single-GPU" in res.stderr
+
+
+def test_help_lists_the_workloads():
+    res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"],
+                         capture_output=True, text=True, timeout=120)
+    assert res.returncode == 0
+    for wl in ("krr", "diffusion3d", "uneven", "surrogate", "lift"):
+        assert wl in res.stdout

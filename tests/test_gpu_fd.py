@@ -305,7 +305,14 @@ def test_lift_3d_many_vectors(k, pad):
         xh = x.cpu().numpy()
         assert np.all(xh[:, n:] == 7.5)
         Qg = M.basis()
-        _check_lift32(xh[:, :n], (Qg @ Y.T).T, Qg, Y)
+        ref = (Qg @ Y.T).T
+        _check_lift32(xh[:, :n], ref, Qg, Y)
+        # FP64 lift with the same leading dimension
+        x64 = torch.full((k, ld), -2.5, dtype=torch.float64, device=dev)
+        B.subap_lift(M.handle, to_dev(Y), x64, B.FP64)
+        x64h = x64.cpu().numpy()
+        assert np.all(x64h[:, n:] == -2.5)
+        assert np.abs(x64h[:, :n] - ref).max() <= 1e-14 * np.abs(ref).max()
     finally:
         M.free()
 
