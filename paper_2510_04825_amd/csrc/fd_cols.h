@@ -200,19 +200,20 @@ __device__ void cols_solve(const ColsModel& M, const double* params, int prec, i
     for (int j = 0; j < r; ++j) {
       const int rowj = cols_row(j, r1);
       const double alpha = (col && lane >= j) ? R[rowj + (lane - j)] : 0.0;
-      // reflector of column j from (R[j][j], block column j): lane j's values count
-      double tau = 0.0, scale = 0.0, beta = alpha;
+      // reflector of column j from (R[j][j], block column j): lane j's values
+      // count.  u = [alpha - beta; block column]; H = I - 2 u u^T / u^T u with
+      // u^T u = -2 beta (alpha - beta), so one division gives the coefficient.
+      double dd = 0.0, coef = 0.0, beta = alpha;
       if (ss > 0.0) {
         const double nrm = sqrt(alpha * alpha + ss);
         beta = (alpha >= 0.0) ? -nrm : nrm;
-        const double d = alpha - beta;
-        tau = -d / beta;
-        scale = 1.0 / d;
+        dd = alpha - beta;
+        coef = -1.0 / (beta * dd);
       }
       if (lane == j) R[rowj] = beta;
-      const double tauj = lane_bcast(tau, j);
+      const double dj = lane_bcast(dd, j);
+      const double cj = lane_bcast(coef, j);
       const double betaj = lane_bcast(beta, j);
-      const double scalej = lane_bcast(scale, j);
       double vj[RB];
 #pragma unroll
       for (int i = 0; i < RB; ++i) vj[i] = lane_bcast(B[i], j);
@@ -225,14 +226,13 @@ __device__ void cols_solve(const ColsModel& M, const double* params, int prec, i
           w2 = fma(vj[i + 2], B[i + 2], w2);
           w3 = fma(vj[i + 3], B[i + 3], w3);
         }
-        // w = tau (alpha + v^T B), v = scale * (lane j's column)
-        const double w = tauj * fma(scalej, (w0 + w1) + (w2 + w3), alpha);
-        R[rowj + (lane - j)] = alpha - w;
-        const double ws = w * scalej;
+        // t = coef u^T x for this column: x <- x - t u
+        const double t = cj * fma(dj, alpha, (w0 + w1) + (w2 + w3));
+        R[rowj + (lane - j)] = fma(-t, dj, alpha);
         double s0 = 0.0, s1 = 0.0;
 #pragma unroll
         for (int i = 0; i < RB; ++i) {
-          B[i] = fma(-ws, vj[i], B[i]);
+          B[i] = fma(-t, vj[i], B[i]);
           if (i % 2 == 0) s0 = fma(B[i], B[i], s0);
           else s1 = fma(B[i], B[i], s1);
         }
@@ -246,12 +246,11 @@ __device__ void cols_solve(const ColsModel& M, const double* params, int prec, i
           w0 = fma(vj[i], Bb[i], w0);
           w1 = fma(vj[i + 1], Bb[i + 1], w1);
         }
-        const double wb = tauj * fma(scalej, w0 + w1, alpha_b);
+        const double tb = cj * fma(dj, alpha_b, w0 + w1);
         wave_sync_lds();  // every lane has read R[j][r] before lane 0 overwrites it
-        if (lane == 0) R[rowj + (r - j)] = alpha_b - wb;
-        const double wsb = wb * scalej;
+        if (lane == 0) R[rowj + (r - j)] = fma(-tb, dj, alpha_b);
 #pragma unroll
-        for (int i = 0; i < RB; ++i) Bb[i] = fma(-wsb, vj[i], Bb[i]);
+        for (int i = 0; i < RB; ++i) Bb[i] = fma(-tb, vj[i], Bb[i]);
       }
       if (last) {
         const double ab = fabs(betaj);
