@@ -46,7 +46,7 @@ __host__ __device__ inline int cols_lds_doubles(int rmax, int smax, bool ref) {
   return (rmax + 1) * (rmax + 2) / 2         // packed [R | Q^T b]
          + kColsRB * 6                       // face coefficients of a block
          + kMaxR                             // y
-         + (ref ? kMaxR + smax : 0);         // correction and residual vector (refinement)
+         + (ref ? kMaxR : 0);                // correction, or 64 residual rows (refinement)
 }
 
 // start of packed row j (columns j..r1-1) for r1 = r + 1 columns
@@ -103,31 +103,29 @@ __device__ __forceinline__ void cols_block(const ColsModel& M, int prec, int k0,
   }
 }
 
-// FP64 residual r_k = (S A(p) Q y - b)_k for all k < s (lanes over rows); y in LDS
+// FP64 residual r_k = (S A(p) Q y - b)_k of row k (0 for k >= s); y in LDS.
+// The rows are taken 64 at a time, one per lane.
 template <int F, int DP>
-__device__ __forceinline__ void cols_residual(const ColsModel& M, const double* pv, const double* y, double* res,
-                                              int lane) {
+__device__ __forceinline__ double cols_residual_row(const ColsModel& M, const double* pv, const double* y, int k) {
   const int r = M.r, s = M.s;
-  for (int k = lane; k < s; k += 64) {
-    double t = 0.0;
+  if (k >= s) return 0.0;
+  double t = 0.0;
 #pragma unroll
-    for (int f = 0; f < F; ++f) {
-      double arg = 0.0;
+  for (int f = 0; f < F; ++f) {
+    double arg = 0.0;
 #pragma unroll
-      for (int q = 0; q < DP; ++q) arg += pv[q] * M.phi[(f * DP + q) * s + k];
-      const double* d = M.d64T + (static_cast<int64_t>(f) * s + k) * r;
-      double u0 = 0.0, u1 = 0.0;
-      int c = 0;
-      for (; c + 1 < r; c += 2) {
-        u0 = fma(d[c], y[c], u0);
-        u1 = fma(d[c + 1], y[c + 1], u1);
-      }
-      if (c < r) u0 = fma(d[c], y[c], u0);
-      t = fma(exp(arg) * M.inv_h2, u0 + u1, t);
+    for (int q = 0; q < DP; ++q) arg += pv[q] * M.phi[(f * DP + q) * s + k];
+    const double* d = M.d64T + (static_cast<int64_t>(f) * s + k) * r;
+    double u0 = 0.0, u1 = 0.0;
+    int c = 0;
+    for (; c + 1 < r; c += 2) {
+      u0 = fma(d[c], y[c], u0);
+      u1 = fma(d[c + 1], y[c + 1], u1);
     }
-    res[k] = t - M.bS[k];
+    if (c < r) u0 = fma(d[c], y[c], u0);
+    t = fma(exp(arg) * M.inv_h2, u0 + u1, t);
   }
-  wave_sync_lds();
+  return t - M.bS[k];
 }
 
 // y <- R^{-1} v in place (v in LDS, every lane computes the same values)
@@ -167,8 +165,8 @@ __device__ void cols_solve(const ColsModel& M, const double* params, int prec, i
   double* R = lds;                     // r1 (r1 + 1) / 2 doubles
   double* a = R + r1 * (r1 + 1) / 2;
   double* yv = a + RB * 6;
-  double* cv = yv + kMaxR;
-  double* res = cv + kMaxR;
+  double* cv = yv + kMaxR;  // refinement: 64 residual rows, then the correction
+  double* res = cv;
   (void)smax;
   const bool col = lane < r || (!BRED && lane == r);
   double pv[DP];
@@ -274,15 +272,19 @@ __device__ void cols_solve(const ColsModel& M, const double* params, int prec, i
   cols_back_solve(R, r1, r, yv);
   // FP64 refinement: R^T R dy = G^T r_S with the factorised G
   for (int it = 0; it < (REF ? refine : 0); ++it) {
-    cols_residual<F, DP>(M, pv, yv, res, lane);
     double g = 0.0;
     for (int k0 = 0; k0 < s; k0 += RB) {
+      if (k0 % 64 == 0) {  // the next 64 residual rows (the previous ones are read)
+        const double v = cols_residual_row<F, DP>(M, pv, yv, k0 + lane);
+        res[lane] = v;
+        wave_sync_lds();
+      }
       cols_faces<F, DP>(M, pv, k0, a, lane);
       double B[RB];
       cols_block<F>(M, prec, k0, a, lane, B);
 #pragma unroll
       for (int i = 0; i < RB; ++i) {
-        const double rk = (k0 + i < s) ? res[k0 + i] : 0.0;
+        const double rk = res[k0 % 64 + i];  // 0 beyond s
         g = fma(B[i], rk, g);
       }
       wave_sync_lds();  // the next block's face coefficients overwrite a
@@ -296,9 +298,11 @@ __device__ void cols_solve(const ColsModel& M, const double* params, int prec, i
   }
   double rho;
   if (REF && (refine > 0 || prec != SUBAP_FP64)) {
-    cols_residual<F, DP>(M, pv, yv, res, lane);
     double t = 0.0;
-    for (int k = lane; k < s; k += 64) t = fma(res[k], res[k], t);
+    for (int k0 = 0; k0 < s; k0 += 64) {
+      const double v = cols_residual_row<F, DP>(M, pv, yv, k0 + lane);
+      t = fma(v, v, t);
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
     rho = sqrt(t);

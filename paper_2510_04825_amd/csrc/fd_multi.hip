@@ -6,7 +6,9 @@
 // optional FP64 refinement).  Every instance with r <= 64 and s <= 256 shares
 // the kernel; items are ordered largest instance first so the long solves
 // start early, and every wavefront leaves once the counter passes the last
-// item.
+// item.  The kernel is built for two waves per SIMD and instantiated per set
+// of model dimensions (2-D, 3-D, both), so a plan of one kind carries one
+// solver.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,7 +45,8 @@ struct MultiInst {
 
 namespace {
 
-constexpr int kMT = 256;  // threads per block (upper bound; launch may use 128)
+constexpr int kMT = 256;        // threads per block (upper bound; launch may use 64 or 128)
+constexpr int kWavesPerCU = 8;  // the kernel is built for two waves per SIMD
 
 struct MultiArgs {
   const MultiInst* inst;
@@ -68,9 +71,11 @@ __device__ __forceinline__ void multi_item(const MultiInst& I, int64_t p, int pr
   else cols_solve<F, DP, false, REF>(M, I.params + p * DP, prec, refine, lds, I.s, lane, yo, ro, so);
 }
 
-// REF: FP32 contraction or refinement steps (uniform over the launch)
-template <bool REF>
-__global__ __launch_bounds__(kMT) void k_fd_multi(MultiArgs A) {
+// REF: FP32 contraction or refinement steps (uniform over the launch).
+// DIMS: bit 0 = the plan holds 2-D models, bit 1 = 3-D models; a kernel that
+// serves one kind only carries one solver and needs fewer registers.
+template <bool REF, int DIMS>
+__global__ __launch_bounds__(kMT, 2) void k_fd_multi(MultiArgs A) {
   extern __shared__ double lds[];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   double* mine = lds + static_cast<int64_t>(wave) * A.ldsw;
@@ -89,7 +94,9 @@ __global__ __launch_bounds__(kMT) void k_fd_multi(MultiArgs A) {
     }
     const MultiInst I = A.inst[lo];
     const int64_t p = static_cast<int64_t>(it) - I.begin;
-    if (I.F == 4) multi_item<4, 2, REF>(I, p, A.prec, A.refine, mine, lane);
+    if constexpr (DIMS == 1) multi_item<4, 2, REF>(I, p, A.prec, A.refine, mine, lane);
+    else if constexpr (DIMS == 2) multi_item<6, 4, REF>(I, p, A.prec, A.refine, mine, lane);
+    else if (I.F == 4) multi_item<4, 2, REF>(I, p, A.prec, A.refine, mine, lane);
     else multi_item<6, 4, REF>(I, p, A.prec, A.refine, mine, lane);
   }
 }
@@ -106,6 +113,7 @@ struct PlanImpl {
   int64_t total = 0;
   int max_s = 0, max_r = 0;
   int prec = 0, refine = 0;
+  int dims = 0;  // bit 0: some model is 2-D, bit 1: some model is 3-D
   int threads = 256, blocks = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -114,19 +122,35 @@ struct PlanImpl {
 
 namespace {
 
+bool plan_ref(const PlanImpl* P);
+
 size_t plan_lds(const PlanImpl* P, int threads) {
-  return sizeof(double) * static_cast<size_t>(threads / 64) * cols_lds_doubles(P->max_r, P->max_s, P->refine > 0 || P->prec != SUBAP_FP64);
+  return sizeof(double) * static_cast<size_t>(threads / 64) * cols_lds_doubles(P->max_r, P->max_s, plan_ref(P));
+}
+
+bool plan_ref(const PlanImpl* P) { return P->refine > 0 || P->prec != SUBAP_FP64; }
+
+using MultiKernel = void (*)(MultiArgs);
+
+MultiKernel plan_kernel(bool ref, int dims) {
+  static const MultiKernel tab[2][3] = {
+      {k_fd_multi<false, 1>, k_fd_multi<false, 2>, k_fd_multi<false, 3>},
+      {k_fd_multi<true, 1>, k_fd_multi<true, 2>, k_fd_multi<true, 3>}};
+  return tab[ref ? 1 : 0][dims - 1];
+}
+
+// counter reset + the persistent kernel, on st (also used under capture)
+void enqueue_plan(const PlanImpl* P, hipStream_t st) {
+  MultiArgs a{P->inst_d, static_cast<int>(P->inst.size()), P->total, P->counter, P->prec, P->refine,
+              cols_lds_doubles(P->max_r, P->max_s, plan_ref(P))};
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, st, P->counter);
+  hipLaunchKernelGGL(plan_kernel(plan_ref(P), P->dims), dim3(P->blocks), dim3(P->threads),
+                     plan_lds(P, P->threads), st, a);
 }
 
 subap_status launch_plan(PlanImpl* P, hipStream_t st) {
-  MultiArgs a{P->inst_d, static_cast<int>(P->inst.size()), P->total, P->counter, P->prec, P->refine,
-              cols_lds_doubles(P->max_r, P->max_s, P->refine > 0 || P->prec != SUBAP_FP64)};
   ProfScope prof("fd_multi_persistent", st);
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, st, P->counter);
-  if (P->refine > 0 || P->prec != SUBAP_FP64)
-    hipLaunchKernelGGL(k_fd_multi<true>, dim3(P->blocks), dim3(P->threads), plan_lds(P, P->threads), st, a);
-  else
-    hipLaunchKernelGGL(k_fd_multi<false>, dim3(P->blocks), dim3(P->threads), plan_lds(P, P->threads), st, a);
+  enqueue_plan(P, st);
   SUBAP_HIP_TRY(hipGetLastError());
   return SUBAP_OK;
 }
@@ -194,7 +218,8 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
     begin += m[oi];
     P->max_s = std::max(P->max_s, M->s);
     P->max_r = std::max(P->max_r, M->r);
-    key << '/' << M->s << 'x' << M->r << 'x' << m[oi];
+    P->dims |= M->F == 4 ? 1 : 2;
+    key << '/' << (M->F == 4 ? 2 : 3) << 'd' << M->s << 'x' << M->r << 'x' << m[oi];
   }
   P->total = begin;
   P->prec = prec;
@@ -211,9 +236,7 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
     return fail(SUBAP_E_HIP);
   }
   const size_t lds_max = plan_lds(P, kMT);
-  if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_fd_multi<true>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_max)) != hipSuccess ||
-      hipFuncSetAttribute(reinterpret_cast<const void*>(k_fd_multi<false>),
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(plan_kernel(plan_ref(P), P->dims)),
                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_max)) != hipSuccess) {
     set_error("cannot reserve LDS for the persistent kernel");
     return fail(SUBAP_E_HIP);
@@ -221,9 +244,13 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const int per_cu = std::max(1, static_cast<int>((160 * 1024) / std::max<size_t>(lds_max, 1)));
-  P->threads = 256;
-  P->blocks = cus * std::min(per_cu, 4);
+  // blocks of th threads that fit one CU: LDS (160 KiB) and two waves per SIMD
+  auto per_cu = [&](int th) {
+    const int by_lds = static_cast<int>((160 * 1024) / std::max<size_t>(plan_lds(P, th), 1));
+    return std::max(1, std::min(by_lds, kWavesPerCU / (th / 64)));
+  };
+  P->threads = 128;
+  P->blocks = cus * per_cu(128);
   const bool tune = flags & SUBAP_PLAN_AUTOTUNE;
   int t_c, b_c;
   if (cache_lookup(P->key, &t_c, &b_c)) {
@@ -236,9 +263,8 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
     (void)hipEventCreate(&e1);
     float best = 1e30f;
     int bt = P->threads, bb = P->blocks;
-    for (int th : {128, 256}) {
-      for (int mult : {1, 2, 4, 8}) {
-        if (mult > per_cu * 2) continue;
+    for (int th : {64, 128, 256}) {
+      for (int mult = 1; mult <= per_cu(th); ++mult) {
         P->threads = th;
         P->blocks = cus * mult;
         float tot = 0.0f;
@@ -273,13 +299,7 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
     }
     bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
-      MultiArgs a{P->inst_d, static_cast<int>(P->inst.size()), P->total, P->counter, P->prec, P->refine,
-                  cols_lds_doubles(P->max_r, P->max_s, P->refine > 0 || P->prec != SUBAP_FP64)};
-      hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, cs, P->counter);
-      if (P->refine > 0 || P->prec != SUBAP_FP64)
-        hipLaunchKernelGGL(k_fd_multi<true>, dim3(P->blocks), dim3(P->threads), plan_lds(P, P->threads), cs, a);
-      else
-        hipLaunchKernelGGL(k_fd_multi<false>, dim3(P->blocks), dim3(P->threads), plan_lds(P, P->threads), cs, a);
+      enqueue_plan(P, cs);
       ok = hipStreamEndCapture(cs, &P->graph) == hipSuccess;
     }
     ok = ok && hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0) == hipSuccess;

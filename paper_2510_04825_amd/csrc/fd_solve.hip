@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256) void k_fd_solve(FDArgs A) {
 
 // Column-per-lane solve (fd_cols.h): one wavefront per parameter, two per block.
 template <int F, int DP, bool BRED, bool REF>
-__global__ __launch_bounds__(128, REF ? 1 : 4) void k_fd_cols(FDArgs A, int ldsw) {
+__global__ __launch_bounds__(128, REF ? 1 : (BRED ? 2 : 4)) void k_fd_cols(FDArgs A, int ldsw) {
   extern __shared__ double lds_cols[];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int64_t p = static_cast<int64_t>(blockIdx.x) * 2 + wave;

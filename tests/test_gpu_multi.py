@@ -61,7 +61,7 @@ def test_plan_matches_oracle(uneven_small, prec, refine, tol, flags, tmp_path, m
                             for p, a, b in zip(w["test_params"], yg, yo))
                     assert d <= tol, (rep, w["r"], w["s"], d)
             t, b = B.subap_plan_shape(plan)
-            assert t in (128, 256) and b > 0
+            assert t in (64, 128, 256) and b > 0
         finally:
             B.subap_plan_free(plan)
     finally:
@@ -105,6 +105,47 @@ def test_autotune_cache_is_reused(uneven_small, tmp_path, monkeypatch):
         assert B.subap_plan_shape(p2) == shape1
         B.subap_plan_free(p2)
         assert len(cache.read_text().strip().splitlines()) == 1  # looked up, not re-tuned
+    finally:
+        for M in models:
+            M.free()
+
+
+@pytest.fixture(scope="module")
+def cubes_small():
+    # 3-D models for plans that hold 3-D instances only or mix them with 2-D ones
+    out = []
+    for N, r, s, m in ((8, 8, 24, 32), (10, 64, 160, 16)):
+        w = si.diffusion3d(N=N, r=r, s=s, m=m, seed=500 + N)
+        off = O.offline(w)
+        out.append((w, off, On.solve(off["family"], off["Q"], off["rows"], w["test_params"])))
+    return out
+
+
+@pytest.mark.parametrize("mix", ["3d_only", "2d_and_3d"])
+@pytest.mark.parametrize("prec,refine,tol", [(B.FP64, 0, 1e-12), (B.FP32, 1, 1e-6)])
+def test_plan_with_3d_models(uneven_small, cubes_small, mix, prec, refine, tol, tmp_path, monkeypatch):
+    import torch
+    monkeypatch.setenv("SUBAP_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    header(f"plan {mix} prec={prec} refine={refine}")
+    cases = list(cubes_small) + (list(uneven_small[:3]) if mix == "2d_and_3d" else [])
+    device()
+    models = [B.Model(w, basis=off["Q"], rows=off["rows"]) for w, off, _ in cases]
+    try:
+        params = [to_dev(w["test_params"]) for w, _, _ in cases]
+        ys = [torch.full((w["m"], w["r"]), -7.0, dtype=torch.float64, device=params[0].device) for w, _, _ in cases]
+        sts = [torch.full((w["m"],), -1, dtype=torch.int32, device=params[0].device) for w, _, _ in cases]
+        plan = B.subap_plan_create([M.handle for M in models], params, ys, None, sts, prec, refine,
+                                   B.PLAN_GRAPH | B.PLAN_AUTOTUNE)
+        try:
+            B.subap_plan_execute(plan)
+            torch.cuda.synchronize()
+            for (w, off, yo), y, st in zip(cases, ys, sts):
+                assert np.all(st.cpu().numpy() == B.OK)
+                d = max(On.delta_res(off["family"], off["Q"], p, a, b)
+                        for p, a, b in zip(w["test_params"], y.cpu().numpy(), yo))
+                assert d <= tol, (mix, w["family"], w["r"], w["s"], d)
+        finally:
+            B.subap_plan_free(plan)
     finally:
         for M in models:
             M.free()
