@@ -14,6 +14,13 @@ Test infrastructure only (see the package docstring).
                      fresh pivoted QR on the columns not chosen yet and takes
                      min(r, s - chosen) pivots.  With s = r this is exactly
                      one pivoted QR (interpolation, Section 3).
+* ``leverage_scores`` / ``leverage_sample``  the randomised selector of
+                     Section 5.3 the paper recommends when s > r: rows drawn
+                     with probability proportional to the squared row norms of
+                     the orthonormal factor of [A(p_sel) X, b(p_sel)] (the span
+                     Section 5.3.1 samples so that the sketched residual
+                     estimates the full one), each sampled row weighted by
+                     1/sqrt(s pi_i) as the Section 5.3 footnote prescribes.
 * ``offline``        all of the above for a workload.
 
 Readings where the paper is silent (kept identical in the GPU library):
@@ -110,18 +117,68 @@ def select_rows(M, s, tie_rtol=TIE_RTOL):
     return np.array(chosen, dtype=np.int64)
 
 
+def leverage_scores(B):
+    """Squared row norms of the orthonormal factor of B (n x k): thin QR of B
+    (Section 5.3, leverage scores of span(B)).  They sum to rank(B)."""
+    Qb, _ = np.linalg.qr(np.asarray(B, dtype=np.float64), mode="reduced")
+    return np.sum(Qb * Qb, axis=1)
+
+
+def leverage_sample(scores, u):
+    """Leverage-score sampling with weights (Section 5.3 and its footnote).
+
+    One row per uniform draw u_k in [0, 1), with replacement: row i is drawn
+    with probability pi_i = scores_i / sum(scores), by taking the first i whose
+    running sum scores_0 + ... + scores_i exceeds u_k * sum(scores) (a draw at
+    or beyond the total, possible only through rounding, takes the last row
+    with a positive score).  Weight w_k = 1 / sqrt(s pi_i), so that
+    E |W S v|^2 = |v|^2 for every v.  Returns (rows int64, weights).
+    """
+    sc = np.asarray(scores, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    s = u.size
+    run = np.cumsum(sc)
+    total = run[-1]
+    rows = np.searchsorted(run, u * total, side="right")
+    last = int(np.flatnonzero(sc > 0.0)[-1])
+    rows = np.where(rows >= sc.size, last, rows)
+    pi = sc[rows] / total
+    return rows.astype(np.int64), 1.0 / np.sqrt(s * pi)
+
+
+def leverage_matrix(family, Q, select_param):
+    """B = [A(p_sel) Q, b(p_sel)] (n x (r+1)), whose span is sampled."""
+    AQ = np.asarray(family.matvec(select_param, Q))
+    return np.column_stack([AQ, family.rhs(select_param)])
+
+
+def residual_bounds(rho, r, s, eps=None):
+    """Bounds on the full relative residual from the weighted sketched one
+    (Section 5.3.1): with probability close to 1 at p_sel,
+    (1 - eps) |Bc - b| <= |W S (Bc - b)| <= (1 + eps) |Bc - b|, so the full
+    value lies in [rho / (1 + eps), rho / (1 - eps)].  eps defaults to the
+    paper's k log k / s with k = r + 1, the dimension of span([B, b])."""
+    if eps is None:
+        k = r + 1
+        eps = k * np.log(k) / s
+    hi = rho / (1.0 - eps) if eps < 1.0 else np.inf
+    return rho / (1.0 + eps), hi
+
+
 def selection_matrix(family, Q, select_param):
     """M = (A(p_sel) Q)^T, the r x n matrix whose columns are pivoted."""
     return np.asarray(family.matvec(select_param, Q)).T
 
 
-def offline(workload: dict, basis=None, rows=None):
+def offline(workload: dict, basis=None, rows=None, sample_u=None):
     """Algorithm 3.1 steps 1-3 for a ``subap_inputs`` workload.
 
     ``basis``: optional n x r matrix used instead of the snapshot solves (it
     is still orthonormalised).  ``rows``: optional row indices used instead of
-    the pivoted-QR selection.  Returns dict(family, X (raw snapshots or None),
-    Q, R, rows).
+    the pivoted-QR selection.  ``sample_u``: s uniforms in [0, 1); when given,
+    rows come from leverage-score sampling of [A(p_sel) Q, b(p_sel)] and carry
+    weights.  Returns dict(family, X (raw snapshots or None), Q, R, rows,
+    weights (None for unweighted rows)).
     """
     family = fam.from_workload(workload)
     if basis is None:
@@ -129,7 +186,11 @@ def offline(workload: dict, basis=None, rows=None):
     else:
         X = np.asarray(basis, dtype=np.float64)
     Q, R = orthonormalise(X)
-    if rows is None:
+    weights = None
+    if sample_u is not None:
+        B = leverage_matrix(family, Q, workload["select_param"])
+        rows, weights = leverage_sample(leverage_scores(B), sample_u)
+    elif rows is None:
         M = selection_matrix(family, Q, workload["select_param"])
         rows = select_rows(M, workload["s"])
-    return dict(family=family, X=X, Q=Q, R=R, rows=np.asarray(rows, dtype=np.int64))
+    return dict(family=family, X=X, Q=Q, R=R, rows=np.asarray(rows, dtype=np.int64), weights=weights)

@@ -16,6 +16,12 @@ residual |A(p) x - b(p)| / |b(p)|; the sketched residual
 |S(A(p) X y - b)| / |S b|; and delta_res(p) = |A(p) X (y1 - y2)| / |b(p)|,
 the residual-norm distance between two coefficient vectors that the GPU
 parity tests use.
+
+With leverage-score rows (Section 5.3) every function takes the row weights:
+row k of S A(p) X and entry k of S b are multiplied by weights[k], and the
+sketched residual is |W S(A(p) X y - b)| / |b| (the weighted sketch estimates
+the full residual norm, Section 5.3.1; b is the same for every p here, so its
+full norm is known).
 """
 from __future__ import annotations
 
@@ -23,10 +29,15 @@ import numpy as np
 import scipy.linalg as sla
 
 
-def reduced_matrix(family, Q, rows, p):
-    """S A(p) Q (s x r): the selected rows of A(p), times Q (eq. (3.4))."""
+def _w(weights, v):
+    return v if weights is None else np.asarray(weights, dtype=np.float64).reshape((-1,) + (1,) * (v.ndim - 1)) * v
+
+
+def reduced_matrix(family, Q, rows, p, weights=None):
+    """S A(p) Q (s x r): the selected rows of A(p), times Q (eq. (3.4));
+    row k scaled by weights[k] when given."""
     A_S = family.rows(p, rows)
-    return np.asarray(A_S @ Q)
+    return _w(weights, np.asarray(A_S @ Q))
 
 
 def householder_lsq(G, b):
@@ -40,18 +51,18 @@ def householder_lsq(G, b):
     return y, Rg, rho
 
 
-def solve_one(family, Q, rows, p):
+def solve_one(family, Q, rows, p, weights=None):
     """SubApSnap coefficients y(p) for one parameter (eq. (3.3))."""
-    G = reduced_matrix(family, Q, rows, p)
-    bS = family.rhs_rows(p, rows)
+    G = reduced_matrix(family, Q, rows, p, weights)
+    bS = _w(weights, np.asarray(family.rhs_rows(p, rows), dtype=np.float64))
     y, _, _ = householder_lsq(G, bS)
     return y
 
 
-def solve(family, Q, rows, params):
+def solve(family, Q, rows, params, weights=None):
     """y for every parameter row of ``params`` (m x d) -> (m x r)."""
     P = np.atleast_2d(np.asarray(params, dtype=np.float64))
-    return np.stack([solve_one(family, Q, rows, p) for p in P])
+    return np.stack([solve_one(family, Q, rows, p, weights) for p in P])
 
 
 def lift(Q, y):
@@ -80,8 +91,11 @@ def delta_res(family, Q, p, y1, y2):
     return float(np.linalg.norm(family.matvec(p, Q @ dy)) / np.linalg.norm(b))
 
 
-def sketched_residual(family, Q, rows, p, y):
-    """|S(A(p) Q y - b(p))|_2 / |S b(p)|_2, from the s selected rows only."""
+def sketched_residual(family, Q, rows, p, y, weights=None):
+    """|S(A(p) Q y - b(p))|_2 / |S b(p)|_2, from the s selected rows only.
+    With weights: |W S(A(p) Q y - b(p))|_2 / |b(p)|_2."""
     A_S = family.rows(p, rows)
-    bS = family.rhs_rows(p, rows)
-    return float(np.linalg.norm(A_S @ (Q @ np.asarray(y)) - bS) / np.linalg.norm(bS))
+    bS = np.asarray(family.rhs_rows(p, rows), dtype=np.float64)
+    res = _w(weights, A_S @ (Q @ np.asarray(y)) - bS)
+    den = np.linalg.norm(bS) if weights is None else np.linalg.norm(family.rhs(p))
+    return float(np.linalg.norm(res) / den)

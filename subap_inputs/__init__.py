@@ -30,12 +30,17 @@ import numpy as np
 
 __all__ = [
     "diffusion2d", "diffusion3d", "krr", "uneven", "tridiag", "identity",
-    "surrogate",
+    "surrogate", "sample_uniforms",
 ]
 
 
 def _streams(base: int, k: int):
     return [np.random.default_rng(s) for s in np.random.SeedSequence(base).spawn(k)]
+
+
+def sample_uniforms(s: int, seed: int = 909) -> np.ndarray:
+    """s seeded uniforms in [0, 1): the draws of a randomised row sampler."""
+    return np.random.default_rng(seed).random(s)
 
 
 def diffusion2d(N: int = 64, r: int = 16, s: int = 32, m: int = 64, seed: int = 101) -> dict:

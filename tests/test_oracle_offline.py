@@ -83,3 +83,128 @@ def test_offline_pipeline_c1_shape():
     assert len(off["rows"]) == 32 and len(set(off["rows"].tolist())) == 32
     sv = np.linalg.svd(off["X"], compute_uv=False)
     assert sv[-1] / sv[0] > 1e-8  # full-rank snapshots: index parity is meaningful
+
+
+# --- leverage-score sampling with weights (Section 5.3) and the residual
+# estimate (Section 5.3.1)
+
+def test_leverage_scores_equal_the_projector_diagonal():
+    # diag(B (B^T B)^{-1} B^T), by normal equations instead of QR; sum = rank
+    rng = np.random.default_rng(11)
+    B = rng.standard_normal((60, 5)) * rng.uniform(0.1, 10.0, size=(60, 1))
+    sc = O.leverage_scores(B)
+    direct = np.einsum("ij,ji->i", B, np.linalg.solve(B.T @ B, B.T))
+    np.testing.assert_allclose(sc, direct, rtol=1e-12, atol=1e-15)
+    assert abs(sc.sum() - 5.0) < 1e-12
+    assert np.all(sc >= 0.0) and np.all(sc <= 1.0 + 1e-12)
+
+
+def test_leverage_sample_with_equal_scores_is_floor_u_n():
+    n, s = 37, 200
+    u = np.random.default_rng(12).random(s)
+    rows, w = O.leverage_sample(np.ones(n), u)
+    np.testing.assert_array_equal(rows, np.floor(u * n).astype(np.int64))
+    np.testing.assert_allclose(w, np.sqrt(n / s), rtol=1e-15)
+
+
+def test_leverage_sample_matches_a_linear_scan():
+    sc = np.array([0.5, 0.0, 2.0, 1e-3, 0.0, 1.25, 0.25])
+    u = np.concatenate([np.linspace(0.0, 0.999999, 97), [0.1249, 0.1251, 0.6253, 0.9999999]])
+    rows, w = O.leverage_sample(sc, u)
+    total = 0.0
+    for v in sc:
+        total += v
+    for k, uk in enumerate(u):
+        acc, pick = 0.0, None
+        for i, v in enumerate(sc):
+            acc += v
+            if acc > uk * total:
+                pick = i
+                break
+        assert rows[k] == pick
+        assert sc[pick] > 0.0
+        assert abs(w[k] - 1.0 / np.sqrt(u.size * sc[pick] / total)) <= 1e-14 * w[k]
+
+
+def test_weighted_sketch_is_unbiased():
+    # E |W S v|^2 = |v|^2; stratified draws u_k = (k + 1/2) / K make the sample
+    # frequencies equal to pi_i up to one count, so the sum converges
+    rng = np.random.default_rng(13)
+    sc = rng.uniform(0.2, 3.0, size=40)
+    v = rng.standard_normal(40)
+    K = 40000
+    rows, w = O.leverage_sample(sc, (np.arange(K) + 0.5) / K)
+    est = np.sum((w * v[rows]) ** 2)
+    assert abs(est / (v @ v) - 1.0) < 2e-3
+
+
+def test_all_rows_once_with_unit_weights_is_apsnap():
+    # equal scores and one draw per row: W S is a permutation, so the weighted
+    # SubApSnap problem is ApSnap's (eq. (3.1))
+    from oracle import online as On
+    w = si.diffusion2d(N=10, r=4, s=100)
+    off = O.offline(w)
+    rows, wt = O.leverage_sample(np.ones(w["n"]), (np.arange(w["n"]) + 0.5) / w["n"])
+    np.testing.assert_array_equal(np.sort(rows), np.arange(w["n"]))
+    np.testing.assert_allclose(wt, 1.0, rtol=1e-15)
+    for p in w["test_params"][:4]:
+        y = On.solve_one(off["family"], off["Q"], rows, p, wt)
+        ya = On.apsnap_solve(off["family"], off["Q"], p)
+        np.testing.assert_allclose(y, ya, rtol=1e-10, atol=1e-12 * np.abs(ya).max())
+
+
+def test_a_repeated_row_equals_one_row_of_summed_squared_weight():
+    from oracle import online as On
+    w = si.diffusion2d(N=10, r=4, s=12)
+    off = O.offline(w)
+    rows = np.array([3, 3, 17, 40, 41, 55, 60, 71, 88, 90, 97, 5])
+    wt = np.linspace(0.5, 2.0, rows.size)
+    wt[1] = wt[0]
+    rows2 = rows[1:]
+    wt2 = wt[1:].copy()
+    wt2[0] = np.sqrt(2.0) * wt[0]
+    p = w["test_params"][0]
+    y1 = On.solve_one(off["family"], off["Q"], rows, p, wt)
+    y2 = On.solve_one(off["family"], off["Q"], rows2, p, wt2)
+    np.testing.assert_allclose(y1, y2, rtol=1e-11, atol=1e-13 * np.abs(y1).max())
+
+
+def test_leverage_selection_estimates_the_full_residual():
+    # At p_sel, the weighted sketch of span([A X, b]) keeps every residual in
+    # that span within (1 +- eps) of its full norm for nearly every draw
+    # (Section 5.3.1); eps = k log k / s with k = r + 1
+    from oracle import online as On
+    w = si.diffusion2d(N=16, r=5, s=96)
+    off = O.offline(w)
+    fam, Q, p = off["family"], off["Q"], w["select_param"]
+    B = O.leverage_matrix(fam, Q, p)
+    sc = O.leverage_scores(B)
+    lo_hi_ok, ratios = 0, []
+    for seed in range(20):
+        rows, wt = O.leverage_sample(sc, si.sample_uniforms(w["s"], seed=seed))
+        y = On.solve_one(fam, Q, rows, p, wt)
+        full = On.residual(fam, Q @ y, p)
+        est = On.sketched_residual(fam, Q, rows, p, y, wt)
+        lo, hi = O.residual_bounds(est, w["r"], w["s"])
+        ratios.append(est / full)
+        lo_hi_ok += lo <= full <= hi
+    assert lo_hi_ok >= 18, ratios
+    assert 0.7 < np.median(ratios) < 1.3
+
+
+def test_residual_bounds_default_eps():
+    lo, hi = O.residual_bounds(1e-3, 15, 64)
+    eps = 16 * np.log(16) / 64
+    assert abs(lo - 1e-3 / (1 + eps)) < 1e-18 and abs(hi - 1e-3 / (1 - eps)) < 1e-18
+    assert O.residual_bounds(1.0, 40, 41)[1] == np.inf
+
+
+def test_offline_with_sample_u_returns_weighted_rows():
+    w = si.diffusion2d(N=12, r=4, s=20)
+    u = si.sample_uniforms(20, seed=3)
+    off = O.offline(w, sample_u=u)
+    B = O.leverage_matrix(off["family"], off["Q"], w["select_param"])
+    rows, wt = O.leverage_sample(O.leverage_scores(B), u)
+    np.testing.assert_array_equal(off["rows"], rows)
+    np.testing.assert_array_equal(off["weights"], wt)
+    assert O.offline(w)["weights"] is None
