@@ -95,6 +95,12 @@ typedef struct {
 
 typedef struct subap_model_s* subap_model;   /* opaque; owns device buffers */
 
+/* How the s rows are chosen (Section 5.3). */
+typedef enum {
+  SUBAP_SELECT_CPQR = 0,     /* rounds of column-pivoted QR on (A(p_sel) X)^T  */
+  SUBAP_SELECT_LEVERAGE = 1  /* leverage-score sampling with weights           */
+} subap_selection;
+
 typedef struct {
   int32_t r;                   /* snapshots / basis columns (1..64)           */
   int32_t s;                   /* selected rows, r <= s <= min(n, 256)        */
@@ -106,6 +112,10 @@ typedef struct {
                                   snapshot solves (still orthonormalised)     */
   const int64_t* rows_in;      /* optional host s row indices: use instead of
                                   pivoted-QR selection                        */
+  int32_t selection;           /* subap_selection (ignored with rows_in)      */
+  const double* sample_u;      /* LEVERAGE: host, s uniforms in [0, 1), one
+                                  per sampled row (the caller owns the random
+                                  stream, so a selection is reproducible)     */
 } subap_offline_opts;
 
 /*
@@ -119,7 +129,18 @@ typedef struct {
  *      min(r, s - chosen) pivots; pivot = smallest index whose residual norm
  *      is >= (1 - 1e-6) max (Section 5.3 names pivoted QR on (A(p_i) X)^T;
  *      the round and tie rules are this library's reading for s > r).
- *   Then builds the per-row tables the online kernels read.
+ *      With selection = SUBAP_SELECT_LEVERAGE instead (Section 5.3, the
+      selector the paper recommends with oversampling, and Section 5.3.1):
+      B = [A(select_param) Q, b] (n x (r+1)) is orthonormalised by
+      Householder QR; leverage score l_i = squared norm of row i of that
+      factor; draw k takes the first row i whose running sum
+      l_0 + ... + l_i exceeds sample_u[k] * sum(l) (sums in a fixed
+      chunked order), with replacement; row k is weighted by
+      w_k = 1 / sqrt(s l_i / sum(l)).  Every row of S A(p) X and entry of
+      S b is multiplied by its weight, and rho (subap_solve_batch) becomes
+      |W S (A(p) X y - b)| / |b|, an estimate of the full relative residual
+      (subap_residual_bounds).  Duplicate rows are allowed.
+   Then builds the per-row tables the online kernels read.
  * Blocks until the model is complete.  On success *out owns device memory;
  * release it with subap_model_free.  SUBAP_E_NOCONV if a snapshot solve
  * stalls (the model is not created).
@@ -296,6 +317,23 @@ SUBAP_API subap_status subap_model_dims(subap_model model, int64_t* n, int32_t* 
                               int32_t* s, int32_t* d);
 /* rows_host: s indices in selection order. */
 SUBAP_API subap_status subap_model_rows(subap_model model, int64_t* rows_host);
+/* Row weights (host, s values): 1 for pivoted-QR rows, 1/sqrt(s pi_i) for
+ * leverage-score rows. */
+SUBAP_API subap_status subap_model_weights(subap_model model, double* weights_host);
+/*
+ * subap_residual_bounds -- Section 5.3.1: with leverage-score rows the
+ * weighted sketch of span([A X, b]) satisfies, with high probability at
+ * select_param, (1 - eps) |v| <= |W S v| <= (1 + eps) |v| for every v in that
+ * span, so the full relative residual lies in
+ * [rho / (1 + eps), rho / (1 - eps)] (upper bound +inf when eps >= 1).  At
+ * other parameters the bounds are the paper's heuristic estimate.
+ *   rho_dev   device, m relative sketched residuals (rho of subap_solve_batch);
+ *   eps       > 0, or <= 0 for the default k ln(k) / s with k = r + 1;
+ *   lo_dev, hi_dev  device, m values each (written).
+ * SUBAP_E_INVALID if the model's rows are not leverage-score rows.
+ */
+SUBAP_API subap_status subap_residual_bounds(subap_model model, const double* rho_dev, int64_t m, double eps,
+                                             double* lo_dev, double* hi_dev, void* hip_stream);
 /* Q_host: n x r col-major orthonormal basis. */
 SUBAP_API subap_status subap_model_basis(subap_model model, double* Q_host);
 

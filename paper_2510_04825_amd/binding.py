@@ -34,8 +34,11 @@ EXPORTS = ("subap_offline", "subap_solve_batch", "subap_lift", "subap_sketched_r
            "subap_plan_shape", "subap_plan_free", "subap_solve_multi", "subap_surrogate_create",
            "subap_surrogate_weights", "subap_surrogate_gradient", "subap_surrogate_train",
            "subap_surrogate_predict", "subap_surrogate_solve_batch", "subap_surrogate_free",
-           "subap_surrogate_nparams", "subap_profile_count", "subap_status_string", "subap_last_error")
+           "subap_surrogate_nparams", "subap_profile_count", "subap_status_string", "subap_last_error",
+           "subap_model_weights", "subap_residual_bounds")
 PLAN_GRAPH, PLAN_AUTOTUNE = 1, 2
+# subap_selection
+SELECT_CPQR, SELECT_LEVERAGE = 0, 1
 
 
 class ProblemDesc(C.Structure):
@@ -46,7 +49,8 @@ class ProblemDesc(C.Structure):
 class OfflineOpts(C.Structure):
     _fields_ = [("r", C.c_int32), ("s", C.c_int32), ("snap_params", C.c_void_p),
                 ("select_param", C.c_void_p), ("snap_tol", C.c_double), ("snap_maxiter", C.c_int32),
-                ("basis_in", C.c_void_p), ("rows_in", C.c_void_p)]
+                ("basis_in", C.c_void_p), ("rows_in", C.c_void_p), ("selection", C.c_int32),
+                ("sample_u", C.c_void_p)]
 
 
 class SolveOpts(C.Structure):
@@ -88,6 +92,8 @@ def load(path: str = LIB_PATH):
     lib.subap_profile_entry.argtypes = [i32, C.POINTER(C.c_char_p), C.POINTER(i64), C.POINTER(C.c_double)]
     lib.subap_model_dims.argtypes = [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     lib.subap_model_rows.argtypes = [vp, vp]
+    lib.subap_model_weights.argtypes = [vp, vp]
+    lib.subap_residual_bounds.argtypes = [vp, vp, i64, C.c_double, vp, vp, vp]
     lib.subap_model_basis.argtypes = [vp, vp]
     lib.subap_model_free.argtypes = [vp]
     pp = C.POINTER(vp)
@@ -154,14 +160,17 @@ def _host(a, dtype):
 # ---------------------------------------------------------------------------
 def subap_offline(family, grid=0, n=0, dim=0, points=None, rhs=None, lam=0.0, r=1, s=1,
                   snap_params=None, select_param=None, snap_tol=0.0, snap_maxiter=0,
-                  basis_in=None, rows_in=None, stream=None):
-    """Run the offline phase; returns the opaque model handle (int)."""
+                  basis_in=None, rows_in=None, sample_u=None, stream=None):
+    """Run the offline phase; returns the opaque model handle (int).  With
+    sample_u (s uniforms in [0, 1)) the rows come from leverage-score sampling."""
     lib = load()
     keep = [_host(points, np.float64), _host(rhs, np.float64), _host(snap_params, np.float64),
-            _host(select_param, np.float64), _host(basis_in, np.float64), _host(rows_in, np.int64)]
+            _host(select_param, np.float64), _host(basis_in, np.float64), _host(rows_in, np.int64),
+            _host(sample_u, np.float64)]
     addr = [None if a is None else a.ctypes.data for a in keep]
     pd = ProblemDesc(family, grid, n, dim, addr[0], addr[1], lam)
-    op = OfflineOpts(r, s, addr[2], addr[3], snap_tol, snap_maxiter, addr[4], addr[5])
+    sel = SELECT_LEVERAGE if sample_u is not None else SELECT_CPQR
+    op = OfflineOpts(r, s, addr[2], addr[3], snap_tol, snap_maxiter, addr[4], addr[5], sel, addr[6])
     h = C.c_void_p()
     _check(lib.subap_offline(C.byref(pd), C.byref(op), _stream(stream), C.byref(h)))
     return h.value
@@ -386,6 +395,23 @@ def subap_model_rows(model):
     return out
 
 
+def subap_model_weights(model):
+    lib = load()
+    _, _, s, _ = subap_model_dims(model)
+    out = np.empty(s, dtype=np.float64)
+    _check(lib.subap_model_weights(C.c_void_p(model), out.ctypes.data))
+    return out
+
+
+def subap_residual_bounds(model, rho, lo, hi, eps=0.0, stream=None):
+    """rho, lo, hi: (m,) float64 cuda tensors; eps <= 0 takes k ln k / s, k = r + 1."""
+    m = rho.shape[0]
+    for t, name in ((rho, "rho"), (lo, "lo"), (hi, "hi")):
+        _expect(t, (m,), "float64", name)
+    _check(load().subap_residual_bounds(C.c_void_p(model), _ptr(rho), m, float(eps), _ptr(lo), _ptr(hi),
+                                        _stream(stream)))
+
+
 def subap_model_basis(model):
     lib = load()
     n, r, _, _ = subap_model_dims(model)
@@ -404,11 +430,13 @@ def subap_model_free(model):
 class Model:
     """Owns a subap_model built from a ``subap_inputs`` workload dict."""
 
-    def __init__(self, workload: dict, basis=None, rows=None, snap_tol=0.0, snap_maxiter=0, stream=None):
+    def __init__(self, workload: dict, basis=None, rows=None, snap_tol=0.0, snap_maxiter=0, stream=None,
+                 sample_u=None):
         w = workload
         fam = FAMILIES[w["family"]]
         kw = dict(r=w["r"], s=w["s"], snap_params=w.get("snap_params"), select_param=w.get("select_param"),
-                  snap_tol=snap_tol, snap_maxiter=snap_maxiter, basis_in=None, rows_in=rows, stream=stream)
+                  snap_tol=snap_tol, snap_maxiter=snap_maxiter, basis_in=None, rows_in=rows, sample_u=sample_u,
+                  stream=stream)
         if basis is not None:
             kw["basis_in"] = np.asfortranarray(basis, dtype=np.float64).T  # column-major n x r
         if fam == FAMILY_KRR:
@@ -423,6 +451,16 @@ class Model:
 
     def basis(self):
         return subap_model_basis(self.handle)
+
+    def weights(self):
+        return subap_model_weights(self.handle)
+
+    def residual_bounds(self, rho, eps=0.0, stream=None):
+        """(lo, hi) cuda tensors bracketing the full relative residual (leverage rows)."""
+        import torch
+        lo, hi = torch.empty_like(rho), torch.empty_like(rho)
+        subap_residual_bounds(self.handle, rho, lo, hi, eps, stream)
+        return lo, hi
 
     def solve(self, params, contraction=FP64, refine_steps=0, stream=None, with_status=True):
         """params: (m, d) float64 cuda tensor -> (y, rho, status) cuda tensors."""

@@ -112,7 +112,7 @@ namespace {
 
 void free_model(subap_model_s* M) {
   if (!M) return;
-  void* bufs[] = {M->Q, M->rows_d, M->bS, M->QS, M->rhs, M->phi, M->delta64, M->delta32, M->delta64T, M->delta32T, M->points,
+  void* bufs[] = {M->Q, M->rows_d, M->wS, M->bS, M->QS, M->rhs, M->phi, M->delta64, M->delta32, M->delta64T, M->delta32T, M->points,
                   M->Dt64, M->D32, M->Qrm, M->Q32, M->Qhi, M->Qlo, M->Qh16, M->Ql16, M->colscale_inv,
                   M->work};
   for (void* b : bufs) dfree(b);
@@ -203,6 +203,13 @@ subap_status subap_offline(const subap_problem_desc* pd, const subap_offline_opt
     return invalid("basis_in has non-finite entries");
   }
   if (!o->rows_in) {
+    if (o->selection != SUBAP_SELECT_CPQR && o->selection != SUBAP_SELECT_LEVERAGE)
+      return invalid("selection must be SUBAP_SELECT_CPQR or SUBAP_SELECT_LEVERAGE");
+    if (o->selection == SUBAP_SELECT_LEVERAGE) {
+      if (!o->sample_u) return invalid("leverage-score selection needs sample_u");
+      for (int k = 0; k < o->s; ++k)
+        if (!(o->sample_u[k] >= 0.0 && o->sample_u[k] < 1.0)) return invalid("sample_u must lie in [0, 1)");
+    }
     if (!o->select_param) return invalid("select_param needed without rows_in");
     if (!all_finite(o->select_param, tmp.d)) return invalid("select_param not finite");
     if (pd->family == SUBAP_FAMILY_KRR && !(o->select_param[0] > 0.0)) return invalid("KRR select_param must be > 0");
@@ -275,6 +282,29 @@ subap_status subap_model_rows(subap_model M, int64_t* rows_host) {
   if (!M || !rows_host) return invalid("model and rows_host must not be NULL");
   std::memcpy(rows_host, M->rows.data(), sizeof(int64_t) * M->rows.size());
   return SUBAP_OK;
+}
+
+subap_status subap_model_weights(subap_model M, double* weights_host) {
+  clear_error();
+  if (!M || !weights_host) return invalid("model and weights_host must not be NULL");
+  std::memcpy(weights_host, M->weights.data(), sizeof(double) * M->weights.size());
+  return SUBAP_OK;
+}
+
+subap_status subap_residual_bounds(subap_model M, const double* rho, int64_t m, double eps, double* lo, double* hi,
+                                   void* hip_stream) {
+  clear_error();
+  if (!M) return invalid("model must not be NULL");
+  if (M->selection != SUBAP_SELECT_LEVERAGE) return invalid("residual bounds need leverage-score rows");
+  if (m < 0) return invalid("m must be >= 0");
+  if (!std::isfinite(eps)) return invalid("eps must be finite");
+  if (m == 0) return SUBAP_OK;
+  if (!rho || !lo || !hi) return invalid("rho_dev, lo_dev and hi_dev must not be NULL");
+  if (!(eps > 0.0)) {
+    const double k = M->r + 1.0;
+    eps = k * std::log(k) / M->s;
+  }
+  return subap::residual_bounds(rho, m, eps, lo, hi, static_cast<hipStream_t>(hip_stream));
 }
 
 subap_status subap_model_basis(subap_model M, double* Q_host) {

@@ -54,20 +54,23 @@ struct subap_model_s {
   int F = 0;          // FD: faces per row (2 * dimx)
   double h = 0.0, inv_h2 = 0.0;
   double lambda = 0.0;
-  double bS_norm = 0.0;               // |S b|_2 (b is p-independent in every family)
+  double bS_norm = 0.0;               // |S b|_2, or |b|_2 with weighted rows (b is p-independent in every family)
+  int selection = 0;                  // subap_selection
+  std::vector<double> weights;        // host copy of wS
   double dmax = 0.0;                  // KRR: upper bound on every squared distance D[k, j]
   std::vector<int64_t> rows;          // host copy, selection order
 
   // basis and selection (device)
   double* Q = nullptr;                // n x r col-major, orthonormal
   int* rows_d = nullptr;              // s
-  double* bS = nullptr;               // s
-  double* QS = nullptr;               // s x r row-major: Q[rows[k], c]
+  double* wS = nullptr;               // s row weights (1 for pivoted-QR rows)
+  double* bS = nullptr;               // s: w_k b[rows[k]]
+  double* QS = nullptr;               // s x r row-major: w_k Q[rows[k], c]
   double* rhs = nullptr;              // n (device copy of b)
 
   // finite-difference tables, layouts [(f * r + c) * s + k] and [(f * d + q) * s + k]
   double* phi = nullptr;              // s x F x d  mode values at face midpoints
-  double* delta64 = nullptr;          // s x F x r  Q[i_k] - Q[nb_f(i_k)] (0 outside)
+  double* delta64 = nullptr;          // s x F x r  w_k (Q[i_k] - Q[nb_f(i_k)]) (0 outside)
   float* delta32 = nullptr;
   double* delta64T = nullptr;         // the same at [(f * s + k) * r + c] (lanes = columns)
   float* delta32T = nullptr;
@@ -95,6 +98,7 @@ namespace subap {
 subap_status offline_build(const subap_problem_desc* pd, const subap_offline_opts* o,
                            hipStream_t st, subap_model_s* M);
 subap_status build_tables(subap_model_s* M, hipStream_t st);
+subap_status residual_bounds(const double* rho, int64_t m, double eps, double* lo, double* hi, hipStream_t st);
 
 // ---- online ----
 subap_status fd_solve(subap_model_s* M, const double* params, int64_t m, double* y,

@@ -415,6 +415,7 @@ struct LArgs {
   const void* G;          // double m x s x r, or float nsplit x m x s x r partials
   int nsplit;             // number of float partials to add (1 for double)
   const double* colscale; // r: multiply column c of the sum by colscale[c] (or nullptr)
+  const double* wS;       // s row weights of the kernel part (QS, bS carry theirs)
   const double* QS;       // s x r
   const double* bS;
   double lambda, bS_norm;
@@ -451,7 +452,7 @@ __global__ __launch_bounds__(256) void k_lsq(LArgs A) {
         for (int z = 0; z < A.nsplit; ++z)
           g += static_cast<double>(G[((z * A.m + p) * s + k) * r + c]);
         if (A.colscale) g *= A.colscale[c];
-        g += A.lambda * A.QS[k * r + c];
+        g = fma(A.wS[k], g, A.lambda * A.QS[k * r + c]);
       }
       qr.a[q][c] = g;
     }
@@ -578,6 +579,7 @@ struct CArgs {
   int64_t m;
   int r, s;
   const double* part;
+  const double* wS;
   const double* QS;
   const double* bS;
   double lambda, bS_norm;
@@ -616,7 +618,7 @@ __global__ __launch_bounds__(256) void k_correct(CArgs A) {
       for (int sp = 0; sp < kRefSplit; ++sp) t += A.part[(static_cast<int64_t>(sp) * A.m + p) * s + k];
       double zs = 0.0;
       for (int c = 0; c < r; ++c) zs = fma(A.QS[k * r + c], s_y[team][c], zs);
-      t += A.lambda * zs - A.bS[k];
+      t = A.wS[k] * t + (A.lambda * zs - A.bS[k]);
     }
     res[q] = k < s ? t : 0.0;
   }
@@ -629,7 +631,8 @@ __global__ __launch_bounds__(256) void k_correct(CArgs A) {
 
 // Sketched residual from the partial sums: one wavefront per parameter.
 __global__ __launch_bounds__(256) void k_resid_finish(const double* params, int64_t m, int r, int s,
-                                                       const double* part, const double* QS, const double* bS,
+                                                       const double* part, const double* wS, const double* QS,
+                                                       const double* bS,
                                                        double lambda, double bS_norm, const double* y,
                                                        double* res, double* norm) {
   const int64_t p = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / 64;
@@ -642,7 +645,7 @@ __global__ __launch_bounds__(256) void k_resid_finish(const double* params, int6
     for (int sp = 0; sp < kRefSplit; ++sp) t += part[(static_cast<int64_t>(sp) * m + p) * s + k];
     double zs = 0.0;
     for (int c = 0; c < r; ++c) zs = fma(QS[k * r + c], y[p * r + c], zs);
-    t += lambda * zs - bS[k];
+    t = wS[k] * t + (lambda * zs - bS[k]);
     if (!ok) t = __longlong_as_double(0x7ff8000000000000LL);
     if (res) res[p * s + k] = t;
     ss += t * t;
@@ -790,7 +793,7 @@ subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double
   }
   SUBAP_HIP_TRY(hipGetLastError());
   // A3: least squares
-  LArgs la{params, m, r, s, G, 1, nullptr, M->QS, M->bS, M->lambda, M->bS_norm, y, rho, stat, fac, fac_stride};
+  LArgs la{params, m, r, s, G, 1, nullptr, M->wS, M->QS, M->bS, M->lambda, M->bS_norm, y, rho, stat, fac, fac_stride};
   {
     ProfScope prof("lsq_householder", st);
     SUBAP_TRY(launch_lsq<double>(sh, la, st));
@@ -798,7 +801,7 @@ subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double
   // A4: refinement
   for (int it = 0; it < refine; ++it) {
     SUBAP_TRY(launch_refine_partial(M, params, m, y, part, it > 0, st));
-    CArgs ca{m, r, s, part, M->QS, M->bS, M->lambda, M->bS_norm, fac, fac_stride, y, rho, stat};
+    CArgs ca{m, r, s, part, M->wS, M->QS, M->bS, M->lambda, M->bS_norm, fac, fac_stride, y, rho, stat};
     ProfScope prof("lsq_correct", st);
     SUBAP_TRY(launch_correct(sh, ca, st));
   }
@@ -813,7 +816,7 @@ subap_status krr_residual(subap_model_s* M, const double* params, int64_t m, con
   SUBAP_TRY(launch_refine_partial(M, params, m, y, part, true, st));
   ProfScope prof("krr_resid_finish", st);
   hipLaunchKernelGGL(k_resid_finish, dim3(static_cast<unsigned>((m + 3) / 4)), dim3(256), 0, st, params, m,
-                     M->r, s, part, M->QS, M->bS, M->lambda, M->bS_norm, y, res, norm);
+                     M->r, s, part, M->wS, M->QS, M->bS, M->lambda, M->bS_norm, y, res, norm);
   SUBAP_HIP_TRY(hipGetLastError());
   return SUBAP_OK;
 }

@@ -568,11 +568,12 @@ subap_status select_rows_gpu(const double* W0, int64_t n, int r, int s, int64_t*
 // Tables for the online kernels.
 // ----------------------------------------------------------------------------
 __global__ void k_fd_tables(const double* Qm, int64_t n, int r, int s, int N, int dimx, int d, double h,
-                            const int* rows, const double* rhs, double* phi, double* delta64,
+                            const int* rows, const double* wS, const double* rhs, double* phi, double* delta64,
                             float* delta32, double* delta64T, float* delta32T, double* bS, double* QS) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= s) return;
   const int64_t i = rows[k];
+  const double wk = wS[k];
   int c[3];
   fd_node(i, N, dimx, c);
   const int F = 2 * dimx;
@@ -594,15 +595,15 @@ __global__ void k_fd_tables(const double* Qm, int64_t n, int r, int s, int N, in
     for (int cc = 0; cc < r; ++cc) {
       const double qi = Qm[static_cast<int64_t>(cc) * n + i];
       const double qn = nb >= 0 ? Qm[static_cast<int64_t>(cc) * n + nb] : 0.0;
-      const double dv = qi - qn;
+      const double dv = wk * (qi - qn);
       delta64[(static_cast<int64_t>(f) * r + cc) * s + k] = dv;
       delta32[(static_cast<int64_t>(f) * r + cc) * s + k] = static_cast<float>(dv);
       delta64T[(static_cast<int64_t>(f) * s + k) * r + cc] = dv;
       delta32T[(static_cast<int64_t>(f) * s + k) * r + cc] = static_cast<float>(dv);
     }
   }
-  bS[k] = rhs[i];
-  for (int cc = 0; cc < r; ++cc) QS[static_cast<int64_t>(k) * r + cc] = Qm[static_cast<int64_t>(cc) * n + i];
+  bS[k] = wk * rhs[i];
+  for (int cc = 0; cc < r; ++cc) QS[static_cast<int64_t>(k) * r + cc] = wk * Qm[static_cast<int64_t>(cc) * n + i];
 }
 
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
@@ -680,13 +681,100 @@ __global__ void k_fp16_split(const double* Qm, int64_t n, int r, const double* s
   }
 }
 
-__global__ void k_gather_rows(const double* Qm, int64_t n, int r, int s, const int* rows, const double* rhs,
-                              double* bS, double* QS) {
+__global__ void k_gather_rows(const double* Qm, int64_t n, int r, int s, const int* rows, const double* wS,
+                              const double* rhs, double* bS, double* QS) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= s) return;
   const int64_t i = rows[k];
-  bS[k] = rhs[i];
-  for (int c = 0; c < r; ++c) QS[static_cast<int64_t>(k) * r + c] = Qm[static_cast<int64_t>(c) * n + i];
+  const double wk = wS[k];
+  bS[k] = wk * rhs[i];
+  for (int c = 0; c < r; ++c) QS[static_cast<int64_t>(k) * r + c] = wk * Qm[static_cast<int64_t>(c) * n + i];
+}
+
+// ----------------------------------------------------------------------------
+// Leverage-score sampling with weights (Section 5.3): scores are the squared
+// row norms of the orthonormal factor Qb (n x k col-major) of [A(p_sel) Q, b].
+// The running sums are taken in chunks of kLevChunk rows: one thread sums each
+// chunk in row order, one thread prefixes the chunk sums, and each draw
+// searches the chunk prefixes, then walks its chunk in row order.
+// ----------------------------------------------------------------------------
+constexpr int kLevChunk = 1024;
+
+__global__ void k_row_sumsq(const double* Qb, int64_t n, int k, double* sc) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double t = 0.0;
+  for (int c = 0; c < k; ++c) {
+    const double v = Qb[static_cast<int64_t>(c) * n + i];
+    t = fma(v, v, t);
+  }
+  sc[i] = t;
+}
+
+__global__ void k_chunk_sums(const double* sc, int64_t n, int64_t nch, double* csum) {
+  const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= nch) return;
+  const int64_t b = c * kLevChunk, e = b + kLevChunk < n ? b + kLevChunk : n;
+  double t = 0.0;
+  for (int64_t i = b; i < e; ++i) t += sc[i];
+  csum[c] = t;
+}
+
+// cpre[c] = csum[0] + ... + csum[c-1] (cpre[0] = 0, cpre[nch] = total);
+// last = the last row with a positive score (-1 if none)
+__global__ void k_chunk_prefix(const double* csum, const double* sc, int64_t n, int64_t nch, double* cpre,
+                               int64_t* last) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double t = 0.0;
+  cpre[0] = 0.0;
+  for (int64_t c = 0; c < nch; ++c) {
+    t += csum[c];
+    cpre[c + 1] = t;
+  }
+  int64_t l = n - 1;
+  while (l >= 0 && !(sc[l] > 0.0)) --l;
+  *last = l;
+}
+
+__global__ void k_leverage_draw(const double* sc, int64_t n, const double* cpre, int64_t nch, const int64_t* last,
+                                const double* u, int s, int64_t* rows, double* w) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= s) return;
+  const double total = cpre[nch];
+  const double t = u[k] * total;
+  int64_t pick = -1;
+  if (t < total) {
+    int64_t lo = 0, hi = nch - 1;  // first chunk whose end exceeds t
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) / 2;
+      if (cpre[mid + 1] > t) hi = mid;
+      else lo = mid + 1;
+    }
+    const int64_t b = lo * kLevChunk, e = b + kLevChunk < n ? b + kLevChunk : n;
+    double acc = cpre[lo];
+    for (int64_t i = b; i < e; ++i) {
+      acc += sc[i];
+      if (acc > t) {
+        pick = i;
+        break;
+      }
+    }
+  }
+  if (pick < 0) pick = *last;  // a draw at the total (rounding): the last positive row
+  rows[k] = pick;
+  w[k] = 1.0 / sqrt(s * (sc[pick] / total));
+}
+
+__global__ void k_fill(double* v, int64_t len, double x) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < len) v[i] = x;
+}
+
+__global__ void k_bounds(const double* rho, int64_t m, double eps, double* lo, double* hi) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  lo[i] = rho[i] / (1.0 + eps);
+  hi[i] = eps < 1.0 ? rho[i] / (1.0 - eps) : __longlong_as_double(0x7ff0000000000000LL);
 }
 
 __global__ void k_copy_rows_i32(const int64_t* a, int* b, int s) {
@@ -699,6 +787,10 @@ __global__ void k_copy_rows_i32(const int64_t* a, int* b, int s) {
 subap_status build_tables(subap_model_s* M, hipStream_t st) {
   const int s = M->s, r = M->r;
   const int64_t n = M->n;
+  if (!M->wS) {  // unweighted rows
+    SUBAP_TRY(dalloc(&M->wS, s));
+    hipLaunchKernelGGL(k_fill, dim3((s + 63) / 64), dim3(64), 0, st, M->wS, static_cast<int64_t>(s), 1.0);
+  }
   SUBAP_TRY(dalloc(&M->bS, s));
   SUBAP_TRY(dalloc(&M->QS, static_cast<size_t>(s) * r));
   if (M->family == SUBAP_FAMILY_KRR) {
@@ -711,8 +803,8 @@ subap_status build_tables(subap_model_s* M, hipStream_t st) {
     hipLaunchKernelGGL(k_krr_tables, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
                        M->Q, M->points, n, r, s, M->dimx, M->rows_d, M->Dt64, M->D32, M->Qrm, M->Q32, M->Qhi,
                        M->Qlo);
-    hipLaunchKernelGGL(k_gather_rows, dim3((s + 63) / 64), dim3(64), 0, st, M->Q, n, r, s, M->rows_d, M->rhs,
-                       M->bS, M->QS);
+    hipLaunchKernelGGL(k_gather_rows, dim3((s + 63) / 64), dim3(64), 0, st, M->Q, n, r, s, M->rows_d, M->wS,
+                       M->rhs, M->bS, M->QS);
     DevVec scale;
     SUBAP_TRY(dalloc(&scale.p, r));
     SUBAP_TRY(dalloc(&M->colscale_inv, r));
@@ -730,15 +822,79 @@ subap_status build_tables(subap_model_s* M, hipStream_t st) {
     SUBAP_TRY(dalloc(&M->delta64T, tab * r));
     SUBAP_TRY(dalloc(&M->delta32T, tab * r));
     hipLaunchKernelGGL(k_fd_tables, dim3((s + 63) / 64), dim3(64), 0, st, M->Q, n, r, s, M->N, M->dimx, M->d, M->h,
-                       M->rows_d, M->rhs, M->phi, M->delta64, M->delta32, M->delta64T, M->delta32T, M->bS, M->QS);
+                       M->rows_d, M->wS, M->rhs, M->phi, M->delta64, M->delta32, M->delta64T, M->delta32T, M->bS,
+                       M->QS);
   }
   SUBAP_HIP_TRY(hipGetLastError());
-  std::vector<double> hb(s);
-  SUBAP_HIP_TRY(hipMemcpyAsync(hb.data(), M->bS, sizeof(double) * s, hipMemcpyDeviceToHost, st));
+  M->weights.resize(s);
+  SUBAP_HIP_TRY(hipMemcpyAsync(M->weights.data(), M->wS, sizeof(double) * s, hipMemcpyDeviceToHost, st));
+  // relative residual denominator: |S b| for interpolating / pivoted rows,
+  // |b| for weighted rows (whose sketch estimates full norms)
+  const bool full = M->selection == SUBAP_SELECT_LEVERAGE;
+  const int64_t len = full ? n : s;
+  std::vector<double> hb(static_cast<size_t>(len));
+  SUBAP_HIP_TRY(hipMemcpyAsync(hb.data(), full ? M->rhs : M->bS, sizeof(double) * len, hipMemcpyDeviceToHost, st));
   SUBAP_HIP_TRY(hipStreamSynchronize(st));
   double t = 0.0;
   for (double v : hb) t += v * v;
   M->bS_norm = std::sqrt(t);
+  return SUBAP_OK;
+}
+
+// Leverage-score rows and weights (Section 5.3): B = [A(p_sel) Q, b],
+// Householder QR, squared row norms, one draw per uniform.
+static subap_status select_leverage(const OpArgs& A, subap_model_s* M, const subap_offline_opts* o,
+                                    int64_t* rows64, hipStream_t st) {
+  const int64_t n = M->n;
+  const int r = M->r, s = M->s, d = M->d, k = r + 1;
+  DevVec B, Qb, diag, pdup, sc, csum, cpre, u;
+  int64_t* last = nullptr;
+  SUBAP_TRY(dalloc(&B.p, static_cast<size_t>(n) * k));
+  std::vector<double> pd_h(static_cast<size_t>(r) * d);
+  for (int c = 0; c < r; ++c)
+    for (int q = 0; q < d; ++q) pd_h[static_cast<size_t>(c) * d + q] = o->select_param[q];
+  SUBAP_TRY(dalloc(&pdup.p, pd_h.size()));
+  SUBAP_HIP_TRY(hipMemcpyAsync(pdup.p, pd_h.data(), sizeof(double) * pd_h.size(), hipMemcpyHostToDevice, st));
+  SUBAP_TRY(apply_op(A, pdup.p, r, M->Q, B.p, nullptr, st));
+  SUBAP_HIP_TRY(hipMemcpyAsync(B.p + static_cast<int64_t>(r) * n, M->rhs, sizeof(double) * n,
+                               hipMemcpyDeviceToDevice, st));
+  SUBAP_TRY(dalloc(&Qb.p, static_cast<size_t>(n) * k));
+  SUBAP_TRY(dalloc(&diag.p, k));
+  SUBAP_TRY(householder_q(B.p, n, k, Qb.p, diag.p, st));
+  const int64_t nch = (n + kLevChunk - 1) / kLevChunk;
+  SUBAP_TRY(dalloc(&sc.p, n));
+  SUBAP_TRY(dalloc(&csum.p, nch));
+  SUBAP_TRY(dalloc(&cpre.p, nch + 1));
+  SUBAP_TRY(dalloc(&u.p, s));
+  SUBAP_TRY(dalloc(&last, 1));
+  struct GL {
+    int64_t* p;
+    ~GL() { dfree(p); }
+  } gl{last};
+  SUBAP_TRY(dalloc(&M->wS, s));
+  SUBAP_HIP_TRY(hipMemcpyAsync(u.p, o->sample_u, sizeof(double) * s, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_row_sumsq, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, Qb.p,
+                     n, k, sc.p);
+  hipLaunchKernelGGL(k_chunk_sums, dim3(static_cast<unsigned>((nch + 63) / 64)), dim3(64), 0, st, sc.p, n, nch,
+                     csum.p);
+  hipLaunchKernelGGL(k_chunk_prefix, dim3(1), dim3(1), 0, st, csum.p, sc.p, n, nch, cpre.p, last);
+  hipLaunchKernelGGL(k_leverage_draw, dim3((s + 63) / 64), dim3(64), 0, st, sc.p, n, cpre.p, nch, last, u.p, s,
+                     rows64, M->wS);
+  SUBAP_HIP_TRY(hipGetLastError());
+  int64_t last_h = -1;
+  SUBAP_HIP_TRY(hipMemcpyAsync(&last_h, last, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  SUBAP_HIP_TRY(hipStreamSynchronize(st));
+  if (last_h < 0) {
+    set_error("leverage scores are all zero");
+    return SUBAP_E_INVALID;
+  }
+  return SUBAP_OK;
+}
+
+subap_status residual_bounds(const double* rho, int64_t m, double eps, double* lo, double* hi, hipStream_t st) {
+  hipLaunchKernelGGL(k_bounds, dim3(static_cast<unsigned>((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, rho, m,
+                     eps, lo, hi);
+  SUBAP_HIP_TRY(hipGetLastError());
   return SUBAP_OK;
 }
 
@@ -791,8 +947,11 @@ subap_status offline_build(const subap_problem_desc* pd, const subap_offline_opt
     int64_t* p;
     ~G64() { dfree(p); }
   } g64{rows64};
+  M->selection = o->rows_in ? SUBAP_SELECT_CPQR : o->selection;
   if (o->rows_in) {
     SUBAP_HIP_TRY(hipMemcpyAsync(rows64, o->rows_in, sizeof(int64_t) * s, hipMemcpyHostToDevice, st));
+  } else if (o->selection == SUBAP_SELECT_LEVERAGE) {
+    SUBAP_TRY(select_leverage(A, M, o, rows64, st));
   } else {
     SUBAP_TRY(dalloc(&W.p, static_cast<size_t>(n) * r));
     std::vector<double> pd_h(static_cast<size_t>(r) * d);
