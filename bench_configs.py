@@ -10,6 +10,9 @@ uneven       64 independent 2-D diffusion instances (grids 32^2..512^2,
 surrogate    the learned p -> y surrogate on the 3-D model: training on 2^18
              pairs from the batched solve, then 2^20 parameters with the
              sketched-residual acceptance test and the plain batched fallback.
+leverage     the 3-D model with leverage-score rows and weights instead of
+             pivoted QR: selection time, the weighted batched solve and the
+             residual estimate with its bounds.
 
 Validity of a form: status OK and sketched distance |S A Q (y - y_fp64)| / |S b|
 <= 1e-6 to the FP64 batched solve of the same model (subap_sketched_residual).
@@ -22,18 +25,20 @@ import numpy as np
 
 
 def _oracle_rate(jobs, budget_s, sample_text):
-    """The FP64 oracle's online solve timed on this host: jobs = [(family, Q, rows, params)],
+    """The FP64 oracle's online solve timed on this host: jobs = [(family, Q, rows, params[, weights])],
     solved in turn, parameter chunks growing until about budget_s seconds are spent."""
     from threadpoolctl import threadpool_info
 
     from oracle import online as On
     done, spent = 0, 0.0
-    for fam, Q, rows, P in jobs:
-        On.solve(fam, Q, rows, P[:1])  # warm caches
+    for job in jobs:
+        fam, Q, rows, P = job[:4]
+        wts = job[4] if len(job) > 4 else None
+        On.solve(fam, Q, rows, P[:1], wts)  # warm caches
         i, chunk = 0, 4
         while i < len(P) and spent < budget_s:
             t0 = time.perf_counter()
-            On.solve(fam, Q, rows, P[i:i + chunk])
+            On.solve(fam, Q, rows, P[i:i + chunk], wts)
             spent += time.perf_counter() - t0
             done += len(P[i:i + chunk])
             i += chunk
@@ -319,3 +324,79 @@ def lift(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
             "forms": out,
             "roofline": {"bound": "hbm", "kernel": "lift", "achieved": best["GB_per_s"], "peak": PEAKS["hbm_gbs"],
                          "unit": "GB/s", "frac": best["frac_hbm"], "traffic": None}}
+
+
+def leverage(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
+    """3-D diffusion (N^3 nodes, r = 40, s = 160) with leverage-score rows and
+    weights (Section 5.3) instead of pivoted QR: offline time of each selector,
+    the weighted FP64 batched solve of 65,536 parameters, and the residual
+    estimate |W S (A Q y - b)| / |b| with its bounds (Section 5.3.1)."""
+    import numpy as np
+    N = args.grid
+    w = si.diffusion3d(N=N)
+    m, n, r, s = w["m"], w["n"], w["r"], w["s"]
+    u = si.sample_uniforms(s, seed=909)
+    t0 = time.perf_counter()
+    M = B.Model(w, snap_tol=1e-10, sample_u=u)
+    torch.cuda.synchronize()
+    offline_s = time.perf_counter() - t0
+    # selection alone: the same basis, pivoted QR and leverage sampling
+    Q = M.basis()
+    t0 = time.perf_counter()
+    Mc = B.Model(w, basis=Q)
+    torch.cuda.synchronize()
+    cpqr_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Ml = B.Model(w, basis=Q, sample_u=u)
+    torch.cuda.synchronize()
+    lev_s = time.perf_counter() - t0
+    rows_equal = bool(np.array_equal(Ml.rows(), M.rows()))
+    Mc.free()
+    Ml.free()
+    P = torch.tensor(w["test_params"], dtype=torch.float64, device=dev)
+    y = torch.empty((m, r), dtype=torch.float64, device=dev)
+    rho = torch.empty(m, dtype=torch.float64, device=dev)
+    st = torch.empty(m, dtype=torch.int32, device=dev)
+    fn = lambda: B.subap_solve_batch(M.handle, P, y, rho, st, B.FP64, 0, stream)
+    fn()
+    torch.cuda.synchronize()
+    ok = int((st == 0).sum())
+    B.subap_profile_reset()
+    B.subap_profile_enable(True)
+    t = timed(fn, args.steps, stream)
+    B.subap_profile_enable(False)
+    prof = B.subap_profile_read()
+    kms = prof["fd_solve"][1] / prof["fd_solve"][0] if "fd_solve" in prof else t
+    lo, hi = M.residual_bounds(rho)
+    torch.cuda.synchronize()
+    wts = M.weights()
+    rows = M.rows()
+    flops = m * (2.0 * s * r * r - 2.0 / 3.0 * r ** 3 + 2.0 * s * 6 * r)
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import families as F
+        cpu = _oracle_rate([(F.from_workload(w), Q, rows, w["test_params"], wts)], 0.5 * args.cpu_seconds,
+                           "FP64 NumPy/SciPy weighted rows, W S A(p) Q and Householder least squares per "
+                           "parameter on the full model (the GPU's basis, leverage rows and weights passed in)")
+    M.free()
+    out = {
+        "metric": "online solves/s at rel. residual <=1e-6: batched/learned vs plain, 1 MI355X",
+        "value": ok / (t / 1e3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": t, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"diffusion3d_n{N}^3_r{r}_s{s}_m{m}_leverage_rows", "n": n,
+                   "form": "FP64 batched solve on leverage-score rows with weights"},
+        "selection": {"offline_s_with_snapshots": offline_s, "cpqr_s_given_basis": cpqr_s,
+                      "leverage_s_given_basis": lev_s, "leverage_rows_reproducible": rows_equal,
+                      "distinct_rows": int(np.unique(rows).size),
+                      "weight_range": [float(wts.min()), float(wts.max())]},
+        "residual_estimate": {"median_rho": float(torch.median(rho)), "median_lo": float(torch.median(lo)),
+                              "median_hi": float(torch.median(hi)),
+                              "eps": (r + 1) * float(np.log(r + 1)) / s},
+        "roofline": {"bound": "alu", "kernel": "fd_solve", "achieved": flops / (kms * 1e-3) / 1e12,
+                     "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s",
+                     "frac": flops / (kms * 1e-3) / 1e12 / PEAKS["fp64_tflops"], "traffic": None},
+    }
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    return out
