@@ -32,6 +32,15 @@ Shifted tridiagonal (eq. (5.7))
 A(p) = A0 - p I with A0 = tridiag(-1, 2, -1); b(p) = exp(b0 sin(p/10) p)
 componentwise.
 
+Delay system (Section 6.2.2), real parameter
+--------------------------------------------
+A(p) = p I - A_0 - e^{tau p} A_1 with A_1 = (T - kappa I) / tau, A_0 = 3 A_1,
+T the n x n matrix with ones on the first off-diagonals and at the two ends
+of the diagonal (T[0,0] = T[n-1,n-1] = 1); b is fixed and the output of
+interest is H(p) = c^T x(p).  The paper evaluates the transfer function; here
+p is real, which keeps A(p) symmetric positive definite for p > -3 (kappa - 2)
+/ tau.
+
 Identity (DEIM special case, eq. (3.5))
 ---------------------------------------
 A(p) = I; b(p) = y(p) with y_i(p) = 1 / (1 + 25 (t_i - p)^2) on t_i = i/(n-1),
@@ -301,6 +310,46 @@ class Identity:
         return self.rhs(p)[np.asarray(idx, dtype=np.int64)]
 
 
+class Delay:
+    """A(p) = p I - A_0 - e^{tau p} A_1, A_1 = (T - kappa I)/tau, A_0 = 3 A_1 (Section 6.2.2)."""
+
+    def __init__(self, n, tau, kappa, rhs, c_out=None):
+        self.n = int(n)
+        self.d = 1
+        self.tau = float(tau)
+        self.kappa = float(kappa)
+        self._rhs = np.asarray(rhs, dtype=np.float64)
+        self.c_out = None if c_out is None else np.asarray(c_out, dtype=np.float64)
+
+    def T(self):
+        n = self.n
+        off = np.ones(n - 1)
+        main = np.zeros(n)
+        main[0] = main[-1] = 1.0
+        return sp.diags([off, main, off], [-1, 0, 1], format="csr")
+
+    def A1(self):
+        return (self.T() - self.kappa * sp.identity(self.n, format="csr")) / self.tau
+
+    def matrix(self, p):
+        pv = float(np.asarray(p).reshape(-1)[0])
+        A1 = self.A1()
+        A0 = 3.0 * A1
+        return (pv * sp.identity(self.n, format="csr") - A0 - np.exp(self.tau * pv) * A1).tocsr()
+
+    def rows(self, p, idx):
+        return self.matrix(p)[np.asarray(idx, dtype=np.int64)]
+
+    def matvec(self, p, x):
+        return self.matrix(p) @ x
+
+    def rhs(self, p=None):
+        return self._rhs.copy()
+
+    def rhs_rows(self, p, idx):
+        return self._rhs[np.asarray(idx, dtype=np.int64)]
+
+
 def from_workload(w: dict):
     """Build the family object described by a ``subap_inputs`` workload dict."""
     fam = w["family"]
@@ -312,4 +361,6 @@ def from_workload(w: dict):
         return ShiftedTridiag(w["b0"])
     if fam == "identity":
         return Identity(w["n"])
+    if fam == "delay":
+        return Delay(w["n"], w["tau"], w["kappa"], w["rhs"], w.get("c_out"))
     raise ValueError(f"unknown family {fam!r}")

@@ -78,6 +78,11 @@ def apsnap_solve(family, Q, p):
     return c
 
 
+def output(c, Q, y):
+    """c^T x for x = Q y (Section 6.2.2: H(p*) ~ (c^T X) c_hat); y (r,) or (m, r)."""
+    return (np.asarray(c, dtype=np.float64) @ np.asarray(Q)) @ np.asarray(y, dtype=np.float64).T
+
+
 def residual(family, x, p):
     """|A(p) x - b(p)|_2 / |b(p)|_2 (the measure of Tables 3-4)."""
     b = family.rhs(p)

@@ -30,7 +30,7 @@ import numpy as np
 
 __all__ = [
     "diffusion2d", "diffusion3d", "krr", "uneven", "tridiag", "identity",
-    "surrogate", "sample_uniforms",
+    "surrogate", "sample_uniforms", "delay",
 ]
 
 
@@ -115,6 +115,23 @@ def uneven(k: int = 64, seed: int = 404, max_m: int = 4096,
             select_param=np.zeros(2),
         ))
     return out
+
+
+def delay(n: int = 10 ** 7, r: int = 10, s: int = 40, m: int = 65536, seed: int = 606,
+          p_range=(0.0, 10.0)) -> dict:
+    """Delay system of Section 6.2.2 (tau = 0.1, kappa = 2.1, n = 10^7 by
+    default) with a real parameter p uniform in p_range; b and the output
+    vector c are seeded standard normal vectors (a constant b would be an
+    eigenvector of T and make every solution a multiple of it)."""
+    g_snap, g_test, g_vec = _streams(seed, 3)
+    lo, hi = p_range
+    return dict(
+        family="delay", n=n, d=1, r=r, s=s, m=m, tau=0.1, kappa=2.1,
+        rhs=g_vec.standard_normal(n), c_out=g_vec.standard_normal(n),
+        snap_params=g_snap.uniform(lo, hi, size=(r, 1)),
+        test_params=g_test.uniform(lo, hi, size=(m, 1)),
+        select_param=np.array([0.5 * (lo + hi)]),
+    )
 
 
 def tridiag(n: int = 100, r: int = 7, m: int = 201, seed: int = 57) -> dict:

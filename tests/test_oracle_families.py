@@ -150,3 +150,60 @@ def test_tridiag_family_definition():
     assert np.allclose(A, [[11.5, -1, 0], [-1, 11.5, -1], [0, -1, 11.5]], rtol=0, atol=0)
     p = -9.5
     assert np.allclose(fam.rhs(np.array([p])), [np.exp(v * np.sin(p / 10) * p) for v in b0], rtol=1e-15)
+
+
+# --- delay system (Section 6.2.2), real parameter
+
+def _delay(n=12):
+    return F.Delay(n, 0.1, 2.1, np.random.default_rng(5).standard_normal(n),
+                   np.random.default_rng(6).standard_normal(n))
+
+
+def test_delay_ones_vector_is_an_eigenvector():
+    # T 1 = 2 * 1 needs the two corner ones, so A(p) 1 = (p - (3 + e^{tau p}) (2 - kappa) / tau) 1
+    fam = _delay(15)
+    for p in (0.0, 2.5, 9.0):
+        lam = p - (3.0 + np.exp(0.1 * p)) * (2.0 - 2.1) / 0.1
+        np.testing.assert_allclose(fam.matvec(p, np.ones(15)), lam * np.ones(15), rtol=1e-13)
+
+
+def test_delay_spectrum_closed_form():
+    # eigenvalues of T are 2 cos(pi k / n), k = 0..n-1, so those of A(p) are
+    # p + (3 + e^{tau p}) (kappa - 2 cos(pi k / n)) / tau: all positive for p >= 0
+    n = 12
+    fam = _delay(n)
+    for p in (0.0, 4.0):
+        ev = np.linalg.eigvalsh(fam.matrix(p).toarray())
+        th = 3.0 + np.exp(0.1 * p)
+        want = np.sort(p + th * (2.1 - 2.0 * np.cos(np.pi * np.arange(n) / n)) / 0.1)
+        np.testing.assert_allclose(ev, want, rtol=1e-12)
+        assert ev.min() > 0.0
+
+
+def test_delay_rows_are_the_affine_combination():
+    # Section 6.2.2: S A(p) X = p S X - S A_0 X - e^{tau p} S A_1 X with A_0 = 3 A_1
+    fam = _delay(20)
+    X = np.random.default_rng(7).standard_normal((20, 4))
+    idx = np.array([0, 3, 19, 7])
+    T = np.zeros((20, 20))
+    for i in range(19):
+        T[i, i + 1] = T[i + 1, i] = 1.0
+    T[0, 0] = T[19, 19] = 1.0
+    A1X = (T @ X - 2.1 * X) / 0.1
+    for p in (0.5, 7.0):
+        want = p * X[idx] - (3.0 + np.exp(0.1 * p)) * A1X[idx]
+        np.testing.assert_allclose(fam.rows(p, idx) @ X, want, rtol=1e-12, atol=1e-12)
+
+
+def test_delay_output_with_a_full_basis_is_the_transfer_function():
+    # r = n snapshots span R^n, and with S = I SubApSnap is the exact solve,
+    # so (c^T Q) y = c^T A(p)^{-1} b
+    from oracle import offline as O
+    from oracle import online as On
+    n = 10
+    fam = _delay(n)
+    Q, _ = O.orthonormalise(np.random.default_rng(8).standard_normal((n, n)))
+    for p in (1.0, 6.0):
+        y = On.solve_one(fam, Q, np.arange(n), p)
+        H = fam.c_out @ np.linalg.solve(fam.matrix(p).toarray(), fam.rhs(p))
+        assert abs(On.output(fam.c_out, Q, y) - H) <= 1e-12 * abs(H)
