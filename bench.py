@@ -50,10 +50,11 @@ def parse():
     ap.add_argument("--plain-sample", type=int, default=256, help="parameters solved one per call")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle timing budget")
-    ap.add_argument("--workload", default="krr", choices=["krr", "diffusion3d", "uneven", "surrogate", "lift", "leverage"],
+    ap.add_argument("--workload", default="krr", choices=["krr", "diffusion3d", "uneven", "surrogate", "lift", "leverage", "delay"],
                     help="krr (default, the headline line) or one of the other configurations "
                          "(lift: the FP32 lift alone on an N^3 grid, --grid N)")
     ap.add_argument("--grid", type=int, default=215, help="diffusion3d/surrogate/lift/leverage: nodes per axis")
+    ap.add_argument("--delay-n", type=int, default=10 ** 7, help="delay: system size n")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a device-to-device copy of MIB MiB (HBM counter calibration)")
     ap.add_argument("--given-basis", action="store_true",

@@ -21,7 +21,16 @@
  *                         with s_x = sin 2 pi x, c_x = cos 2 pi x, ...;
  *   SUBAP_FAMILY_KRR      kernel ridge regression (Section 6.3, eqs.
  *                         (6.3)-(6.4)): A(p) = K_p + lambda I,
- *                         K_p[i,j] = exp(-|t_i - t_j|^2 / (2 p^2)), d = 1.
+ *                         K_p[i,j] = exp(-|t_i - t_j|^2 / (2 p^2)), d = 1;
+ *   SUBAP_FAMILY_DELAY    the delay system of Section 6.2.2 with a real
+ *                         parameter: A(p) = p I - A_0 - e^{tau p} A_1,
+ *                         A_1 = (T - kappa I) / tau, A_0 = 3 A_1, T the n x n
+ *                         matrix with ones on the first off-diagonals and at
+ *                         T[0,0] and T[n-1,n-1], d = 1.  Symmetric positive
+ *                         definite for p > -3 (kappa - 2) / tau.  The online
+ *                         solve assembles S A(p) X = p S X - (3 + e^{tau p})
+ *                         S A_1 X from the two precomputed s x r pieces
+ *                         (Section 3.1, "Computing S A(p*) X").
  * Finite-difference layout: node (ix, iy[, iz]) sits at ((ix+1) h, ...),
  * h = 1/(N+1), index ix + N iy (+ N^2 iz); the face coefficient is a at
  * the face midpoint; row i holds sum_f a_f / h^2 on the diagonal and
@@ -69,7 +78,8 @@ typedef enum {
 typedef enum {
   SUBAP_FAMILY_DIFF2D = 1,
   SUBAP_FAMILY_DIFF3D = 2,
-  SUBAP_FAMILY_KRR = 3
+  SUBAP_FAMILY_KRR = 3,
+  SUBAP_FAMILY_DELAY = 4
 } subap_family;
 
 /* Arithmetic of the bulk contraction S A(p) X.  The least-squares solve is
@@ -91,6 +101,10 @@ typedef struct {
   const double* points;    /* KRR: host, n x dim row-major                    */
   const double* rhs;       /* host, n entries; NULL = all ones (DIFF* only)   */
   double lambda;           /* KRR ridge parameter (> 0)                       */
+  double tau;              /* DELAY: delay tau (> 0)                          */
+  double kappa;            /* DELAY: shift kappa (> 2)                        */
+  const double* c_out;     /* optional host n entries: output vector c of
+                              subap_output (the transfer function's c)        */
 } subap_problem_desc;
 
 typedef struct subap_model_s* subap_model;   /* opaque; owns device buffers */
@@ -133,7 +147,8 @@ typedef struct {
       selector the paper recommends with oversampling, and Section 5.3.1):
       B = [A(select_param) Q, b] (n x (r+1)) is orthonormalised by
       Householder QR; leverage score l_i = squared norm of row i of that
-      factor; draw k takes the first row i whose running sum
+      factor (of its first r columns when |R[r,r]| <= 1e-8 |b|: b then lies
+      in span(A Q) and its direction is rounding noise); draw k takes the first row i whose running sum
       l_0 + ... + l_i exceeds sample_u[k] * sum(l) (sums in a fixed
       chunked order), with replacement; row k is weighted by
       w_k = 1 / sqrt(s l_i / sum(l)).  Every row of S A(p) X and entry of
@@ -317,6 +332,15 @@ SUBAP_API subap_status subap_model_dims(subap_model model, int64_t* n, int32_t* 
                               int32_t* s, int32_t* d);
 /* rows_host: s indices in selection order. */
 SUBAP_API subap_status subap_model_rows(subap_model model, int64_t* rows_host);
+/*
+ * subap_output -- the linear output c^T x of x = X y without forming x
+ * (Section 6.2.2: H(p*) ~ (c^T X) c_hat with c^T X precomputed offline):
+ *   y_dev    device, m x r row-major coefficients (subap_solve_batch);
+ *   out_dev  device, m values (written): out[k] = sum_c (c^T Q)_c y[k, c].
+ * SUBAP_E_INVALID if the model was built without c_out.
+ */
+SUBAP_API subap_status subap_output(subap_model model, const double* y_dev, int64_t m, double* out_dev,
+                                    void* hip_stream);
 /* Row weights (host, s values): 1 for pivoted-QR rows, 1/sqrt(s pi_i) for
  * leverage-score rows. */
 SUBAP_API subap_status subap_model_weights(subap_model model, double* weights_host);

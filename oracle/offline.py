@@ -14,7 +14,7 @@ Test infrastructure only (see the package docstring).
                      fresh pivoted QR on the columns not chosen yet and takes
                      min(r, s - chosen) pivots.  With s = r this is exactly
                      one pivoted QR (interpolation, Section 3).
-* ``leverage_scores`` / ``leverage_sample``  the randomised selector of
+* ``leverage_scores`` / ``span_scores`` / ``leverage_sample``  the randomised selector of
                      Section 5.3 the paper recommends when s > r: rows drawn
                      with probability proportional to the squared row norms of
                      the orthonormal factor of [A(p_sel) X, b(p_sel)] (the span
@@ -146,10 +146,26 @@ def leverage_sample(scores, u):
     return rows.astype(np.int64), 1.0 / np.sqrt(s * pi)
 
 
+SPAN_RTOL = 1e-8
+
+
 def leverage_matrix(family, Q, select_param):
     """B = [A(p_sel) Q, b(p_sel)] (n x (r+1)), whose span is sampled."""
     AQ = np.asarray(family.matvec(select_param, Q))
     return np.column_stack([AQ, family.rhs(select_param)])
+
+
+def span_scores(B, rtol=SPAN_RTOL):
+    """Leverage scores of span([A(p_sel) Q, b]) for B = that n x (r+1) matrix.
+
+    When b lies in span(A(p_sel) Q) up to |R[r, r]| <= rtol |b| (R of the
+    Householder QR of B), the last direction is rounding noise and the span
+    is r-dimensional: the scores come from the first r columns only."""
+    B = np.asarray(B, dtype=np.float64)
+    r = B.shape[1] - 1
+    Qb, Rb = np.linalg.qr(B, mode="reduced")
+    k = r if abs(Rb[r, r]) <= rtol * np.linalg.norm(B[:, r]) else r + 1
+    return np.sum(Qb[:, :k] * Qb[:, :k], axis=1)
 
 
 def residual_bounds(rho, r, s, eps=None):
@@ -189,7 +205,7 @@ def offline(workload: dict, basis=None, rows=None, sample_u=None):
     weights = None
     if sample_u is not None:
         B = leverage_matrix(family, Q, workload["select_param"])
-        rows, weights = leverage_sample(leverage_scores(B), sample_u)
+        rows, weights = leverage_sample(span_scores(B), sample_u)
     elif rows is None:
         M = selection_matrix(family, Q, workload["select_param"])
         rows = select_rows(M, workload["s"])

@@ -22,11 +22,11 @@ LIB_PATH = os.path.join(_HERE, "libsubap.so")
 # subap_status
 OK, E_INVALID, E_NOMEM, E_HIP, E_RANK, E_NOCONV, E_NONFINITE, E_UNSUPPORTED = range(8)
 # subap_family
-FAMILY_DIFF2D, FAMILY_DIFF3D, FAMILY_KRR = 1, 2, 3
+FAMILY_DIFF2D, FAMILY_DIFF3D, FAMILY_KRR, FAMILY_DELAY = 1, 2, 3, 4
 # subap_precision
 FP64, FP32, BF16X3, FP16X3 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3}
-FAMILIES = {"diff2d": FAMILY_DIFF2D, "diff3d": FAMILY_DIFF3D, "krr": FAMILY_KRR}
+FAMILIES = {"diff2d": FAMILY_DIFF2D, "diff3d": FAMILY_DIFF3D, "krr": FAMILY_KRR, "delay": FAMILY_DELAY}
 
 EXPORTS = ("subap_offline", "subap_solve_batch", "subap_lift", "subap_sketched_residual", "subap_model_dims",
            "subap_model_rows", "subap_model_basis", "subap_model_free", "subap_profile_enable",
@@ -35,7 +35,7 @@ EXPORTS = ("subap_offline", "subap_solve_batch", "subap_lift", "subap_sketched_r
            "subap_surrogate_weights", "subap_surrogate_gradient", "subap_surrogate_train",
            "subap_surrogate_predict", "subap_surrogate_solve_batch", "subap_surrogate_free",
            "subap_surrogate_nparams", "subap_profile_count", "subap_status_string", "subap_last_error",
-           "subap_model_weights", "subap_residual_bounds")
+           "subap_model_weights", "subap_residual_bounds", "subap_output")
 PLAN_GRAPH, PLAN_AUTOTUNE = 1, 2
 # subap_selection
 SELECT_CPQR, SELECT_LEVERAGE = 0, 1
@@ -43,7 +43,8 @@ SELECT_CPQR, SELECT_LEVERAGE = 0, 1
 
 class ProblemDesc(C.Structure):
     _fields_ = [("family", C.c_int32), ("grid", C.c_int32), ("n", C.c_int64), ("dim", C.c_int32),
-                ("points", C.c_void_p), ("rhs", C.c_void_p), ("lam", C.c_double)]
+                ("points", C.c_void_p), ("rhs", C.c_void_p), ("lam", C.c_double), ("tau", C.c_double),
+                ("kappa", C.c_double), ("c_out", C.c_void_p)]
 
 
 class OfflineOpts(C.Structure):
@@ -93,6 +94,7 @@ def load(path: str = LIB_PATH):
     lib.subap_model_dims.argtypes = [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     lib.subap_model_rows.argtypes = [vp, vp]
     lib.subap_model_weights.argtypes = [vp, vp]
+    lib.subap_output.argtypes = [vp, vp, i64, vp, vp]
     lib.subap_residual_bounds.argtypes = [vp, vp, i64, C.c_double, vp, vp, vp]
     lib.subap_model_basis.argtypes = [vp, vp]
     lib.subap_model_free.argtypes = [vp]
@@ -160,15 +162,15 @@ def _host(a, dtype):
 # ---------------------------------------------------------------------------
 def subap_offline(family, grid=0, n=0, dim=0, points=None, rhs=None, lam=0.0, r=1, s=1,
                   snap_params=None, select_param=None, snap_tol=0.0, snap_maxiter=0,
-                  basis_in=None, rows_in=None, sample_u=None, stream=None):
+                  basis_in=None, rows_in=None, sample_u=None, tau=0.0, kappa=0.0, c_out=None, stream=None):
     """Run the offline phase; returns the opaque model handle (int).  With
     sample_u (s uniforms in [0, 1)) the rows come from leverage-score sampling."""
     lib = load()
     keep = [_host(points, np.float64), _host(rhs, np.float64), _host(snap_params, np.float64),
             _host(select_param, np.float64), _host(basis_in, np.float64), _host(rows_in, np.int64),
-            _host(sample_u, np.float64)]
+            _host(sample_u, np.float64), _host(c_out, np.float64)]
     addr = [None if a is None else a.ctypes.data for a in keep]
-    pd = ProblemDesc(family, grid, n, dim, addr[0], addr[1], lam)
+    pd = ProblemDesc(family, grid, n, dim, addr[0], addr[1], lam, tau, kappa, addr[7])
     sel = SELECT_LEVERAGE if sample_u is not None else SELECT_CPQR
     op = OfflineOpts(r, s, addr[2], addr[3], snap_tol, snap_maxiter, addr[4], addr[5], sel, addr[6])
     h = C.c_void_p()
@@ -395,6 +397,15 @@ def subap_model_rows(model):
     return out
 
 
+def subap_output(model, y, out, stream=None):
+    """y: (m, r) float64 cuda tensor; out: (m,) float64 -> c^T Q y per row."""
+    m = y.shape[0]
+    _, r, _, _ = subap_model_dims(model)
+    _expect(y, (m, r), "float64", "y")
+    _expect(out, (m,), "float64", "out")
+    _check(load().subap_output(C.c_void_p(model), _ptr(y), m, _ptr(out), _stream(stream)))
+
+
 def subap_model_weights(model):
     lib = load()
     _, _, s, _ = subap_model_dims(model)
@@ -442,6 +453,9 @@ class Model:
         if fam == FAMILY_KRR:
             self.handle = subap_offline(fam, n=w["n"], dim=w["dim"], points=w["points"], rhs=w["rhs"],
                                         lam=w["lam"], **kw)
+        elif fam == FAMILY_DELAY:
+            self.handle = subap_offline(fam, n=w["n"], rhs=w["rhs"], tau=w["tau"], kappa=w["kappa"],
+                                        c_out=w.get("c_out"), **kw)
         else:
             self.handle = subap_offline(fam, grid=w["grid"][0], rhs=w.get("rhs"), **kw)
         self.n, self.r, self.s, self.d = subap_model_dims(self.handle)
@@ -454,6 +468,13 @@ class Model:
 
     def weights(self):
         return subap_model_weights(self.handle)
+
+    def output(self, y, stream=None):
+        """c^T Q y for each row of y (m, r) -> (m,) cuda tensor."""
+        import torch
+        out = torch.empty(y.shape[0], dtype=torch.float64, device=y.device)
+        subap_output(self.handle, y, out, stream)
+        return out
 
     def residual_bounds(self, rho, eps=0.0, stream=None):
         """(lo, hi) cuda tensors bracketing the full relative residual (leverage rows)."""

@@ -112,7 +112,7 @@ namespace {
 
 void free_model(subap_model_s* M) {
   if (!M) return;
-  void* bufs[] = {M->Q, M->rows_d, M->wS, M->bS, M->QS, M->rhs, M->phi, M->delta64, M->delta32, M->delta64T, M->delta32T, M->points,
+  void* bufs[] = {M->Q, M->rows_d, M->wS, M->cQ, M->bS, M->QS, M->rhs, M->phi, M->delta64, M->delta32, M->delta64T, M->delta32T, M->points,
                   M->Dt64, M->D32, M->Qrm, M->Q32, M->Qhi, M->Qlo, M->Qh16, M->Ql16, M->colscale_inv,
                   M->work};
   for (void* b : bufs) dfree(b);
@@ -184,9 +184,24 @@ subap_status subap_offline(const subap_problem_desc* pd, const subap_offline_opt
     tmp.lambda = pd->lambda;
     if (!all_finite(pd->points, pd->n * pd->dim) || !all_finite(pd->rhs, pd->n))
       return invalid("points or rhs have non-finite entries");
+  } else if (pd->family == SUBAP_FAMILY_DELAY) {
+    if (pd->n < 2 || pd->n > 2147483647LL) return invalid("delay n must be in [2, 2^31 - 1]");
+    if (!(pd->tau > 0.0) || !std::isfinite(pd->tau)) return invalid("delay tau must be finite and > 0");
+    if (!(pd->kappa > 2.0) || !std::isfinite(pd->kappa)) return invalid("delay kappa must be finite and > 2");
+    if (!pd->rhs || !all_finite(pd->rhs, pd->n)) return invalid("delay needs a finite rhs");
+    tmp.n = pd->n;
+    tmp.dimx = 1;
+    tmp.d = 1;
+    tmp.F = 2;
+    tmp.h = 1.0;
+    tmp.inv_h2 = 1.0;
+    tmp.tau = pd->tau;
+    tmp.kappa = pd->kappa;
+    tmp.aff_c0 = 3.0;  // A_0 = 3 A_1
   } else {
     return invalid("unknown family");
   }
+  if (pd->c_out && !all_finite(pd->c_out, tmp.n)) return invalid("c_out has non-finite entries");
   if (o->r < 1 || o->r > kMaxR) return invalid("r must be in [1, 64]");
   if (o->s < o->r || o->s > kMaxS || o->s > tmp.n) return invalid("s must satisfy r <= s <= min(n, 256)");
   if (o->snap_tol < 0.0 || !std::isfinite(o->snap_tol)) return invalid("snap_tol must be finite and >= 0");
@@ -282,6 +297,16 @@ subap_status subap_model_rows(subap_model M, int64_t* rows_host) {
   if (!M || !rows_host) return invalid("model and rows_host must not be NULL");
   std::memcpy(rows_host, M->rows.data(), sizeof(int64_t) * M->rows.size());
   return SUBAP_OK;
+}
+
+subap_status subap_output(subap_model M, const double* y, int64_t m, double* out, void* hip_stream) {
+  clear_error();
+  if (!M) return invalid("model must not be NULL");
+  if (!M->cQ) return invalid("the model was built without an output vector (c_out)");
+  if (m < 0) return invalid("m must be >= 0");
+  if (m == 0) return SUBAP_OK;
+  if (!y || !out) return invalid("y_dev and out_dev must not be NULL");
+  return subap::output_apply(M, y, m, out, static_cast<hipStream_t>(hip_stream));
 }
 
 subap_status subap_model_weights(subap_model M, double* weights_host) {

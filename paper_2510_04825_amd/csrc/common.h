@@ -54,6 +54,8 @@ struct subap_model_s {
   int F = 0;          // FD: faces per row (2 * dimx)
   double h = 0.0, inv_h2 = 0.0;
   double lambda = 0.0;
+  double tau = 0.0, kappa = 0.0;      // delay family
+  double aff_c0 = 0.0;                // delay family: A_0 = aff_c0 A_1 (3)
   double bS_norm = 0.0;               // |S b|_2, or |b|_2 with weighted rows (b is p-independent in every family)
   int selection = 0;                  // subap_selection
   std::vector<double> weights;        // host copy of wS
@@ -67,6 +69,7 @@ struct subap_model_s {
   double* bS = nullptr;               // s: w_k b[rows[k]]
   double* QS = nullptr;               // s x r row-major: w_k Q[rows[k], c]
   double* rhs = nullptr;              // n (device copy of b)
+  double* cQ = nullptr;               // r: c^T Q (models built with an output vector)
 
   // finite-difference tables, layouts [(f * r + c) * s + k] and [(f * d + q) * s + k]
   double* phi = nullptr;              // s x F x d  mode values at face midpoints
@@ -99,6 +102,7 @@ subap_status offline_build(const subap_problem_desc* pd, const subap_offline_opt
                            hipStream_t st, subap_model_s* M);
 subap_status build_tables(subap_model_s* M, hipStream_t st);
 subap_status residual_bounds(const double* rho, int64_t m, double eps, double* lo, double* hi, hipStream_t st);
+subap_status output_apply(const subap_model_s* M, const double* y, int64_t m, double* out, hipStream_t st);
 
 // ---- online ----
 subap_status fd_solve(subap_model_s* M, const double* params, int64_t m, double* y,

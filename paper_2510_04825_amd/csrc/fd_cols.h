@@ -40,7 +40,29 @@ struct ColsModel {
   const float* d32T;    // [(f * s + k) * r + c]
   const double* bS;
   double inv_h2, bS_norm;
+  double aff_c0 = 0.0, aff_tau = 0.0;  // delay family: A(p) = p I - (c0 + e^{tau p}) A_1
 };
+
+// Coefficients of the term form G_k = sum_f a_f(p, k) Delta_{k,f} that every
+// family here shares:
+//   kCoefDiffusion  a_f = exp(sum_q p_q phi_{f,q}(face of row k)) / h^2, the
+//                   face coefficients of the diffusion stencil;
+//   kCoefDelay      F = 2, DP = 1: a_0 = p, a_1 = -(c0 + e^{tau p}), the
+//                   affine weights of S Q and S A_1 Q (Section 3.1, computing
+//                   S A(p*) X from precomputed pieces; Section 6.2.2).
+constexpr int kCoefDiffusion = 0, kCoefDelay = 1;
+
+template <int F, int DP, int COEF>
+__device__ __forceinline__ double cols_coef(const ColsModel& M, const double* pv, int f, int k) {
+  if constexpr (COEF == kCoefDelay) {
+    return f == 0 ? pv[0] : -(M.aff_c0 + exp(M.aff_tau * pv[0]));
+  } else {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < DP; ++q) t += pv[q] * M.phi[(f * DP + q) * M.s + k];
+    return exp(t) * M.inv_h2;
+  }
+}
 
 __host__ __device__ inline int cols_lds_doubles(int rmax, int smax, bool ref) {
   return (rmax + 1) * (rmax + 2) / 2         // packed [R | Q^T b]
@@ -63,18 +85,13 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// face coefficients / h^2 of rows k0 .. k0 + kColsRB - 1 into a[i * F + f]
-template <int F, int DP>
+// term coefficients of rows k0 .. k0 + kColsRB - 1 into a[i * F + f]
+template <int F, int DP, int COEF>
 __device__ __forceinline__ void cols_faces(const ColsModel& M, const double* pv, int k0, double* a, int lane) {
   for (int idx = lane; idx < kColsRB * F; idx += 64) {
     const int i = idx / F, f = idx % F;
     const int k = k0 + i;
-    double t = 0.0;
-    if (k < M.s) {
-#pragma unroll
-      for (int q = 0; q < DP; ++q) t += pv[q] * M.phi[(f * DP + q) * M.s + k];
-    }
-    a[idx] = (k < M.s) ? exp(t) * M.inv_h2 : 0.0;
+    a[idx] = (k < M.s) ? cols_coef<F, DP, COEF>(M, pv, f, k) : 0.0;
   }
   wave_sync_lds();
 }
@@ -105,16 +122,13 @@ __device__ __forceinline__ void cols_block(const ColsModel& M, int prec, int k0,
 
 // FP64 residual r_k = (S A(p) Q y - b)_k of row k (0 for k >= s); y in LDS.
 // The rows are taken 64 at a time, one per lane.
-template <int F, int DP>
+template <int F, int DP, int COEF>
 __device__ __forceinline__ double cols_residual_row(const ColsModel& M, const double* pv, const double* y, int k) {
   const int r = M.r, s = M.s;
   if (k >= s) return 0.0;
   double t = 0.0;
 #pragma unroll
   for (int f = 0; f < F; ++f) {
-    double arg = 0.0;
-#pragma unroll
-    for (int q = 0; q < DP; ++q) arg += pv[q] * M.phi[(f * DP + q) * s + k];
     const double* d = M.d64T + (static_cast<int64_t>(f) * s + k) * r;
     double u0 = 0.0, u1 = 0.0;
     int c = 0;
@@ -123,7 +137,7 @@ __device__ __forceinline__ double cols_residual_row(const ColsModel& M, const do
       u1 = fma(d[c + 1], y[c + 1], u1);
     }
     if (c < r) u0 = fma(d[c], y[c], u0);
-    t = fma(exp(arg) * M.inv_h2, u0 + u1, t);
+    t = fma(cols_coef<F, DP, COEF>(M, pv, f, k), u0 + u1, t);
   }
   return t - M.bS[k];
 }
@@ -157,7 +171,7 @@ __device__ __forceinline__ void cols_forward_solve(const double* R, int r1, int 
 // contraction or refinement steps (FP64 residuals); without it prec must be
 // FP64 and refine 0.  Writes y (r values), rho and status when the pointers
 // are not NULL.
-template <int F, int DP, bool BRED, bool REF>
+template <int F, int DP, bool BRED, bool REF, int COEF = kCoefDiffusion>
 __device__ void cols_solve(const ColsModel& M, const double* params, int prec, int refine, double* lds, int smax,
                            int lane, double* y_out, double* rho_out, int32_t* status_out) {
   constexpr int RB = kColsRB;
@@ -181,7 +195,7 @@ __device__ void cols_solve(const ColsModel& M, const double* params, int prec, i
   double rho2 = 0.0, r00 = 0.0;
   bool full_rank = true;
   for (int k0 = 0; k0 < s; k0 += RB) {
-    cols_faces<F, DP>(M, pv, k0, a, lane);
+    cols_faces<F, DP, COEF>(M, pv, k0, a, lane);
     double B[RB];
     cols_block<F>(M, REF ? prec : SUBAP_FP64, k0, a, lane, B);
     double Bb[BRED ? RB : 1];
@@ -275,11 +289,11 @@ __device__ void cols_solve(const ColsModel& M, const double* params, int prec, i
     double g = 0.0;
     for (int k0 = 0; k0 < s; k0 += RB) {
       if (k0 % 64 == 0) {  // the next 64 residual rows (the previous ones are read)
-        const double v = cols_residual_row<F, DP>(M, pv, yv, k0 + lane);
+        const double v = cols_residual_row<F, DP, COEF>(M, pv, yv, k0 + lane);
         res[lane] = v;
         wave_sync_lds();
       }
-      cols_faces<F, DP>(M, pv, k0, a, lane);
+      cols_faces<F, DP, COEF>(M, pv, k0, a, lane);
       double B[RB];
       cols_block<F>(M, prec, k0, a, lane, B);
 #pragma unroll
@@ -300,7 +314,7 @@ __device__ void cols_solve(const ColsModel& M, const double* params, int prec, i
   if (REF && (refine > 0 || prec != SUBAP_FP64)) {
     double t = 0.0;
     for (int k0 = 0; k0 < s; k0 += 64) {
-      const double v = cols_residual_row<F, DP>(M, pv, yv, k0 + lane);
+      const double v = cols_residual_row<F, DP, COEF>(M, pv, yv, k0 + lane);
       t = fma(v, v, t);
     }
 #pragma unroll

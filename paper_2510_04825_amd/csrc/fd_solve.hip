@@ -32,6 +32,7 @@ struct FDArgs {
   int32_t* status;
   int prec;
   int refine;
+  double aff_c0, aff_tau;  // delay family only
 };
 
 template <int TEAM, int R, int RM, int F, int DP>
@@ -171,24 +172,25 @@ __global__ __launch_bounds__(256) void k_fd_solve(FDArgs A) {
 }
 
 // Column-per-lane solve (fd_cols.h): one wavefront per parameter, two per block.
-template <int F, int DP, bool BRED, bool REF>
+template <int F, int DP, bool BRED, bool REF, int COEF>
 __global__ __launch_bounds__(128, REF ? 1 : (BRED ? 2 : 4)) void k_fd_cols(FDArgs A, int ldsw) {
   extern __shared__ double lds_cols[];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int64_t p = static_cast<int64_t>(blockIdx.x) * 2 + wave;
   if (p >= A.m) return;  // uniform per wavefront; no block-level barrier follows
-  const ColsModel M{A.r, A.s, A.phi, A.delta64T, A.delta32T, A.bS, A.inv_h2, A.bS_norm};
-  cols_solve<F, DP, BRED, REF>(M, A.params + p * DP, A.prec, A.refine, lds_cols + static_cast<int64_t>(wave) * ldsw, A.s,
+  const ColsModel M{A.r, A.s, A.phi, A.delta64T, A.delta32T, A.bS, A.inv_h2, A.bS_norm, A.aff_c0, A.aff_tau};
+  cols_solve<F, DP, BRED, REF, COEF>(M, A.params + p * DP, A.prec, A.refine, lds_cols + static_cast<int64_t>(wave) * ldsw, A.s,
                           lane, A.y + p * A.r, A.rho ? A.rho + p : nullptr, A.status ? A.status + p : nullptr);
 }
 
 // Sketched residual S(A(p) Q y - b) of given coefficients, FP64: one
 // wavefront per parameter, lanes over the selected rows.
-template <int F, int DP>
+template <int F, int DP, int COEF>
 __global__ __launch_bounds__(256) void k_fd_resid(const double* params, int64_t m, int r, int s,
                                                    const double* phi, const double* delta64, const double* bS,
-                                                   double inv_h2, double bS_norm, const double* y, double* res,
-                                                   double* norm) {
+                                                   double inv_h2, double bS_norm, double aff_c0, double aff_tau,
+                                                   const double* y, double* res, double* norm) {
+  ColsModel CM{r, s, phi, nullptr, nullptr, bS, inv_h2, bS_norm, aff_c0, aff_tau};
   const int64_t p = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (p >= m) return;
@@ -202,11 +204,9 @@ __global__ __launch_bounds__(256) void k_fd_resid(const double* params, int64_t 
   for (int k = lane; k < s; k += 64) {
     double t = 0.0;
     for (int f = 0; f < F; ++f) {
-      double arg = 0.0;
-      for (int q = 0; q < DP; ++q) arg += pv[q] * phi[(f * DP + q) * s + k];
       double u = 0.0;
       for (int c = 0; c < r; ++c) u += delta64[(f * r + c) * s + k] * y[p * r + c];
-      t += exp(arg) * inv_h2 * u;
+      t += cols_coef<F, DP, COEF>(CM, pv, f, k) * u;
     }
     t -= bS[k];
     if (!finite) t = __longlong_as_double(0x7ff8000000000000LL);
@@ -232,7 +232,7 @@ subap_status launch(const FDArgs& a, hipStream_t st) {
 }
 
 // Instantiated shapes: (TEAM, R) from s, RM from r.
-template <int F, int DP>
+template <int F, int DP, int COEF = kCoefDiffusion>
 subap_status launch_cols(const FDArgs& a, hipStream_t st) {
   const int64_t nb = (a.m + 1) / 2;
   if (nb > 0x7fffffff) {
@@ -245,11 +245,11 @@ subap_status launch_cols(const FDArgs& a, hipStream_t st) {
   ProfScope prof("fd_solve", st);
   const dim3 grid(static_cast<unsigned>(nb)), block(128);
   if (a.r == 64) {
-    if (ref) hipLaunchKernelGGL((k_fd_cols<F, DP, true, true>), grid, block, lds, st, a, ldsw);
-    else hipLaunchKernelGGL((k_fd_cols<F, DP, true, false>), grid, block, lds, st, a, ldsw);
+    if (ref) hipLaunchKernelGGL((k_fd_cols<F, DP, true, true, COEF>), grid, block, lds, st, a, ldsw);
+    else hipLaunchKernelGGL((k_fd_cols<F, DP, true, false, COEF>), grid, block, lds, st, a, ldsw);
   } else {
-    if (ref) hipLaunchKernelGGL((k_fd_cols<F, DP, false, true>), grid, block, lds, st, a, ldsw);
-    else hipLaunchKernelGGL((k_fd_cols<F, DP, false, false>), grid, block, lds, st, a, ldsw);
+    if (ref) hipLaunchKernelGGL((k_fd_cols<F, DP, false, true, COEF>), grid, block, lds, st, a, ldsw);
+    else hipLaunchKernelGGL((k_fd_cols<F, DP, false, false, COEF>), grid, block, lds, st, a, ldsw);
   }
   SUBAP_HIP_TRY(hipGetLastError());
   return SUBAP_OK;
@@ -274,7 +274,9 @@ subap_status dispatch(const FDArgs& a, hipStream_t st) {
 subap_status fd_solve(subap_model_s* M, const double* params, int64_t m, double* y, double* rho,
                       int32_t* status, int prec, int refine, hipStream_t st) {
   FDArgs a{params, m, M->r, M->s, M->phi, M->delta64, M->delta32, M->delta64T, M->delta32T, M->bS, M->inv_h2,
-           M->bS_norm, y, rho, status, prec, refine};
+           M->bS_norm, y, rho, status, prec, refine, M->aff_c0, M->tau};
+  // the delay family's two affine terms: column-per-lane solver for every shape
+  if (M->family == SUBAP_FAMILY_DELAY) return launch_cols<2, 1, kCoefDelay>(a, st);
   return M->dimx == 2 ? dispatch<4, 2>(a, st) : dispatch<6, 4>(a, st);
 }
 
@@ -282,12 +284,15 @@ subap_status fd_residual(subap_model_s* M, const double* params, int64_t m, cons
                          double* norm, hipStream_t st) {
   const unsigned grid = static_cast<unsigned>((m + 3) / 4);
   ProfScope prof("fd_residual", st);
-  if (M->dimx == 2)
-    hipLaunchKernelGGL((k_fd_resid<4, 2>), dim3(grid), dim3(256), 0, st, params, m, M->r, M->s, M->phi, M->delta64,
-                       M->bS, M->inv_h2, M->bS_norm, y, res, norm);
+  if (M->family == SUBAP_FAMILY_DELAY)
+    hipLaunchKernelGGL((k_fd_resid<2, 1, kCoefDelay>), dim3(grid), dim3(256), 0, st, params, m, M->r, M->s, M->phi,
+                       M->delta64, M->bS, M->inv_h2, M->bS_norm, M->aff_c0, M->tau, y, res, norm);
+  else if (M->dimx == 2)
+    hipLaunchKernelGGL((k_fd_resid<4, 2, kCoefDiffusion>), dim3(grid), dim3(256), 0, st, params, m, M->r, M->s,
+                       M->phi, M->delta64, M->bS, M->inv_h2, M->bS_norm, 0.0, 0.0, y, res, norm);
   else
-    hipLaunchKernelGGL((k_fd_resid<6, 4>), dim3(grid), dim3(256), 0, st, params, m, M->r, M->s, M->phi, M->delta64,
-                       M->bS, M->inv_h2, M->bS_norm, y, res, norm);
+    hipLaunchKernelGGL((k_fd_resid<6, 4, kCoefDiffusion>), dim3(grid), dim3(256), 0, st, params, m, M->r, M->s,
+                       M->phi, M->delta64, M->bS, M->inv_h2, M->bS_norm, 0.0, 0.0, y, res, norm);
   SUBAP_HIP_TRY(hipGetLastError());
   return SUBAP_OK;
 }

@@ -35,6 +35,7 @@ struct OpArgs {
   double h, inv_h2;
   double lambda;
   const double* points;   // KRR n x dimx
+  double tau, kappa, c0;  // delay family
 };
 
 __device__ __forceinline__ void fd_node(int64_t i, int N, int dimx, int* c) {
@@ -88,6 +89,26 @@ __global__ void k_fd_apply(OpArgs A, const double* params, int ncol, const doubl
   if (diag_out) diag_out[static_cast<int64_t>(col) * A.n + i] = dg;
 }
 
+// Delay family: Y[:, c] = (p I - (c0 + e^{tau p}) (T - kappa I) / tau) X[:, c],
+// T with ones on the first off-diagonals and at both ends of the diagonal.
+__global__ void k_delay_apply(OpArgs A, const double* params, int ncol, const double* X, double* Y,
+                              double* diag_out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int col = blockIdx.y;
+  if (i >= A.n || col >= ncol) return;
+  const double p = params[col];
+  const double g = (A.c0 + exp(A.tau * p)) / A.tau;
+  const bool end = i == 0 || i == A.n - 1;
+  if (Y) {
+    const double* x = X + static_cast<int64_t>(col) * A.n;
+    const double xi = x[i];
+    double tx = (i > 0 ? x[i - 1] : 0.0) + (i + 1 < A.n ? x[i + 1] : 0.0);
+    if (end) tx += xi;
+    Y[static_cast<int64_t>(col) * A.n + i] = p * xi - g * (tx - A.kappa * xi);
+  }
+  if (diag_out) diag_out[static_cast<int64_t>(col) * A.n + i] = p - g * ((end ? 1.0 : 0.0) - A.kappa);
+}
+
 // KRR: Y[i, c] = sum_j exp(-|t_i - t_j|^2 / (2 p_c^2)) X[j, c] + lambda X[i, c]
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_krr_apply(OpArgs A, const double* params, int ncol,
@@ -138,6 +159,8 @@ subap_status apply_op(const OpArgs& A, const double* params_d, int ncol, const d
         set_error("KRR point dimension must be 1..16");
         return SUBAP_E_INVALID;
     }
+  } else if (A.family == SUBAP_FAMILY_DELAY) {
+    hipLaunchKernelGGL(k_delay_apply, grid, dim3(kBlock), 0, st, A, params_d, ncol, X, Y, diag);
   } else {
     hipLaunchKernelGGL(k_fd_apply, grid, dim3(kBlock), 0, st, A, params_d, ncol, X, Y, diag);
   }
@@ -606,6 +629,46 @@ __global__ void k_fd_tables(const double* Qm, int64_t n, int r, int s, int N, in
   for (int cc = 0; cc < r; ++cc) QS[static_cast<int64_t>(k) * r + cc] = wk * Qm[static_cast<int64_t>(cc) * n + i];
 }
 
+// Delay family: the two affine pieces of row k, term 0 = w_k Q[i_k] (S Q) and
+// term 1 = w_k ((T Q)[i_k] - kappa Q[i_k]) / tau (S A_1 Q), in the layouts of
+// the finite-difference tables (F = 2).
+__global__ void k_delay_tables(const double* Qm, int64_t n, int r, int s, const int* rows, const double* wS,
+                               const double* rhs, double tau, double kappa, double* delta64, float* delta32,
+                               double* delta64T, float* delta32T, double* bS, double* QS) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= s) return;
+  const int64_t i = rows[k];
+  const double wk = wS[k];
+  const bool end = i == 0 || i == n - 1;
+  for (int cc = 0; cc < r; ++cc) {
+    const double* q = Qm + static_cast<int64_t>(cc) * n;
+    const double qi = q[i];
+    double tq = (i > 0 ? q[i - 1] : 0.0) + (i + 1 < n ? q[i + 1] : 0.0);
+    if (end) tq += qi;
+    const double t0 = wk * qi;
+    const double t1 = wk * ((tq - kappa * qi) / tau);
+    delta64[static_cast<int64_t>(cc) * s + k] = t0;
+    delta64[(static_cast<int64_t>(r) + cc) * s + k] = t1;
+    delta32[static_cast<int64_t>(cc) * s + k] = static_cast<float>(t0);
+    delta32[(static_cast<int64_t>(r) + cc) * s + k] = static_cast<float>(t1);
+    delta64T[static_cast<int64_t>(k) * r + cc] = t0;
+    delta64T[(static_cast<int64_t>(s) + k) * r + cc] = t1;
+    delta32T[static_cast<int64_t>(k) * r + cc] = static_cast<float>(t0);
+    delta32T[(static_cast<int64_t>(s) + k) * r + cc] = static_cast<float>(t1);
+    QS[static_cast<int64_t>(k) * r + cc] = t0;
+  }
+  bS[k] = wk * rhs[i];
+}
+
+// out[k] = sum_c cQ[c] y[k, c]
+__global__ void k_output(const double* cQ, int r, const double* y, int64_t m, double* out) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  double t = 0.0;
+  for (int c = 0; c < r; ++c) t = fma(cQ[c], y[k * r + c], t);
+  out[k] = t;
+}
+
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
   uint32_t u = __float_as_uint(x);
   if ((u & 0x7f800000u) == 0x7f800000u) return static_cast<uint16_t>(u >> 16);  // inf / nan
@@ -699,6 +762,7 @@ __global__ void k_gather_rows(const double* Qm, int64_t n, int r, int s, const i
 // searches the chunk prefixes, then walks its chunk in row order.
 // ----------------------------------------------------------------------------
 constexpr int kLevChunk = 1024;
+constexpr double kSpanRtol = 1e-8;  // b counts as inside span(A(p_sel) Q) below this
 
 __global__ void k_row_sumsq(const double* Qb, int64_t n, int k, double* sc) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -814,6 +878,14 @@ subap_status build_tables(subap_model_s* M, hipStream_t st) {
     hipLaunchKernelGGL(k_fp16_split, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
                        M->Q, n, r, scale.p, M->Qh16, M->Ql16);
     SUBAP_HIP_TRY(hipStreamSynchronize(st));
+  } else if (M->family == SUBAP_FAMILY_DELAY) {
+    const size_t tab = static_cast<size_t>(s) * M->F;
+    SUBAP_TRY(dalloc(&M->delta64, tab * r));
+    SUBAP_TRY(dalloc(&M->delta32, tab * r));
+    SUBAP_TRY(dalloc(&M->delta64T, tab * r));
+    SUBAP_TRY(dalloc(&M->delta32T, tab * r));
+    hipLaunchKernelGGL(k_delay_tables, dim3((s + 63) / 64), dim3(64), 0, st, M->Q, n, r, s, M->rows_d, M->wS,
+                       M->rhs, M->tau, M->kappa, M->delta64, M->delta32, M->delta64T, M->delta32T, M->bS, M->QS);
   } else {
     const size_t tab = static_cast<size_t>(s) * M->F;
     SUBAP_TRY(dalloc(&M->phi, tab * M->d));
@@ -860,7 +932,20 @@ static subap_status select_leverage(const OpArgs& A, subap_model_s* M, const sub
                                hipMemcpyDeviceToDevice, st));
   SUBAP_TRY(dalloc(&Qb.p, static_cast<size_t>(n) * k));
   SUBAP_TRY(dalloc(&diag.p, k));
+  // |b| before the QR overwrites B with its reflectors
+  DevVec part, bb;
+  SUBAP_TRY(dalloc(&part.p, kMaxPartials));
+  SUBAP_TRY(dalloc(&bb.p, 1));
+  SUBAP_TRY(col_dots(M->rhs, 0, M->rhs, 0, 0, n, 1, part.p, bb.p, st));
   SUBAP_TRY(householder_q(B.p, n, k, Qb.p, diag.p, st));
+  // b inside span(A(p_sel) Q) up to |R[r, r]| <= kSpanRtol |b|: its direction is
+  // rounding noise, so the sampled span is that of the first r columns
+  std::vector<double> dg(k);
+  double b2 = 0.0;
+  SUBAP_HIP_TRY(hipMemcpyAsync(dg.data(), diag.p, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+  SUBAP_HIP_TRY(hipMemcpyAsync(&b2, bb.p, sizeof(double), hipMemcpyDeviceToHost, st));
+  SUBAP_HIP_TRY(hipStreamSynchronize(st));
+  const int kspan = std::fabs(dg[r]) <= kSpanRtol * std::sqrt(b2) ? r : k;
   const int64_t nch = (n + kLevChunk - 1) / kLevChunk;
   SUBAP_TRY(dalloc(&sc.p, n));
   SUBAP_TRY(dalloc(&csum.p, nch));
@@ -874,7 +959,7 @@ static subap_status select_leverage(const OpArgs& A, subap_model_s* M, const sub
   SUBAP_TRY(dalloc(&M->wS, s));
   SUBAP_HIP_TRY(hipMemcpyAsync(u.p, o->sample_u, sizeof(double) * s, hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_row_sumsq, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, Qb.p,
-                     n, k, sc.p);
+                     n, kspan, sc.p);
   hipLaunchKernelGGL(k_chunk_sums, dim3(static_cast<unsigned>((nch + 63) / 64)), dim3(64), 0, st, sc.p, n, nch,
                      csum.p);
   hipLaunchKernelGGL(k_chunk_prefix, dim3(1), dim3(1), 0, st, csum.p, sc.p, n, nch, cpre.p, last);
@@ -888,6 +973,13 @@ static subap_status select_leverage(const OpArgs& A, subap_model_s* M, const sub
     set_error("leverage scores are all zero");
     return SUBAP_E_INVALID;
   }
+  return SUBAP_OK;
+}
+
+subap_status output_apply(const subap_model_s* M, const double* y, int64_t m, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_output, dim3(static_cast<unsigned>((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, M->cQ,
+                     M->r, y, m, out);
+  SUBAP_HIP_TRY(hipGetLastError());
   return SUBAP_OK;
 }
 
@@ -923,7 +1015,7 @@ subap_status offline_build(const subap_problem_desc* pd, const subap_offline_opt
     }
     M->dmax = 4.0 * rmax;
   }
-  OpArgs A{M->family, M->N, M->dimx, n, d, M->h, M->inv_h2, M->lambda, M->points};
+  OpArgs A{M->family, M->N, M->dimx, n, d, M->h, M->inv_h2, M->lambda, M->points, M->tau, M->kappa, M->aff_c0};
 
   DevVec X, params, diagR, W, pdup;
   SUBAP_TRY(dalloc(&X.p, static_cast<size_t>(n) * r));
@@ -961,6 +1053,15 @@ subap_status offline_build(const subap_problem_desc* pd, const subap_offline_opt
     SUBAP_HIP_TRY(hipMemcpyAsync(pdup.p, pd_h.data(), sizeof(double) * pd_h.size(), hipMemcpyHostToDevice, st));
     SUBAP_TRY(apply_op(A, pdup.p, r, M->Q, W.p, nullptr, st));
     SUBAP_TRY(select_rows_gpu(W.p, n, r, s, rows64, st));
+  }
+  if (pd->c_out) {  // c^T Q for subap_output
+    DevVec c, part;
+    SUBAP_TRY(dalloc(&c.p, n));
+    SUBAP_TRY(dalloc(&part.p, static_cast<size_t>(kMaxPartials) * r));
+    SUBAP_TRY(dalloc(&M->cQ, r));
+    SUBAP_HIP_TRY(hipMemcpyAsync(c.p, pd->c_out, sizeof(double) * n, hipMemcpyHostToDevice, st));
+    SUBAP_TRY(col_dots(M->Q, n, c.p, 0, 0, n, r, part.p, M->cQ, st));
+    SUBAP_HIP_TRY(hipStreamSynchronize(st));
   }
   SUBAP_TRY(dalloc(&M->rows_d, s));
   hipLaunchKernelGGL(k_copy_rows_i32, dim3((s + 63) / 64), dim3(64), 0, st, rows64, M->rows_d, s);

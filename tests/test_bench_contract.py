@@ -17,5 +17,5 @@ def test_help_lists_the_workloads():
     res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"],
                          capture_output=True, text=True, timeout=120)
     assert res.returncode == 0
-    for wl in ("krr", "diffusion3d", "uneven", "surrogate", "lift", "leverage"):
+    for wl in ("krr", "diffusion3d", "uneven", "surrogate", "lift", "leverage", "delay"):
         assert wl in res.stdout

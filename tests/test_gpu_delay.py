@@ -1,0 +1,148 @@
+"""GPU parity for the delay system of Section 6.2.2 (real parameter): the
+online solve assembles S A(p) X = p S X - (3 + e^{tau p}) S A_1 X from two
+precomputed s x r pieces, and the output H(p) = (c^T X) y.
+
+Bars, as for the other families: row indices bit-exact for a given basis;
+delta_res <= 1e-12 for the FP64 contraction and <= 1e-6 for FP32 + one FP64
+refinement step; the sketched residual within 1e-9 relative or 1e-13
+absolute (this family's residuals sit near FP64 rounding, about 1e-15, where
+two evaluation orders differ in the last bits); the output
+within 1e-12 relative of the oracle's c^T Q y on the GPU's y.  The full chain
+(GPU snapshots by conjugate gradients) is compared by residual: within 1e-8
+of the oracle's relative residual.
+"""
+import numpy as np
+import pytest
+
+import subap_inputs as si
+from oracle import offline as O
+from oracle import online as On
+from paper_2510_04825_amd import binding as B
+from tests.gpu_util import device, header, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def delay_small():
+    w = si.delay(n=3000, r=10, s=40, m=48)
+    return w, O.offline(w)
+
+
+@pytest.fixture(scope="module")
+def delay_model(delay_small):
+    w, off = delay_small
+    device()
+    M = B.Model(w, basis=off["Q"])
+    yield M
+    M.free()
+
+
+def test_delay_rows_bit_exact_given_basis(delay_small, delay_model):
+    w, off = delay_small
+    header("delay rows")
+    assert np.array_equal(delay_model.rows(), off["rows"])
+    np.testing.assert_array_equal(delay_model.weights(), 1.0)
+
+
+@pytest.mark.parametrize("prec,ref,tol", [(B.FP64, 0, 1e-12), (B.FP32, 1, 1e-6), (B.FP32, 2, 1e-6)])
+def test_delay_solve_matches_oracle(delay_small, delay_model, prec, ref, tol):
+    import torch
+    w, off = delay_small
+    header(f"delay solve prec={prec} refine={ref}")
+    fam, Q = off["family"], off["Q"]
+    P = w["test_params"]
+    yo = On.solve(fam, Q, off["rows"], P)
+    y, rho, st = delay_model.solve(to_dev(P), prec, ref)
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == B.OK)
+    yg = y.cpu().numpy()
+    d = max(On.delta_res(fam, Q, p, a, b) for p, a, b in zip(P, yg, yo))
+    assert d <= tol, d
+    rho_o = np.array([On.sketched_residual(fam, Q, off["rows"], p, a) for p, a in zip(P, yg)])
+    np.testing.assert_allclose(rho.cpu().numpy(), rho_o, rtol=1e-9 if prec == B.FP64 else 1e-6, atol=1e-13)
+
+
+def test_delay_output_is_c_transpose_q_y(delay_small, delay_model):
+    import torch
+    w, off = delay_small
+    header("delay output")
+    P = to_dev(w["test_params"])
+    y, _, _ = delay_model.solve(P)
+    H = delay_model.output(y)
+    torch.cuda.synchronize()
+    Ho = On.output(w["c_out"], off["Q"], y.cpu().numpy())
+    np.testing.assert_allclose(H.cpu().numpy(), Ho, rtol=1e-12)
+    # and the transfer function itself: the method's accuracy here is far below 1e-6
+    fam = off["family"]
+    for p, h in zip(w["test_params"][:4], H.cpu().numpy()[:4]):
+        x = np.linalg.solve(fam.matrix(p).toarray(), fam.rhs(p))
+        assert abs(h - w["c_out"] @ x) <= 1e-8 * abs(w["c_out"] @ x)
+
+
+def test_delay_sketched_residual_entry_point(delay_small, delay_model):
+    import torch
+    w, off = delay_small
+    header("delay sketched residual")
+    P = to_dev(w["test_params"][:16])
+    y, rho, _ = delay_model.solve(P)
+    res, norm = delay_model.sketched_residual(P, y, vector=True)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(norm.cpu().numpy(), rho.cpu().numpy(), rtol=1e-9, atol=1e-13)
+    fam, Q = off["family"], off["Q"]
+    for p, a, rv in zip(w["test_params"][:16], y.cpu().numpy(), res.cpu().numpy()):
+        want = fam.rows(p, off["rows"]) @ (Q @ a) - fam.rhs_rows(p, off["rows"])
+        np.testing.assert_allclose(rv, want, rtol=1e-9, atol=1e-12 * np.abs(fam.rhs(p)).max())
+
+
+def test_delay_full_chain_by_residual(delay_small):
+    import torch
+    w, off = delay_small
+    header("delay full chain")
+    device()
+    M = B.Model(w, snap_tol=1e-13)
+    try:
+        P = w["test_params"][:12]
+        y, _, st = M.solve(to_dev(P))
+        torch.cuda.synchronize()
+        assert np.all(st.cpu().numpy() == B.OK)
+        Qg, rows = M.basis(), M.rows()
+        fam = off["family"]
+        yo = On.solve(fam, off["Q"], off["rows"], P)
+        for p, a, b in zip(P, y.cpu().numpy(), yo):
+            rg = On.residual(fam, Qg @ a, p)
+            ro = On.residual(fam, off["Q"] @ b, p)
+            assert abs(rg - ro) <= 1e-8, (p, rg, ro)
+    finally:
+        M.free()
+
+
+def test_delay_leverage_rows(delay_small):
+    import torch
+    w, off = delay_small
+    header("delay leverage rows")
+    u = si.sample_uniforms(w["s"], seed=77)
+    offl = O.offline(w, basis=off["Q"], sample_u=u)
+    device()
+    M = B.Model(w, basis=off["Q"], sample_u=u)
+    try:
+        assert np.array_equal(M.rows(), offl["rows"])
+        np.testing.assert_allclose(M.weights(), offl["weights"], rtol=1e-12)
+        P = w["test_params"][:16]
+        y, _, _ = M.solve(to_dev(P))
+        torch.cuda.synchronize()
+        yo = On.solve(offl["family"], offl["Q"], offl["rows"], P, offl["weights"])
+        d = max(On.delta_res(offl["family"], offl["Q"], p, a, b) for p, a, b in zip(P, y.cpu().numpy(), yo))
+        assert d <= 1e-12, d
+    finally:
+        M.free()
+
+
+def test_delay_rejects_bad_problems():
+    w = si.delay(n=100, r=4, s=8, m=4)
+    device()
+    for key, bad in (("tau", 0.0), ("kappa", 2.0), ("rhs", None)):
+        ww = dict(w)
+        ww[key] = bad
+        with pytest.raises((B.SubapError, TypeError)):
+            B.Model(ww)

@@ -37,7 +37,7 @@ def lev(request):
     u = si.sample_uniforms(w["s"], seed=31)
     off = O.offline(w, sample_u=u)
     B_ = O.leverage_matrix(off["family"], off["Q"], w["select_param"])
-    sc = O.leverage_scores(B_)
+    sc = O.span_scores(B_)
     device()
     M = B.Model(w, basis=off["Q"], sample_u=u)
     yield request.param, w, off, u, sc, M

@@ -178,7 +178,7 @@ def test_leverage_selection_estimates_the_full_residual():
     off = O.offline(w)
     fam, Q, p = off["family"], off["Q"], w["select_param"]
     B = O.leverage_matrix(fam, Q, p)
-    sc = O.leverage_scores(B)
+    sc = O.span_scores(B)
     lo_hi_ok, ratios = 0, []
     for seed in range(20):
         rows, wt = O.leverage_sample(sc, si.sample_uniforms(w["s"], seed=seed))
@@ -204,7 +204,20 @@ def test_offline_with_sample_u_returns_weighted_rows():
     u = si.sample_uniforms(20, seed=3)
     off = O.offline(w, sample_u=u)
     B = O.leverage_matrix(off["family"], off["Q"], w["select_param"])
-    rows, wt = O.leverage_sample(O.leverage_scores(B), u)
+    rows, wt = O.leverage_sample(O.span_scores(B), u)
     np.testing.assert_array_equal(off["rows"], rows)
     np.testing.assert_array_equal(off["weights"], wt)
     assert O.offline(w)["weights"] is None
+
+
+def test_span_scores_drop_a_right_hand_side_inside_the_span():
+    # b in span(A Q): span([A Q, b]) is r-dimensional, the scores are those of
+    # A Q and sum to r; a generic b adds its direction and the sum is r + 1
+    rng = np.random.default_rng(14)
+    AQ = rng.standard_normal((80, 6))
+    inside = np.column_stack([AQ, AQ @ rng.standard_normal(6)])
+    np.testing.assert_allclose(O.span_scores(inside), O.leverage_scores(AQ), rtol=1e-10, atol=1e-14)
+    assert abs(O.span_scores(inside).sum() - 6.0) < 1e-12
+    generic = np.column_stack([AQ, rng.standard_normal(80)])
+    np.testing.assert_allclose(O.span_scores(generic), O.leverage_scores(generic), rtol=1e-12)
+    assert abs(O.span_scores(generic).sum() - 7.0) < 1e-12
