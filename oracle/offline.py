@@ -21,6 +21,11 @@ Test infrastructure only (see the package docstring).
                      Section 5.3.1 samples so that the sketched residual
                      estimates the full one), each sampled row weighted by
                      1/sqrt(s pi_i) as the Section 5.3 footnote prescribes.
+* ``lupp_pivots`` / ``select_rows_lu``  LU with partial pivoting on
+                     A(p_sel) X, the other deterministic selector of Section
+                     5.3 (rounds for s > r, as for pivoted QR).
+* ``union_rows``     the union of the pivots found at several points
+                     (Section 5.3.2).
 * ``offline``        all of the above for a workload.
 
 Readings where the paper is silent (kept identical in the GPU library):
@@ -181,19 +186,80 @@ def residual_bounds(rho, r, s, eps=None):
     return rho / (1.0 + eps), hi
 
 
+def lupp_pivots(W, k, tie_rtol=TIE_RTOL):
+    """First k pivot rows of Gaussian elimination with partial pivoting on the
+    n x r matrix W (Section 5.3, LUPP on A(p_i) X).
+
+    At step j the pivot is the smallest row index, among rows not pivoted yet,
+    whose |W[i, j]| is >= (1 - tie_rtol) * max; every other row not pivoted
+    yet then loses the multiple W[i, j] / W[piv, j] of the pivot row."""
+    W = np.array(W, dtype=np.float64, copy=True)
+    n, r = W.shape
+    k = min(k, n, r)
+    free = np.ones(n, dtype=bool)
+    piv = []
+    for j in range(k):
+        mag = np.abs(W[:, j])
+        mag[~free] = -1.0
+        top = mag.max()
+        i = int(np.flatnonzero(mag >= (1.0 - tie_rtol) * top)[0])
+        piv.append(i)
+        free[i] = False
+        if W[i, j] != 0.0:
+            f = W[free, j] / W[i, j]
+            W[np.ix_(free, np.arange(j + 1, r))] -= np.outer(f, W[i, j + 1:])
+    return np.array(piv, dtype=np.int64)
+
+
+def select_rows_lu(W, s, tie_rtol=TIE_RTOL):
+    """s row indices of W = A(p_sel) X by rounds of LUPP: each round runs a
+    fresh elimination on the rows not chosen yet and takes min(r, s - chosen)
+    pivots (s = r is one LUPP)."""
+    W = np.asarray(W, dtype=np.float64)
+    n, r = W.shape
+    if not (r <= s <= n):
+        raise ValueError("need r <= s <= n")
+    chosen = []
+    remaining = np.arange(n)
+    while len(chosen) < s:
+        take = min(r, s - len(chosen))
+        piv = lupp_pivots(W[remaining], take, tie_rtol)
+        new = remaining[piv]
+        chosen.extend(int(v) for v in new)
+        keep = np.ones(remaining.size, dtype=bool)
+        keep[piv] = False
+        remaining = remaining[keep]
+    return np.array(chosen, dtype=np.int64)
+
+
+def union_rows(row_sets):
+    """Union of several row selections in order of first appearance
+    (Section 5.3.2: r pivots at each of t points, collected)."""
+    out, seen = [], set()
+    for rows in row_sets:
+        for v in rows:
+            if int(v) not in seen:
+                seen.add(int(v))
+                out.append(int(v))
+    return np.array(out, dtype=np.int64)
+
+
 def selection_matrix(family, Q, select_param):
     """M = (A(p_sel) Q)^T, the r x n matrix whose columns are pivoted."""
     return np.asarray(family.matvec(select_param, Q)).T
 
 
-def offline(workload: dict, basis=None, rows=None, sample_u=None):
+def offline(workload: dict, basis=None, rows=None, sample_u=None, selection="cpqr", select_params=None):
     """Algorithm 3.1 steps 1-3 for a ``subap_inputs`` workload.
 
     ``basis``: optional n x r matrix used instead of the snapshot solves (it
     is still orthonormalised).  ``rows``: optional row indices used instead of
     the pivoted-QR selection.  ``sample_u``: s uniforms in [0, 1); when given,
     rows come from leverage-score sampling of [A(p_sel) Q, b(p_sel)] and carry
-    weights.  Returns dict(family, X (raw snapshots or None), Q, R, rows,
+    weights.  ``selection``: "cpqr" (pivoted QR on (A(p_sel) Q)^T) or "lu"
+    (LUPP on A(p_sel) Q).  ``select_params``: several points (t x d); the rows
+    are then the union of r pivots at each (Section 5.3.2), and s is their
+    count.  Returns dict(family, X (raw snapshots or None), Q, R, rows,
     weights (None for unweighted rows)).
     """
     family = fam.from_workload(workload)
@@ -207,6 +273,11 @@ def offline(workload: dict, basis=None, rows=None, sample_u=None):
         B = leverage_matrix(family, Q, workload["select_param"])
         rows, weights = leverage_sample(span_scores(B), sample_u)
     elif rows is None:
-        M = selection_matrix(family, Q, workload["select_param"])
-        rows = select_rows(M, workload["s"])
+        def pick(p, k):
+            M = selection_matrix(family, Q, p)
+            return select_rows_lu(M.T, k) if selection == "lu" else select_rows(M, k)
+        if select_params is not None:
+            rows = union_rows([pick(p, Q.shape[1]) for p in np.atleast_2d(select_params)])
+        else:
+            rows = pick(workload["select_param"], workload["s"])
     return dict(family=family, X=X, Q=Q, R=R, rows=np.asarray(rows, dtype=np.int64), weights=weights)

@@ -221,3 +221,49 @@ def test_span_scores_drop_a_right_hand_side_inside_the_span():
     generic = np.column_stack([AQ, rng.standard_normal(80)])
     np.testing.assert_allclose(O.span_scores(generic), O.leverage_scores(generic), rtol=1e-12)
     assert abs(O.span_scores(generic).sum() - 7.0) < 1e-12
+
+
+# --- LU with partial pivoting (Section 5.3) and the union of pivots (Section 5.3.2)
+
+def test_lupp_pivots_equal_lapack_partial_pivoting():
+    rng = np.random.default_rng(15)
+    W = rng.standard_normal((40, 7))
+    _, ipiv = sla.lu_factor(W)
+    perm = np.arange(40)
+    for j, pj in enumerate(ipiv):
+        perm[[j, pj]] = perm[[pj, j]]
+    np.testing.assert_array_equal(O.lupp_pivots(W, 7), perm[:7])
+
+
+def test_lupp_on_a_basis_is_the_deim_greedy_selection():
+    # DEIM's indices (eq. (3.5)): first argmax |u_1|, then argmax of the
+    # residual of interpolating u_l at the indices so far
+    rng = np.random.default_rng(16)
+    U, _ = np.linalg.qr(rng.standard_normal((60, 6)))
+    idx = [int(np.argmax(np.abs(U[:, 0])))]
+    for l in range(1, 6):
+        c = np.linalg.solve(U[idx, :l], U[idx, l])
+        res = U[:, l] - U[:, :l] @ c
+        idx.append(int(np.argmax(np.abs(res))))
+    np.testing.assert_array_equal(O.lupp_pivots(U, 6), idx)
+
+
+def test_lu_rounds_and_union():
+    rng = np.random.default_rng(17)
+    W = rng.standard_normal((50, 5))
+    rows = O.select_rows_lu(W, 12)
+    assert rows.size == 12 and np.unique(rows).size == 12
+    np.testing.assert_array_equal(rows[:5], O.lupp_pivots(W, 5))
+    rest = np.setdiff1d(np.arange(50), rows[:5])
+    np.testing.assert_array_equal(rows[5:10], rest[O.lupp_pivots(W[rest], 5)])
+    np.testing.assert_array_equal(O.union_rows([[3, 1, 4], [1, 5, 9], [2, 6, 5]]), [3, 1, 4, 5, 9, 2, 6])
+
+
+def test_offline_union_of_pivots_at_several_points():
+    w = si.diffusion2d(N=12, r=4, s=4)
+    pts = np.array([[-0.5, 0.5], [0.0, 0.0], [0.7, -0.2]])
+    off = O.offline(w, selection="lu", select_params=pts)
+    fam, Q = off["family"], off["Q"]
+    sets = [O.select_rows_lu(O.selection_matrix(fam, Q, p).T, 4) for p in pts]
+    np.testing.assert_array_equal(off["rows"], O.union_rows(sets))
+    assert 4 <= off["rows"].size <= 12
