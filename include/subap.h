@@ -112,7 +112,8 @@ typedef struct subap_model_s* subap_model;   /* opaque; owns device buffers */
 /* How the s rows are chosen (Section 5.3). */
 typedef enum {
   SUBAP_SELECT_CPQR = 0,     /* rounds of column-pivoted QR on (A(p_sel) X)^T  */
-  SUBAP_SELECT_LEVERAGE = 1  /* leverage-score sampling with weights           */
+  SUBAP_SELECT_LEVERAGE = 1, /* leverage-score sampling with weights           */
+  SUBAP_SELECT_LU = 2        /* rounds of LU with partial pivoting on A(p_sel) X */
 } subap_selection;
 
 typedef struct {
@@ -130,6 +131,10 @@ typedef struct {
   const double* sample_u;      /* LEVERAGE: host, s uniforms in [0, 1), one
                                   per sampled row (the caller owns the random
                                   stream, so a selection is reproducible)     */
+  int32_t n_select;            /* CPQR / LU: > 1 selects the union of the r
+                                  pivots found at each of n_select points
+                                  (Section 5.3.2); 0 or 1 = one point         */
+  const double* select_params; /* host, n_select x d row-major (n_select > 1) */
 } subap_offline_opts;
 
 /*
@@ -155,6 +160,14 @@ typedef struct {
       S b is multiplied by its weight, and rho (subap_solve_batch) becomes
       |W S (A(p) X y - b)| / |b|, an estimate of the full relative residual
       (subap_residual_bounds).  Duplicate rows are allowed.
+      With selection = SUBAP_SELECT_LU the rounds run LU with partial
+      pivoting on W = A(select_param) Q (n x r) instead (Section 5.3): pivot
+      of column j = smallest free row index with |W[i,j]| >= (1 - 1e-6) max,
+      then every free row i loses W[i,j] / W[piv,j] times the pivot row.
+      With n_select > 1 (CPQR or LU) the rows are the union, in order of
+      first appearance, of the r pivots found at each of select_params
+      (Section 5.3.2); the model's s is then the union's size (r..256, read it
+      with subap_model_dims) and opts->s is ignored.
    Then builds the per-row tables the online kernels read.
  * Blocks until the model is complete.  On success *out owns device memory;
  * release it with subap_model_free.  SUBAP_E_NOCONV if a snapshot solve

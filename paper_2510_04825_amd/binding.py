@@ -38,7 +38,7 @@ EXPORTS = ("subap_offline", "subap_solve_batch", "subap_lift", "subap_sketched_r
            "subap_model_weights", "subap_residual_bounds", "subap_output")
 PLAN_GRAPH, PLAN_AUTOTUNE = 1, 2
 # subap_selection
-SELECT_CPQR, SELECT_LEVERAGE = 0, 1
+SELECT_CPQR, SELECT_LEVERAGE, SELECT_LU = 0, 1, 2
 
 
 class ProblemDesc(C.Structure):
@@ -51,7 +51,7 @@ class OfflineOpts(C.Structure):
     _fields_ = [("r", C.c_int32), ("s", C.c_int32), ("snap_params", C.c_void_p),
                 ("select_param", C.c_void_p), ("snap_tol", C.c_double), ("snap_maxiter", C.c_int32),
                 ("basis_in", C.c_void_p), ("rows_in", C.c_void_p), ("selection", C.c_int32),
-                ("sample_u", C.c_void_p)]
+                ("sample_u", C.c_void_p), ("n_select", C.c_int32), ("select_params", C.c_void_p)]
 
 
 class SolveOpts(C.Structure):
@@ -162,17 +162,23 @@ def _host(a, dtype):
 # ---------------------------------------------------------------------------
 def subap_offline(family, grid=0, n=0, dim=0, points=None, rhs=None, lam=0.0, r=1, s=1,
                   snap_params=None, select_param=None, snap_tol=0.0, snap_maxiter=0,
-                  basis_in=None, rows_in=None, sample_u=None, tau=0.0, kappa=0.0, c_out=None, stream=None):
+                  basis_in=None, rows_in=None, sample_u=None, tau=0.0, kappa=0.0, c_out=None, selection=None,
+                  select_params=None, stream=None):
     """Run the offline phase; returns the opaque model handle (int).  With
-    sample_u (s uniforms in [0, 1)) the rows come from leverage-score sampling."""
+    sample_u (s uniforms in [0, 1)) the rows come from leverage-score sampling;
+    selection SELECT_LU picks rows by LU with partial pivoting; select_params
+    (t x d, t > 1) takes the union of the r pivots at each point."""
     lib = load()
     keep = [_host(points, np.float64), _host(rhs, np.float64), _host(snap_params, np.float64),
             _host(select_param, np.float64), _host(basis_in, np.float64), _host(rows_in, np.int64),
-            _host(sample_u, np.float64), _host(c_out, np.float64)]
+            _host(sample_u, np.float64), _host(c_out, np.float64), _host(select_params, np.float64)]
     addr = [None if a is None else a.ctypes.data for a in keep]
     pd = ProblemDesc(family, grid, n, dim, addr[0], addr[1], lam, tau, kappa, addr[7])
-    sel = SELECT_LEVERAGE if sample_u is not None else SELECT_CPQR
-    op = OfflineOpts(r, s, addr[2], addr[3], snap_tol, snap_maxiter, addr[4], addr[5], sel, addr[6])
+    if selection is None:
+        selection = SELECT_LEVERAGE if sample_u is not None else SELECT_CPQR
+    nsel = 0 if select_params is None else int(np.atleast_2d(select_params).shape[0])
+    op = OfflineOpts(r, s, addr[2], addr[3], snap_tol, snap_maxiter, addr[4], addr[5], selection, addr[6], nsel,
+                     addr[8])
     h = C.c_void_p()
     _check(lib.subap_offline(C.byref(pd), C.byref(op), _stream(stream), C.byref(h)))
     return h.value
@@ -442,12 +448,12 @@ class Model:
     """Owns a subap_model built from a ``subap_inputs`` workload dict."""
 
     def __init__(self, workload: dict, basis=None, rows=None, snap_tol=0.0, snap_maxiter=0, stream=None,
-                 sample_u=None):
+                 sample_u=None, selection=None, select_params=None):
         w = workload
         fam = FAMILIES[w["family"]]
         kw = dict(r=w["r"], s=w["s"], snap_params=w.get("snap_params"), select_param=w.get("select_param"),
                   snap_tol=snap_tol, snap_maxiter=snap_maxiter, basis_in=None, rows_in=rows, sample_u=sample_u,
-                  stream=stream)
+                  selection=selection, select_params=select_params, stream=stream)
         if basis is not None:
             kw["basis_in"] = np.asfortranarray(basis, dtype=np.float64).T  # column-major n x r
         if fam == FAMILY_KRR:

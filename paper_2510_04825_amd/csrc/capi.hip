@@ -203,11 +203,18 @@ subap_status subap_offline(const subap_problem_desc* pd, const subap_offline_opt
   }
   if (pd->c_out && !all_finite(pd->c_out, tmp.n)) return invalid("c_out has non-finite entries");
   if (o->r < 1 || o->r > kMaxR) return invalid("r must be in [1, 64]");
-  if (o->s < o->r || o->s > kMaxS || o->s > tmp.n) return invalid("s must satisfy r <= s <= min(n, 256)");
+  const bool uni = !o->rows_in && o->n_select > 1 && o->selection != SUBAP_SELECT_LEVERAGE;
+  if (o->n_select < 0) return invalid("n_select must be >= 0");
+  if (uni) {
+    if (!o->select_params) return invalid("n_select > 1 needs select_params");
+    if (o->r > tmp.n) return invalid("r must not exceed n");
+  } else if (o->s < o->r || o->s > kMaxS || o->s > tmp.n) {
+    return invalid("s must satisfy r <= s <= min(n, 256)");
+  }
   if (o->snap_tol < 0.0 || !std::isfinite(o->snap_tol)) return invalid("snap_tol must be finite and >= 0");
   if (o->snap_maxiter < 0) return invalid("snap_maxiter must be >= 0");
   tmp.r = o->r;
-  tmp.s = o->s;
+  tmp.s = uni ? o->r : o->s;  // a union of pivots sets s after the selection
   if (!o->basis_in) {
     if (!o->snap_params) return invalid("snap_params needed without basis_in");
     if (!all_finite(o->snap_params, static_cast<int64_t>(o->r) * tmp.d)) return invalid("snap_params not finite");
@@ -218,16 +225,26 @@ subap_status subap_offline(const subap_problem_desc* pd, const subap_offline_opt
     return invalid("basis_in has non-finite entries");
   }
   if (!o->rows_in) {
-    if (o->selection != SUBAP_SELECT_CPQR && o->selection != SUBAP_SELECT_LEVERAGE)
-      return invalid("selection must be SUBAP_SELECT_CPQR or SUBAP_SELECT_LEVERAGE");
+    if (o->selection != SUBAP_SELECT_CPQR && o->selection != SUBAP_SELECT_LEVERAGE &&
+        o->selection != SUBAP_SELECT_LU)
+      return invalid("selection must be SUBAP_SELECT_CPQR, SUBAP_SELECT_LEVERAGE or SUBAP_SELECT_LU");
     if (o->selection == SUBAP_SELECT_LEVERAGE) {
       if (!o->sample_u) return invalid("leverage-score selection needs sample_u");
       for (int k = 0; k < o->s; ++k)
         if (!(o->sample_u[k] >= 0.0 && o->sample_u[k] < 1.0)) return invalid("sample_u must lie in [0, 1)");
     }
-    if (!o->select_param) return invalid("select_param needed without rows_in");
-    if (!all_finite(o->select_param, tmp.d)) return invalid("select_param not finite");
-    if (pd->family == SUBAP_FAMILY_KRR && !(o->select_param[0] > 0.0)) return invalid("KRR select_param must be > 0");
+    if (uni) {
+      if (!all_finite(o->select_params, static_cast<int64_t>(o->n_select) * tmp.d))
+        return invalid("select_params not finite");
+      if (pd->family == SUBAP_FAMILY_KRR)
+        for (int t = 0; t < o->n_select; ++t)
+          if (!(o->select_params[t] > 0.0)) return invalid("KRR select_params must be > 0");
+    } else {
+      if (!o->select_param) return invalid("select_param needed without rows_in");
+      if (!all_finite(o->select_param, tmp.d)) return invalid("select_param not finite");
+      if (pd->family == SUBAP_FAMILY_KRR && !(o->select_param[0] > 0.0))
+        return invalid("KRR select_param must be > 0");
+    }
   } else {
     std::unordered_set<int64_t> seen;
     for (int k = 0; k < o->s; ++k) {

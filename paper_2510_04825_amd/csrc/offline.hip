@@ -588,6 +588,95 @@ subap_status select_rows_gpu(const double* W0, int64_t n, int r, int s, int64_t*
 }
 
 // ----------------------------------------------------------------------------
+// Row selection by LU with partial pivoting on W = A(p_sel) Q (n x r), in
+// rounds like the pivoted QR above: the pivot of column j is the smallest row
+// index, among rows not chosen yet, whose |W[i, j]| is >= (1 - kTieRtol) * max;
+// every other free row then loses W[i, j] / W[piv, j] times the pivot row.
+// ----------------------------------------------------------------------------
+__global__ void k_col_abs(const double* W, int64_t n, int j, const int* chosen, double* v) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  v[i] = chosen[i] ? -1.0 : fabs(W[static_cast<int64_t>(j) * n + i]);
+}
+
+// pick the pivot, record it, keep a copy of its row (r entries) in prow
+__global__ void k_lu_pivot(const double* W, int64_t n, int r, const int64_t* ipart, int nblk, int* chosen,
+                           int64_t* piv_out, int slot, double* prow, int* bad) {
+  int64_t best = INT64_MAX;
+  for (int k = 0; k < nblk; ++k) best = min(best, ipart[k]);
+  if (best == INT64_MAX) {
+    *bad = 1;
+    return;
+  }
+  chosen[best] = 1;
+  piv_out[slot] = best;
+  for (int c = 0; c < r; ++c) prow[c] = W[static_cast<int64_t>(c) * n + best];
+}
+
+__global__ void k_lu_eliminate(double* W, int64_t n, int r, int j, const double* prow, const int* chosen) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n || chosen[i]) return;
+  const double pj = prow[j];
+  if (pj == 0.0) return;  // an all-zero column: nothing to eliminate
+  const double f = W[static_cast<int64_t>(j) * n + i] / pj;
+  for (int c = j + 1; c < r; ++c) {
+    double* w = W + static_cast<int64_t>(c) * n + i;
+    *w = *w - f * prow[c];
+  }
+}
+
+subap_status select_rows_lu_gpu(const double* W0, int64_t n, int r, int s, int64_t* rows_d, hipStream_t st) {
+  DevVec W, mag, mpart, prow;
+  int* chosen = nullptr;
+  int64_t* ipart = nullptr;
+  SUBAP_TRY(dalloc(&W.p, n * r));
+  SUBAP_TRY(dalloc(&mag.p, n));
+  SUBAP_TRY(dalloc(&mpart.p, kMaxPartials));
+  SUBAP_TRY(dalloc(&prow.p, r));
+  subap_status rc = dalloc(&chosen, n + 1);
+  if (rc != SUBAP_OK) return rc;
+  rc = dalloc(&ipart, kMaxPartials);
+  if (rc != SUBAP_OK) {
+    dfree(chosen);
+    return rc;
+  }
+  struct Guard {
+    int* a;
+    int64_t* b;
+    ~Guard() { dfree(a); dfree(b); }
+  } guard{chosen, ipart};
+  int* bad = chosen + n;
+  SUBAP_HIP_TRY(hipMemsetAsync(chosen, 0, sizeof(int) * (n + 1), st));
+  const unsigned gb = static_cast<unsigned>((n + kBlock - 1) / kBlock);
+  const int nb = nblocks_for(n);
+  int taken = 0;
+  while (taken < s) {
+    const int take = std::min(r, s - taken);
+    SUBAP_HIP_TRY(hipMemcpyAsync(W.p, W0, sizeof(double) * n * r, hipMemcpyDeviceToDevice, st));
+    for (int j = 0; j < take; ++j) {
+      hipLaunchKernelGGL(k_col_abs, dim3(gb), dim3(kBlock), 0, st, W.p, n, j, chosen, mag.p);
+      hipLaunchKernelGGL(k_max_partial, dim3(nb), dim3(kBlock), 0, st, mag.p, n, mpart.p, nb);
+      hipLaunchKernelGGL(k_argfirst_partial, dim3(nb), dim3(kBlock), 0, st, mag.p, n, mpart.p, nb,
+                         1.0 - kTieRtol, ipart, nb);
+      hipLaunchKernelGGL(k_lu_pivot, dim3(1), dim3(1), 0, st, W.p, n, r, ipart, nb, chosen, rows_d, taken + j,
+                         prow.p, bad);
+      if (j + 1 < take)
+        hipLaunchKernelGGL(k_lu_eliminate, dim3(gb), dim3(kBlock), 0, st, W.p, n, r, j, prow.p, chosen);
+    }
+    SUBAP_HIP_TRY(hipGetLastError());
+    taken += take;
+  }
+  int hbad = 0;
+  SUBAP_HIP_TRY(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  SUBAP_HIP_TRY(hipStreamSynchronize(st));
+  if (hbad) {
+    set_error("row selection ran out of candidate rows");
+    return SUBAP_E_INVALID;
+  }
+  return SUBAP_OK;
+}
+
+// ----------------------------------------------------------------------------
 // Tables for the online kernels.
 // ----------------------------------------------------------------------------
 __global__ void k_fd_tables(const double* Qm, int64_t n, int r, int s, int N, int dimx, int d, double h,
@@ -1045,14 +1134,48 @@ subap_status offline_build(const subap_problem_desc* pd, const subap_offline_opt
   } else if (o->selection == SUBAP_SELECT_LEVERAGE) {
     SUBAP_TRY(select_leverage(A, M, o, rows64, st));
   } else {
+    // pivoted QR or LUPP at one point (s rows in rounds), or the union of r
+    // pivots at each of n_select points (Section 5.3.2; s = the union's size)
     SUBAP_TRY(dalloc(&W.p, static_cast<size_t>(n) * r));
-    std::vector<double> pd_h(static_cast<size_t>(r) * d);
-    for (int c = 0; c < r; ++c)
-      for (int q = 0; q < d; ++q) pd_h[static_cast<size_t>(c) * d + q] = o->select_param[q];
-    SUBAP_TRY(dalloc(&pdup.p, pd_h.size()));
-    SUBAP_HIP_TRY(hipMemcpyAsync(pdup.p, pd_h.data(), sizeof(double) * pd_h.size(), hipMemcpyHostToDevice, st));
-    SUBAP_TRY(apply_op(A, pdup.p, r, M->Q, W.p, nullptr, st));
-    SUBAP_TRY(select_rows_gpu(W.p, n, r, s, rows64, st));
+    SUBAP_TRY(dalloc(&pdup.p, static_cast<size_t>(r) * d));
+    const bool uni = o->n_select > 1;
+    const int npts = uni ? o->n_select : 1;
+    std::vector<int64_t> all;
+    int64_t* pick = nullptr;
+    SUBAP_TRY(dalloc(&pick, uni ? r : s));
+    struct GP {
+      int64_t* p;
+      ~GP() { dfree(p); }
+    } gp{pick};
+    for (int t = 0; t < npts; ++t) {
+      const double* pt = uni ? o->select_params + static_cast<int64_t>(t) * d : o->select_param;
+      std::vector<double> pd_h(static_cast<size_t>(r) * d);
+      for (int c = 0; c < r; ++c)
+        for (int q = 0; q < d; ++q) pd_h[static_cast<size_t>(c) * d + q] = pt[q];
+      SUBAP_HIP_TRY(hipMemcpyAsync(pdup.p, pd_h.data(), sizeof(double) * pd_h.size(), hipMemcpyHostToDevice, st));
+      SUBAP_TRY(apply_op(A, pdup.p, r, M->Q, W.p, nullptr, st));
+      const int k = uni ? r : s;
+      if (o->selection == SUBAP_SELECT_LU) SUBAP_TRY(select_rows_lu_gpu(W.p, n, r, k, pick, st));
+      else SUBAP_TRY(select_rows_gpu(W.p, n, r, k, pick, st));
+      std::vector<int64_t> h(k);
+      SUBAP_HIP_TRY(hipMemcpyAsync(h.data(), pick, sizeof(int64_t) * k, hipMemcpyDeviceToHost, st));
+      SUBAP_HIP_TRY(hipStreamSynchronize(st));
+      for (int64_t v : h)
+        if (std::find(all.begin(), all.end(), v) == all.end()) all.push_back(v);
+    }
+    if (uni) {
+      if (static_cast<int>(all.size()) > kMaxS) {
+        set_error("the union of pivots has more than 256 rows");
+        return SUBAP_E_INVALID;
+      }
+      M->s = static_cast<int>(all.size());
+      dfree(rows64);
+      g64.p = nullptr;
+      SUBAP_TRY(dalloc(&rows64, M->s));
+      g64.p = rows64;
+    }
+    SUBAP_HIP_TRY(hipMemcpyAsync(rows64, all.data(), sizeof(int64_t) * all.size(), hipMemcpyHostToDevice, st));
+    SUBAP_HIP_TRY(hipStreamSynchronize(st));
   }
   if (pd->c_out) {  // c^T Q for subap_output
     DevVec c, part;
@@ -1063,10 +1186,11 @@ subap_status offline_build(const subap_problem_desc* pd, const subap_offline_opt
     SUBAP_TRY(col_dots(M->Q, n, c.p, 0, 0, n, r, part.p, M->cQ, st));
     SUBAP_HIP_TRY(hipStreamSynchronize(st));
   }
-  SUBAP_TRY(dalloc(&M->rows_d, s));
-  hipLaunchKernelGGL(k_copy_rows_i32, dim3((s + 63) / 64), dim3(64), 0, st, rows64, M->rows_d, s);
-  M->rows.resize(s);
-  SUBAP_HIP_TRY(hipMemcpyAsync(M->rows.data(), rows64, sizeof(int64_t) * s, hipMemcpyDeviceToHost, st));
+  const int s_sel = M->s;  // the union of pivots sets it
+  SUBAP_TRY(dalloc(&M->rows_d, s_sel));
+  hipLaunchKernelGGL(k_copy_rows_i32, dim3((s_sel + 63) / 64), dim3(64), 0, st, rows64, M->rows_d, s_sel);
+  M->rows.resize(s_sel);
+  SUBAP_HIP_TRY(hipMemcpyAsync(M->rows.data(), rows64, sizeof(int64_t) * s_sel, hipMemcpyDeviceToHost, st));
   SUBAP_HIP_TRY(hipStreamSynchronize(st));
   SUBAP_TRY(build_tables(M, st));
   SUBAP_HIP_TRY(hipStreamSynchronize(st));
