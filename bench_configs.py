@@ -409,8 +409,8 @@ def delay(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
     """Delay system of Section 6.2.2 (n = 10^7, tau = 0.1, kappa = 2.1, real p in
     [0, 10]), r = 10 snapshots, s = 40 rows: 65,536 parameters per batch, each
     S A(p) X assembled from the two precomputed pieces p S X and S A_1 X, the
-    FP64 least squares and the output H(p) = (c^T X) y; pivoted-QR and
-    leverage-score rows."""
+    FP64 least squares and the output H(p) = (c^T X) y; pivoted-QR,
+    leverage-score, LU and union-of-LU-pivots rows."""
     import numpy as np
     n = args.delay_n
     w = si.delay(n=n)
@@ -424,13 +424,21 @@ def delay(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
     Ml = B.Model(w, basis=Q, sample_u=si.sample_uniforms(s, seed=909))
     torch.cuda.synchronize()
     lev_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Mu = B.Model(w, basis=Q, selection=B.SELECT_LU)
+    torch.cuda.synchronize()
+    lu_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Mn = B.Model(w, basis=Q, selection=B.SELECT_LU, select_params=np.array([[1.0], [5.0], [9.0]]))
+    torch.cuda.synchronize()
+    union_s = time.perf_counter() - t0
     P = torch.tensor(w["test_params"], dtype=torch.float64, device=dev)
     y = torch.empty((m, r), dtype=torch.float64, device=dev)
     rho = torch.empty(m, dtype=torch.float64, device=dev)
     st = torch.empty(m, dtype=torch.int32, device=dev)
     H = torch.empty(m, dtype=torch.float64, device=dev)
     forms = {}
-    for tag, Mx in (("cpqr_rows", M), ("leverage_rows", Ml)):
+    for tag, Mx in (("cpqr_rows", M), ("leverage_rows", Ml), ("lu_rows", Mu), ("lu_union_3_points", Mn)):
         def step(Mx=Mx):
             B.subap_solve_batch(Mx.handle, P, y, rho, st, B.FP64, 0, stream)
             B.subap_output(Mx.handle, y, H, stream)
@@ -442,7 +450,7 @@ def delay(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
         t = timed(step, args.steps, stream)
         B.subap_profile_enable(False)
         prof = B.subap_profile_read()
-        forms[tag] = {"ms_per_batch": t, "solves_per_s": ok / (t / 1e3), "valid": ok,
+        forms[tag] = {"ms_per_batch": t, "solves_per_s": ok / (t / 1e3), "valid": ok, "s": Mx.s,
                       "median_rho": float(torch.median(rho)), "max_rho": float(rho.max()),
                       "kernels_ms": {k: v[1] / v[0] for k, v in prof.items()}}
         if tag == "leverage_rows":
@@ -461,6 +469,8 @@ def delay(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
                            "parameter on the n = 10^7 model (the GPU's basis and rows passed in)")
     M.free()
     Ml.free()
+    Mu.free()
+    Mn.free()
     out = {
         "metric": "online solves/s at rel. residual <=1e-6: batched/learned vs plain, 1 MI355X",
         "value": best["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
@@ -469,6 +479,7 @@ def delay(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
         "config": {"workload": f"delay_n{n}_r{r}_s{s}_m{m}", "n": n,
                    "form": "affine assembly p SX - (3 + e^{tau p}) SA_1X + FP64 least squares + output c^T X y"},
         "forms": forms, "offline_s": offline_s, "leverage_selection_s_given_basis": lev_s,
+        "lu_selection_s_given_basis": lu_s, "lu_union_selection_s_given_basis": union_s,
         "roofline": {"bound": "alu", "kernel": "fd_solve", "achieved": flops / (kms * 1e-3) / 1e12,
                      "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s",
                      "frac": flops / (kms * 1e-3) / 1e12 / PEAKS["fp64_tflops"], "traffic": None},
