@@ -83,6 +83,35 @@ def output(c, Q, y):
     return (np.asarray(c, dtype=np.float64) @ np.asarray(Q)) @ np.asarray(y, dtype=np.float64).T
 
 
+def cg_polish(family, p, x0, iters, jacobi=True):
+    """Polishing from x0 by conjugate gradients on A(p) x = b (Section 3.1
+    mentions polishing the SubApSnap solution; every family here is
+    symmetric positive definite, so CG is the Krylov method).  ``jacobi``:
+    precondition with 1 / diag(A(p)).  Exactly ``iters`` iterations (a step
+    with p^T A p = 0 or r^T z = 0 leaves the iterate unchanged).  Returns
+    (x, |r| / |b|) with r the recursively updated residual."""
+    A = family.matrix(p)
+    b = np.asarray(family.rhs(p), dtype=np.float64)
+    dinv = 1.0 / np.asarray(A.diagonal()) if jacobi else np.ones(b.size)
+    x = np.array(x0, dtype=np.float64, copy=True)
+    r = b - A @ x
+    z = dinv * r
+    d = z.copy()
+    rz = r @ z
+    for _ in range(iters):
+        q = A @ d
+        dq = d @ q
+        alpha = 0.0 if dq == 0.0 else rz / dq
+        x = x + alpha * d
+        r = r - alpha * q
+        z = dinv * r
+        rz_new = r @ z
+        beta = 0.0 if rz == 0.0 else rz_new / rz
+        rz = rz_new
+        d = z + beta * d
+    return x, float(np.linalg.norm(r) / np.linalg.norm(b))
+
+
 def residual(family, x, p):
     """|A(p) x - b(p)|_2 / |b(p)|_2 (the measure of Tables 3-4)."""
     b = family.rhs(p)

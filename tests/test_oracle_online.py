@@ -166,3 +166,36 @@ def test_sketched_residual_is_zero_for_interpolation():
     assert On.sketched_residual(fam, Q, rows, p, y) < 1e-10
     # and delta_res of a vector with itself is zero
     assert On.delta_res(fam, Q, p, y, y) == 0.0
+
+
+# --- polishing by conjugate gradients (Section 3.1)
+
+def test_cg_polish_terminates_in_n_steps():
+    # CG on an SPD n x n system reaches the solution within n iterations
+    from oracle import families as Fm
+    w = si.diffusion2d(N=5, r=3, s=6)
+    fam = Fm.from_workload(w)
+    p = w["test_params"][0]
+    xs = np.linalg.solve(fam.matrix(p).toarray(), fam.rhs(p))
+    for jac in (True, False):
+        x, rr = On.cg_polish(fam, p, np.zeros(fam.n), fam.n, jacobi=jac)
+        np.testing.assert_allclose(x, xs, rtol=1e-9, atol=1e-12 * np.abs(xs).max())
+        assert rr < 1e-9
+
+
+def test_cg_polish_keeps_the_solution_and_lowers_the_energy_error():
+    from oracle import families as Fm
+    w = si.diffusion2d(N=12, r=3, s=6)
+    fam = Fm.from_workload(w)
+    p = w["test_params"][1]
+    A = fam.matrix(p)
+    xs = np.linalg.solve(A.toarray(), fam.rhs(p))
+    x, rr = On.cg_polish(fam, p, xs, 3)
+    assert rr < 1e-12 and np.abs(x - xs).max() <= 1e-12 * np.abs(xs).max()
+    x0 = np.zeros(fam.n)
+    errs = []
+    for k in range(0, 12, 2):
+        xk, _ = On.cg_polish(fam, p, x0, k)
+        e = xk - xs
+        errs.append(float(e @ (A @ e)))
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(errs, errs[1:])), errs
