@@ -354,6 +354,32 @@ SUBAP_API subap_status subap_model_rows(subap_model model, int64_t* rows_host);
  */
 SUBAP_API subap_status subap_output(subap_model model, const double* y_dev, int64_t m, double* out_dev,
                                     void* hip_stream);
+/*
+ * Full-size reference paths (all n rows; meant for checking a method's
+ * quality on a few parameters, not for throughput).  Each blocks until done.
+ *
+ * subap_full_residual -- res[k] = |A(p_k) x_k - b| / |b| (the measure of the
+ *   paper's Tables 3-4) for full vectors x_dev (device, n x m col-major,
+ *   column k = x_k, e.g. from subap_lift).
+ * subap_apsnap_solve -- ApSnap (eq. (3.1)): y_k = argmin_c |A(p_k) X c - b|
+ *   over all n rows, by Householder QR of the n x r matrix A(p_k) Q.
+ *   y_dev (device, m x r row-major), rho_dev (device, m, or NULL): the full
+ *   relative residual of y_k.
+ * subap_polish -- conjugate gradients on A(p_k) x = b warm-started from
+ *   x_dev (device, n x m col-major, overwritten with the iterate): the
+ *   polishing from the SubApSnap solution that Section 3.1 mentions (CG,
+ *   Jacobi-preconditioned for the stencil families, since every family here
+ *   is symmetric positive definite).  Stops a column once |b - A x| <= tol
+ *   |b| (checked every 16 iterations and at the end) or after max_iter
+ *   iterations; reaching max_iter is not an error.  res_dev (device, m, or
+ *   NULL): the final relative residuals.
+ */
+SUBAP_API subap_status subap_full_residual(subap_model model, const double* params_dev, int64_t m,
+                                           const double* x_dev, double* res_dev, void* hip_stream);
+SUBAP_API subap_status subap_apsnap_solve(subap_model model, const double* params_dev, int64_t m, double* y_dev,
+                                          double* rho_dev, void* hip_stream);
+SUBAP_API subap_status subap_polish(subap_model model, const double* params_dev, int64_t m, double* x_dev,
+                                    int32_t max_iter, double tol, double* res_dev, void* hip_stream);
 /* Row weights (host, s values): 1 for pivoted-QR rows, 1/sqrt(s pi_i) for
  * leverage-score rows. */
 SUBAP_API subap_status subap_model_weights(subap_model model, double* weights_host);

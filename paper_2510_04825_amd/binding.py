@@ -35,7 +35,8 @@ EXPORTS = ("subap_offline", "subap_solve_batch", "subap_lift", "subap_sketched_r
            "subap_surrogate_weights", "subap_surrogate_gradient", "subap_surrogate_train",
            "subap_surrogate_predict", "subap_surrogate_solve_batch", "subap_surrogate_free",
            "subap_surrogate_nparams", "subap_profile_count", "subap_status_string", "subap_last_error",
-           "subap_model_weights", "subap_residual_bounds", "subap_output")
+           "subap_model_weights", "subap_residual_bounds", "subap_output", "subap_full_residual",
+           "subap_apsnap_solve", "subap_polish")
 PLAN_GRAPH, PLAN_AUTOTUNE = 1, 2
 # subap_selection
 SELECT_CPQR, SELECT_LEVERAGE, SELECT_LU = 0, 1, 2
@@ -95,6 +96,9 @@ def load(path: str = LIB_PATH):
     lib.subap_model_rows.argtypes = [vp, vp]
     lib.subap_model_weights.argtypes = [vp, vp]
     lib.subap_output.argtypes = [vp, vp, i64, vp, vp]
+    lib.subap_full_residual.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.subap_apsnap_solve.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.subap_polish.argtypes = [vp, vp, i64, vp, i32, C.c_double, vp, vp]
     lib.subap_residual_bounds.argtypes = [vp, vp, i64, C.c_double, vp, vp, vp]
     lib.subap_model_basis.argtypes = [vp, vp]
     lib.subap_model_free.argtypes = [vp]
@@ -401,6 +405,38 @@ def subap_model_rows(model):
     out = np.empty(s, dtype=np.int64)
     _check(lib.subap_model_rows(C.c_void_p(model), out.ctypes.data))
     return out
+
+
+def subap_full_residual(model, params, x, res, stream=None):
+    """params (m, d); x (m, n) float64 cuda tensor, row k = x_k (column-major n x m); res (m,)."""
+    n, _, _, d = subap_model_dims(model)
+    m = params.shape[0]
+    _expect(params, (m, d), "float64", "params")
+    _expect(x, (m, n), "float64", "x")
+    _expect(res, (m,), "float64", "res")
+    _check(load().subap_full_residual(C.c_void_p(model), _ptr(params), m, _ptr(x), _ptr(res), _stream(stream)))
+
+
+def subap_apsnap_solve(model, params, y, rho=None, stream=None):
+    _, r, _, d = subap_model_dims(model)
+    m = params.shape[0]
+    _expect(params, (m, d), "float64", "params")
+    _expect(y, (m, r), "float64", "y")
+    if rho is not None:
+        _expect(rho, (m,), "float64", "rho")
+    _check(load().subap_apsnap_solve(C.c_void_p(model), _ptr(params), m, _ptr(y), _ptr(rho), _stream(stream)))
+
+
+def subap_polish(model, params, x, max_iter, tol=0.0, res=None, stream=None):
+    """x (m, n) float64 cuda tensor (row k = x_k), overwritten by the CG iterate."""
+    n, _, _, d = subap_model_dims(model)
+    m = params.shape[0]
+    _expect(params, (m, d), "float64", "params")
+    _expect(x, (m, n), "float64", "x")
+    if res is not None:
+        _expect(res, (m,), "float64", "res")
+    _check(load().subap_polish(C.c_void_p(model), _ptr(params), m, _ptr(x), int(max_iter), float(tol), _ptr(res),
+                               _stream(stream)))
 
 
 def subap_output(model, y, out, stream=None):

@@ -316,6 +316,38 @@ subap_status subap_model_rows(subap_model M, int64_t* rows_host) {
   return SUBAP_OK;
 }
 
+subap_status subap_full_residual(subap_model M, const double* params, int64_t m, const double* x, double* res,
+                                 void* hip_stream) {
+  clear_error();
+  if (!M) return invalid("model must not be NULL");
+  if (m < 0) return invalid("m must be >= 0");
+  if (m == 0) return SUBAP_OK;
+  if (!params || !x || !res) return invalid("params_dev, x_dev and res_dev must not be NULL");
+  return subap::full_residual(M, params, m, x, res, static_cast<hipStream_t>(hip_stream));
+}
+
+subap_status subap_apsnap_solve(subap_model M, const double* params, int64_t m, double* y, double* rho,
+                                void* hip_stream) {
+  clear_error();
+  if (!M) return invalid("model must not be NULL");
+  if (m < 0) return invalid("m must be >= 0");
+  if (m == 0) return SUBAP_OK;
+  if (!params || !y) return invalid("params_dev and y_dev must not be NULL");
+  return subap::apsnap_solve(M, params, m, y, rho, static_cast<hipStream_t>(hip_stream));
+}
+
+subap_status subap_polish(subap_model M, const double* params, int64_t m, double* x, int32_t max_iter, double tol,
+                          double* res, void* hip_stream) {
+  clear_error();
+  if (!M) return invalid("model must not be NULL");
+  if (m < 0) return invalid("m must be >= 0");
+  if (max_iter < 0) return invalid("max_iter must be >= 0");
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return invalid("tol must be finite and >= 0");
+  if (m == 0) return SUBAP_OK;
+  if (!params || !x) return invalid("params_dev and x_dev must not be NULL");
+  return subap::polish(M, params, m, x, max_iter, tol, res, static_cast<hipStream_t>(hip_stream));
+}
+
 subap_status subap_output(subap_model M, const double* y, int64_t m, double* out, void* hip_stream) {
   clear_error();
   if (!M) return invalid("model must not be NULL");

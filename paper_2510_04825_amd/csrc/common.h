@@ -57,6 +57,7 @@ struct subap_model_s {
   double tau = 0.0, kappa = 0.0;      // delay family
   double aff_c0 = 0.0;                // delay family: A_0 = aff_c0 A_1 (3)
   double bS_norm = 0.0;               // |S b|_2, or |b|_2 with weighted rows (b is p-independent in every family)
+  double b_norm = 0.0;                // |b|_2
   int selection = 0;                  // subap_selection
   std::vector<double> weights;        // host copy of wS
   double dmax = 0.0;                  // KRR: upper bound on every squared distance D[k, j]
@@ -103,6 +104,12 @@ subap_status offline_build(const subap_problem_desc* pd, const subap_offline_opt
 subap_status build_tables(subap_model_s* M, hipStream_t st);
 subap_status residual_bounds(const double* rho, int64_t m, double eps, double* lo, double* hi, hipStream_t st);
 subap_status output_apply(const subap_model_s* M, const double* y, int64_t m, double* out, hipStream_t st);
+subap_status full_residual(subap_model_s* M, const double* params, int64_t m, const double* x, double* res,
+                           hipStream_t st);
+subap_status apsnap_solve(subap_model_s* M, const double* params, int64_t m, double* y, double* rho,
+                          hipStream_t st);
+subap_status polish(subap_model_s* M, const double* params, int64_t m, double* x, int max_iter, double tol,
+                    double* res, hipStream_t st);
 
 // ---- online ----
 subap_status fd_solve(subap_model_s* M, const double* params, int64_t m, double* y,

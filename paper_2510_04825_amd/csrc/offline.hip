@@ -284,8 +284,30 @@ struct DevVec {
   ~DevVec() { dfree(p); }
 };
 
-subap_status snapshot_cg(const OpArgs& A, const double* params_d, int r, const double* b_d,
-                         double tol, int maxiter, double* X, hipStream_t st) {
+// r = b - r (r holds A x on entry), z = dinv r, p = z: a warm start from x
+__global__ void k_cg_init_warm(int64_t n, const double* b, const double* dinv, double* r, double* z, double* p) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n) return;
+  const int64_t k = static_cast<int64_t>(c) * n + i;
+  const double ri = b[i] - r[k];
+  r[k] = ri;
+  const double zi = dinv ? ri * dinv[k] : ri;
+  z[k] = zi;
+  p[k] = zi;
+}
+
+__global__ void k_sqrt_ratio(const double* num, const double* den, int ncol, double* out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncol) out[c] = sqrt(num[c]) / sqrt(den[c]);
+}
+
+// Conjugate gradients (Jacobi-preconditioned for the stencil families) on
+// A(p_c) x_c = b for ncol columns at once, one parameter per column.  warm:
+// start from X instead of 0.  relres (device, ncol, optional): final
+// |b - A x| / |b|.  require_conv: SUBAP_E_NOCONV if a column misses tol.
+subap_status cg_solve(const OpArgs& A, const double* params_d, int r, const double* b_d, double tol, int maxiter,
+                      double* X, bool warm, double* relres, bool require_conv, hipStream_t st) {
   const int64_t n = A.n;
   const int64_t nr = n * r;
   DevVec R, Z, P, Qv, Dinv, scal;
@@ -313,7 +335,12 @@ subap_status snapshot_cg(const OpArgs& A, const double* params_d, int r, const d
   SUBAP_HIP_TRY(hipMemsetAsync(done, 0, sizeof(int) * r, st));
   dim3 g2(static_cast<unsigned>((n + kBlock - 1) / kBlock), r);
   dim3 gs((r + 63) / 64);
-  hipLaunchKernelGGL(k_cg_init, g2, dim3(kBlock), 0, st, n, r, b_d, int64_t(0), dinv, X, R.p, Z.p, P.p);
+  if (warm) {
+    SUBAP_TRY(apply_op(A, params_d, r, X, R.p, nullptr, st));
+    hipLaunchKernelGGL(k_cg_init_warm, g2, dim3(kBlock), 0, st, n, b_d, dinv, R.p, Z.p, P.p);
+  } else {
+    hipLaunchKernelGGL(k_cg_init, g2, dim3(kBlock), 0, st, n, r, b_d, int64_t(0), dinv, X, R.p, Z.p, P.p);
+  }
   SUBAP_TRY(col_dots(R.p, n, Z.p, n, 0, n, r, part, rz, st));
   SUBAP_TRY(col_dots(b_d, 0, b_d, 0, 0, n, r, part, bb, st));
   std::vector<double> h_rr(r), h_bb(r);
@@ -343,8 +370,12 @@ subap_status snapshot_cg(const OpArgs& A, const double* params_d, int r, const d
       SUBAP_HIP_TRY(hipMemcpyAsync(done, h_done.data(), sizeof(int) * r, hipMemcpyHostToDevice, st));
     }
   }
+  if (relres) {
+    SUBAP_TRY(col_dots(R.p, n, R.p, n, 0, n, r, part, rr, st));
+    hipLaunchKernelGGL(k_sqrt_ratio, gs, dim3(64), 0, st, rr, bb, r, relres);
+  }
   SUBAP_HIP_TRY(hipStreamSynchronize(st));
-  if (!all_done) {
+  if (require_conv && !all_done) {
     set_error("snapshot conjugate gradients did not reach snap_tol within snap_maxiter");
     return SUBAP_E_NOCONV;
   }
@@ -677,6 +708,47 @@ subap_status select_rows_lu_gpu(const double* W0, int64_t n, int r, int s, int64
 }
 
 // ----------------------------------------------------------------------------
+// Full-size reference paths: the residual over all n rows, ApSnap (eq. (3.1))
+// and polishing by conjugate gradients from x = Q y.
+// ----------------------------------------------------------------------------
+// out[c * d + q] = p[q] for c < ncol (one parameter repeated over ncol columns)
+__global__ void k_dup_param(const double* p, int d, int ncol, double* out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < ncol * d) out[t] = p[t % d];
+}
+
+// Y[:, c] -= b
+__global__ void k_sub_b(double* Y, int64_t n, const double* b) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i < n) Y[static_cast<int64_t>(c) * n + i] -= b[i];
+}
+
+// y = R^{-1} c, R upper triangular r x r col-major (R[i + r j]); one thread
+__global__ void k_trisolve(const double* R, const double* c, int r, double* y) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  for (int i = r - 1; i >= 0; --i) {
+    double t = c[i];
+    for (int j = i + 1; j < r; ++j) t -= R[i + static_cast<int64_t>(r) * j] * y[j];
+    y[i] = t / R[i + static_cast<int64_t>(r) * i];
+  }
+}
+
+// e = B y - b for B n x r col-major
+__global__ void k_bres(const double* B, int64_t n, int r, const double* y, const double* b, double* e) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double t = 0.0;
+  for (int c = 0; c < r; ++c) t = fma(B[static_cast<int64_t>(c) * n + i], y[c], t);
+  e[i] = t - b[i];
+}
+
+__global__ void k_norm_ratio(const double* ss, int ncol, double den, double* out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncol) out[c] = sqrt(ss[c]) / den;
+}
+
+// ----------------------------------------------------------------------------
 // Tables for the online kernels.
 // ----------------------------------------------------------------------------
 __global__ void k_fd_tables(const double* Qm, int64_t n, int r, int s, int N, int dimx, int d, double h,
@@ -989,16 +1061,17 @@ subap_status build_tables(subap_model_s* M, hipStream_t st) {
   SUBAP_HIP_TRY(hipGetLastError());
   M->weights.resize(s);
   SUBAP_HIP_TRY(hipMemcpyAsync(M->weights.data(), M->wS, sizeof(double) * s, hipMemcpyDeviceToHost, st));
-  // relative residual denominator: |S b| for interpolating / pivoted rows,
-  // |b| for weighted rows (whose sketch estimates full norms)
-  const bool full = M->selection == SUBAP_SELECT_LEVERAGE;
-  const int64_t len = full ? n : s;
-  std::vector<double> hb(static_cast<size_t>(len));
-  SUBAP_HIP_TRY(hipMemcpyAsync(hb.data(), full ? M->rhs : M->bS, sizeof(double) * len, hipMemcpyDeviceToHost, st));
+  // relative residual denominators: |b| (full), and |S b| for interpolating /
+  // pivoted rows or |b| for weighted rows (whose sketch estimates full norms)
+  std::vector<double> hb(static_cast<size_t>(n)), hs(static_cast<size_t>(s));
+  SUBAP_HIP_TRY(hipMemcpyAsync(hb.data(), M->rhs, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+  SUBAP_HIP_TRY(hipMemcpyAsync(hs.data(), M->bS, sizeof(double) * s, hipMemcpyDeviceToHost, st));
   SUBAP_HIP_TRY(hipStreamSynchronize(st));
-  double t = 0.0;
+  double t = 0.0, u = 0.0;
   for (double v : hb) t += v * v;
-  M->bS_norm = std::sqrt(t);
+  for (double v : hs) u += v * v;
+  M->b_norm = std::sqrt(t);
+  M->bS_norm = M->selection == SUBAP_SELECT_LEVERAGE ? M->b_norm : std::sqrt(u);
   return SUBAP_OK;
 }
 
@@ -1065,6 +1138,87 @@ static subap_status select_leverage(const OpArgs& A, subap_model_s* M, const sub
   return SUBAP_OK;
 }
 
+static OpArgs op_args(const subap_model_s* M) {
+  return OpArgs{M->family, M->N, M->dimx, M->n, M->d, M->h, M->inv_h2, M->lambda, M->points, M->tau, M->kappa,
+                M->aff_c0};
+}
+
+// columns per pass so that one n x cols FP64 work array stays near 2 GiB
+static int64_t pass_cols(int64_t n, int64_t m) {
+  return std::max<int64_t>(1, std::min<int64_t>(m, (int64_t(1) << 28) / std::max<int64_t>(n, 1)));
+}
+
+subap_status full_residual(subap_model_s* M, const double* params, int64_t m, const double* x, double* res,
+                           hipStream_t st) {
+  const OpArgs A = op_args(M);
+  const int64_t n = M->n, per = std::min<int64_t>(pass_cols(n, m), 65535);
+  DevVec Y, part, ss;
+  SUBAP_TRY(dalloc(&Y.p, static_cast<size_t>(n) * per));
+  SUBAP_TRY(dalloc(&part.p, static_cast<size_t>(kMaxPartials) * per));
+  SUBAP_TRY(dalloc(&ss.p, per));
+  for (int64_t c0 = 0; c0 < m; c0 += per) {
+    const int cnt = static_cast<int>(std::min<int64_t>(per, m - c0));
+    SUBAP_TRY(apply_op(A, params + c0 * M->d, cnt, x + c0 * n, Y.p, nullptr, st));
+    hipLaunchKernelGGL(k_sub_b, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock), cnt), dim3(kBlock), 0, st,
+                       Y.p, n, M->rhs);
+    SUBAP_TRY(col_dots(Y.p, n, Y.p, n, 0, n, cnt, part.p, ss.p, st));
+    hipLaunchKernelGGL(k_norm_ratio, dim3((cnt + 63) / 64), dim3(64), 0, st, ss.p, cnt, M->b_norm, res + c0);
+  }
+  SUBAP_HIP_TRY(hipGetLastError());
+  return SUBAP_OK;
+}
+
+subap_status apsnap_solve(subap_model_s* M, const double* params, int64_t m, double* y, double* rho,
+                          hipStream_t st) {
+  const OpArgs A = op_args(M);
+  const int64_t n = M->n;
+  const int r = M->r, d = M->d;
+  DevVec pdup, B, Bc, QB, diag, R, cvec, part, e, ss;
+  SUBAP_TRY(dalloc(&pdup.p, static_cast<size_t>(r) * d));
+  SUBAP_TRY(dalloc(&B.p, static_cast<size_t>(n) * r));
+  SUBAP_TRY(dalloc(&Bc.p, static_cast<size_t>(n) * r));
+  SUBAP_TRY(dalloc(&QB.p, static_cast<size_t>(n) * r));
+  SUBAP_TRY(dalloc(&diag.p, r));
+  SUBAP_TRY(dalloc(&R.p, static_cast<size_t>(r) * r));
+  SUBAP_TRY(dalloc(&cvec.p, r));
+  SUBAP_TRY(dalloc(&part.p, static_cast<size_t>(kMaxPartials) * r));
+  SUBAP_TRY(dalloc(&e.p, n));
+  SUBAP_TRY(dalloc(&ss.p, 1));
+  const unsigned gb = static_cast<unsigned>((n + kBlock - 1) / kBlock);
+  for (int64_t k = 0; k < m; ++k) {
+    // B = A(p_k) Q, thin QR B = QB R, y = R^{-1} QB^T b
+    hipLaunchKernelGGL(k_dup_param, dim3((r * d + 63) / 64), dim3(64), 0, st, params + k * d, d, r, pdup.p);
+    SUBAP_TRY(apply_op(A, pdup.p, r, M->Q, B.p, nullptr, st));
+    SUBAP_HIP_TRY(hipMemcpyAsync(Bc.p, B.p, sizeof(double) * n * r, hipMemcpyDeviceToDevice, st));
+    SUBAP_TRY(householder_q(B.p, n, r, QB.p, diag.p, st));
+    for (int c = 0; c < r; ++c)
+      SUBAP_TRY(col_dots(QB.p, n, Bc.p + static_cast<int64_t>(c) * n, 0, 0, n, r, part.p,
+                         R.p + static_cast<int64_t>(c) * r, st));
+    SUBAP_TRY(col_dots(QB.p, n, M->rhs, 0, 0, n, r, part.p, cvec.p, st));
+    hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(1), 0, st, R.p, cvec.p, r, y + k * r);
+    if (rho) {
+      hipLaunchKernelGGL(k_bres, dim3(gb), dim3(kBlock), 0, st, Bc.p, n, r, y + k * r, M->rhs, e.p);
+      SUBAP_TRY(col_dots(e.p, n, e.p, n, 0, n, 1, part.p, ss.p, st));
+      hipLaunchKernelGGL(k_norm_ratio, dim3(1), dim3(64), 0, st, ss.p, 1, M->b_norm, rho + k);
+    }
+    SUBAP_HIP_TRY(hipGetLastError());
+  }
+  SUBAP_HIP_TRY(hipStreamSynchronize(st));
+  return SUBAP_OK;
+}
+
+subap_status polish(subap_model_s* M, const double* params, int64_t m, double* x, int max_iter, double tol,
+                    double* res, hipStream_t st) {
+  const OpArgs A = op_args(M);
+  const int64_t per = std::min<int64_t>(pass_cols(M->n, m) / 4 + 1, 4096);
+  for (int64_t c0 = 0; c0 < m; c0 += per) {
+    const int cnt = static_cast<int>(std::min<int64_t>(per, m - c0));
+    SUBAP_TRY(cg_solve(A, params + c0 * M->d, cnt, M->rhs, tol, max_iter, x + c0 * M->n, true,
+                       res ? res + c0 : nullptr, false, st));
+  }
+  return SUBAP_OK;
+}
+
 subap_status output_apply(const subap_model_s* M, const double* y, int64_t m, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_output, dim3(static_cast<unsigned>((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, M->cQ,
                      M->r, y, m, out);
@@ -1115,7 +1269,7 @@ subap_status offline_build(const subap_problem_desc* pd, const subap_offline_opt
     SUBAP_HIP_TRY(hipMemcpyAsync(params.p, o->snap_params, sizeof(double) * r * d, hipMemcpyHostToDevice, st));
     const double tol = o->snap_tol > 0.0 ? o->snap_tol : 1e-12;
     const int maxit = o->snap_maxiter > 0 ? o->snap_maxiter : 20000;
-    SUBAP_TRY(snapshot_cg(A, params.p, r, M->rhs, tol, maxit, X.p, st));
+    SUBAP_TRY(cg_solve(A, params.p, r, M->rhs, tol, maxit, X.p, false, nullptr, true, st));
   }
   // 2. orthonormalise
   SUBAP_TRY(dalloc(&M->Q, static_cast<size_t>(n) * r));

@@ -1,0 +1,113 @@
+"""GPU parity of the full-size reference paths against the FP64 oracle:
+the residual over all n rows, ApSnap (eq. (3.1)) and CG polishing from the
+SubApSnap solution (Section 3.1).
+
+Bars: full residual within 1e-10 relative (or 1e-14 absolute); ApSnap within
+delta_res <= 1e-12 of numpy's least squares; the polished iterate after a
+fixed number of CG steps (tol = 0) within 1e-9 relative of the oracle's CG
+with the same preconditioner (the two differ only in summation order, which
+CG propagates); to tolerance, the full residual reaches it."""
+import numpy as np
+import pytest
+
+import subap_inputs as si
+from oracle import offline as O
+from oracle import online as On
+from paper_2510_04825_amd import binding as B
+from tests.gpu_util import device, header, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "diff2d": lambda: si.diffusion2d(N=24, r=6, s=18, m=8),
+    "krr": lambda: si.krr(n=700, r=6, s=18, m=8),
+    "delay": lambda: si.delay(n=2000, r=5, s=15, m=8),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def ref(request):
+    w = CASES[request.param]()
+    off = O.offline(w)
+    device()
+    M = B.Model(w, basis=off["Q"], rows=off["rows"])
+    yield request.param, w, off, M
+    M.free()
+
+
+def test_full_residual(ref):
+    import torch
+    name, w, off, M = ref
+    header(f"full residual {name}")
+    fam, Q = off["family"], off["Q"]
+    P = w["test_params"]
+    y = On.solve(fam, Q, off["rows"], P)
+    X = (Q @ y.T).T.copy()  # row k = x_k
+    X[1] += 1e-3 * np.random.default_rng(3).standard_normal(X.shape[1])
+    res = torch.empty(len(P), dtype=torch.float64, device="cuda")
+    B.subap_full_residual(M.handle, to_dev(P), to_dev(X), res)
+    torch.cuda.synchronize()
+    want = np.array([On.residual(fam, x, p) for x, p in zip(X, P)])
+    np.testing.assert_allclose(res.cpu().numpy(), want, rtol=1e-10, atol=1e-14)
+
+
+def test_apsnap_matches_least_squares(ref):
+    import torch
+    name, w, off, M = ref
+    header(f"apsnap {name}")
+    fam, Q = off["family"], off["Q"]
+    P = w["test_params"][:5]
+    y = torch.empty((len(P), w["r"]), dtype=torch.float64, device="cuda")
+    rho = torch.empty(len(P), dtype=torch.float64, device="cuda")
+    B.subap_apsnap_solve(M.handle, to_dev(P), y, rho)
+    torch.cuda.synchronize()
+    yg = y.cpu().numpy()
+    for p, a, rg in zip(P, yg, rho.cpu().numpy()):
+        yo = On.apsnap_solve(fam, Q, p)
+        assert On.delta_res(fam, Q, p, a, yo) <= 1e-12
+        full = On.residual(fam, Q @ yo, p)
+        assert abs(rg - full) <= 1e-8 * full + 1e-14
+        # ApSnap is never worse than SubApSnap on the same basis
+        ys = On.solve_one(fam, Q, off["rows"], p)
+        assert full <= On.residual(fam, Q @ ys, p) * (1 + 1e-9)
+
+
+def test_polish_fixed_steps_matches_oracle_cg(ref):
+    import torch
+    name, w, off, M = ref
+    header(f"polish {name}")
+    fam, Q = off["family"], off["Q"]
+    P = w["test_params"][:4]
+    y = On.solve(fam, Q, off["rows"], P)
+    X0 = (Q @ y.T).T.copy()
+    X = to_dev(X0)
+    res = torch.empty(len(P), dtype=torch.float64, device="cuda")
+    B.subap_polish(M.handle, to_dev(P), X, 6, 0.0, res)
+    torch.cuda.synchronize()
+    Xg = X.cpu().numpy()
+    for k, p in enumerate(P):
+        xo, rr = On.cg_polish(fam, p, X0[k], 6, jacobi=(name != "krr"))
+        assert np.linalg.norm(Xg[k] - xo) <= 1e-9 * np.linalg.norm(xo), name
+        assert abs(res.cpu().numpy()[k] - rr) <= 1e-6 * rr + 1e-15
+        # CG lowers the energy norm of the error (not necessarily |r|)
+        A = fam.matrix(p)
+        A = A.toarray() if hasattr(A, "toarray") else np.asarray(A)
+        xs = np.linalg.solve(A, fam.rhs(p))
+        e0, e1 = X0[k] - xs, Xg[k] - xs
+        assert e1 @ (A @ e1) <= e0 @ (A @ e0) * (1 + 1e-12)
+
+
+def test_polish_to_tolerance(ref):
+    import torch
+    name, w, off, M = ref
+    header(f"polish to tolerance {name}")
+    fam, Q = off["family"], off["Q"]
+    P = w["test_params"][:3]
+    y = On.solve(fam, Q, off["rows"], P)
+    X = to_dev((Q @ y.T).T.copy())
+    res = torch.empty(len(P), dtype=torch.float64, device="cuda")
+    B.subap_polish(M.handle, to_dev(P), X, 5000, 1e-10, res)
+    torch.cuda.synchronize()
+    assert np.all(res.cpu().numpy() <= 1e-10)
+    for x, p in zip(X.cpu().numpy(), P):
+        assert On.residual(fam, x, p) <= 1e-9
