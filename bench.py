@@ -55,6 +55,9 @@ def parse():
                          "(lift: the FP32 lift alone on an N^3 grid, --grid N)")
     ap.add_argument("--grid", type=int, default=215, help="diffusion3d/surrogate/lift/leverage: nodes per axis")
     ap.add_argument("--delay-n", type=int, default=10 ** 7, help="delay: system size n")
+    ap.add_argument("--table-sample", type=int, default=64,
+                    help="delay: parameters for the full-residual / transfer-function error columns")
+    ap.add_argument("--apsnap-sample", type=int, default=8, help="delay: parameters solved by ApSnap")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a device-to-device copy of MIB MiB (HBM counter calibration)")
     ap.add_argument("--given-basis", action="store_true",

@@ -458,6 +458,45 @@ def delay(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
             forms[tag]["median_bounds"] = [float(torch.median(lo)), float(torch.median(hi))]
     tp = _plain(B, M, P, r, min(256, args.plain_sample), stream, timed, torch, dev)
     forms["fp64_per_p_plain"] = {"solves_per_s": 1e3 / tp}
+    # the columns of the paper's Table 4 on a sample of parameters: the full
+    # relative residual (max, median) and max |H - H_hat|, with H from CG
+    # polished to 1e-13 (the reference "full" solve) and ApSnap beside
+    k = args.table_sample
+    Ps = P[:k].contiguous()
+    ys = torch.empty((k, r), dtype=torch.float64, device=dev)
+    Hs = torch.empty(k, dtype=torch.float64, device=dev)
+    res = torch.empty(k, dtype=torch.float64, device=dev)
+    B.subap_solve_batch(M.handle, Ps, ys, None, None, B.FP64, 0, stream)
+    Xf = M.lift(ys, B.FP64, stream).contiguous()
+    t0 = time.perf_counter()
+    B.subap_polish(M.handle, Ps, Xf, 5000, 1e-13, res, stream)
+    torch.cuda.synchronize()
+    full_s = (time.perf_counter() - t0) / k
+    cvec = torch.tensor(w["c_out"], dtype=torch.float64, device=dev)
+    H_ref = Xf @ cvec
+    table = {"sample": k, "full_cg_s_per_p": full_s}
+    for tag, Mx in (("subapsnap_cpqr", M), ("subapsnap_lu", Mu), ("subapsnap_leverage", Ml),
+                    ("subapsnap_lu_union", Mn)):
+        B.subap_solve_batch(Mx.handle, Ps, ys, None, None, B.FP64, 0, stream)
+        B.subap_output(Mx.handle, ys, Hs, stream)
+        X = Mx.lift(ys, B.FP64, stream).contiguous()
+        B.subap_full_residual(Mx.handle, Ps, X, res, stream)
+        torch.cuda.synchronize()
+        table[tag] = {"max_H_error": float((Hs - H_ref).abs().max()), "residual_max": float(res.max()),
+                      "residual_median": float(res.median())}
+        del X
+    ka = min(k, args.apsnap_sample)
+    ya = torch.empty((ka, r), dtype=torch.float64, device=dev)
+    rho_a = torch.empty(ka, dtype=torch.float64, device=dev)
+    t0 = time.perf_counter()
+    B.subap_apsnap_solve(M.handle, Ps[:ka].contiguous(), ya, rho_a, stream)
+    torch.cuda.synchronize()
+    B.subap_output(M.handle, ya, Hs[:ka], stream)
+    torch.cuda.synchronize()
+    table["apsnap"] = {"sample": ka, "s_per_p": (time.perf_counter() - t0) / ka,
+                       "max_H_error": float((Hs[:ka] - H_ref[:ka]).abs().max()),
+                       "residual_max": float(rho_a.max()), "residual_median": float(rho_a.median())}
+    del Xf
     best = forms["cpqr_rows"]
     kms = best["kernels_ms"].get("fd_solve", best["ms_per_batch"])
     flops = m * (2.0 * s * r * r - 2.0 / 3.0 * r ** 3 + 2.0 * 2 * s * r)
@@ -480,6 +519,7 @@ def delay(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
                    "form": "affine assembly p SX - (3 + e^{tau p}) SA_1X + FP64 least squares + output c^T X y"},
         "forms": forms, "offline_s": offline_s, "leverage_selection_s_given_basis": lev_s,
         "lu_selection_s_given_basis": lu_s, "lu_union_selection_s_given_basis": union_s,
+        "table4_columns": table,
         "roofline": {"bound": "alu", "kernel": "fd_solve", "achieved": flops / (kms * 1e-3) / 1e12,
                      "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s",
                      "frac": flops / (kms * 1e-3) / 1e12 / PEAKS["fp64_tflops"], "traffic": None},
