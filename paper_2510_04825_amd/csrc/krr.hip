@@ -514,12 +514,16 @@ __global__ __launch_bounds__(256, 4) void k_refine_partial(const double* params,
     s_y[c][w] = (p0 + w < m && c < r) ? y[(p0 + w) * r + c] : 0.0;
   }
   // per-parameter factor: entry = 2^(cv D), cv = -log2(e) / (2 p^2)
+  // (the same for every thread of the block: kept in scalar registers, which
+  // leaves the vector registers to the accumulators)
   double cv[kRefPB];
   double cmax = 0.0;
 #pragma unroll
   for (int w = 0; w < kRefPB; ++w) {
     const double sig = p0 + w < m ? params[p0 + w] : 1.0;
-    cv[w] = krr_param_ok(sig) ? -0.5 * kLog2e / (sig * sig) : 0.0;
+    const double c = krr_param_ok(sig) ? -0.5 * kLog2e / (sig * sig) : 0.0;
+    cv[w] = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(c)),
+                             __builtin_amdgcn_readfirstlane(__double2loint(c)));
     cmax = fmax(cmax, -cv[w]);
   }
   // every |cv D| of the block below 2^30: unclamped reduction (uniform branch)
