@@ -101,3 +101,54 @@ def test_null_model_calls(lib):
     assert lib.subap_lift(None, None, 1, None, 0, 0, None) == B.E_INVALID
     assert lib.subap_model_rows(None, None) == B.E_INVALID
     assert lib.subap_model_free(None) == B.OK
+
+
+@pytest.mark.parametrize("opt_kw", [
+    dict(selection=7),
+    dict(selection=B.SELECT_LEVERAGE),                     # sample_u missing
+    dict(selection=B.SELECT_LU, n_select=3),               # select_params missing
+    dict(n_select=-1),
+])
+def test_offline_rejects_bad_selection(lib, opt_kw):
+    pd = _pd()
+    op, keep = _opts(**opt_kw)
+    h = C.c_void_p()
+    assert lib.subap_offline(C.byref(pd), C.byref(op), None, C.byref(h)) == B.E_INVALID
+    assert h.value is None
+
+
+def test_offline_rejects_uniforms_outside_the_unit_interval(lib):
+    pd = _pd()
+    for bad in (1.0, -0.25, np.nan):
+        u = np.full(8, 0.5)
+        u[3] = bad
+        op, keep = _opts(selection=B.SELECT_LEVERAGE, sample_u=u.ctypes.data)
+        h = C.c_void_p()
+        assert lib.subap_offline(C.byref(pd), C.byref(op), None, C.byref(h)) == B.E_INVALID
+
+
+@pytest.mark.parametrize("pd_kw", [
+    dict(tau=0.0, kappa=2.1),
+    dict(tau=0.1, kappa=2.0),
+    dict(tau=0.1, kappa=2.1, rhs=None),
+    dict(tau=0.1, kappa=2.1, n=1),
+])
+def test_offline_rejects_bad_delay_problems(lib, pd_kw):
+    b = np.ones(50)
+    base = dict(family=B.FAMILY_DELAY, n=50, rhs=b.ctypes.data)
+    base.update(pd_kw)
+    pd = _pd(**base)
+    snap = np.zeros((4, 1))
+    sel = np.zeros(1)
+    op, keep = _opts(snap_params=snap.ctypes.data, select_param=sel.ctypes.data)
+    h = C.c_void_p()
+    assert lib.subap_offline(C.byref(pd), C.byref(op), None, C.byref(h)) == B.E_INVALID
+
+
+def test_null_model_calls_of_the_other_entry_points(lib):
+    assert lib.subap_model_weights(None, None) == B.E_INVALID
+    assert lib.subap_output(None, None, 1, None, None) == B.E_INVALID
+    assert lib.subap_full_residual(None, None, 1, None, None, None) == B.E_INVALID
+    assert lib.subap_apsnap_solve(None, None, 1, None, None, None) == B.E_INVALID
+    assert lib.subap_polish(None, None, 1, None, 5, 0.0, None, None) == B.E_INVALID
+    assert lib.subap_residual_bounds(None, None, 1, 0.0, None, None, None) == B.E_INVALID
