@@ -132,6 +132,7 @@ def diffusion3d(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
         del x
     # dominant solve kernel: FP64 ALU (Householder 2 s r^2 - 2/3 r^3 + face contraction 2 s F r per p)
     flops = m * (2.0 * s * r * r - 2.0 / 3.0 * r ** 3 + 2.0 * s * 6 * r)
+    hbm_bytes = m * (8.0 * 4 + 8.0 * r + 8.0 + 4.0) + 8.0 * s * 6 * r + 8.0 * s * 6 * 4 + 8.0 * s
     kms = forms["fp64_batched"]["kernels_ms"].get("fd_solve", forms["fp64_batched"]["ms_per_batch"])
     best = max(("fp64_batched", "fp32_refine1", "fp64_persistent_plan_graph"),
                key=lambda f: forms[f]["valid"] / forms[f]["ms_per_batch"])
@@ -153,6 +154,11 @@ def diffusion3d(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
         "roofline": {"bound": "alu", "kernel": "fd_solve", "achieved": flops / (kms * 1e-3) / 1e12,
                      "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s",
                      "frac": flops / (kms * 1e-3) / 1e12 / PEAKS["fp64_tflops"], "traffic": None},
+        # the configuration's HBM figure: with S fixed, a batch moves the
+        # parameters in (32 B each), y, rho and status out (r 8 + 8 + 4 B each)
+        # and the s x F x r FP64 face tables and s x F x d mode values once
+        "hbm": {"bytes_per_batch": hbm_bytes, "GB_per_s": hbm_bytes / (kms * 1e-3) / 1e9,
+                "frac": hbm_bytes / (kms * 1e-3) / 1e9 / PEAKS["hbm_gbs"]},
         "lift": lift,
         "offline_s": offline_s,
     }
