@@ -401,6 +401,18 @@ SUBAP_API subap_status subap_residual_bounds(subap_model model, const double* rh
 SUBAP_API subap_status subap_model_basis(subap_model model, double* Q_host);
 
 SUBAP_API subap_status subap_model_free(subap_model model);
+/*
+ * subap_model_save / subap_model_load -- keep the offline result (Algorithm
+ * 3.1 steps 1-3) for later sessions: the file holds the problem data (b,
+ * KRR points, family constants), the basis Q, the rows, their weights and
+ * c^T Q.  Loading uploads them and rebuilds the per-row tables on the GPU,
+ * so a loaded model solves bit-identically to the saved one.  Both block.
+ * The file uses the host's byte order.  SUBAP_E_INVALID for a path that
+ * cannot be opened, a file that is not a model file, or a truncated or
+ * inconsistent one (nothing is allocated on the device then).
+ */
+SUBAP_API subap_status subap_model_save(subap_model model, const char* path);
+SUBAP_API subap_status subap_model_load(const char* path, void* hip_stream, subap_model* out);
 
 SUBAP_API const char* subap_status_string(subap_status status);
 /* Message of the last failing call on this thread ("" if none). */

@@ -36,7 +36,7 @@ EXPORTS = ("subap_offline", "subap_solve_batch", "subap_lift", "subap_sketched_r
            "subap_surrogate_predict", "subap_surrogate_solve_batch", "subap_surrogate_free",
            "subap_surrogate_nparams", "subap_profile_count", "subap_status_string", "subap_last_error",
            "subap_model_weights", "subap_residual_bounds", "subap_output", "subap_full_residual",
-           "subap_apsnap_solve", "subap_polish")
+           "subap_apsnap_solve", "subap_polish", "subap_model_save", "subap_model_load")
 PLAN_GRAPH, PLAN_AUTOTUNE = 1, 2
 # subap_selection
 SELECT_CPQR, SELECT_LEVERAGE, SELECT_LU = 0, 1, 2
@@ -95,6 +95,8 @@ def load(path: str = LIB_PATH):
     lib.subap_model_dims.argtypes = [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
     lib.subap_model_rows.argtypes = [vp, vp]
     lib.subap_model_weights.argtypes = [vp, vp]
+    lib.subap_model_save.argtypes = [vp, C.c_char_p]
+    lib.subap_model_load.argtypes = [C.c_char_p, vp, C.POINTER(vp)]
     lib.subap_output.argtypes = [vp, vp, i64, vp, vp]
     lib.subap_full_residual.argtypes = [vp, vp, i64, vp, vp, vp]
     lib.subap_apsnap_solve.argtypes = [vp, vp, i64, vp, vp, vp]
@@ -473,6 +475,16 @@ def subap_model_basis(model):
     return out.T
 
 
+def subap_model_save(model, path):
+    _check(load().subap_model_save(C.c_void_p(model), os.fsencode(path)))
+
+
+def subap_model_load(path, stream=None):
+    h = C.c_void_p()
+    _check(load().subap_model_load(os.fsencode(path), _stream(stream), C.byref(h)))
+    return h.value
+
+
 def subap_model_free(model):
     _check(load().subap_model_free(C.c_void_p(model)))
 
@@ -510,6 +522,17 @@ class Model:
 
     def weights(self):
         return subap_model_weights(self.handle)
+
+    def save(self, path):
+        subap_model_save(self.handle, path)
+
+    @classmethod
+    def load(cls, path, stream=None):
+        """A model rebuilt from a file written by save()."""
+        self = cls.__new__(cls)
+        self.handle = subap_model_load(path, stream)
+        self.n, self.r, self.s, self.d = subap_model_dims(self.handle)
+        return self
 
     def output(self, y, stream=None):
         """c^T Q y for each row of y (m, r) -> (m,) cuda tensor."""

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -356,6 +357,115 @@ subap_status subap_output(subap_model M, const double* y, int64_t m, double* out
   if (m == 0) return SUBAP_OK;
   if (!y || !out) return invalid("y_dev and out_dev must not be NULL");
   return subap::output_apply(M, y, m, out, static_cast<hipStream_t>(hip_stream));
+}
+
+// ---- model files ----
+// Layout (native byte order): 8-byte magic, a header of 12 int64 and 8 double
+// fields, then the arrays Q (n r), rhs (n), rows (s int64), weights (s),
+// points (n dimx, KRR only) and c^T Q (r, when present).
+namespace {
+constexpr char kMagic[8] = {'S', 'U', 'B', 'A', 'P', 'M', 'D', '1'};
+constexpr int kHdrInts = 12, kHdrDoubles = 8;
+
+struct FileCloser {
+  std::FILE* f;
+  ~FileCloser() {
+    if (f) std::fclose(f);
+  }
+};
+
+bool put(std::FILE* f, const void* p, size_t bytes) { return bytes == 0 || std::fwrite(p, 1, bytes, f) == bytes; }
+bool get(std::FILE* f, void* p, size_t bytes) { return bytes == 0 || std::fread(p, 1, bytes, f) == bytes; }
+}  // namespace
+
+subap_status subap_model_save(subap_model M, const char* path) {
+  clear_error();
+  if (!M || !path) return invalid("model and path must not be NULL");
+  const int64_t n = M->n;
+  const int r = M->r, s = M->s;
+  std::vector<double> Q(static_cast<size_t>(n) * r), rhs(static_cast<size_t>(n)), pts, cq;
+  SUBAP_HIP_TRY(hipDeviceSynchronize());
+  SUBAP_HIP_TRY(hipMemcpy(Q.data(), M->Q, sizeof(double) * Q.size(), hipMemcpyDeviceToHost));
+  SUBAP_HIP_TRY(hipMemcpy(rhs.data(), M->rhs, sizeof(double) * n, hipMemcpyDeviceToHost));
+  if (M->family == SUBAP_FAMILY_KRR) {
+    pts.resize(static_cast<size_t>(n) * M->dimx);
+    SUBAP_HIP_TRY(hipMemcpy(pts.data(), M->points, sizeof(double) * pts.size(), hipMemcpyDeviceToHost));
+  }
+  if (M->cQ) {
+    cq.resize(r);
+    SUBAP_HIP_TRY(hipMemcpy(cq.data(), M->cQ, sizeof(double) * r, hipMemcpyDeviceToHost));
+  }
+  const int64_t hi[kHdrInts] = {M->family, M->N, M->dimx, n, r, s, M->d, M->F, M->selection,
+                                 M->cQ ? 1 : 0, static_cast<int64_t>(pts.size()), 0};
+  const double hd[kHdrDoubles] = {M->h, M->inv_h2, M->lambda, M->tau, M->kappa, M->aff_c0, M->dmax, 0.0};
+  FileCloser fc{std::fopen(path, "wb")};
+  if (!fc.f) return invalid(std::string("cannot open ") + path + " for writing");
+  const bool ok = put(fc.f, kMagic, sizeof(kMagic)) && put(fc.f, hi, sizeof(hi)) && put(fc.f, hd, sizeof(hd)) &&
+                  put(fc.f, Q.data(), sizeof(double) * Q.size()) && put(fc.f, rhs.data(), sizeof(double) * n) &&
+                  put(fc.f, M->rows.data(), sizeof(int64_t) * s) &&
+                  put(fc.f, M->weights.data(), sizeof(double) * s) &&
+                  put(fc.f, pts.data(), sizeof(double) * pts.size()) && put(fc.f, cq.data(), sizeof(double) * cq.size());
+  if (!ok || std::fflush(fc.f) != 0) return invalid(std::string("writing ") + path + " failed");
+  return SUBAP_OK;
+}
+
+subap_status subap_model_load(const char* path, void* hip_stream, subap_model* out) {
+  clear_error();
+  if (!path || !out) return invalid("path and out must not be NULL");
+  *out = nullptr;
+  FileCloser fc{std::fopen(path, "rb")};
+  if (!fc.f) return invalid(std::string("cannot open ") + path);
+  char magic[8];
+  int64_t hi[kHdrInts];
+  double hd[kHdrDoubles];
+  if (!get(fc.f, magic, sizeof(magic)) || std::memcmp(magic, kMagic, sizeof(kMagic)) != 0)
+    return invalid(std::string(path) + " is not a SubApSnap model file");
+  if (!get(fc.f, hi, sizeof(hi)) || !get(fc.f, hd, sizeof(hd))) return invalid(std::string(path) + " is truncated");
+  subap_model_s tmp;
+  tmp.family = static_cast<int>(hi[0]);
+  tmp.N = static_cast<int>(hi[1]);
+  tmp.dimx = static_cast<int>(hi[2]);
+  tmp.n = hi[3];
+  tmp.r = static_cast<int>(hi[4]);
+  tmp.s = static_cast<int>(hi[5]);
+  tmp.d = static_cast<int>(hi[6]);
+  tmp.F = static_cast<int>(hi[7]);
+  tmp.selection = static_cast<int>(hi[8]);
+  const bool has_cq = hi[9] != 0;
+  const int64_t npts = hi[10];
+  tmp.h = hd[0];
+  tmp.inv_h2 = hd[1];
+  tmp.lambda = hd[2];
+  tmp.tau = hd[3];
+  tmp.kappa = hd[4];
+  tmp.aff_c0 = hd[5];
+  tmp.dmax = hd[6];
+  const bool fam_ok = tmp.family >= SUBAP_FAMILY_DIFF2D && tmp.family <= SUBAP_FAMILY_DELAY;
+  if (!fam_ok || tmp.n < 1 || tmp.n > 2147483647LL || tmp.r < 1 || tmp.r > kMaxR || tmp.s < tmp.r ||
+      tmp.s > kMaxS || tmp.s > tmp.n || tmp.dimx < 1 || tmp.dimx > 16 || tmp.d < 1 || tmp.d > 4 ||
+      npts != (tmp.family == SUBAP_FAMILY_KRR ? tmp.n * tmp.dimx : 0))
+    return invalid(std::string(path) + " has an inconsistent header");
+  std::vector<double> Q(static_cast<size_t>(tmp.n) * tmp.r), rhs(static_cast<size_t>(tmp.n)),
+      w(static_cast<size_t>(tmp.s)), pts(static_cast<size_t>(npts)), cq(has_cq ? tmp.r : 0);
+  std::vector<int64_t> rows(static_cast<size_t>(tmp.s));
+  if (!get(fc.f, Q.data(), sizeof(double) * Q.size()) || !get(fc.f, rhs.data(), sizeof(double) * rhs.size()) ||
+      !get(fc.f, rows.data(), sizeof(int64_t) * rows.size()) || !get(fc.f, w.data(), sizeof(double) * w.size()) ||
+      !get(fc.f, pts.data(), sizeof(double) * pts.size()) || !get(fc.f, cq.data(), sizeof(double) * cq.size()))
+    return invalid(std::string(path) + " is truncated");
+  for (int64_t v : rows)
+    if (v < 0 || v >= tmp.n) return invalid(std::string(path) + " has a row index out of range");
+  subap_model_s* M = new (std::nothrow) subap_model_s(tmp);
+  if (!M) return SUBAP_E_NOMEM;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  subap_status rc = subap::restore_model(M, Q.data(), rows.data(), w.data(), rhs.data(),
+                                         npts ? pts.data() : nullptr, has_cq ? cq.data() : nullptr, st);
+  if (rc != SUBAP_OK) {
+    (void)hipStreamSynchronize(st);
+    free_model(M);
+    return rc;
+  }
+  *out = M;
+  return SUBAP_OK;
 }
 
 subap_status subap_model_weights(subap_model M, double* weights_host) {

@@ -104,6 +104,8 @@ subap_status offline_build(const subap_problem_desc* pd, const subap_offline_opt
 subap_status build_tables(subap_model_s* M, hipStream_t st);
 subap_status residual_bounds(const double* rho, int64_t m, double eps, double* lo, double* hi, hipStream_t st);
 subap_status output_apply(const subap_model_s* M, const double* y, int64_t m, double* out, hipStream_t st);
+subap_status restore_model(subap_model_s* M, const double* Q, const int64_t* rows, const double* weights,
+                           const double* rhs, const double* points, const double* cQ, hipStream_t st);
 subap_status full_residual(subap_model_s* M, const double* params, int64_t m, const double* x, double* res,
                            hipStream_t st);
 subap_status apsnap_solve(subap_model_s* M, const double* params, int64_t m, double* y, double* rho,

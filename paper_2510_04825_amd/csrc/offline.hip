@@ -1219,6 +1219,37 @@ subap_status polish(subap_model_s* M, const double* params, int64_t m, double* x
   return SUBAP_OK;
 }
 
+// A model read back from a file: upload what the offline phase produced
+// (basis, rows, weights, problem data) and rebuild the tables from it, so the
+// online kernels see exactly the arrays the saved model had.
+subap_status restore_model(subap_model_s* M, const double* Q, const int64_t* rows, const double* weights,
+                           const double* rhs, const double* points, const double* cQ, hipStream_t st) {
+  const int64_t n = M->n;
+  const int r = M->r, s = M->s;
+  SUBAP_TRY(dalloc(&M->Q, static_cast<size_t>(n) * r));
+  SUBAP_TRY(dalloc(&M->rhs, n));
+  SUBAP_TRY(dalloc(&M->wS, s));
+  SUBAP_TRY(dalloc(&M->rows_d, s));
+  SUBAP_HIP_TRY(hipMemcpyAsync(M->Q, Q, sizeof(double) * n * r, hipMemcpyHostToDevice, st));
+  SUBAP_HIP_TRY(hipMemcpyAsync(M->rhs, rhs, sizeof(double) * n, hipMemcpyHostToDevice, st));
+  SUBAP_HIP_TRY(hipMemcpyAsync(M->wS, weights, sizeof(double) * s, hipMemcpyHostToDevice, st));
+  std::vector<int> r32(rows, rows + s);
+  SUBAP_HIP_TRY(hipMemcpyAsync(M->rows_d, r32.data(), sizeof(int) * s, hipMemcpyHostToDevice, st));
+  if (points) {
+    SUBAP_TRY(dalloc(&M->points, static_cast<size_t>(n) * M->dimx));
+    SUBAP_HIP_TRY(hipMemcpyAsync(M->points, points, sizeof(double) * n * M->dimx, hipMemcpyHostToDevice, st));
+  }
+  if (cQ) {
+    SUBAP_TRY(dalloc(&M->cQ, r));
+    SUBAP_HIP_TRY(hipMemcpyAsync(M->cQ, cQ, sizeof(double) * r, hipMemcpyHostToDevice, st));
+  }
+  M->rows.assign(rows, rows + s);
+  SUBAP_HIP_TRY(hipStreamSynchronize(st));
+  SUBAP_TRY(build_tables(M, st));
+  SUBAP_HIP_TRY(hipStreamSynchronize(st));
+  return SUBAP_OK;
+}
+
 subap_status output_apply(const subap_model_s* M, const double* y, int64_t m, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_output, dim3(static_cast<unsigned>((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, M->cQ,
                      M->r, y, m, out);

@@ -152,3 +152,23 @@ def test_null_model_calls_of_the_other_entry_points(lib):
     assert lib.subap_apsnap_solve(None, None, 1, None, None, None) == B.E_INVALID
     assert lib.subap_polish(None, None, 1, None, 5, 0.0, None, None) == B.E_INVALID
     assert lib.subap_residual_bounds(None, None, 1, 0.0, None, None, None) == B.E_INVALID
+
+
+def test_model_load_rejects_bad_files(lib, tmp_path):
+    h = C.c_void_p()
+    assert lib.subap_model_load(os.fsencode(str(tmp_path / "missing.bin")), None, C.byref(h)) == B.E_INVALID
+    bad = tmp_path / "garbage.bin"
+    bad.write_bytes(b"not a model file at all")
+    assert lib.subap_model_load(os.fsencode(str(bad)), None, C.byref(h)) == B.E_INVALID
+    # right magic, inconsistent header (r = 0)
+    hdr = np.zeros(12, dtype=np.int64)
+    hdr[:9] = [1, 8, 2, 64, 0, 4, 2, 4, 0]
+    cut = tmp_path / "header.bin"
+    cut.write_bytes(b"SUBAPMD1" + hdr.tobytes() + np.zeros(8).tobytes())
+    assert lib.subap_model_load(os.fsencode(str(cut)), None, C.byref(h)) == B.E_INVALID
+    # consistent header, arrays missing
+    hdr[4] = 2
+    cut.write_bytes(b"SUBAPMD1" + hdr.tobytes() + np.zeros(8).tobytes() + np.zeros(10).tobytes())
+    assert lib.subap_model_load(os.fsencode(str(cut)), None, C.byref(h)) == B.E_INVALID
+    assert h.value is None
+    assert lib.subap_model_save(None, b"x") == B.E_INVALID
