@@ -2,6 +2,7 @@
 // lifetime, and dispatch to the offline and online kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -440,10 +441,29 @@ subap_status subap_model_load(const char* path, void* hip_stream, subap_model* o
   tmp.kappa = hd[4];
   tmp.aff_c0 = hd[5];
   tmp.dmax = hd[6];
-  const bool fam_ok = tmp.family >= SUBAP_FAMILY_DIFF2D && tmp.family <= SUBAP_FAMILY_DELAY;
-  if (!fam_ok || tmp.n < 1 || tmp.n > 2147483647LL || tmp.r < 1 || tmp.r > kMaxR || tmp.s < tmp.r ||
-      tmp.s > kMaxS || tmp.s > tmp.n || tmp.dimx < 1 || tmp.dimx > 16 || tmp.d < 1 || tmp.d > 4 ||
-      npts != (tmp.family == SUBAP_FAMILY_KRR ? tmp.n * tmp.dimx : 0))
+  // the family's geometry must agree with n (the table builders index
+  // neighbours from it); derived constants are recomputed, not trusted
+  bool geo = false;
+  if (tmp.family == SUBAP_FAMILY_DIFF2D || tmp.family == SUBAP_FAMILY_DIFF3D) {
+    const int dx = tmp.family == SUBAP_FAMILY_DIFF2D ? 2 : 3;
+    geo = tmp.N >= 2 && tmp.N <= 46340 && tmp.dimx == dx && tmp.d == (dx == 2 ? 2 : 4) && tmp.F == 2 * dx &&
+          std::pow(static_cast<double>(tmp.N), dx) == static_cast<double>(tmp.n);
+    tmp.h = 1.0 / (tmp.N + 1);
+    tmp.inv_h2 = 1.0 / (tmp.h * tmp.h);
+  } else if (tmp.family == SUBAP_FAMILY_KRR) {
+    geo = tmp.dimx >= 1 && tmp.dimx <= 16 && tmp.d == 1 && npts == tmp.n * tmp.dimx && tmp.lambda > 0.0 &&
+          std::isfinite(tmp.lambda);
+  } else if (tmp.family == SUBAP_FAMILY_DELAY) {
+    geo = tmp.n >= 2 && tmp.dimx == 1 && tmp.d == 1 && tmp.F == 2 && tmp.tau > 0.0 && std::isfinite(tmp.tau) &&
+          tmp.kappa > 2.0 && std::isfinite(tmp.kappa);
+    tmp.h = 1.0;
+    tmp.inv_h2 = 1.0;
+    tmp.aff_c0 = 3.0;
+  }
+  if (!geo || tmp.n < 1 || tmp.n > 2147483647LL || tmp.r < 1 || tmp.r > kMaxR || tmp.s < tmp.r ||
+      tmp.s > kMaxS || tmp.s > tmp.n || (tmp.family != SUBAP_FAMILY_KRR && npts != 0) ||
+      (tmp.selection != SUBAP_SELECT_CPQR && tmp.selection != SUBAP_SELECT_LEVERAGE &&
+       tmp.selection != SUBAP_SELECT_LU))
     return invalid(std::string(path) + " has an inconsistent header");
   std::vector<double> Q(static_cast<size_t>(tmp.n) * tmp.r), rhs(static_cast<size_t>(tmp.n)),
       w(static_cast<size_t>(tmp.s)), pts(static_cast<size_t>(npts)), cq(has_cq ? tmp.r : 0);
@@ -454,6 +474,18 @@ subap_status subap_model_load(const char* path, void* hip_stream, subap_model* o
     return invalid(std::string(path) + " is truncated");
   for (int64_t v : rows)
     if (v < 0 || v >= tmp.n) return invalid(std::string(path) + " has a row index out of range");
+  if (!all_finite(Q.data(), static_cast<int64_t>(Q.size())) || !all_finite(rhs.data(), tmp.n) ||
+      !all_finite(w.data(), tmp.s) || !all_finite(pts.data(), npts) || !all_finite(cq.data(), static_cast<int64_t>(cq.size())))
+    return invalid(std::string(path) + " has non-finite entries");
+  if (tmp.family == SUBAP_FAMILY_KRR) {  // bound on every squared distance, as the offline phase computes it
+    double rmax = 0.0;
+    for (int64_t i = 0; i < tmp.n; ++i) {
+      double t2 = 0.0;
+      for (int q = 0; q < tmp.dimx; ++q) t2 += pts[i * tmp.dimx + q] * pts[i * tmp.dimx + q];
+      rmax = std::max(rmax, t2);
+    }
+    tmp.dmax = 4.0 * rmax;
+  }
   subap_model_s* M = new (std::nothrow) subap_model_s(tmp);
   if (!M) return SUBAP_E_NOMEM;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);

@@ -172,3 +172,16 @@ def test_model_load_rejects_bad_files(lib, tmp_path):
     assert lib.subap_model_load(os.fsencode(str(cut)), None, C.byref(h)) == B.E_INVALID
     assert h.value is None
     assert lib.subap_model_save(None, b"x") == B.E_INVALID
+
+
+def test_model_load_rejects_a_grid_that_does_not_match_n(lib, tmp_path):
+    # a 2-D model whose N disagrees with n would index neighbours outside the
+    # basis; the header check refuses it before any device work
+    n, r, s = 64, 2, 4
+    hdr = np.array([B.FAMILY_DIFF2D, 7, 2, n, r, s, 2, 4, 0, 0, 0, 0], dtype=np.int64)
+    body = np.zeros(n * r + n).tobytes() + np.arange(s, dtype=np.int64).tobytes() + np.ones(s).tobytes()
+    f = tmp_path / "grid.bin"
+    f.write_bytes(b"SUBAPMD1" + hdr.tobytes() + np.zeros(8).tobytes() + body)
+    h = C.c_void_p()
+    assert lib.subap_model_load(os.fsencode(str(f)), None, C.byref(h)) == B.E_INVALID
+    assert b"inconsistent" in lib.subap_last_error()
