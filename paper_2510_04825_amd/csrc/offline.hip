@@ -986,6 +986,11 @@ __global__ void k_leverage_draw(const double* sc, int64_t n, const double* cpre,
     }
   }
   if (pick < 0) pick = *last;  // a draw at the total (rounding): the last positive row
+  if (pick < 0) {             // no positive score at all: the host reports the error
+    rows[k] = 0;
+    w[k] = 0.0;
+    return;
+  }
   rows[k] = pick;
   w[k] = 1.0 / sqrt(s * (sc[pick] / total));
 }
