@@ -208,6 +208,7 @@ __device__ void cols_solve(const ColsModel& M, const double* params, int prec, i
     double ss = 0.0;
 #pragma unroll
     for (int i = 0; i < RB; ++i) ss = fma(B[i], B[i], ss);
+    double ss_ref = ss;  // the last exactly computed value
     const bool last = k0 + RB >= s;  // the pivots of the last block are final
     for (int j = 0; j < r; ++j) {
       const int rowj = cols_row(j, r1);
@@ -226,6 +227,7 @@ __device__ void cols_solve(const ColsModel& M, const double* params, int prec, i
       const double dj = lane_bcast(dd, j);
       const double cj = lane_bcast(coef, j);
       const double betaj = lane_bcast(beta, j);
+      const double ssj = lane_bcast(ss, j);
       double vj[RB];
 #pragma unroll
       for (int i = 0; i < RB; ++i) vj[i] = lane_bcast(B[i], j);
@@ -239,16 +241,26 @@ __device__ void cols_solve(const ColsModel& M, const double* params, int prec, i
           w3 = fma(vj[i + 3], B[i + 3], w3);
         }
         // t = coef u^T x for this column: x <- x - t u
-        const double t = cj * fma(dj, alpha, (w0 + w1) + (w2 + w3));
+        const double dot = (w0 + w1) + (w2 + w3);
+        const double t = cj * fma(dj, alpha, dot);
         R[rowj + (lane - j)] = fma(-t, dj, alpha);
-        double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-        for (int i = 0; i < RB; ++i) {
-          B[i] = fma(-t, vj[i], B[i]);
-          if (i % 2 == 0) s0 = fma(B[i], B[i], s0);
-          else s1 = fma(B[i], B[i], s1);
+        for (int i = 0; i < RB; ++i) B[i] = fma(-t, vj[i], B[i]);
+        // |x - t v|^2 = |x|^2 - 2 t (v.x) + t^2 |v|^2, recomputed when it has
+        // lost more than three quarters of its last exact value
+        const double down = fma(t * t, ssj, fma(-2.0 * t, dot, ss));
+        if (down >= 0.25 * ss_ref) {
+          ss = down;
+        } else {
+          double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+          for (int i = 0; i < RB; i += 2) {
+            s0 = fma(B[i], B[i], s0);
+            s1 = fma(B[i + 1], B[i + 1], s1);
+          }
+          ss = s0 + s1;
+          ss_ref = ss;
         }
-        ss = s0 + s1;
       }
       if constexpr (BRED) {
         const double alpha_b = R[rowj + (r - j)];
