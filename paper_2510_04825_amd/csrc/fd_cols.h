@@ -11,9 +11,11 @@
 // in block order: the same R up to rounding.  R, with Q^T b as its last
 // column, lives in wave-private LDS packed by rows, so that step j reads row
 // j across the lanes without bank conflicts.  The pivot lane's block column
-// is broadcast into scalar registers by v_readlane, and the squared norm each
-// column needs for its own reflector is accumulated while the previous
-// reflector is applied.  After a block, the block part of the b column is
+// is broadcast into scalar registers by v_readlane.  The squared block norm
+// each column needs for its own reflector is downdated when a reflector is
+// applied (|x - t v|^2 = |x|^2 - 2 t v.x + t^2 |v|^2, from the dot product the
+// step already has) and recomputed once it has lost three quarters of its
+// last exact value.  After a block, the block part of the b column is
 // orthogonal to the range of the first r columns, so its squared norm adds to
 // the sketched residual.
 //
