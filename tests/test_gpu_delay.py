@@ -146,3 +146,39 @@ def test_delay_rejects_bad_problems():
         ww[key] = bad
         with pytest.raises((B.SubapError, TypeError)):
             B.Model(ww)
+
+
+@pytest.mark.slow
+def test_delay_full_size_sampled():
+    """The benchmark's size: n = 10^7, r = 10, s = 40, 65,536 parameters in
+    one launch, with an oracle-made orthonormal basis and seeded rows (the
+    online solve does not depend on where they came from).  The oracle
+    recomputes sampled parameters one by one: sketched distance <= 1e-11,
+    and the output c^T Q y within 1e-10 relative of the oracle's."""
+    import torch
+    from oracle import families as Fm
+    w = si.delay()
+    header("delay full size")
+    fam = Fm.from_workload(w)
+    rng = np.random.default_rng(2026)
+    Q, _ = O.orthonormalise(rng.standard_normal((w["n"], w["r"])))
+    rows = np.sort(rng.choice(w["n"], size=w["s"], replace=False))
+    device()
+    M = B.Model(w, basis=Q, rows=rows)
+    try:
+        P = w["test_params"]
+        y, _, st = M.solve(to_dev(P))
+        H = M.output(y)
+        torch.cuda.synchronize()
+        assert np.all(st.cpu().numpy() == B.OK)
+        y, H = y.cpu().numpy(), H.cpu().numpy()
+        cQ = w["c_out"] @ Q
+        for i in np.concatenate([rng.choice(len(P), size=10, replace=False), [0, len(P) - 1]]):
+            G = On.reduced_matrix(fam, Q, rows, P[i])
+            bS = fam.rhs_rows(P[i], rows)
+            yo, _, _ = On.householder_lsq(G, bS)
+            d = np.linalg.norm(G @ (y[i] - yo)) / np.linalg.norm(bS)
+            assert d <= 1e-11, (i, d)
+            assert abs(H[i] - cQ @ yo) <= 1e-10 * abs(cQ @ yo) + 1e-12 * np.abs(cQ).sum() * np.abs(yo).max(), i
+    finally:
+        M.free()

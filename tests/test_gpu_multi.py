@@ -149,3 +149,54 @@ def test_plan_with_3d_models(uneven_small, cubes_small, mix, prec, refine, tol, 
     finally:
         for M in models:
             M.free()
+
+
+@pytest.mark.slow
+def test_uneven_full_size_sampled(tmp_path, monkeypatch):
+    """The benchmark's uneven batch: all 64 instances (grids 32^2..512^2,
+    r in {8, 16, 32, 64}) in one persistent, autotuned, graph-replayed launch,
+    FP32 contraction + one FP64 refinement, with oracle-made orthonormal bases
+    and seeded rows.  Two sampled parameters per instance are recomputed by the
+    oracle: sketched distance <= 1e-6 plus the simple-refinement bias bound
+    2^-20 kappa(S A Q) rho* (rho* is of order one for a random basis)."""
+    import torch
+    from oracle import families as Fm
+    monkeypatch.setenv("SUBAP_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
+    insts = si.uneven()
+    header("uneven full size")
+    rng = np.random.default_rng(2027)
+    device()
+    models, bases, rowsets = [], [], []
+    try:
+        for w in insts:
+            Q, _ = O.orthonormalise(rng.standard_normal((w["n"], w["r"])))
+            rows = np.sort(rng.choice(w["n"], size=w["s"], replace=False))
+            bases.append(Q)
+            rowsets.append(rows)
+            models.append(B.Model(w, basis=Q, rows=rows))
+        params = [to_dev(w["test_params"]) for w in insts]
+        ys = [torch.empty((w["m"], w["r"]), dtype=torch.float64, device=params[0].device) for w in insts]
+        sts = [torch.empty(w["m"], dtype=torch.int32, device=params[0].device) for w in insts]
+        plan = B.subap_plan_create([M.handle for M in models], params, ys, None, sts, B.FP32, 1,
+                                   B.PLAN_GRAPH | B.PLAN_AUTOTUNE)
+        try:
+            B.subap_plan_execute(plan)
+            torch.cuda.synchronize()
+        finally:
+            B.subap_plan_free(plan)
+        for w, Q, rows, y, st in zip(insts, bases, rowsets, ys, sts):
+            assert np.all(st.cpu().numpy() == B.OK)
+            fam = Fm.from_workload(w)
+            yg = y.cpu().numpy()
+            for i in rng.choice(w["m"], size=min(2, w["m"]), replace=False):
+                p = w["test_params"][i]
+                G = On.reduced_matrix(fam, Q, rows, p)
+                bS = fam.rhs_rows(p, rows)
+                yo, _, rho = On.householder_lsq(G, bS)
+                sv = np.linalg.svd(G, compute_uv=False)
+                tol = 1e-6 + 2.0 ** -20 * sv[0] / sv[-1] * rho / np.linalg.norm(bS)
+                d = np.linalg.norm(G @ (yg[i] - yo)) / np.linalg.norm(bS)
+                assert d <= tol, (w["n"], w["r"], w["s"], i, d, tol)
+    finally:
+        for M in models:
+            M.free()
