@@ -129,3 +129,47 @@ def test_leverage_rejects_bad_uniforms():
     for bad in (np.full(6, 1.0), np.array([0.1, 0.2, np.nan, 0.3, 0.4, 0.5]), np.full(6, -0.1)):
         with pytest.raises(B.SubapError):
             B.Model(w, sample_u=bad)
+
+
+@pytest.mark.slow
+def test_leverage_full_size_3d():
+    """The 3-D benchmark size (215^3 nodes, r = 40, s = 160) with an oracle-made
+    orthonormal basis: the GPU's leverage rows and weights against the
+    oracle's sampling of the same uniforms (a draw may differ only on a
+    running-sum boundary), then the weighted batch of 65,536 parameters,
+    sampled parameters recomputed by the oracle (sketched distance <= 1e-11)."""
+    import torch
+    from oracle import families as Fm
+    w = si.diffusion3d()
+    header("leverage full size 3-D")
+    fam = Fm.from_workload(w)
+    rng = np.random.default_rng(2028)
+    Q, _ = O.orthonormalise(rng.standard_normal((w["n"], w["r"])))
+    u = si.sample_uniforms(w["s"], seed=909)
+    sc = O.span_scores(O.leverage_matrix(fam, Q, w["select_param"]))
+    rows_o, wt_o = O.leverage_sample(sc, u)
+    device()
+    M = B.Model(w, basis=Q, sample_u=u)
+    try:
+        rows, wt = M.rows(), M.weights()
+        run = np.cumsum(sc)
+        for k in np.flatnonzero(rows != rows_o):
+            lo = min(rows[k], rows_o[k])
+            # two QR codes on a 9.9M-row matrix agree to about eps kappa(A) in the
+            # scores, so the running sums may differ by ~1e-11 of the total
+            assert abs(run[lo] - u[k] * run[-1]) <= 1e-9 * run[-1], (k, rows[k], rows_o[k])
+        same = rows == rows_o
+        np.testing.assert_allclose(wt[same], wt_o[same], rtol=1e-9)
+        P = w["test_params"]
+        y, _, st = M.solve(to_dev(P))
+        torch.cuda.synchronize()
+        assert np.all(st.cpu().numpy() == B.OK)
+        y = y.cpu().numpy()
+        for i in np.concatenate([rng.choice(len(P), size=8, replace=False), [0, len(P) - 1]]):
+            G = On.reduced_matrix(fam, Q, rows, P[i], wt)
+            bS = wt * fam.rhs_rows(P[i], rows)
+            yo, _, _ = On.householder_lsq(G, bS)
+            d = np.linalg.norm(G @ (y[i] - yo)) / np.linalg.norm(bS)
+            assert d <= 1e-11, (i, d)
+    finally:
+        M.free()
