@@ -287,7 +287,18 @@ def surrogate(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
     _, rho_h = M.sketched_residual(Pin, yh)
     rel = float(torch.linalg.norm(yh - y64) / torch.linalg.norm(y64))
     B.subap_surrogate_free(S)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # every prediction is rejected at 1e-5, so the oracle's cost per
+        # parameter is its FP64 fallback solve; the MLP forward (77k MACs) and
+        # the sketched check (s F r) are small next to it
+        from oracle import families as F
+        cpu = _oracle_rate([(F.from_workload(w), M.basis(), M.rows(), sg["infer_params"])], 0.5 * args.cpu_seconds,
+                           "FP64 oracle fallback solve per parameter on the full 215^3 model (all predictions "
+                           "rejected at 1e-5; the GPU's basis and rows passed in)")
     M.free()
+    # MLP inference: 2 (4*256 + 256*256 + 256*r) flops per parameter on bf16 MFMA
+    mlp_flops = mi * 2.0 * (4 * 256 + 256 * 256 + 256 * r)
     return {
         "metric": "online solves/s at rel. residual <=1e-6: batched/learned vs plain, 1 MI355X",
         "value": out["literal_1e-5"]["valid"] / (out["literal_1e-5"]["ms"] / 1e3), "unit": "solves/s",
@@ -298,6 +309,10 @@ def surrogate(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
         "surrogate": out, "plain_batched_fp64": {"ms": t_plain, "solves_per_s": mi / (t_plain / 1e3)},
         "predict_ms": t_pred, "prediction_rel_error": rel,
         "sketched_residual_median": {"prediction": float(torch.median(rho_h)), "subapsnap": floor},
+        "cpu_baseline": cpu,
+        "roofline": {"bound": "mfma", "kernel": "surrogate_predict", "achieved": mlp_flops / (t_pred * 1e-3) / 1e12,
+                     "peak": 2500.0, "unit": "TFLOP/s", "frac": mlp_flops / (t_pred * 1e-3) / 1e12 / 2500.0,
+                     "traffic": None},
         "train": {"pairs_generation_s": gen_s, "train_s": train_s, "loss_first": float(losses[0]),
                   "loss_last": float(losses[-1])},
     }
@@ -324,9 +339,27 @@ def lift(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
         out[tag] = {"ldx": ld, "ms": t, "GB_per_s": byt / (t * 1e-3) / 1e9,
                     "frac_hbm": byt / (t * 1e-3) / 1e9 / PEAKS["hbm_gbs"]}
         del x
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's lift x = Q y^T (FP64 BLAS) on a bounded number of vectors
+        from threadpoolctl import threadpool_info
+        from oracle import online as On
+        Qh = M.basis()
+        kk = 16
+        Yh = Y[:kk].cpu().numpy()
+        On.lift(Qh, Yh[:1])
+        t0 = time.perf_counter()
+        On.lift(Qh, Yh)
+        dt = time.perf_counter() - t0
+        bk = 8.0 * n * r + 4.0 * n * kk + 8.0 * kk * r
+        cpu = {"value": bk / dt / 1e9, "unit": "GB/s", "cores": int(max([d.get("num_threads", 1) for d in
+                                                                          threadpool_info()] or [1])),
+               "kind": "oracle", "sample": f"{kk} vectors: FP64 Q y^T with NumPy on the same basis", "seconds": dt}
+        del Qh
     M.free()
     best = min(out.values(), key=lambda v: v["ms"])
     return {"metric": "FP32 lift bandwidth (x = Q y, 1024 vectors)", "value": best["GB_per_s"], "unit": "GB/s",
+            "cpu_baseline": cpu,
             "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": best["ms"], "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "bf16x6 mfma, f32 out", "data": "synthetic",
             "config": {"workload": f"lift_diffusion3d_n{N}^3_r{r}_k{k}", "n": n, "bytes": byt},
