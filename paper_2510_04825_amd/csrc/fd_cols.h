@@ -4,8 +4,9 @@
 //
 // Lane c < r owns column c of G = S A(p) Q; S b is owned by lane r when
 // r < 64 and carried identically by every lane when r = 64.  No dot product
-// needs a cross-lane reduction.  The s rows arrive in blocks of kColsRB held
-// in registers; each block is merged into the running triangular factor by
+// needs a cross-lane reduction.  The s rows arrive in blocks of RB rows
+// (kColsRB unless the caller picks another multiple of 4) held in registers;
+// each block is merged into the running triangular factor by
 // Householder reflections of the stacked matrix [R; block] (reflector j acts
 // on row j of R and on all block rows).  This is Householder QR of G applied
 // in block order: the same R up to rounding.  R, with Q^T b as its last
@@ -66,9 +67,9 @@ __device__ __forceinline__ double cols_coef(const ColsModel& M, const double* pv
   }
 }
 
-__host__ __device__ inline int cols_lds_doubles(int rmax, int smax, bool ref) {
+__host__ __device__ inline int cols_lds_doubles(int rmax, int smax, bool ref, int rb = kColsRB) {
   return (rmax + 1) * (rmax + 2) / 2         // packed [R | Q^T b]
-         + kColsRB * 6                       // face coefficients of a block
+         + rb * 6                            // face coefficients of a block
          + kMaxR                             // y
          + (ref ? kMaxR : 0);                // correction, or 64 residual rows (refinement)
 }
@@ -87,10 +88,10 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// term coefficients of rows k0 .. k0 + kColsRB - 1 into a[i * F + f]
-template <int F, int DP, int COEF>
+// term coefficients of rows k0 .. k0 + RB - 1 into a[i * F + f]
+template <int F, int DP, int COEF, int RB = kColsRB>
 __device__ __forceinline__ void cols_faces(const ColsModel& M, const double* pv, int k0, double* a, int lane) {
-  for (int idx = lane; idx < kColsRB * F; idx += 64) {
+  for (int idx = lane; idx < RB * F; idx += 64) {
     const int i = idx / F, f = idx % F;
     const int k = k0 + i;
     a[idx] = (k < M.s) ? cols_coef<F, DP, COEF>(M, pv, f, k) : 0.0;
@@ -99,11 +100,11 @@ __device__ __forceinline__ void cols_faces(const ColsModel& M, const double* pv,
 }
 
 // this block's rows of column `lane` of G in the contraction precision
-template <int F>
+template <int F, int RB = kColsRB>
 __device__ __forceinline__ void cols_block(const ColsModel& M, int prec, int k0, const double* a, int lane,
-                                           double (&B)[kColsRB]) {
+                                           double (&B)[RB]) {
 #pragma unroll
-  for (int i = 0; i < kColsRB; ++i) {
+  for (int i = 0; i < RB; ++i) {
     const int k = k0 + i;
     double t = 0.0;
     if (k < M.s && lane < M.r) {
@@ -173,10 +174,11 @@ __device__ __forceinline__ void cols_forward_solve(const double* R, int r1, int 
 // contraction or refinement steps (FP64 residuals); without it prec must be
 // FP64 and refine 0.  Writes y (r values), rho and status when the pointers
 // are not NULL.
-template <int F, int DP, bool BRED, bool REF, int COEF = kCoefDiffusion>
+template <int F, int DP, bool BRED, bool REF, int COEF = kCoefDiffusion, int RB = kColsRB>
 __device__ void cols_solve(const ColsModel& M, const double* params, int prec, int refine, double* lds, int smax,
                            int lane, double* y_out, double* rho_out, int32_t* status_out) {
-  constexpr int RB = kColsRB;
+  static_assert(RB % 4 == 0, "the dot products run four rows at a time");
+  static_assert(!REF || 64 % RB == 0, "the refinement's 64-row residual slices hold whole blocks");
   const int r = M.r, s = M.s, r1 = r + 1;
   double* R = lds;                     // r1 (r1 + 1) / 2 doubles
   double* a = R + r1 * (r1 + 1) / 2;
@@ -197,9 +199,9 @@ __device__ void cols_solve(const ColsModel& M, const double* params, int prec, i
   double rho2 = 0.0, r00 = 0.0;
   bool full_rank = true;
   for (int k0 = 0; k0 < s; k0 += RB) {
-    cols_faces<F, DP, COEF>(M, pv, k0, a, lane);
+    cols_faces<F, DP, COEF, RB>(M, pv, k0, a, lane);
     double B[RB];
-    cols_block<F>(M, REF ? prec : SUBAP_FP64, k0, a, lane, B);
+    cols_block<F, RB>(M, REF ? prec : SUBAP_FP64, k0, a, lane, B);
     double Bb[BRED ? RB : 1];
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
@@ -307,9 +309,9 @@ __device__ void cols_solve(const ColsModel& M, const double* params, int prec, i
         res[lane] = v;
         wave_sync_lds();
       }
-      cols_faces<F, DP, COEF>(M, pv, k0, a, lane);
+      cols_faces<F, DP, COEF, RB>(M, pv, k0, a, lane);
       double B[RB];
-      cols_block<F>(M, prec, k0, a, lane, B);
+      cols_block<F, RB>(M, prec, k0, a, lane, B);
 #pragma unroll
       for (int i = 0; i < RB; ++i) {
         const double rk = res[k0 % 64 + i];  // 0 beyond s

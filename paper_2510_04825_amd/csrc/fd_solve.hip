@@ -172,14 +172,14 @@ __global__ __launch_bounds__(256) void k_fd_solve(FDArgs A) {
 }
 
 // Column-per-lane solve (fd_cols.h): one wavefront per parameter, two per block.
-template <int F, int DP, bool BRED, bool REF, int COEF>
+template <int F, int DP, bool BRED, bool REF, int COEF, int RB = kColsRB>
 __global__ __launch_bounds__(128, REF ? 1 : (BRED ? 2 : 4)) void k_fd_cols(FDArgs A, int ldsw) {
   extern __shared__ double lds_cols[];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int64_t p = static_cast<int64_t>(blockIdx.x) * 2 + wave;
   if (p >= A.m) return;  // uniform per wavefront; no block-level barrier follows
   const ColsModel M{A.r, A.s, A.phi, A.delta64T, A.delta32T, A.bS, A.inv_h2, A.bS_norm, A.aff_c0, A.aff_tau};
-  cols_solve<F, DP, BRED, REF, COEF>(M, A.params + p * DP, A.prec, A.refine, lds_cols + static_cast<int64_t>(wave) * ldsw, A.s,
+  cols_solve<F, DP, BRED, REF, COEF, RB>(M, A.params + p * DP, A.prec, A.refine, lds_cols + static_cast<int64_t>(wave) * ldsw, A.s,
                           lane, A.y + p * A.r, A.rho ? A.rho + p : nullptr, A.status ? A.status + p : nullptr);
 }
 
@@ -231,8 +231,10 @@ subap_status launch(const FDArgs& a, hipStream_t st) {
   return SUBAP_OK;
 }
 
-// Instantiated shapes: (TEAM, R) from s, RM from r.
-template <int F, int DP, int COEF = kCoefDiffusion>
+// Column-per-lane launch.  RB is the row block of the FP64 form without
+// refinement at r < 64; the other forms keep blocks of kColsRB rows (their
+// residual slices of 64 rows hold whole blocks).
+template <int F, int DP, int COEF = kCoefDiffusion, int RB = kColsRB>
 subap_status launch_cols(const FDArgs& a, hipStream_t st) {
   const int64_t nb = (a.m + 1) / 2;
   if (nb > 0x7fffffff) {
@@ -240,7 +242,8 @@ subap_status launch_cols(const FDArgs& a, hipStream_t st) {
     return SUBAP_E_INVALID;
   }
   const bool ref = a.refine > 0 || a.prec != SUBAP_FP64;
-  const int ldsw = cols_lds_doubles(a.r, a.s, ref);
+  const bool own_rb = !ref && a.r < 64;
+  const int ldsw = cols_lds_doubles(a.r, a.s, ref, own_rb ? RB : kColsRB);
   const size_t lds = sizeof(double) * 2 * static_cast<size_t>(ldsw);
   ProfScope prof("fd_solve", st);
   const dim3 grid(static_cast<unsigned>(nb)), block(128);
@@ -249,12 +252,13 @@ subap_status launch_cols(const FDArgs& a, hipStream_t st) {
     else hipLaunchKernelGGL((k_fd_cols<F, DP, true, false, COEF>), grid, block, lds, st, a, ldsw);
   } else {
     if (ref) hipLaunchKernelGGL((k_fd_cols<F, DP, false, true, COEF>), grid, block, lds, st, a, ldsw);
-    else hipLaunchKernelGGL((k_fd_cols<F, DP, false, false, COEF>), grid, block, lds, st, a, ldsw);
+    else hipLaunchKernelGGL((k_fd_cols<F, DP, false, false, COEF, RB>), grid, block, lds, st, a, ldsw);
   }
   SUBAP_HIP_TRY(hipGetLastError());
   return SUBAP_OK;
 }
 
+// Instantiated shapes: (TEAM, R) from s, RM from r.
 template <int F, int DP>
 subap_status dispatch(const FDArgs& a, hipStream_t st) {
   const int s = a.s, r = a.r;
@@ -275,8 +279,14 @@ subap_status fd_solve(subap_model_s* M, const double* params, int64_t m, double*
                       int32_t* status, int prec, int refine, hipStream_t st) {
   FDArgs a{params, m, M->r, M->s, M->phi, M->delta64, M->delta32, M->delta64T, M->delta32T, M->bS, M->inv_h2,
            M->bS_norm, y, rho, status, prec, refine, M->aff_c0, M->tau};
-  // the delay family's two affine terms: column-per-lane solver for every shape
-  if (M->family == SUBAP_FAMILY_DELAY) return launch_cols<2, 1, kCoefDelay>(a, st);
+  // the delay family's two affine terms: column-per-lane solver for every
+  // shape.  Its FP64 form fits blocks of 40 rows in registers (no spills at
+  // F = 2), which shortens the reflector chain when that saves a block: at
+  // s = 40, one block of 40 rows instead of 32 + 8 (padded to 32).
+  if (M->family == SUBAP_FAMILY_DELAY) {
+    if ((a.s + 39) / 40 < (a.s + 31) / 32) return launch_cols<2, 1, kCoefDelay, 40>(a, st);
+    return launch_cols<2, 1, kCoefDelay>(a, st);
+  }
   return M->dimx == 2 ? dispatch<4, 2>(a, st) : dispatch<6, 4>(a, st);
 }
 

@@ -182,3 +182,30 @@ def test_delay_full_size_sampled():
             assert abs(H[i] - cQ @ yo) <= 1e-10 * abs(cQ @ yo) + 1e-12 * np.abs(cQ).sum() * np.abs(yo).max(), i
     finally:
         M.free()
+
+
+@pytest.mark.parametrize("r,s", [(6, 24), (12, 72), (20, 100)])
+def test_delay_fp64_solve_block_shapes(r, s):
+    """FP64 solves at shapes that take one block of 32 rows (s = 24), and
+    blocks of 40 rows with a ragged last block (s = 72, 100)."""
+    import torch
+    w = si.delay(n=2000, r=r, s=s, m=40, seed=611)
+    off = O.offline(w)
+    header(f"delay fp64 block shapes r={r} s={s}")
+    device()
+    M = B.Model(w, basis=off["Q"])
+    try:
+        assert np.array_equal(M.rows(), off["rows"])
+        P = w["test_params"]
+        y, rho, st = M.solve(to_dev(P))
+        torch.cuda.synchronize()
+        assert np.all(st.cpu().numpy() == B.OK)
+        fam, Q = off["family"], off["Q"]
+        yo = On.solve(fam, Q, off["rows"], P)
+        yg = y.cpu().numpy()
+        d = max(On.delta_res(fam, Q, p, a, b) for p, a, b in zip(P, yg, yo))
+        assert d <= 1e-12, d
+        rho_o = np.array([On.sketched_residual(fam, Q, off["rows"], p, a) for p, a in zip(P, yg)])
+        np.testing.assert_allclose(rho.cpu().numpy(), rho_o, rtol=1e-9, atol=1e-13)
+    finally:
+        M.free()
