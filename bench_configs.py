@@ -194,6 +194,20 @@ def uneven(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
         dmax = max(dmax, d)
     t_plan = timed(lambda: B.subap_plan_execute(plan, stream), args.steps, stream)
     threads, blocks = B.subap_plan_shape(plan)
+    # the same plan in FP64 without refinement
+    plan64 = B.subap_plan_create([M.handle for M in models], Ps, ys, None, sts, B.FP64, 0,
+                                 B.PLAN_GRAPH | B.PLAN_AUTOTUNE, stream)
+    B.subap_plan_execute(plan64, stream)
+    torch.cuda.synchronize()
+    valid64, dmax64 = 0, 0.0
+    for M, P, y, y6, st in zip(models, Ps, ys, y64, sts):
+        v, d = _validity(B, M, P, y, y6, st, TOL)
+        valid64 += v
+        dmax64 = max(dmax64, d)
+    t_plan64 = timed(lambda: B.subap_plan_execute(plan64, stream), args.steps, stream)
+    shape64 = B.subap_plan_shape(plan64)
+    B.subap_plan_free(plan64)
+    fp64_best = valid64 / t_plan64 > valid / t_plan
 
     def per_instance():
         for M, P, y, st in zip(models, Ps, ys, sts):
@@ -218,21 +232,27 @@ def uneven(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
                            "passed in)")
     for M in models:
         M.free()
+    t_best = t_plan64 if fp64_best else t_plan
     out = {
         "metric": "online solves/s at rel. residual <=1e-6: batched/learned vs plain, 1 MI355X",
-        "value": valid / (t_plan / 1e3), "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
-        "ms_per_step": t_plan, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64", "data": "synthetic",
+        "value": (valid64 if fp64_best else valid) / (t_best / 1e3), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1,
+        "ms_per_step": t_best, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if fp64_best else "f32+f64", "data": "synthetic",
         "config": {"workload": "uneven_64_instances_diffusion2d", "parameters": total,
-                   "form": "one persistent hipGraph launch, FP32 contraction + FP64 LSQ + 1 refinement",
-                   "autotuned_shape": {"threads": threads, "blocks": blocks}},
-        "valid": {"count": valid, "of": total, "max_sketched_distance": dmax},
-        "forms": {"plan_graph": {"ms": t_plan, "solves_per_s": total / (t_plan / 1e3)},
+                   "form": ("one persistent hipGraph launch, FP64 contraction + FP64 LSQ" if fp64_best else
+                            "one persistent hipGraph launch, FP32 contraction + FP64 LSQ + 1 refinement"),
+                   "autotuned_shape": ({"threads": shape64[0], "blocks": shape64[1]} if fp64_best else
+                                       {"threads": threads, "blocks": blocks})},
+        "valid": ({"count": valid64, "of": total, "max_sketched_distance": dmax64} if fp64_best else
+                  {"count": valid, "of": total, "max_sketched_distance": dmax}),
+        "forms": {"plan_graph": {"ms": t_plan, "solves_per_s": total / (t_plan / 1e3), "valid": valid},
+                  "plan_graph_fp64": {"ms": t_plan64, "solves_per_s": total / (t_plan64 / 1e3), "valid": valid64},
                   "per_instance_calls": {"ms": t_inst, "solves_per_s": total / (t_inst / 1e3)},
                   "fp64_per_p_plain": {"solves_per_s": plain_rate}},
         "roofline": {"bound": "alu", "kernel": "fd_multi_persistent",
-                     "achieved": flops / (t_plan * 1e-3) / 1e12, "peak": PEAKS["fp64_tflops"],
-                     "unit": "TFLOP/s", "frac": flops / (t_plan * 1e-3) / 1e12 / PEAKS["fp64_tflops"],
+                     "achieved": flops / (t_best * 1e-3) / 1e12, "peak": PEAKS["fp64_tflops"],
+                     "unit": "TFLOP/s", "frac": flops / (t_best * 1e-3) / 1e12 / PEAKS["fp64_tflops"],
                      "traffic": None},
         "offline_s": offline_s, "plan_create_s": plan_s,
     }

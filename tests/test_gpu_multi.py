@@ -155,10 +155,13 @@ def test_plan_with_3d_models(uneven_small, cubes_small, mix, prec, refine, tol, 
 def test_uneven_full_size_sampled(tmp_path, monkeypatch):
     """The benchmark's uneven batch: all 64 instances (grids 32^2..512^2,
     r in {8, 16, 32, 64}) in one persistent, autotuned, graph-replayed launch,
-    FP32 contraction + one FP64 refinement, with oracle-made orthonormal bases
-    and seeded rows.  Two sampled parameters per instance are recomputed by the
-    oracle: sketched distance <= 1e-6 plus the simple-refinement bias bound
-    2^-20 kappa(S A Q) rho* (rho* is of order one for a random basis)."""
+    in both forms the benchmark times (FP64 without refinement, and FP32
+    contraction + one FP64 refinement), with oracle-made orthonormal bases and
+    seeded rows.  Two sampled parameters per instance are recomputed by the
+    oracle.  Bars on the sketched distance: FP64 1e-12 plus the backward-error
+    term 2^-46 kappa(S A Q) rho*; FP32 + refinement 1e-6 plus the
+    simple-refinement bias bound 2^-20 kappa(S A Q) rho* (rho* is of order one
+    for a random basis)."""
     import torch
     from oracle import families as Fm
     monkeypatch.setenv("SUBAP_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
@@ -177,26 +180,29 @@ def test_uneven_full_size_sampled(tmp_path, monkeypatch):
         params = [to_dev(w["test_params"]) for w in insts]
         ys = [torch.empty((w["m"], w["r"]), dtype=torch.float64, device=params[0].device) for w in insts]
         sts = [torch.empty(w["m"], dtype=torch.int32, device=params[0].device) for w in insts]
-        plan = B.subap_plan_create([M.handle for M in models], params, ys, None, sts, B.FP32, 1,
-                                   B.PLAN_GRAPH | B.PLAN_AUTOTUNE)
-        try:
-            B.subap_plan_execute(plan)
-            torch.cuda.synchronize()
-        finally:
-            B.subap_plan_free(plan)
-        for w, Q, rows, y, st in zip(insts, bases, rowsets, ys, sts):
-            assert np.all(st.cpu().numpy() == B.OK)
-            fam = Fm.from_workload(w)
-            yg = y.cpu().numpy()
-            for i in rng.choice(w["m"], size=min(2, w["m"]), replace=False):
-                p = w["test_params"][i]
-                G = On.reduced_matrix(fam, Q, rows, p)
-                bS = fam.rhs_rows(p, rows)
-                yo, _, rho = On.householder_lsq(G, bS)
-                sv = np.linalg.svd(G, compute_uv=False)
-                tol = 1e-6 + 2.0 ** -20 * sv[0] / sv[-1] * rho / np.linalg.norm(bS)
-                d = np.linalg.norm(G @ (yg[i] - yo)) / np.linalg.norm(bS)
-                assert d <= tol, (w["n"], w["r"], w["s"], i, d, tol)
+        picks = [rng.choice(w["m"], size=min(2, w["m"]), replace=False) for w in insts]
+        for prec, refine, base, scale in ((B.FP64, 0, 1e-12, 2.0 ** -46), (B.FP32, 1, 1e-6, 2.0 ** -20)):
+            header(f"uneven full size prec={prec} refine={refine}")
+            plan = B.subap_plan_create([M.handle for M in models], params, ys, None, sts, prec, refine,
+                                       B.PLAN_GRAPH | B.PLAN_AUTOTUNE)
+            try:
+                B.subap_plan_execute(plan)
+                torch.cuda.synchronize()
+            finally:
+                B.subap_plan_free(plan)
+            for w, Q, rows, y, st, pick in zip(insts, bases, rowsets, ys, sts, picks):
+                assert np.all(st.cpu().numpy() == B.OK)
+                fam = Fm.from_workload(w)
+                yg = y.cpu().numpy()
+                for i in pick:
+                    p = w["test_params"][i]
+                    G = On.reduced_matrix(fam, Q, rows, p)
+                    bS = fam.rhs_rows(p, rows)
+                    yo, _, rho = On.householder_lsq(G, bS)
+                    sv = np.linalg.svd(G, compute_uv=False)
+                    tol = base + scale * sv[0] / sv[-1] * rho / np.linalg.norm(bS)
+                    d = np.linalg.norm(G @ (yg[i] - yo)) / np.linalg.norm(bS)
+                    assert d <= tol, (prec, w["n"], w["r"], w["s"], i, d, tol)
     finally:
         for M in models:
             M.free()
