@@ -22,9 +22,45 @@ Validity of a form: status OK and sketched distance |S A Q (y - y_fp64)| / |S b|
 """
 from __future__ import annotations
 
+import hashlib
+import os
 import time
 
 import numpy as np
+
+# HBM traffic per launch of each line's dominant kernel, from two rocprofv3
+# counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch of the timed
+# launch), scaled by the factors a 1 GiB device copy gives (FETCH 2.0,
+# WRITE 1.0).  A record holds only for the kernel sources it was taken with:
+# the hash covers them, and a changed source reports traffic null.
+FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
+TRAFFIC = {
+    # k_fd_cols<6, 4, false, false, 0, 32>, one launch of 65,536 parameters
+    "diffusion3d": {"sources": ("fd_solve.hip", "fd_cols.h", "common.h"), "sha256_16": "9e8638a8e6655acf",
+                    "fetch_kib": 6600.1, "write_kib": 30217.4},
+    # k_fd_cols<2, 1, false, false, 1, 40>, one launch of 65,536 parameters
+    "delay": {"sources": ("fd_solve.hip", "fd_cols.h", "common.h"), "sha256_16": "9e8638a8e6655acf",
+              "fetch_kib": 2198.5, "write_kib": 7168.0},
+    # k_fd_multi<false, 1>, one replay over the 64 instances (autotuned shape)
+    "uneven": {"sources": ("fd_multi.hip", "fd_cols.h", "common.h"), "sha256_16": "ab6faf56978d9362",
+               "fetch_kib": 28210.2, "write_kib": 15870.7},
+    # k_lift_x6<3>, 1,024 vectors on 215^3 nodes with a 32-aligned leading dimension
+    # (FETCH: mean over the three leading dimensions, which differ by under 2%)
+    "lift": {"sources": ("lift.hip", "common.h"), "sha256_16": "732764698a562428",
+             "fetch_kib": 2454592.2, "write_kib": 39753504.0},
+}
+
+
+def _traffic(workload):
+    rec = TRAFFIC[workload]
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2510_04825_amd", "csrc", f),
+                  "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != rec["sha256_16"]:
+        return None
+    return 1024.0 * (rec["fetch_kib"] * FETCH_FACTOR + rec["write_kib"] * WRITE_FACTOR)
 
 
 def _oracle_rate(jobs, budget_s, sample_text):
@@ -153,7 +189,8 @@ def diffusion3d(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
         "forms": forms,
         "roofline": {"bound": "alu", "kernel": "fd_solve", "achieved": flops / (kms * 1e-3) / 1e12,
                      "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s",
-                     "frac": flops / (kms * 1e-3) / 1e12 / PEAKS["fp64_tflops"], "traffic": None},
+                     "frac": flops / (kms * 1e-3) / 1e12 / PEAKS["fp64_tflops"],
+                     "traffic": _traffic("diffusion3d") if best == "fp64_batched" else None},
         # the configuration's HBM figure: with S fixed, a batch moves the
         # parameters in (32 B each), y, rho and status out (r 8 + 8 + 4 B each)
         # and the s x F x r FP64 face tables and s x F x d mode values once
@@ -253,7 +290,7 @@ def uneven(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
         "roofline": {"bound": "alu", "kernel": "fd_multi_persistent",
                      "achieved": flops / (t_best * 1e-3) / 1e12, "peak": PEAKS["fp64_tflops"],
                      "unit": "TFLOP/s", "frac": flops / (t_best * 1e-3) / 1e12 / PEAKS["fp64_tflops"],
-                     "traffic": None},
+                     "traffic": _traffic("uneven") if fp64_best else None},
         "offline_s": offline_s, "plan_create_s": plan_s,
     }
     if cpu is not None:
@@ -385,7 +422,8 @@ def lift(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
             "config": {"workload": f"lift_diffusion3d_n{N}^3_r{r}_k{k}", "n": n, "bytes": byt},
             "forms": out,
             "roofline": {"bound": "hbm", "kernel": "lift", "achieved": best["GB_per_s"], "peak": PEAKS["hbm_gbs"],
-                         "unit": "GB/s", "frac": best["frac_hbm"], "traffic": None}}
+                         "unit": "GB/s", "frac": best["frac_hbm"],
+                         "traffic": _traffic("lift") if best["ldx"] % 32 == 0 else None}}
 
 
 def leverage(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
@@ -581,7 +619,8 @@ def delay(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
         "table4_columns": table,
         "roofline": {"bound": "alu", "kernel": "fd_solve", "achieved": flops / (kms * 1e-3) / 1e12,
                      "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s",
-                     "frac": flops / (kms * 1e-3) / 1e12 / PEAKS["fp64_tflops"], "traffic": None},
+                     "frac": flops / (kms * 1e-3) / 1e12 / PEAKS["fp64_tflops"],
+                     "traffic": _traffic("delay") if (r, s) == (10, 40) else None},
     }
     if cpu is not None:
         out["cpu_baseline"] = cpu
