@@ -81,3 +81,50 @@ def test_union_of_pivots(name, selection):
         assert dd <= 1e-12, dd
     finally:
         M.free()
+
+
+@pytest.mark.parametrize("name", ["diff2d_rounds", "diff3d"])
+def test_rows_per_nearest_snapshot(name):
+    """The other variant of Section 5.3.2: each parameter takes the rows
+    selected at its nearest snapshot point.  It is built from existing parts:
+    one model per snapshot on the shared basis, each selecting at its own
+    point, and one plan that solves every parameter with its snapshot's
+    model.  Rows bit-exact per snapshot; FP64 delta_res <= 1e-12 for every
+    parameter against the oracle on the same rows."""
+    import torch
+    w = CASES[name]()
+    w = dict(w, test_params=np.random.default_rng(31).uniform(-1.0, 1.0, size=(48, w["d"])), m=48)
+    header(f"nearest-snapshot rows {name}")
+    Q = _basis(w)
+    snaps = w["snap_params"]
+    P = w["test_params"]
+    near = np.argmin(((P[:, None, :] - snaps[None, :, :]) ** 2).sum(axis=2), axis=1)
+    used = [i for i in range(len(snaps)) if np.any(near == i)]
+    assert len(used) >= 2
+    offs = {i: O.offline(dict(w, select_param=snaps[i]), basis=Q) for i in used}
+    device()
+    models = {}
+    try:
+        for i in used:
+            models[i] = B.Model(dict(w, select_param=snaps[i]), basis=Q)
+            assert np.array_equal(models[i].rows(), offs[i]["rows"]), i
+        params = [to_dev(P[near == i]) for i in used]
+        ys = [torch.full((int(np.sum(near == i)), w["r"]), -7.0, dtype=torch.float64, device=params[0].device)
+              for i in used]
+        sts = [torch.full((int(np.sum(near == i)),), -1, dtype=torch.int32, device=params[0].device) for i in used]
+        plan = B.subap_plan_create([models[i].handle for i in used], params, ys, None, sts, B.FP64, 0, 0)
+        try:
+            B.subap_plan_execute(plan)
+            torch.cuda.synchronize()
+        finally:
+            B.subap_plan_free(plan)
+        for i, y, st in zip(used, ys, sts):
+            assert np.all(st.cpu().numpy() == B.OK)
+            Pi = P[near == i]
+            off = offs[i]
+            yo = On.solve(off["family"], off["Q"], off["rows"], Pi)
+            dd = max(On.delta_res(off["family"], off["Q"], p, a, b) for p, a, b in zip(Pi, y.cpu().numpy(), yo))
+            assert dd <= 1e-12, (i, dd)
+    finally:
+        for M in models.values():
+            M.free()
