@@ -493,9 +493,12 @@ def leverage(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
         "residual_estimate": {"median_rho": float(torch.median(rho)), "median_lo": float(torch.median(lo)),
                               "median_hi": float(torch.median(hi)),
                               "eps": (r + 1) * float(np.log(r + 1)) / s},
+        # the 3-D record: the same kernel at the same m, r, s and F (the
+        # weights live in the tables), so the same bytes per launch
         "roofline": {"bound": "alu", "kernel": "fd_solve", "achieved": flops / (kms * 1e-3) / 1e12,
                      "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s",
-                     "frac": flops / (kms * 1e-3) / 1e12 / PEAKS["fp64_tflops"], "traffic": None},
+                     "frac": flops / (kms * 1e-3) / 1e12 / PEAKS["fp64_tflops"],
+                     "traffic": _traffic("diffusion3d") if (r, s, m) == (40, 160, 65536) else None},
     }
     if cpu is not None:
         out["cpu_baseline"] = cpu
