@@ -72,7 +72,7 @@ typedef enum {
   SUBAP_E_RANK = 4,        /* per-p: S A(p) X numerically rank deficient     */
   SUBAP_E_NOCONV = 5,      /* snapshot solver did not reach its tolerance    */
   SUBAP_E_NONFINITE = 6,   /* per-p: non-finite parameter or coefficient     */
-  SUBAP_E_UNSUPPORTED = 7  /* valid request this build does not implement    */
+  SUBAP_E_UNSUPPORTED = 7  /* valid request this library does not implement  */
 } subap_status;
 
 typedef enum {
