@@ -96,7 +96,9 @@ __device__ __forceinline__ f32x16 mfma(bf16x8 a, bf16x8 b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
-constexpr int kLiftTiles = 2;          // 32-row tiles of Q per wave
+// 32-row tiles of Q per wave: four tiles (1 wave per SIMD) write 512-byte runs
+// of each column per wave and beat two tiles (2 waves per SIMD) by about 9%
+constexpr int kLiftTiles = 4;
 constexpr int kLiftRowsPerBlock = 4 * kLiftTiles * 32;
 
 template <int NKB>
