@@ -36,11 +36,11 @@ import numpy as np
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 TRAFFIC = {
     # k_fd_cols<6, 4, false, false, 0, 32>, one launch of 65,536 parameters
-    "diffusion3d": {"sources": ("fd_solve.hip", "fd_cols.h", "common.h"), "sha256_16": "9e8638a8e6655acf",
-                    "fetch_kib": 6600.1, "write_kib": 30217.4},
+    "diffusion3d": {"sources": ("fd_solve.hip", "fd_cols.h", "common.h"), "sha256_16": "a92a869da535684e",
+                    "fetch_kib": 6607.4, "write_kib": 29655.2},
     # k_fd_cols<2, 1, false, false, 1, 40>, one launch of 65,536 parameters
-    "delay": {"sources": ("fd_solve.hip", "fd_cols.h", "common.h"), "sha256_16": "9e8638a8e6655acf",
-              "fetch_kib": 2198.5, "write_kib": 7168.0},
+    "delay": {"sources": ("fd_solve.hip", "fd_cols.h", "common.h"), "sha256_16": "a92a869da535684e",
+              "fetch_kib": 2201.1, "write_kib": 7168.0},
     # k_fd_multi<false, 1>, one replay over the 64 instances (autotuned shape)
     "uneven": {"sources": ("fd_multi.hip", "fd_cols.h", "common.h"), "sha256_16": "ab6faf56978d9362",
                "fetch_kib": 28210.2, "write_kib": 15870.7},

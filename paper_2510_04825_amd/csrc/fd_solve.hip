@@ -282,8 +282,11 @@ subap_status fd_solve(subap_model_s* M, const double* params, int64_t m, double*
   // the delay family's two affine terms: column-per-lane solver for every
   // shape.  Its FP64 form fits blocks of 40 rows in registers (no spills at
   // F = 2), which shortens the reflector chain when that saves a block: at
-  // s = 40, one block of 40 rows instead of 32 + 8 (padded to 32).
+  // s = 40, one block of 40 rows instead of 32 + 8 (padded to 32).  Short
+  // row sets take one block of 24 or 28 rows, which pads less than 32.
   if (M->family == SUBAP_FAMILY_DELAY) {
+    if (a.s <= 24) return launch_cols<2, 1, kCoefDelay, 24>(a, st);
+    if (a.s <= 28) return launch_cols<2, 1, kCoefDelay, 28>(a, st);
     if ((a.s + 39) / 40 < (a.s + 31) / 32) return launch_cols<2, 1, kCoefDelay, 40>(a, st);
     return launch_cols<2, 1, kCoefDelay>(a, st);
   }

@@ -184,10 +184,11 @@ def test_delay_full_size_sampled():
         M.free()
 
 
-@pytest.mark.parametrize("r,s", [(6, 24), (12, 72), (20, 100)])
+@pytest.mark.parametrize("r,s", [(6, 24), (8, 26), (8, 30), (12, 72), (20, 100)])
 def test_delay_fp64_solve_block_shapes(r, s):
-    """FP64 solves at shapes that take one block of 32 rows (s = 24), and
-    blocks of 40 rows with a ragged last block (s = 72, 100)."""
+    """FP64 solves at shapes that take one block of 24 rows (s = 24), one
+    ragged block of 28 (s = 26) or 32 rows (s = 30), and blocks of 40 rows
+    with a ragged last block (s = 72, 100)."""
     import torch
     w = si.delay(n=2000, r=r, s=s, m=40, seed=611)
     off = O.offline(w)
