@@ -9,6 +9,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <stdexcept>
 #include <string>
 #include <unordered_set>
 #include <vector>
@@ -132,6 +133,26 @@ bool all_finite(const double* v, int64_t len) {
   return true;
 }
 
+// Maps a host-side C++ exception escaping an entry point to a status code:
+// no exception crosses the C ABI.
+subap_status host_exception() {
+  try {
+    throw;
+  } catch (const std::bad_alloc&) {
+    set_error("host memory allocation failed");
+    return SUBAP_E_NOMEM;
+  } catch (const std::length_error&) {
+    set_error("host buffer size out of range");
+    return SUBAP_E_NOMEM;
+  } catch (const std::exception& e) {
+    set_error(std::string("host exception: ") + e.what());
+    return SUBAP_E_INVALID;
+  } catch (...) {
+    set_error("unknown host exception");
+    return SUBAP_E_INVALID;
+  }
+}
+
 }  // namespace
 }  // namespace subap
 
@@ -157,207 +178,243 @@ const char* subap_last_error(void) { return g_last_error.c_str(); }
 
 subap_status subap_offline(const subap_problem_desc* pd, const subap_offline_opts* o, void* hip_stream,
                            subap_model* out) {
-  clear_error();
-  if (!pd || !o || !out) return invalid("problem, opts and out must not be NULL");
-  *out = nullptr;
-  subap_model_s tmp;
-  tmp.family = pd->family;
-  if (pd->family == SUBAP_FAMILY_DIFF2D || pd->family == SUBAP_FAMILY_DIFF3D) {
-    const int dimx = pd->family == SUBAP_FAMILY_DIFF2D ? 2 : 3;
-    if (pd->grid < 2 || pd->grid > 46340) return invalid("grid must be in [2, 46340]");
-    double nn = std::pow(static_cast<double>(pd->grid), dimx);
-    if (nn > 2147483647.0) return invalid("grid^dim exceeds 2^31 - 1 unknowns");
-    tmp.N = pd->grid;
-    tmp.dimx = dimx;
-    tmp.n = static_cast<int64_t>(nn);
-    tmp.d = dimx == 2 ? 2 : 4;
-    tmp.F = 2 * dimx;
-    tmp.h = 1.0 / (pd->grid + 1);
-    tmp.inv_h2 = 1.0 / (tmp.h * tmp.h);
-    if (pd->rhs && !all_finite(pd->rhs, tmp.n)) return invalid("rhs has non-finite entries");
-  } else if (pd->family == SUBAP_FAMILY_KRR) {
-    if (pd->n < 1 || pd->n > 2147483647LL) return invalid("KRR n must be in [1, 2^31 - 1]");
-    if (pd->dim < 1 || pd->dim > 16) return invalid("KRR point dimension must be in [1, 16]");
-    if (!pd->points || !pd->rhs) return invalid("KRR needs points and rhs");
-    if (!(pd->lambda > 0.0) || !std::isfinite(pd->lambda)) return invalid("KRR lambda must be finite and > 0");
-    tmp.n = pd->n;
-    tmp.dimx = pd->dim;
-    tmp.d = 1;
-    tmp.lambda = pd->lambda;
-    if (!all_finite(pd->points, pd->n * pd->dim) || !all_finite(pd->rhs, pd->n))
-      return invalid("points or rhs have non-finite entries");
-  } else if (pd->family == SUBAP_FAMILY_DELAY) {
-    if (pd->n < 2 || pd->n > 2147483647LL) return invalid("delay n must be in [2, 2^31 - 1]");
-    if (!(pd->tau > 0.0) || !std::isfinite(pd->tau)) return invalid("delay tau must be finite and > 0");
-    if (!(pd->kappa > 2.0) || !std::isfinite(pd->kappa)) return invalid("delay kappa must be finite and > 2");
-    if (!pd->rhs || !all_finite(pd->rhs, pd->n)) return invalid("delay needs a finite rhs");
-    tmp.n = pd->n;
-    tmp.dimx = 1;
-    tmp.d = 1;
-    tmp.F = 2;
-    tmp.h = 1.0;
-    tmp.inv_h2 = 1.0;
-    tmp.tau = pd->tau;
-    tmp.kappa = pd->kappa;
-    tmp.aff_c0 = 3.0;  // A_0 = 3 A_1
-  } else {
-    return invalid("unknown family");
-  }
-  if (pd->c_out && !all_finite(pd->c_out, tmp.n)) return invalid("c_out has non-finite entries");
-  if (o->r < 1 || o->r > kMaxR) return invalid("r must be in [1, 64]");
-  const bool uni = !o->rows_in && o->n_select > 1 && o->selection != SUBAP_SELECT_LEVERAGE;
-  if (o->n_select < 0) return invalid("n_select must be >= 0");
-  if (uni) {
-    if (!o->select_params) return invalid("n_select > 1 needs select_params");
-    if (o->r > tmp.n) return invalid("r must not exceed n");
-  } else if (o->s < o->r || o->s > kMaxS || o->s > tmp.n) {
-    return invalid("s must satisfy r <= s <= min(n, 256)");
-  }
-  if (o->snap_tol < 0.0 || !std::isfinite(o->snap_tol)) return invalid("snap_tol must be finite and >= 0");
-  if (o->snap_maxiter < 0) return invalid("snap_maxiter must be >= 0");
-  tmp.r = o->r;
-  tmp.s = uni ? o->r : o->s;  // a union of pivots sets s after the selection
-  if (!o->basis_in) {
-    if (!o->snap_params) return invalid("snap_params needed without basis_in");
-    if (!all_finite(o->snap_params, static_cast<int64_t>(o->r) * tmp.d)) return invalid("snap_params not finite");
-    if (pd->family == SUBAP_FAMILY_KRR)
-      for (int i = 0; i < o->r; ++i)
-        if (!(o->snap_params[i] > 0.0)) return invalid("KRR length scales must be > 0");
-  } else if (!all_finite(o->basis_in, tmp.n * o->r)) {
-    return invalid("basis_in has non-finite entries");
-  }
-  if (!o->rows_in) {
-    if (o->selection != SUBAP_SELECT_CPQR && o->selection != SUBAP_SELECT_LEVERAGE &&
-        o->selection != SUBAP_SELECT_LU)
-      return invalid("selection must be SUBAP_SELECT_CPQR, SUBAP_SELECT_LEVERAGE or SUBAP_SELECT_LU");
-    if (o->selection == SUBAP_SELECT_LEVERAGE) {
-      if (!o->sample_u) return invalid("leverage-score selection needs sample_u");
-      for (int k = 0; k < o->s; ++k)
-        if (!(o->sample_u[k] >= 0.0 && o->sample_u[k] < 1.0)) return invalid("sample_u must lie in [0, 1)");
-    }
-    if (uni) {
-      if (!all_finite(o->select_params, static_cast<int64_t>(o->n_select) * tmp.d))
-        return invalid("select_params not finite");
-      if (pd->family == SUBAP_FAMILY_KRR)
-        for (int t = 0; t < o->n_select; ++t)
-          if (!(o->select_params[t] > 0.0)) return invalid("KRR select_params must be > 0");
+  try {
+    clear_error();
+    if (!pd || !o || !out) return invalid("problem, opts and out must not be NULL");
+    *out = nullptr;
+    subap_model_s tmp;
+    tmp.family = pd->family;
+    if (pd->family == SUBAP_FAMILY_DIFF2D || pd->family == SUBAP_FAMILY_DIFF3D) {
+      const int dimx = pd->family == SUBAP_FAMILY_DIFF2D ? 2 : 3;
+      if (pd->grid < 2 || pd->grid > 46340) return invalid("grid must be in [2, 46340]");
+      double nn = std::pow(static_cast<double>(pd->grid), dimx);
+      if (nn > 2147483647.0) return invalid("grid^dim exceeds 2^31 - 1 unknowns");
+      tmp.N = pd->grid;
+      tmp.dimx = dimx;
+      tmp.n = static_cast<int64_t>(nn);
+      tmp.d = dimx == 2 ? 2 : 4;
+      tmp.F = 2 * dimx;
+      tmp.h = 1.0 / (pd->grid + 1);
+      tmp.inv_h2 = 1.0 / (tmp.h * tmp.h);
+      if (pd->rhs && !all_finite(pd->rhs, tmp.n)) return invalid("rhs has non-finite entries");
+    } else if (pd->family == SUBAP_FAMILY_KRR) {
+      if (pd->n < 1 || pd->n > 2147483647LL) return invalid("KRR n must be in [1, 2^31 - 1]");
+      if (pd->dim < 1 || pd->dim > 16) return invalid("KRR point dimension must be in [1, 16]");
+      if (!pd->points || !pd->rhs) return invalid("KRR needs points and rhs");
+      if (!(pd->lambda > 0.0) || !std::isfinite(pd->lambda)) return invalid("KRR lambda must be finite and > 0");
+      tmp.n = pd->n;
+      tmp.dimx = pd->dim;
+      tmp.d = 1;
+      tmp.lambda = pd->lambda;
+      if (!all_finite(pd->points, pd->n * pd->dim) || !all_finite(pd->rhs, pd->n))
+        return invalid("points or rhs have non-finite entries");
+    } else if (pd->family == SUBAP_FAMILY_DELAY) {
+      if (pd->n < 2 || pd->n > 2147483647LL) return invalid("delay n must be in [2, 2^31 - 1]");
+      if (!(pd->tau > 0.0) || !std::isfinite(pd->tau)) return invalid("delay tau must be finite and > 0");
+      if (!(pd->kappa > 2.0) || !std::isfinite(pd->kappa)) return invalid("delay kappa must be finite and > 2");
+      if (!pd->rhs || !all_finite(pd->rhs, pd->n)) return invalid("delay needs a finite rhs");
+      tmp.n = pd->n;
+      tmp.dimx = 1;
+      tmp.d = 1;
+      tmp.F = 2;
+      tmp.h = 1.0;
+      tmp.inv_h2 = 1.0;
+      tmp.tau = pd->tau;
+      tmp.kappa = pd->kappa;
+      tmp.aff_c0 = 3.0;  // A_0 = 3 A_1
     } else {
-      if (!o->select_param) return invalid("select_param needed without rows_in");
-      if (!all_finite(o->select_param, tmp.d)) return invalid("select_param not finite");
-      if (pd->family == SUBAP_FAMILY_KRR && !(o->select_param[0] > 0.0))
-        return invalid("KRR select_param must be > 0");
+      return invalid("unknown family");
     }
-  } else {
-    std::unordered_set<int64_t> seen;
-    for (int k = 0; k < o->s; ++k) {
-      const int64_t v = o->rows_in[k];
-      if (v < 0 || v >= tmp.n) return invalid("rows_in index out of range");
-      if (!seen.insert(v).second) return invalid("rows_in has duplicates");
+    if (pd->c_out && !all_finite(pd->c_out, tmp.n)) return invalid("c_out has non-finite entries");
+    if (o->r < 1 || o->r > kMaxR) return invalid("r must be in [1, 64]");
+    const bool uni = !o->rows_in && o->n_select > 1 && o->selection != SUBAP_SELECT_LEVERAGE;
+    if (o->n_select < 0) return invalid("n_select must be >= 0");
+    if (uni) {
+      if (!o->select_params) return invalid("n_select > 1 needs select_params");
+      if (o->r > tmp.n) return invalid("r must not exceed n");
+    } else if (o->s < o->r || o->s > kMaxS || o->s > tmp.n) {
+      return invalid("s must satisfy r <= s <= min(n, 256)");
     }
+    if (o->snap_tol < 0.0 || !std::isfinite(o->snap_tol)) return invalid("snap_tol must be finite and >= 0");
+    if (o->snap_maxiter < 0) return invalid("snap_maxiter must be >= 0");
+    tmp.r = o->r;
+    tmp.s = uni ? o->r : o->s;  // a union of pivots sets s after the selection
+    if (!o->basis_in) {
+      if (!o->snap_params) return invalid("snap_params needed without basis_in");
+      if (!all_finite(o->snap_params, static_cast<int64_t>(o->r) * tmp.d)) return invalid("snap_params not finite");
+      if (pd->family == SUBAP_FAMILY_KRR)
+        for (int i = 0; i < o->r; ++i)
+          if (!(o->snap_params[i] > 0.0)) return invalid("KRR length scales must be > 0");
+    } else if (!all_finite(o->basis_in, tmp.n * o->r)) {
+      return invalid("basis_in has non-finite entries");
+    }
+    if (!o->rows_in) {
+      if (o->selection != SUBAP_SELECT_CPQR && o->selection != SUBAP_SELECT_LEVERAGE &&
+          o->selection != SUBAP_SELECT_LU)
+        return invalid("selection must be SUBAP_SELECT_CPQR, SUBAP_SELECT_LEVERAGE or SUBAP_SELECT_LU");
+      if (o->selection == SUBAP_SELECT_LEVERAGE) {
+        if (!o->sample_u) return invalid("leverage-score selection needs sample_u");
+        for (int k = 0; k < o->s; ++k)
+          if (!(o->sample_u[k] >= 0.0 && o->sample_u[k] < 1.0)) return invalid("sample_u must lie in [0, 1)");
+      }
+      if (uni) {
+        if (!all_finite(o->select_params, static_cast<int64_t>(o->n_select) * tmp.d))
+          return invalid("select_params not finite");
+        if (pd->family == SUBAP_FAMILY_KRR)
+          for (int t = 0; t < o->n_select; ++t)
+            if (!(o->select_params[t] > 0.0)) return invalid("KRR select_params must be > 0");
+      } else {
+        if (!o->select_param) return invalid("select_param needed without rows_in");
+        if (!all_finite(o->select_param, tmp.d)) return invalid("select_param not finite");
+        if (pd->family == SUBAP_FAMILY_KRR && !(o->select_param[0] > 0.0))
+          return invalid("KRR select_param must be > 0");
+      }
+    } else {
+      std::unordered_set<int64_t> seen;
+      for (int k = 0; k < o->s; ++k) {
+        const int64_t v = o->rows_in[k];
+        if (v < 0 || v >= tmp.n) return invalid("rows_in index out of range");
+        if (!seen.insert(v).second) return invalid("rows_in has duplicates");
+      }
+    }
+    subap_model_s* M = new (std::nothrow) subap_model_s(tmp);
+    if (!M) return SUBAP_E_NOMEM;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    subap_status rc = offline_build(pd, o, st, M);
+    if (rc != SUBAP_OK) {
+      (void)hipStreamSynchronize(st);
+      free_model(M);
+      return rc;
+    }
+    *out = M;
+    return SUBAP_OK;
+  } catch (...) {
+    return host_exception();
   }
-  subap_model_s* M = new (std::nothrow) subap_model_s(tmp);
-  if (!M) return SUBAP_E_NOMEM;
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  subap_status rc = offline_build(pd, o, st, M);
-  if (rc != SUBAP_OK) {
-    (void)hipStreamSynchronize(st);
-    free_model(M);
-    return rc;
-  }
-  *out = M;
-  return SUBAP_OK;
 }
 
 subap_status subap_solve_batch(subap_model M, const double* params, int64_t m, double* y, double* rho,
                                int32_t* status, const subap_solve_opts* opts, void* hip_stream) {
-  clear_error();
-  if (!M) return invalid("model must not be NULL");
-  if (m < 0) return invalid("m must be >= 0");
-  if (m == 0) return SUBAP_OK;
-  if (!params || !y) return invalid("params and y must not be NULL");
-  const int prec = opts ? opts->contraction : SUBAP_FP64;
-  const int refine = opts ? opts->refine_steps : 0;
-  if (prec < SUBAP_FP64 || prec > SUBAP_FP16X3) return invalid("unknown contraction precision");
-  if (refine < 0 || refine > 4) return invalid("refine_steps must be in [0, 4]");
-  if (m > (int64_t(1) << 31) / 64) return invalid("m too large for one call");
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  if (M->family == SUBAP_FAMILY_KRR) return krr_solve(M, params, m, y, rho, status, prec, refine, st);
-  if (prec == SUBAP_BF16X3 || prec == SUBAP_FP16X3) {
-    set_error("the split 16-bit contractions are implemented for the kernel family only");
-    return SUBAP_E_UNSUPPORTED;
+  try {
+    clear_error();
+    if (!M) return invalid("model must not be NULL");
+    if (m < 0) return invalid("m must be >= 0");
+    if (m == 0) return SUBAP_OK;
+    if (!params || !y) return invalid("params and y must not be NULL");
+    const int prec = opts ? opts->contraction : SUBAP_FP64;
+    const int refine = opts ? opts->refine_steps : 0;
+    if (prec < SUBAP_FP64 || prec > SUBAP_FP16X3) return invalid("unknown contraction precision");
+    if (refine < 0 || refine > 4) return invalid("refine_steps must be in [0, 4]");
+    if (m > (int64_t(1) << 31) / 64) return invalid("m too large for one call");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (M->family == SUBAP_FAMILY_KRR) return krr_solve(M, params, m, y, rho, status, prec, refine, st);
+    if (prec == SUBAP_BF16X3 || prec == SUBAP_FP16X3) {
+      set_error("the split 16-bit contractions are implemented for the kernel family only");
+      return SUBAP_E_UNSUPPORTED;
+    }
+    return fd_solve(M, params, m, y, rho, status, prec, refine, st);
+  } catch (...) {
+    return host_exception();
   }
-  return fd_solve(M, params, m, y, rho, status, prec, refine, st);
 }
 
 subap_status subap_lift(subap_model M, const double* y, int64_t k, void* x, int64_t ldx, int32_t precision,
                         void* hip_stream) {
-  clear_error();
-  if (!M) return invalid("model must not be NULL");
-  if (k < 0) return invalid("k must be >= 0");
-  if (ldx != 0 && ldx < M->n) return invalid("ldx must be 0 or >= n");
-  if (k == 0) return SUBAP_OK;
-  if (!y || !x) return invalid("y and x must not be NULL");
-  if (precision != SUBAP_FP64 && precision != SUBAP_FP32) return invalid("lift precision must be FP64 or FP32");
-  return lift(M, y, k, x, ldx == 0 ? M->n : ldx, precision, static_cast<hipStream_t>(hip_stream));
+  try {
+    clear_error();
+    if (!M) return invalid("model must not be NULL");
+    if (k < 0) return invalid("k must be >= 0");
+    if (ldx != 0 && ldx < M->n) return invalid("ldx must be 0 or >= n");
+    if (k == 0) return SUBAP_OK;
+    if (!y || !x) return invalid("y and x must not be NULL");
+    if (precision != SUBAP_FP64 && precision != SUBAP_FP32) return invalid("lift precision must be FP64 or FP32");
+    return lift(M, y, k, x, ldx == 0 ? M->n : ldx, precision, static_cast<hipStream_t>(hip_stream));
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 subap_status subap_model_dims(subap_model M, int64_t* n, int32_t* r, int32_t* s, int32_t* d) {
-  clear_error();
-  if (!M) return invalid("model must not be NULL");
-  if (n) *n = M->n;
-  if (r) *r = M->r;
-  if (s) *s = M->s;
-  if (d) *d = M->d;
-  return SUBAP_OK;
+  try {
+    clear_error();
+    if (!M) return invalid("model must not be NULL");
+    if (n) *n = M->n;
+    if (r) *r = M->r;
+    if (s) *s = M->s;
+    if (d) *d = M->d;
+    return SUBAP_OK;
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 subap_status subap_model_rows(subap_model M, int64_t* rows_host) {
-  clear_error();
-  if (!M || !rows_host) return invalid("model and rows_host must not be NULL");
-  std::memcpy(rows_host, M->rows.data(), sizeof(int64_t) * M->rows.size());
-  return SUBAP_OK;
+  try {
+    clear_error();
+    if (!M || !rows_host) return invalid("model and rows_host must not be NULL");
+    std::memcpy(rows_host, M->rows.data(), sizeof(int64_t) * M->rows.size());
+    return SUBAP_OK;
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 subap_status subap_full_residual(subap_model M, const double* params, int64_t m, const double* x, double* res,
                                  void* hip_stream) {
-  clear_error();
-  if (!M) return invalid("model must not be NULL");
-  if (m < 0) return invalid("m must be >= 0");
-  if (m == 0) return SUBAP_OK;
-  if (!params || !x || !res) return invalid("params_dev, x_dev and res_dev must not be NULL");
-  return subap::full_residual(M, params, m, x, res, static_cast<hipStream_t>(hip_stream));
+  try {
+    clear_error();
+    if (!M) return invalid("model must not be NULL");
+    if (m < 0) return invalid("m must be >= 0");
+    if (m == 0) return SUBAP_OK;
+    if (!params || !x || !res) return invalid("params_dev, x_dev and res_dev must not be NULL");
+    return subap::full_residual(M, params, m, x, res, static_cast<hipStream_t>(hip_stream));
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 subap_status subap_apsnap_solve(subap_model M, const double* params, int64_t m, double* y, double* rho,
                                 void* hip_stream) {
-  clear_error();
-  if (!M) return invalid("model must not be NULL");
-  if (m < 0) return invalid("m must be >= 0");
-  if (m == 0) return SUBAP_OK;
-  if (!params || !y) return invalid("params_dev and y_dev must not be NULL");
-  return subap::apsnap_solve(M, params, m, y, rho, static_cast<hipStream_t>(hip_stream));
+  try {
+    clear_error();
+    if (!M) return invalid("model must not be NULL");
+    if (m < 0) return invalid("m must be >= 0");
+    if (m == 0) return SUBAP_OK;
+    if (!params || !y) return invalid("params_dev and y_dev must not be NULL");
+    return subap::apsnap_solve(M, params, m, y, rho, static_cast<hipStream_t>(hip_stream));
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 subap_status subap_polish(subap_model M, const double* params, int64_t m, double* x, int32_t max_iter, double tol,
                           double* res, void* hip_stream) {
-  clear_error();
-  if (!M) return invalid("model must not be NULL");
-  if (m < 0) return invalid("m must be >= 0");
-  if (max_iter < 0) return invalid("max_iter must be >= 0");
-  if (!(tol >= 0.0) || !std::isfinite(tol)) return invalid("tol must be finite and >= 0");
-  if (m == 0) return SUBAP_OK;
-  if (!params || !x) return invalid("params_dev and x_dev must not be NULL");
-  return subap::polish(M, params, m, x, max_iter, tol, res, static_cast<hipStream_t>(hip_stream));
+  try {
+    clear_error();
+    if (!M) return invalid("model must not be NULL");
+    if (m < 0) return invalid("m must be >= 0");
+    if (max_iter < 0) return invalid("max_iter must be >= 0");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return invalid("tol must be finite and >= 0");
+    if (m == 0) return SUBAP_OK;
+    if (!params || !x) return invalid("params_dev and x_dev must not be NULL");
+    return subap::polish(M, params, m, x, max_iter, tol, res, static_cast<hipStream_t>(hip_stream));
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 subap_status subap_output(subap_model M, const double* y, int64_t m, double* out, void* hip_stream) {
-  clear_error();
-  if (!M) return invalid("model must not be NULL");
-  if (!M->cQ) return invalid("the model was built without an output vector (c_out)");
-  if (m < 0) return invalid("m must be >= 0");
-  if (m == 0) return SUBAP_OK;
-  if (!y || !out) return invalid("y_dev and out_dev must not be NULL");
-  return subap::output_apply(M, y, m, out, static_cast<hipStream_t>(hip_stream));
+  try {
+    clear_error();
+    if (!M) return invalid("model must not be NULL");
+    if (!M->cQ) return invalid("the model was built without an output vector (c_out)");
+    if (m < 0) return invalid("m must be >= 0");
+    if (m == 0) return SUBAP_OK;
+    if (!y || !out) return invalid("y_dev and out_dev must not be NULL");
+    return subap::output_apply(M, y, m, out, static_cast<hipStream_t>(hip_stream));
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 // ---- model files ----
@@ -380,169 +437,202 @@ bool get(std::FILE* f, void* p, size_t bytes) { return bytes == 0 || std::fread(
 }  // namespace
 
 subap_status subap_model_save(subap_model M, const char* path) {
-  clear_error();
-  if (!M || !path) return invalid("model and path must not be NULL");
-  const int64_t n = M->n;
-  const int r = M->r, s = M->s;
-  std::vector<double> Q(static_cast<size_t>(n) * r), rhs(static_cast<size_t>(n)), pts, cq;
-  SUBAP_HIP_TRY(hipDeviceSynchronize());
-  SUBAP_HIP_TRY(hipMemcpy(Q.data(), M->Q, sizeof(double) * Q.size(), hipMemcpyDeviceToHost));
-  SUBAP_HIP_TRY(hipMemcpy(rhs.data(), M->rhs, sizeof(double) * n, hipMemcpyDeviceToHost));
-  if (M->family == SUBAP_FAMILY_KRR) {
-    pts.resize(static_cast<size_t>(n) * M->dimx);
-    SUBAP_HIP_TRY(hipMemcpy(pts.data(), M->points, sizeof(double) * pts.size(), hipMemcpyDeviceToHost));
+  try {
+    clear_error();
+    if (!M || !path) return invalid("model and path must not be NULL");
+    const int64_t n = M->n;
+    const int r = M->r, s = M->s;
+    std::vector<double> Q(static_cast<size_t>(n) * r), rhs(static_cast<size_t>(n)), pts, cq;
+    SUBAP_HIP_TRY(hipDeviceSynchronize());
+    SUBAP_HIP_TRY(hipMemcpy(Q.data(), M->Q, sizeof(double) * Q.size(), hipMemcpyDeviceToHost));
+    SUBAP_HIP_TRY(hipMemcpy(rhs.data(), M->rhs, sizeof(double) * n, hipMemcpyDeviceToHost));
+    if (M->family == SUBAP_FAMILY_KRR) {
+      pts.resize(static_cast<size_t>(n) * M->dimx);
+      SUBAP_HIP_TRY(hipMemcpy(pts.data(), M->points, sizeof(double) * pts.size(), hipMemcpyDeviceToHost));
+    }
+    if (M->cQ) {
+      cq.resize(r);
+      SUBAP_HIP_TRY(hipMemcpy(cq.data(), M->cQ, sizeof(double) * r, hipMemcpyDeviceToHost));
+    }
+    const int64_t hi[kHdrInts] = {M->family, M->N, M->dimx, n, r, s, M->d, M->F, M->selection,
+                                   M->cQ ? 1 : 0, static_cast<int64_t>(pts.size()), 0};
+    const double hd[kHdrDoubles] = {M->h, M->inv_h2, M->lambda, M->tau, M->kappa, M->aff_c0, M->dmax, 0.0};
+    FileCloser fc{std::fopen(path, "wb")};
+    if (!fc.f) return invalid(std::string("cannot open ") + path + " for writing");
+    const bool ok = put(fc.f, kMagic, sizeof(kMagic)) && put(fc.f, hi, sizeof(hi)) && put(fc.f, hd, sizeof(hd)) &&
+                    put(fc.f, Q.data(), sizeof(double) * Q.size()) && put(fc.f, rhs.data(), sizeof(double) * n) &&
+                    put(fc.f, M->rows.data(), sizeof(int64_t) * s) &&
+                    put(fc.f, M->weights.data(), sizeof(double) * s) &&
+                    put(fc.f, pts.data(), sizeof(double) * pts.size()) && put(fc.f, cq.data(), sizeof(double) * cq.size());
+    if (!ok || std::fflush(fc.f) != 0) return invalid(std::string("writing ") + path + " failed");
+    return SUBAP_OK;
+  } catch (...) {
+    return host_exception();
   }
-  if (M->cQ) {
-    cq.resize(r);
-    SUBAP_HIP_TRY(hipMemcpy(cq.data(), M->cQ, sizeof(double) * r, hipMemcpyDeviceToHost));
-  }
-  const int64_t hi[kHdrInts] = {M->family, M->N, M->dimx, n, r, s, M->d, M->F, M->selection,
-                                 M->cQ ? 1 : 0, static_cast<int64_t>(pts.size()), 0};
-  const double hd[kHdrDoubles] = {M->h, M->inv_h2, M->lambda, M->tau, M->kappa, M->aff_c0, M->dmax, 0.0};
-  FileCloser fc{std::fopen(path, "wb")};
-  if (!fc.f) return invalid(std::string("cannot open ") + path + " for writing");
-  const bool ok = put(fc.f, kMagic, sizeof(kMagic)) && put(fc.f, hi, sizeof(hi)) && put(fc.f, hd, sizeof(hd)) &&
-                  put(fc.f, Q.data(), sizeof(double) * Q.size()) && put(fc.f, rhs.data(), sizeof(double) * n) &&
-                  put(fc.f, M->rows.data(), sizeof(int64_t) * s) &&
-                  put(fc.f, M->weights.data(), sizeof(double) * s) &&
-                  put(fc.f, pts.data(), sizeof(double) * pts.size()) && put(fc.f, cq.data(), sizeof(double) * cq.size());
-  if (!ok || std::fflush(fc.f) != 0) return invalid(std::string("writing ") + path + " failed");
-  return SUBAP_OK;
 }
 
 subap_status subap_model_load(const char* path, void* hip_stream, subap_model* out) {
-  clear_error();
-  if (!path || !out) return invalid("path and out must not be NULL");
-  *out = nullptr;
-  FileCloser fc{std::fopen(path, "rb")};
-  if (!fc.f) return invalid(std::string("cannot open ") + path);
-  char magic[8];
-  int64_t hi[kHdrInts];
-  double hd[kHdrDoubles];
-  if (!get(fc.f, magic, sizeof(magic)) || std::memcmp(magic, kMagic, sizeof(kMagic)) != 0)
-    return invalid(std::string(path) + " is not a SubApSnap model file");
-  if (!get(fc.f, hi, sizeof(hi)) || !get(fc.f, hd, sizeof(hd))) return invalid(std::string(path) + " is truncated");
-  subap_model_s tmp;
-  tmp.family = static_cast<int>(hi[0]);
-  tmp.N = static_cast<int>(hi[1]);
-  tmp.dimx = static_cast<int>(hi[2]);
-  tmp.n = hi[3];
-  tmp.r = static_cast<int>(hi[4]);
-  tmp.s = static_cast<int>(hi[5]);
-  tmp.d = static_cast<int>(hi[6]);
-  tmp.F = static_cast<int>(hi[7]);
-  tmp.selection = static_cast<int>(hi[8]);
-  const bool has_cq = hi[9] != 0;
-  const int64_t npts = hi[10];
-  tmp.h = hd[0];
-  tmp.inv_h2 = hd[1];
-  tmp.lambda = hd[2];
-  tmp.tau = hd[3];
-  tmp.kappa = hd[4];
-  tmp.aff_c0 = hd[5];
-  tmp.dmax = hd[6];
-  // the family's geometry must agree with n (the table builders index
-  // neighbours from it); derived constants are recomputed, not trusted
-  bool geo = false;
-  if (tmp.family == SUBAP_FAMILY_DIFF2D || tmp.family == SUBAP_FAMILY_DIFF3D) {
-    const int dx = tmp.family == SUBAP_FAMILY_DIFF2D ? 2 : 3;
-    geo = tmp.N >= 2 && tmp.N <= 46340 && tmp.dimx == dx && tmp.d == (dx == 2 ? 2 : 4) && tmp.F == 2 * dx &&
-          std::pow(static_cast<double>(tmp.N), dx) == static_cast<double>(tmp.n);
-    tmp.h = 1.0 / (tmp.N + 1);
-    tmp.inv_h2 = 1.0 / (tmp.h * tmp.h);
-  } else if (tmp.family == SUBAP_FAMILY_KRR) {
-    geo = tmp.dimx >= 1 && tmp.dimx <= 16 && tmp.d == 1 && npts == tmp.n * tmp.dimx && tmp.lambda > 0.0 &&
-          std::isfinite(tmp.lambda);
-  } else if (tmp.family == SUBAP_FAMILY_DELAY) {
-    geo = tmp.n >= 2 && tmp.dimx == 1 && tmp.d == 1 && tmp.F == 2 && tmp.tau > 0.0 && std::isfinite(tmp.tau) &&
-          tmp.kappa > 2.0 && std::isfinite(tmp.kappa);
-    tmp.h = 1.0;
-    tmp.inv_h2 = 1.0;
-    tmp.aff_c0 = 3.0;
-  }
-  if (!geo || tmp.n < 1 || tmp.n > 2147483647LL || tmp.r < 1 || tmp.r > kMaxR || tmp.s < tmp.r ||
-      tmp.s > kMaxS || tmp.s > tmp.n || (tmp.family != SUBAP_FAMILY_KRR && npts != 0) ||
-      (tmp.selection != SUBAP_SELECT_CPQR && tmp.selection != SUBAP_SELECT_LEVERAGE &&
-       tmp.selection != SUBAP_SELECT_LU))
-    return invalid(std::string(path) + " has an inconsistent header");
-  std::vector<double> Q(static_cast<size_t>(tmp.n) * tmp.r), rhs(static_cast<size_t>(tmp.n)),
-      w(static_cast<size_t>(tmp.s)), pts(static_cast<size_t>(npts)), cq(has_cq ? tmp.r : 0);
-  std::vector<int64_t> rows(static_cast<size_t>(tmp.s));
-  if (!get(fc.f, Q.data(), sizeof(double) * Q.size()) || !get(fc.f, rhs.data(), sizeof(double) * rhs.size()) ||
-      !get(fc.f, rows.data(), sizeof(int64_t) * rows.size()) || !get(fc.f, w.data(), sizeof(double) * w.size()) ||
-      !get(fc.f, pts.data(), sizeof(double) * pts.size()) || !get(fc.f, cq.data(), sizeof(double) * cq.size()))
-    return invalid(std::string(path) + " is truncated");
-  for (int64_t v : rows)
-    if (v < 0 || v >= tmp.n) return invalid(std::string(path) + " has a row index out of range");
-  if (!all_finite(Q.data(), static_cast<int64_t>(Q.size())) || !all_finite(rhs.data(), tmp.n) ||
-      !all_finite(w.data(), tmp.s) || !all_finite(pts.data(), npts) || !all_finite(cq.data(), static_cast<int64_t>(cq.size())))
-    return invalid(std::string(path) + " has non-finite entries");
-  if (tmp.family == SUBAP_FAMILY_KRR) {  // bound on every squared distance, as the offline phase computes it
-    double rmax = 0.0;
-    for (int64_t i = 0; i < tmp.n; ++i) {
-      double t2 = 0.0;
-      for (int q = 0; q < tmp.dimx; ++q) t2 += pts[i * tmp.dimx + q] * pts[i * tmp.dimx + q];
-      rmax = std::max(rmax, t2);
+  try {
+    clear_error();
+    if (!path || !out) return invalid("path and out must not be NULL");
+    *out = nullptr;
+    FileCloser fc{std::fopen(path, "rb")};
+    if (!fc.f) return invalid(std::string("cannot open ") + path);
+    char magic[8];
+    int64_t hi[kHdrInts];
+    double hd[kHdrDoubles];
+    if (!get(fc.f, magic, sizeof(magic)) || std::memcmp(magic, kMagic, sizeof(kMagic)) != 0)
+      return invalid(std::string(path) + " is not a SubApSnap model file");
+    if (!get(fc.f, hi, sizeof(hi)) || !get(fc.f, hd, sizeof(hd))) return invalid(std::string(path) + " is truncated");
+    subap_model_s tmp;
+    tmp.family = static_cast<int>(hi[0]);
+    tmp.N = static_cast<int>(hi[1]);
+    tmp.dimx = static_cast<int>(hi[2]);
+    tmp.n = hi[3];
+    tmp.r = static_cast<int>(hi[4]);
+    tmp.s = static_cast<int>(hi[5]);
+    tmp.d = static_cast<int>(hi[6]);
+    tmp.F = static_cast<int>(hi[7]);
+    tmp.selection = static_cast<int>(hi[8]);
+    const bool has_cq = hi[9] != 0;
+    const int64_t npts = hi[10];
+    tmp.h = hd[0];
+    tmp.inv_h2 = hd[1];
+    tmp.lambda = hd[2];
+    tmp.tau = hd[3];
+    tmp.kappa = hd[4];
+    tmp.aff_c0 = hd[5];
+    tmp.dmax = hd[6];
+    // the family's geometry must agree with n (the table builders index
+    // neighbours from it); derived constants are recomputed, not trusted
+    bool geo = false;
+    if (tmp.family == SUBAP_FAMILY_DIFF2D || tmp.family == SUBAP_FAMILY_DIFF3D) {
+      const int dx = tmp.family == SUBAP_FAMILY_DIFF2D ? 2 : 3;
+      geo = tmp.N >= 2 && tmp.N <= 46340 && tmp.dimx == dx && tmp.d == (dx == 2 ? 2 : 4) && tmp.F == 2 * dx &&
+            std::pow(static_cast<double>(tmp.N), dx) == static_cast<double>(tmp.n);
+      tmp.h = 1.0 / (tmp.N + 1);
+      tmp.inv_h2 = 1.0 / (tmp.h * tmp.h);
+    } else if (tmp.family == SUBAP_FAMILY_KRR) {
+      geo = tmp.dimx >= 1 && tmp.dimx <= 16 && tmp.d == 1 && npts == tmp.n * tmp.dimx && tmp.lambda > 0.0 &&
+            std::isfinite(tmp.lambda);
+    } else if (tmp.family == SUBAP_FAMILY_DELAY) {
+      geo = tmp.n >= 2 && tmp.dimx == 1 && tmp.d == 1 && tmp.F == 2 && tmp.tau > 0.0 && std::isfinite(tmp.tau) &&
+            tmp.kappa > 2.0 && std::isfinite(tmp.kappa);
+      tmp.h = 1.0;
+      tmp.inv_h2 = 1.0;
+      tmp.aff_c0 = 3.0;
     }
-    tmp.dmax = 4.0 * rmax;
+    if (!geo || tmp.n < 1 || tmp.n > 2147483647LL || tmp.r < 1 || tmp.r > kMaxR || tmp.s < tmp.r ||
+        tmp.s > kMaxS || tmp.s > tmp.n || (tmp.family != SUBAP_FAMILY_KRR && npts != 0) ||
+        (tmp.selection != SUBAP_SELECT_CPQR && tmp.selection != SUBAP_SELECT_LEVERAGE &&
+         tmp.selection != SUBAP_SELECT_LU))
+      return invalid(std::string(path) + " has an inconsistent header");
+    {  // the payload the header implies must be exactly what the file holds, before anything is allocated
+      const int64_t payload = 8 * (tmp.n * tmp.r + tmp.n + 2 * int64_t(tmp.s) + npts + (has_cq ? tmp.r : 0));
+      const long here = std::ftell(fc.f);
+      if (here < 0 || std::fseek(fc.f, 0, SEEK_END) != 0) return invalid(std::string("cannot seek in ") + path);
+      const long end = std::ftell(fc.f);
+      if (end < 0 || std::fseek(fc.f, here, SEEK_SET) != 0) return invalid(std::string("cannot seek in ") + path);
+      if (static_cast<int64_t>(end - here) != payload)
+        return invalid(std::string(path) + " does not hold the payload its header describes");
+    }
+    std::vector<double> Q(static_cast<size_t>(tmp.n) * tmp.r), rhs(static_cast<size_t>(tmp.n)),
+        w(static_cast<size_t>(tmp.s)), pts(static_cast<size_t>(npts)), cq(has_cq ? tmp.r : 0);
+    std::vector<int64_t> rows(static_cast<size_t>(tmp.s));
+    if (!get(fc.f, Q.data(), sizeof(double) * Q.size()) || !get(fc.f, rhs.data(), sizeof(double) * rhs.size()) ||
+        !get(fc.f, rows.data(), sizeof(int64_t) * rows.size()) || !get(fc.f, w.data(), sizeof(double) * w.size()) ||
+        !get(fc.f, pts.data(), sizeof(double) * pts.size()) || !get(fc.f, cq.data(), sizeof(double) * cq.size()))
+      return invalid(std::string(path) + " is truncated");
+    for (int64_t v : rows)
+      if (v < 0 || v >= tmp.n) return invalid(std::string(path) + " has a row index out of range");
+    if (!all_finite(Q.data(), static_cast<int64_t>(Q.size())) || !all_finite(rhs.data(), tmp.n) ||
+        !all_finite(w.data(), tmp.s) || !all_finite(pts.data(), npts) || !all_finite(cq.data(), static_cast<int64_t>(cq.size())))
+      return invalid(std::string(path) + " has non-finite entries");
+    if (tmp.family == SUBAP_FAMILY_KRR) {  // bound on every squared distance, as the offline phase computes it
+      double rmax = 0.0;
+      for (int64_t i = 0; i < tmp.n; ++i) {
+        double t2 = 0.0;
+        for (int q = 0; q < tmp.dimx; ++q) t2 += pts[i * tmp.dimx + q] * pts[i * tmp.dimx + q];
+        rmax = std::max(rmax, t2);
+      }
+      tmp.dmax = 4.0 * rmax;
+    }
+    subap_model_s* M = new (std::nothrow) subap_model_s(tmp);
+    if (!M) return SUBAP_E_NOMEM;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    subap_status rc = subap::restore_model(M, Q.data(), rows.data(), w.data(), rhs.data(),
+                                           npts ? pts.data() : nullptr, has_cq ? cq.data() : nullptr, st);
+    if (rc != SUBAP_OK) {
+      (void)hipStreamSynchronize(st);
+      free_model(M);
+      return rc;
+    }
+    *out = M;
+    return SUBAP_OK;
+  } catch (...) {
+    return host_exception();
   }
-  subap_model_s* M = new (std::nothrow) subap_model_s(tmp);
-  if (!M) return SUBAP_E_NOMEM;
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  subap_status rc = subap::restore_model(M, Q.data(), rows.data(), w.data(), rhs.data(),
-                                         npts ? pts.data() : nullptr, has_cq ? cq.data() : nullptr, st);
-  if (rc != SUBAP_OK) {
-    (void)hipStreamSynchronize(st);
-    free_model(M);
-    return rc;
-  }
-  *out = M;
-  return SUBAP_OK;
 }
 
 subap_status subap_model_weights(subap_model M, double* weights_host) {
-  clear_error();
-  if (!M || !weights_host) return invalid("model and weights_host must not be NULL");
-  std::memcpy(weights_host, M->weights.data(), sizeof(double) * M->weights.size());
-  return SUBAP_OK;
+  try {
+    clear_error();
+    if (!M || !weights_host) return invalid("model and weights_host must not be NULL");
+    std::memcpy(weights_host, M->weights.data(), sizeof(double) * M->weights.size());
+    return SUBAP_OK;
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 subap_status subap_residual_bounds(subap_model M, const double* rho, int64_t m, double eps, double* lo, double* hi,
                                    void* hip_stream) {
-  clear_error();
-  if (!M) return invalid("model must not be NULL");
-  if (M->selection != SUBAP_SELECT_LEVERAGE) return invalid("residual bounds need leverage-score rows");
-  if (m < 0) return invalid("m must be >= 0");
-  if (!std::isfinite(eps)) return invalid("eps must be finite");
-  if (m == 0) return SUBAP_OK;
-  if (!rho || !lo || !hi) return invalid("rho_dev, lo_dev and hi_dev must not be NULL");
-  if (!(eps > 0.0)) {
-    const double k = M->r + 1.0;
-    eps = k * std::log(k) / M->s;
+  try {
+    clear_error();
+    if (!M) return invalid("model must not be NULL");
+    if (M->selection != SUBAP_SELECT_LEVERAGE) return invalid("residual bounds need leverage-score rows");
+    if (m < 0) return invalid("m must be >= 0");
+    if (!std::isfinite(eps)) return invalid("eps must be finite");
+    if (m == 0) return SUBAP_OK;
+    if (!rho || !lo || !hi) return invalid("rho_dev, lo_dev and hi_dev must not be NULL");
+    if (!(eps > 0.0)) {
+      const double k = M->r + 1.0;
+      eps = k * std::log(k) / M->s;
+    }
+    return subap::residual_bounds(rho, m, eps, lo, hi, static_cast<hipStream_t>(hip_stream));
+  } catch (...) {
+    return host_exception();
   }
-  return subap::residual_bounds(rho, m, eps, lo, hi, static_cast<hipStream_t>(hip_stream));
 }
 
 subap_status subap_model_basis(subap_model M, double* Q_host) {
-  clear_error();
-  if (!M || !Q_host) return invalid("model and Q_host must not be NULL");
-  SUBAP_HIP_TRY(hipDeviceSynchronize());
-  SUBAP_HIP_TRY(hipMemcpy(Q_host, M->Q, sizeof(double) * M->n * M->r, hipMemcpyDeviceToHost));
-  return SUBAP_OK;
+  try {
+    clear_error();
+    if (!M || !Q_host) return invalid("model and Q_host must not be NULL");
+    SUBAP_HIP_TRY(hipDeviceSynchronize());
+    SUBAP_HIP_TRY(hipMemcpy(Q_host, M->Q, sizeof(double) * M->n * M->r, hipMemcpyDeviceToHost));
+    return SUBAP_OK;
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 subap_status subap_sketched_residual(subap_model M, const double* params, int64_t m, const double* y, double* res,
                                      double* norm, void* hip_stream) {
-  clear_error();
-  if (!M) return invalid("model must not be NULL");
-  if (m < 0) return invalid("m must be >= 0");
-  if (m == 0) return SUBAP_OK;
-  if (!params || !y) return invalid("params and y must not be NULL");
-  if (!res && !norm) return invalid("at least one of res and norm must be given");
-  if (m > (int64_t(1) << 31) / 64) return invalid("m too large for one call");
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  if (M->family == SUBAP_FAMILY_KRR) return krr_residual(M, params, m, y, res, norm, st);
-  return fd_residual(M, params, m, y, res, norm, st);
+  try {
+    clear_error();
+    if (!M) return invalid("model must not be NULL");
+    if (m < 0) return invalid("m must be >= 0");
+    if (m == 0) return SUBAP_OK;
+    if (!params || !y) return invalid("params and y must not be NULL");
+    if (!res && !norm) return invalid("at least one of res and norm must be given");
+    if (m > (int64_t(1) << 31) / 64) return invalid("m too large for one call");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (M->family == SUBAP_FAMILY_KRR) return krr_residual(M, params, m, y, res, norm, st);
+    return fd_residual(M, params, m, y, res, norm, st);
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 static subap_status plan_args(const subap_model* models, int32_t k, const double* const* params, const int64_t* m,
@@ -568,77 +658,101 @@ static subap_status plan_args(const subap_model* models, int32_t k, const double
 subap_status subap_plan_create(const subap_model* models, int32_t k, const double* const* params, const int64_t* m,
                                double* const* y, double* const* rho, int32_t* const* status,
                                const subap_solve_opts* opts, int32_t flags, void* hip_stream, subap_plan* out) {
-  clear_error();
-  if (!out) return invalid("out must not be NULL");
-  *out = nullptr;
-  int prec = 0, refine = 0;
-  SUBAP_TRY(plan_args(models, k, params, m, y, opts, &prec, &refine));
-  subap_plan_s* h = new (std::nothrow) subap_plan_s{nullptr};
-  if (!h) return SUBAP_E_NOMEM;
-  subap_status rc = plan_build(models, k, params, m, y, rho, status, prec, refine, flags,
-                               static_cast<hipStream_t>(hip_stream), &h->impl);
-  if (rc != SUBAP_OK) {
-    delete h;
-    return rc;
+  try {
+    clear_error();
+    if (!out) return invalid("out must not be NULL");
+    *out = nullptr;
+    int prec = 0, refine = 0;
+    SUBAP_TRY(plan_args(models, k, params, m, y, opts, &prec, &refine));
+    subap_plan_s* h = new (std::nothrow) subap_plan_s{nullptr};
+    if (!h) return SUBAP_E_NOMEM;
+    subap_status rc = plan_build(models, k, params, m, y, rho, status, prec, refine, flags,
+                                 static_cast<hipStream_t>(hip_stream), &h->impl);
+    if (rc != SUBAP_OK) {
+      delete h;
+      return rc;
+    }
+    *out = h;
+    return SUBAP_OK;
+  } catch (...) {
+    return host_exception();
   }
-  *out = h;
-  return SUBAP_OK;
 }
 
 subap_status subap_plan_execute(subap_plan plan, void* hip_stream) {
-  clear_error();
-  if (!plan || !plan->impl) return invalid("plan must not be NULL");
-  return plan_execute(plan->impl, static_cast<hipStream_t>(hip_stream));
+  try {
+    clear_error();
+    if (!plan || !plan->impl) return invalid("plan must not be NULL");
+    return plan_execute(plan->impl, static_cast<hipStream_t>(hip_stream));
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 subap_status subap_plan_shape(subap_plan plan, int32_t* threads, int32_t* blocks) {
-  clear_error();
-  if (!plan || !plan->impl) return invalid("plan must not be NULL");
-  int t = 0, b = 0;
-  plan_shape(plan->impl, &t, &b);
-  if (threads) *threads = t;
-  if (blocks) *blocks = b;
-  return SUBAP_OK;
+  try {
+    clear_error();
+    if (!plan || !plan->impl) return invalid("plan must not be NULL");
+    int t = 0, b = 0;
+    plan_shape(plan->impl, &t, &b);
+    if (threads) *threads = t;
+    if (blocks) *blocks = b;
+    return SUBAP_OK;
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 subap_status subap_plan_free(subap_plan plan) {
-  clear_error();
-  if (!plan) return SUBAP_OK;
-  (void)hipDeviceSynchronize();
-  plan_free(plan->impl);
-  delete plan;
-  return SUBAP_OK;
+  try {
+    clear_error();
+    if (!plan) return SUBAP_OK;
+    (void)hipDeviceSynchronize();
+    plan_free(plan->impl);
+    delete plan;
+    return SUBAP_OK;
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 subap_status subap_solve_multi(const subap_model* models, int32_t k, const double* const* params, const int64_t* m,
                                double* const* y, double* const* rho, int32_t* const* status,
                                const subap_solve_opts* opts, void* hip_stream) {
-  subap_plan plan = nullptr;
-  SUBAP_TRY(subap_plan_create(models, k, params, m, y, rho, status, opts, 0, hip_stream, &plan));
-  subap_status rc = subap_plan_execute(plan, hip_stream);
-  if (rc == SUBAP_OK) rc = hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)) == hipSuccess
-                               ? SUBAP_OK : SUBAP_E_HIP;
-  subap_plan_free(plan);
-  return rc;
+  try {
+    subap_plan plan = nullptr;
+    SUBAP_TRY(subap_plan_create(models, k, params, m, y, rho, status, opts, 0, hip_stream, &plan));
+    subap_status rc = subap_plan_execute(plan, hip_stream);
+    if (rc == SUBAP_OK) rc = hipStreamSynchronize(static_cast<hipStream_t>(hip_stream)) == hipSuccess
+                                 ? SUBAP_OK : SUBAP_E_HIP;
+    subap_plan_free(plan);
+    return rc;
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 subap_status subap_surrogate_create(int32_t d, int32_t r, int32_t hidden, const double* w, subap_surrogate* out) {
-  clear_error();
-  if (!out || !w) return invalid("weights and out must not be NULL");
-  *out = nullptr;
-  if (d < 1 || d > 16 || r < 1 || r > kMaxR || hidden < 1 || hidden > 4096)
-    return invalid("need 1 <= d <= 16, 1 <= r <= 64, 1 <= hidden <= 4096");
-  const int64_t nw = int64_t(hidden) * d + hidden + int64_t(hidden) * hidden + hidden + int64_t(r) * hidden + r;
-  if (!all_finite(w, nw)) return invalid("weights have non-finite entries");
-  subap_surrogate_s* h = new (std::nothrow) subap_surrogate_s{nullptr};
-  if (!h) return SUBAP_E_NOMEM;
-  subap_status rc = surrogate_create(d, r, hidden, w, &h->impl);
-  if (rc != SUBAP_OK) {
-    delete h;
-    return rc;
+  try {
+    clear_error();
+    if (!out || !w) return invalid("weights and out must not be NULL");
+    *out = nullptr;
+    if (d < 1 || d > 16 || r < 1 || r > kMaxR || hidden < 1 || hidden > 4096)
+      return invalid("need 1 <= d <= 16, 1 <= r <= 64, 1 <= hidden <= 4096");
+    const int64_t nw = int64_t(hidden) * d + hidden + int64_t(hidden) * hidden + hidden + int64_t(r) * hidden + r;
+    if (!all_finite(w, nw)) return invalid("weights have non-finite entries");
+    subap_surrogate_s* h = new (std::nothrow) subap_surrogate_s{nullptr};
+    if (!h) return SUBAP_E_NOMEM;
+    subap_status rc = surrogate_create(d, r, hidden, w, &h->impl);
+    if (rc != SUBAP_OK) {
+      delete h;
+      return rc;
+    }
+    *out = h;
+    return SUBAP_OK;
+  } catch (...) {
+    return host_exception();
   }
-  *out = h;
-  return SUBAP_OK;
 }
 
 int64_t subap_surrogate_nparams(subap_surrogate s) {
@@ -646,86 +760,118 @@ int64_t subap_surrogate_nparams(subap_surrogate s) {
 }
 
 subap_status subap_surrogate_weights(subap_surrogate s, double* w) {
-  clear_error();
-  if (!s || !s->impl || !w) return invalid("surrogate and weights must not be NULL");
-  return surrogate_weights(s->impl, w);
+  try {
+    clear_error();
+    if (!s || !s->impl || !w) return invalid("surrogate and weights must not be NULL");
+    return surrogate_weights(s->impl, w);
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 subap_status subap_surrogate_gradient(subap_surrogate s, const double* P, const double* T, int64_t m, double* g,
                                       double* loss, void* hip_stream) {
-  clear_error();
-  if (!s || !s->impl || !P || !T || !g || !loss) return invalid("arguments must not be NULL");
-  if (m < 1 || m > 65536) return invalid("m must be in [1, 65536]");
-  return surrogate_gradient(s->impl, P, T, m, g, loss, static_cast<hipStream_t>(hip_stream));
+  try {
+    clear_error();
+    if (!s || !s->impl || !P || !T || !g || !loss) return invalid("arguments must not be NULL");
+    if (m < 1 || m > 65536) return invalid("m must be in [1, 65536]");
+    return surrogate_gradient(s->impl, P, T, m, g, loss, static_cast<hipStream_t>(hip_stream));
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 subap_status subap_surrogate_train(subap_surrogate s, const double* P, const double* Y, int64_t m,
                                    const subap_train_opts* o, double* loss, void* hip_stream) {
-  clear_error();
-  if (!s || !s->impl || !P || !Y || !o) return invalid("arguments must not be NULL");
-  if (m < 1 || m > (int64_t(1) << 31) - 1) return invalid("m must be in [1, 2^31)");
-  if (o->epochs < 1) return invalid("epochs must be >= 1");
-  const int batch = o->batch == 0 ? 4096 : o->batch;
-  if (batch < 1 || batch > 65536) return invalid("batch must be in [1, 65536]");
-  const double lr = o->lr == 0.0 ? 1e-3 : o->lr;
-  if (!(lr > 0.0) || !(o->lr_min >= 0.0) || !std::isfinite(lr)) return invalid("learning rates must be finite, lr > 0");
-  return surrogate_train(s->impl, P, Y, m, o->epochs, batch, lr, o->lr_min, o->seed, loss,
-                         static_cast<hipStream_t>(hip_stream));
+  try {
+    clear_error();
+    if (!s || !s->impl || !P || !Y || !o) return invalid("arguments must not be NULL");
+    if (m < 1 || m > (int64_t(1) << 31) - 1) return invalid("m must be in [1, 2^31)");
+    if (o->epochs < 1) return invalid("epochs must be >= 1");
+    const int batch = o->batch == 0 ? 4096 : o->batch;
+    if (batch < 1 || batch > 65536) return invalid("batch must be in [1, 65536]");
+    const double lr = o->lr == 0.0 ? 1e-3 : o->lr;
+    if (!(lr > 0.0) || !(o->lr_min >= 0.0) || !std::isfinite(lr)) return invalid("learning rates must be finite, lr > 0");
+    return surrogate_train(s->impl, P, Y, m, o->epochs, batch, lr, o->lr_min, o->seed, loss,
+                           static_cast<hipStream_t>(hip_stream));
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 subap_status subap_surrogate_predict(subap_surrogate s, const double* P, int64_t m, double* y, void* hip_stream) {
-  clear_error();
-  if (!s || !s->impl) return invalid("surrogate must not be NULL");
-  if (m < 0) return invalid("m must be >= 0");
-  if (m == 0) return SUBAP_OK;
-  if (!P || !y) return invalid("params and y must not be NULL");
-  return surrogate_predict(s->impl, P, m, y, static_cast<hipStream_t>(hip_stream));
+  try {
+    clear_error();
+    if (!s || !s->impl) return invalid("surrogate must not be NULL");
+    if (m < 0) return invalid("m must be >= 0");
+    if (m == 0) return SUBAP_OK;
+    if (!P || !y) return invalid("params and y must not be NULL");
+    return surrogate_predict(s->impl, P, m, y, static_cast<hipStream_t>(hip_stream));
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 subap_status subap_surrogate_solve_batch(subap_model M, subap_surrogate s, const double* P, int64_t m, double tol,
                                          double* y, uint8_t* accepted, int32_t* status,
                                          const subap_solve_opts* fb, int64_t* n_acc, void* hip_stream) {
-  clear_error();
-  if (!M || !s || !s->impl || !n_acc) return invalid("model, surrogate and n_accepted must not be NULL");
-  if (m < 0) return invalid("m must be >= 0");
-  *n_acc = 0;
-  if (m == 0) return SUBAP_OK;
-  if (!P || !y) return invalid("params and y must not be NULL");
-  if (!(tol >= 0.0)) return invalid("accept_tol must be >= 0");
-  int sd_ = 0, sr_ = 0;
-  surrogate_shape(s->impl, &sd_, &sr_);
-  if (M->d != sd_ || M->r != sr_) return invalid("surrogate shape does not match the model");
-  const int prec = fb ? fb->contraction : SUBAP_FP64;
-  const int refine = fb ? fb->refine_steps : 0;
-  if (prec < SUBAP_FP64 || prec > SUBAP_FP16X3 || refine < 0 || refine > 4) return invalid("bad fallback options");
-  if (M->family != SUBAP_FAMILY_KRR && (prec == SUBAP_BF16X3 || prec == SUBAP_FP16X3))
-    return invalid("split 16-bit fallback is for the kernel family only");
-  if (m > (int64_t(1) << 31) / 64) return invalid("m too large for one call");
-  return surrogate_solve(M, s->impl, P, m, tol, y, accepted, status, prec, refine, n_acc,
-                         static_cast<hipStream_t>(hip_stream));
+  try {
+    clear_error();
+    if (!M || !s || !s->impl || !n_acc) return invalid("model, surrogate and n_accepted must not be NULL");
+    if (m < 0) return invalid("m must be >= 0");
+    *n_acc = 0;
+    if (m == 0) return SUBAP_OK;
+    if (!P || !y) return invalid("params and y must not be NULL");
+    if (!(tol >= 0.0)) return invalid("accept_tol must be >= 0");
+    int sd_ = 0, sr_ = 0;
+    surrogate_shape(s->impl, &sd_, &sr_);
+    if (M->d != sd_ || M->r != sr_) return invalid("surrogate shape does not match the model");
+    const int prec = fb ? fb->contraction : SUBAP_FP64;
+    const int refine = fb ? fb->refine_steps : 0;
+    if (prec < SUBAP_FP64 || prec > SUBAP_FP16X3 || refine < 0 || refine > 4) return invalid("bad fallback options");
+    if (M->family != SUBAP_FAMILY_KRR && (prec == SUBAP_BF16X3 || prec == SUBAP_FP16X3))
+      return invalid("split 16-bit fallback is for the kernel family only");
+    if (m > (int64_t(1) << 31) / 64) return invalid("m too large for one call");
+    return surrogate_solve(M, s->impl, P, m, tol, y, accepted, status, prec, refine, n_acc,
+                           static_cast<hipStream_t>(hip_stream));
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 subap_status subap_surrogate_free(subap_surrogate s) {
-  clear_error();
-  if (!s) return SUBAP_OK;
-  (void)hipDeviceSynchronize();
-  surrogate_free(s->impl);
-  delete s;
-  return SUBAP_OK;
+  try {
+    clear_error();
+    if (!s) return SUBAP_OK;
+    (void)hipDeviceSynchronize();
+    surrogate_free(s->impl);
+    delete s;
+    return SUBAP_OK;
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 subap_status subap_profile_enable(int32_t on) {
-  std::lock_guard<std::mutex> lk(g_prof_mu);
-  g_prof_on = on != 0;
-  return SUBAP_OK;
+  try {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return SUBAP_OK;
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 subap_status subap_profile_reset(void) {
-  std::lock_guard<std::mutex> lk(g_prof_mu);
-  prof_drain();
-  g_prof_totals.clear();
-  g_prof_names.clear();
-  return SUBAP_OK;
+  try {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    prof_drain();
+    g_prof_totals.clear();
+    g_prof_names.clear();
+    return SUBAP_OK;
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 int32_t subap_profile_count(void) {
@@ -735,25 +881,33 @@ int32_t subap_profile_count(void) {
 }
 
 subap_status subap_profile_entry(int32_t i, const char** name, int64_t* calls, double* total_ms) {
-  std::lock_guard<std::mutex> lk(g_prof_mu);
-  if (i < 0 || i >= static_cast<int32_t>(g_prof_names.size())) {
-    set_error("profile entry index out of range");
-    return SUBAP_E_INVALID;
+  try {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (i < 0 || i >= static_cast<int32_t>(g_prof_names.size())) {
+      set_error("profile entry index out of range");
+      return SUBAP_E_INVALID;
+    }
+    const std::string& nm = g_prof_names[i];
+    const ProfTotal& t = g_prof_totals[nm];
+    if (name) *name = nm.c_str();
+    if (calls) *calls = t.calls;
+    if (total_ms) *total_ms = t.ms;
+    return SUBAP_OK;
+  } catch (...) {
+    return host_exception();
   }
-  const std::string& nm = g_prof_names[i];
-  const ProfTotal& t = g_prof_totals[nm];
-  if (name) *name = nm.c_str();
-  if (calls) *calls = t.calls;
-  if (total_ms) *total_ms = t.ms;
-  return SUBAP_OK;
 }
 
 subap_status subap_model_free(subap_model M) {
-  clear_error();
-  if (!M) return SUBAP_OK;
-  (void)hipDeviceSynchronize();
-  free_model(M);
-  return SUBAP_OK;
+  try {
+    clear_error();
+    if (!M) return SUBAP_OK;
+    (void)hipDeviceSynchronize();
+    free_model(M);
+    return SUBAP_OK;
+  } catch (...) {
+    return host_exception();
+  }
 }
 
 }  // extern "C"

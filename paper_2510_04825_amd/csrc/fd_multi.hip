@@ -253,7 +253,10 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
   P->blocks = cus * per_cu(128);
   const bool tune = flags & SUBAP_PLAN_AUTOTUNE;
   int t_c, b_c;
-  if (cache_lookup(P->key, &t_c, &b_c)) {
+  // a cached shape is used only if it is one this plan could have chosen
+  const bool cached = cache_lookup(P->key, &t_c, &b_c) && (t_c == 64 || t_c == 128 || t_c == 256) && b_c >= 1 &&
+                      b_c <= cus * per_cu(t_c);
+  if (cached) {
     P->threads = t_c;
     P->blocks = b_c;
   } else if (tune) {

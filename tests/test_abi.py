@@ -185,3 +185,24 @@ def test_model_load_rejects_a_grid_that_does_not_match_n(lib, tmp_path):
     h = C.c_void_p()
     assert lib.subap_model_load(os.fsencode(str(f)), None, C.byref(h)) == B.E_INVALID
     assert b"inconsistent" in lib.subap_last_error()
+
+
+def test_model_load_checks_the_payload_size_before_allocating(lib, tmp_path):
+    # a self-consistent header that describes a 3-D model of 1290^3 nodes and
+    # 64 columns (about 1.1 TB of basis) over a file of a few bytes: refused
+    # from the file size, with no host or device allocation attempted
+    N, r, s = 1290, 64, 128
+    hdr = np.array([B.FAMILY_DIFF3D, N, 3, N ** 3, r, s, 4, 6, 0, 0, 0, 0], dtype=np.int64)
+    f = tmp_path / "huge.bin"
+    f.write_bytes(b"SUBAPMD1" + hdr.tobytes() + np.zeros(8).tobytes() + np.zeros(16).tobytes())
+    h = C.c_void_p()
+    assert lib.subap_model_load(os.fsencode(str(f)), None, C.byref(h)) == B.E_INVALID
+    assert b"payload" in lib.subap_last_error()
+    assert h.value is None
+    # one byte too many is refused as well
+    n, r, s = 64, 2, 4
+    hdr = np.array([B.FAMILY_DIFF2D, 8, 2, n, r, s, 2, 4, 0, 0, 0, 0], dtype=np.int64)
+    body = np.zeros(n * r + n).tobytes() + np.arange(s, dtype=np.int64).tobytes() + np.ones(s).tobytes()
+    f.write_bytes(b"SUBAPMD1" + hdr.tobytes() + np.zeros(8).tobytes() + body + b"x")
+    assert lib.subap_model_load(os.fsencode(str(f)), None, C.byref(h)) == B.E_INVALID
+    assert b"payload" in lib.subap_last_error()
