@@ -1,23 +1,27 @@
 #!/usr/bin/env python3
 """Online-solve throughput of SubApSnap on one MI355X.
 
-Workload: kernel ridge regression A(p) = K_p + lambda I with a Gaussian
-kernel of length scale p (the paper's Section 6.3 problem class), n = 16384
-points in R^8 from a seeded 8-component Gaussian mixture, r = 32 snapshots,
-s = 128 selected rows, a batch of 4096 parameters p* log-uniform in [0.5, 2],
-lambda = 1e-2.  All inputs are synthetic and seeded (subap_inputs.krr).
+Default workload: 3-D diffusion -div(a grad u) = 1 on the unit cube, 7-point
+finite differences on a 215^3 grid (n = 9,938,375),
+a = exp(sum_k p_k phi_k) with four sin/cos product modes, r = 40 snapshots
+(GPU conjugate-gradient solves, Householder QR), s = 160 rows by rounds of
+pivoted QR, and a batch of 65,536 parameters p* uniform in [-1, 1]^4, all
+resident in HBM.  All inputs are synthetic and seeded (subap_inputs).
 
-A step is one call of subap_solve_batch on the resident batch: kernel rows
-generated on the fly and contracted with Q (split fp16 MFMA, FP32
-accumulation in four point ranges summed in FP64), FP64 Householder least
-squares, and one FP64 refinement step.
-A solve counts toward the metric when its status is OK and its sketched
-distance |S A(p) Q (y - y_fp64)| / |S b| to the FP64 plain solve is <= 1e-6
-(both residual vectors come from subap_sketched_residual, with FP64-accurate
-kernel entries).  The plain per-parameter FP64 solve (one call per p) and the
-other batched forms are timed on the same inputs.
+A step is one subap_solve_batch call on the whole batch: the face
+coefficients of the selected rows, S A(p) Q from the FP64 face-difference
+table, the FP64 Householder least squares, y, the sketched residual and the
+status of every parameter, fused in one kernel.
+A solve counts toward the metric when its status is OK and it is within
+delta_res = |A(p) Q (y - y_ref)| / |b| <= 1e-6 over all n rows of the
+reference: the FP64 form is the reference itself and is checked against the
+FP64 CPU oracle on sampled parameters of the same launch; reduced-precision
+forms are measured against the FP64 form by subap_delta_residual on the GPU.
 
-Prints one JSON line.  --gpus N with N > 1 exits: this benchmark uses one GPU.
+--workload selects the other lines (bench_configs.py): krr (kernel ridge
+regression, n = 16384, 4096 parameters), uneven, surrogate, lift, leverage,
+delay.  Prints one JSON line.  --gpus N with N > 1 exits: this benchmark uses
+one GPU.
 """
 from __future__ import annotations
 
@@ -25,22 +29,19 @@ import argparse
 import json
 import os
 import sys
-import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 TOL = 1e-6
-# headline form: (contraction precision, FP64 refinement steps); the FP16X3 split
-# leaves a contraction error near 1e-7, which one FP64 refinement takes below 1e-6
-HEADLINE = (3, 1)   # FP16X3 split MFMA contraction + one FP64 refinement
 PEAKS = {  # MI355X published dense peaks
     "bf16_mfma_tflops": 2500.0,
     "fp32_mfma_tflops": 157.3,
     "fp64_tflops": 78.6,
     "hbm_gbs": 8000.0,
 }
+WORKLOADS = ["diffusion3d", "krr", "uneven", "surrogate", "lift", "leverage", "delay"]
 
 
 def parse():
@@ -51,8 +52,10 @@ def parse():
     ap.add_argument("--plain-sample", type=int, default=256, help="parameters solved one per call")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle timing budget")
-    ap.add_argument("--workload", default="krr", choices=["krr", "diffusion3d", "uneven", "surrogate", "lift", "leverage", "delay"],
-                    help="krr (default, the headline line) or one of the other configurations "
+    ap.add_argument("--oracle-sample", type=int, default=4,
+                    help="parameters of the timed launch the FP64 CPU oracle recomputes")
+    ap.add_argument("--workload", default="diffusion3d", choices=WORKLOADS,
+                    help="diffusion3d (default, the headline line) or one of the other configurations "
                          "(lift: the FP32 lift alone on an N^3 grid, --grid N)")
     ap.add_argument("--grid", type=int, default=215, help="diffusion3d/surrogate/lift/leverage: nodes per axis")
     ap.add_argument("--delay-n", type=int, default=10 ** 7, help="delay: system size n")
@@ -62,14 +65,16 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a device-to-device copy of MIB MiB (HBM counter calibration)")
     ap.add_argument("--given-basis", action="store_true",
-                    help="krr: seeded random orthonormal basis instead of snapshot solves (profiling runs; "
-                         "the online kernels do the same work for any basis)")
+                    help="diffusion3d, krr: seeded orthonormal basis instead of snapshot solves (profiling "
+                         "runs; the online kernels do the same work for any basis)")
     ap.add_argument("--profile-only", action="store_true",
-                    help="krr: time the headline form only (no validity check, other forms or CPU baseline)")
+                    help="diffusion3d, krr: time the headline form only (no validity check, other forms or "
+                         "CPU baseline)")
     return ap.parse_args()
 
 
 def timed(fn, steps, stream):
+    """Average milliseconds of fn over steps calls, HIP events on the launch stream."""
     import torch
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
@@ -82,110 +87,6 @@ def timed(fn, steps, stream):
     return start.elapsed_time(end) / steps
 
 
-# FP64 flops of one entry 2^(c D) z of the first refinement step: the reduction
-# (two FMAs and a subtraction), the degree-7 Horner polynomial (7 FMAs), ldexp
-# and the accumulating FMA; FMAs count 2.
-REFINE_FLOPS_PER_ENTRY = 2 * 2 + 1 + 7 * 2 + 1 + 2
-
-
-# HBM traffic of the dominant kernel from two rocprofv3 counter runs (FETCH_SIZE,
-# then WRITE_SIZE, KiB per dispatch of k_refine_partial<32, 7> on this workload),
-# scaled by the factors a 1 GiB device copy gives (FETCH 2.0, WRITE 1.0).  Valid
-# only for the kernel sources they were taken with: the hash below covers them,
-# and a changed source reports traffic null.
-TRAFFIC_SOURCES = ("krr.hip", "family.h", "exp2_poly.h")
-TRAFFIC = {"kernel": "krr_refine_partial", "sources_sha256_16": "ce2e7692d68d07a3",
-           "fetch_kib": 14674.2, "write_kib": 32768.0, "fetch_factor": 2.0, "write_factor": 1.0}
-
-
-def traffic_bytes(kernel):
-    import hashlib
-    if kernel != TRAFFIC["kernel"]:
-        return None
-    h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, "paper_2510_04825_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest()[:16] != TRAFFIC["sources_sha256_16"]:
-        return None
-    return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_factor"] + TRAFFIC["write_kib"] * TRAFFIC["write_factor"])
-
-
-def roofline(prof, m, n, r, s):
-    """Roofline of the dominant kernel of the timed step (per-launch averages)."""
-    avg = {k: v[1] / max(v[0], 1) for k, v in prof.items()}
-    dname = max(prof.items(), key=lambda kv: kv[1][1])[0]
-    mfma_flops = 3 * 2.0 * m * s * n * r          # three split products per entry and column
-    contract = None
-    for k in ("krr_contract_fp16x3", "krr_contract_bf16x3"):
-        if k in avg:
-            contract = {"kernel": k, "avg_ms": avg[k], "bound": "mfma",
-                        "achieved": mfma_flops / (avg[k] * 1e-3) / 1e12, "peak": PEAKS["bf16_mfma_tflops"],
-                        "unit": "TFLOP/s"}
-            contract["frac"] = contract["achieved"] / contract["peak"]
-    if dname == "krr_refine_partial":
-        flops = m * (REFINE_FLOPS_PER_ENTRY * s * n + 2.0 * n * r)
-        roof = {"bound": "alu", "achieved": flops / (avg[dname] * 1e-3) / 1e12,
-                "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s"}
-    elif contract is not None and dname == contract["kernel"]:
-        roof = {k: contract[k] for k in ("bound", "achieved", "peak", "unit")}
-    else:
-        roof = {"bound": "alu", "achieved": None, "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"] if roof["achieved"] is not None else None
-    roof.update({"kernel": dname, "avg_ms": avg[dname], "traffic": traffic_bytes(dname)})
-    if contract is not None and contract["kernel"] != dname:
-        roof["contraction"] = contract
-    return roof
-
-
-def calibrate_copy(args, torch, dev):
-    """Known-size device copies (3 x MIB MiB read and written) for scaling HBM counters."""
-    if args.calibrate_copy <= 0:
-        return 0
-    nb = args.calibrate_copy << 20
-    a = torch.empty(nb // 4, dtype=torch.float32, device=dev).fill_(1.0)
-    b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    return nb
-
-
-def cpu_baseline(w, budget_s):
-    """The FP64 oracle's online solve, timed on this host on a bounded sample."""
-    import numpy as np
-    from threadpoolctl import threadpool_info
-
-    from oracle import families as F
-    from oracle import offline as O
-    from oracle import online as On
-
-    fam = F.from_workload(w)
-    rng = np.random.default_rng(99)
-    Q, _ = O.orthonormalise(rng.standard_normal((w["n"], w["r"])))
-    rows = np.sort(rng.choice(w["n"], size=w["s"], replace=False))
-    P = w["test_params"]
-    On.solve(fam, Q, rows, P[:2])  # warm caches
-    t0 = time.perf_counter()
-    k = 8
-    On.solve(fam, Q, rows, P[:k])
-    dt = time.perf_counter() - t0
-    per = dt / k
-    k2 = int(max(8, min(len(P), budget_s / max(per, 1e-6))))
-    t0 = time.perf_counter()
-    On.solve(fam, Q, rows, P[:k2])
-    dt = time.perf_counter() - t0
-    threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    return {
-        "value": k2 / dt, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-        "sample": (f"{k2} of the {len(P)} parameters at the full sizes (n={w['n']}, r={w['r']}, s={w['s']}): "
-                   "FP64 NumPy row generation, S A(p) Q and Householder least squares per parameter, "
-                   "with a seeded orthonormal basis and seeded rows (the online cost does not depend on "
-                   "their values)"),
-        "seconds": dt,
-    }
-
-
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -194,135 +95,16 @@ def main():
               "benchmark (the batch shards over parameters with no exchange).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
+    import bench_configs
     import subap_inputs as si
     from paper_2510_04825_amd import binding as B
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
-    if args.workload != "krr":
-        import bench_configs
-        out = getattr(bench_configs, args.workload)(args, B, si, torch, dev, stream, timed, PEAKS, TOL)
-        print(json.dumps(out), flush=True)
-        return
-    w = si.krr()
-    m, n, r, s = w["m"], w["n"], w["r"], w["s"]
-
-    t0 = time.perf_counter()
-    if args.given_basis:
-        Q0, _ = np.linalg.qr(np.random.default_rng(7).standard_normal((n, r)))
-        M = B.Model(w, basis=Q0)
-    else:
-        M = B.Model(w, snap_tol=1e-10)
-    torch.cuda.synchronize()
-    offline_s = time.perf_counter() - t0
-
-    P = torch.tensor(w["test_params"], dtype=torch.float64, device=dev)
-    y = torch.empty((m, r), dtype=torch.float64, device=dev)
-    rho = torch.empty(m, dtype=torch.float64, device=dev)
-    st = torch.empty(m, dtype=torch.int32, device=dev)
-
-    def solve(prec, refine, out=y):
-        B.subap_solve_batch(M.handle, P, out, rho, st, prec, refine, stream)
-
-    # reference FP64 plain batched solution; validity of a form = status OK and
-    # sketched distance |S A Q (y - y_fp64)| / |S b| <= TOL
-    y64 = torch.empty_like(y)
-    solve(B.FP64, 0, y64)
-    res64, nrm64 = M.sketched_residual(P, y64, vector=True)
-    bS_norm = float(torch.median(torch.linalg.norm(res64, dim=1) / nrm64))
-
-    def validity(prec, ref):
-        solve(prec, ref)
-        torch.cuda.synchronize()
-        res, _ = M.sketched_residual(P, y, vector=True)
-        dist = torch.linalg.norm(res - res64, dim=1) / bS_norm
-        ok = (st == 0) & (dist <= TOL)
-        return {"valid": int(ok.sum()), "max_sketched_distance": float(dist.max())}
-
-    if args.profile_only:
-        for _ in range(args.warmup):
-            solve(*HEADLINE)
-        B.subap_profile_reset()
-        B.subap_profile_enable(True)
-        ms = timed(lambda: solve(*HEADLINE), args.steps, stream)
-        B.subap_profile_enable(False)
-        prof = B.subap_profile_read()
-        calibrate_copy(args, torch, dev)
-        print(json.dumps({"profile_only": True, "ms_per_step": ms, "steps": args.steps,
-                          "kernels_ms_per_step": {k2: v[1] / max(args.steps, 1) for k2, v in prof.items()},
-                          "kernels_avg_ms": {k2: v[1] / max(v[0], 1) for k2, v in prof.items()}}), flush=True)
-        M.free()
-        return
-
-    head_valid = validity(*HEADLINE)
-    n_valid = head_valid["valid"]
-
-    # headline timing, per-kernel HIP-event profile over the same region
-    for _ in range(args.warmup):
-        solve(*HEADLINE)
-    B.subap_profile_reset()
-    B.subap_profile_enable(True)
-    ms = timed(lambda: solve(*HEADLINE), args.steps, stream)
-    B.subap_profile_enable(False)
-    prof = B.subap_profile_read()
-
-    # other forms on the same inputs
-    forms = {}
-    for name, prec, ref in (("fp64_batched", B.FP64, 0), ("fp32_refine1", B.FP32, 1),
-                            ("bf16x3_norefine", B.BF16X3, 0), ("bf16x3_refine1", B.BF16X3, 1),
-                            ("fp16x3_norefine", B.FP16X3, 0), ("fp16x3_refine1", B.FP16X3, 1)):
-        solve(prec, ref)
-        t = ms if (prec, ref) == HEADLINE else timed(lambda: solve(prec, ref), 3, stream)
-        forms[name] = {"ms_per_batch": t, "solves_per_s": m / (t / 1e3), **validity(prec, ref)}
-    # plain per-parameter FP64 solve: one library call per p
-    k = min(args.plain_sample, m)
-    y1 = torch.empty((1, r), dtype=torch.float64, device=dev)
-    r1 = torch.empty(1, dtype=torch.float64, device=dev)
-    s1 = torch.empty(1, dtype=torch.int32, device=dev)
-    singles = [P[i:i + 1] for i in range(k)]
-
-    def plain():
-        for pi in singles:
-            B.subap_solve_batch(M.handle, pi, y1, r1, s1, B.FP64, 0, stream)
-    plain()
-    tp = timed(plain, 1, stream)
-    forms["fp64_per_p_plain"] = {"ms_per_batch": tp * m / k, "solves_per_s": k / (tp / 1e3),
-                                 "sample": k}
-
-    # roofline of the dominant kernel of the timed step, plus the contraction's
-    roof = roofline(prof, m, n, r, s)
-    out = {
-        "metric": "online solves/s at rel. residual <=1e-6: batched/learned vs plain, 1 MI355X",
-        "value": n_valid / (ms / 1e3),
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f16x3+f64",
-        "data": "synthetic",
-        "config": {"workload": "krr_gauss_n16384_d8_r32_s128_m4096", "n": n, "r": r, "s": s, "batch": m,
-                   "form": "fp16x3 MFMA contraction + FP64 Householder LSQ + 1 FP64 refinement"},
-        "valid": {"count": n_valid, "of": m, "max_sketched_distance": head_valid["max_sketched_distance"],
-                  "tolerance": TOL},
-        "forms": forms,
-        "speedup_vs_plain": (n_valid / (ms / 1e3)) / forms["fp64_per_p_plain"]["solves_per_s"],
-        "kernels_ms_per_step": {k2: v[1] / max(args.steps, 1) for k2, v in prof.items()},
-        "roofline": roof,
-        "offline_s": offline_s,
-    }
-    if args.calibrate_copy > 0:
-        out["calibration_copy_bytes"] = calibrate_copy(args, torch, dev)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
-    M.free()
+    out = getattr(bench_configs, args.workload)(args, B, si, torch, dev, stream, timed, PEAKS, TOL)
     print(json.dumps(out), flush=True)
 
 

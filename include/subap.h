@@ -31,6 +31,23 @@
  *                         solve assembles S A(p) X = p S X - (3 + e^{tau p})
  *                         S A_1 X from the two precomputed s x r pieces
  *                         (Section 3.1, "Computing S A(p*) X").
+ *   SUBAP_FAMILY_TRIDIAG_SHIFT  the example of eq. (5.7): A(p) = A_0 - p I with
+ *                         A_0 = tridiag(-1, 2, -1) (n x n) and the
+ *                         p-dependent right-hand side b_i(p) =
+ *                         exp(b0_i sin(p / 10) p), b0 = problem->rhs; d = 1.
+ *                         Online S A(p) X = S A_0 X - p S X from the two
+ *                         precomputed pieces.  The snapshot solves (conjugate
+ *                         gradients) need A(p_i) positive definite, i.e. p_i <
+ *                         2 - 2 cos(pi / (n + 1)); other snapshot points need
+ *                         basis_in.
+ *   SUBAP_FAMILY_IDENTITY  A(p) = I with b_i(p) = 1 / (1 + 25 (t_i - p)^2) on
+ *                         t_i = i / (n - 1): SubApSnap is then DEIM (eq.
+ *                         (3.5)); d = 1, problem->rhs ignored.
+ *   For these two families the right-hand side varies with p: the sketched
+ *   residual of subap_solve_batch and subap_sketched_residual is relative to
+ *   |S b(p)| and subap_delta_residual to |b(p)|.  Leverage-score selection,
+ *   subap_apsnap_solve, subap_polish, plans and the surrogate are not
+ *   available for them (SUBAP_E_UNSUPPORTED).
  * Finite-difference layout: node (ix, iy[, iz]) sits at ((ix+1) h, ...),
  * h = 1/(N+1), index ix + N iy (+ N^2 iz); the face coefficient is a at
  * the face midpoint; row i holds sum_f a_f / h^2 on the diagonal and
@@ -79,7 +96,9 @@ typedef enum {
   SUBAP_FAMILY_DIFF2D = 1,
   SUBAP_FAMILY_DIFF3D = 2,
   SUBAP_FAMILY_KRR = 3,
-  SUBAP_FAMILY_DELAY = 4
+  SUBAP_FAMILY_DELAY = 4,
+  SUBAP_FAMILY_TRIDIAG_SHIFT = 5,
+  SUBAP_FAMILY_IDENTITY = 6
 } subap_family;
 
 /* Arithmetic of the bulk contraction S A(p) X.  The least-squares solve is
@@ -99,7 +118,8 @@ typedef struct {
   int64_t n;               /* KRR: number of points (ignored for DIFF*)       */
   int32_t dim;             /* KRR: point dimension (1..16)                    */
   const double* points;    /* KRR: host, n x dim row-major                    */
-  const double* rhs;       /* host, n entries; NULL = all ones (DIFF* only)   */
+  const double* rhs;       /* host, n entries; NULL = all ones (DIFF* only);
+                              TRIDIAG_SHIFT: b0 of b_i(p) (required)        */
   double lambda;           /* KRR ridge parameter (> 0)                       */
   double tau;              /* DELAY: delay tau (> 0)                          */
   double kappa;            /* DELAY: shift kappa (> 2)                        */
@@ -180,8 +200,19 @@ SUBAP_API subap_status subap_offline(const subap_problem_desc* problem,
 typedef struct {
   int32_t contraction;   /* subap_precision of S A(p) X                        */
   int32_t refine_steps;  /* FP64 refinement steps after the solve (0..4): the
-                            residual S(A(p) X y - b) is re-evaluated in FP64
-                            and the correction solved with the same QR        */
+                            residual r_S = S(A(p) X y - b) is re-evaluated in
+                            FP64 and a correction dy subtracted from y        */
+  int32_t refine_csne;   /* 0: simple refinement, dy = R^{-1} Q_G^T r_S with
+                            the QR of the contraction-precision S A(p) X; its
+                            fixed point is the least-squares solution of that
+                            rounded matrix, off the exact one by about
+                            (contraction error) x cond x (sketched residual)
+                            when s > r.
+                            1: corrected semi-normal equations (Bjorck):
+                            R^T R dy = G^T r_S with G^T r_S = X^T A(p)_S^T r_S
+                            evaluated in FP64 from the generated rows, whose
+                            fixed point is the exact eq. (3.3) solution.
+                            Costs a second pass over the rows per step.      */
 } subap_solve_opts;
 
 /*
@@ -361,6 +392,11 @@ SUBAP_API subap_status subap_output(subap_model model, const double* y_dev, int6
  * subap_full_residual -- res[k] = |A(p_k) x_k - b| / |b| (the measure of the
  *   paper's Tables 3-4) for full vectors x_dev (device, n x m col-major,
  *   column k = x_k, e.g. from subap_lift).
+ * subap_delta_residual -- res[k] = |A(p_k) Q (y1_k - y2_k)| / |b| over all n
+ *   rows: the distance between two coefficient vectors in the residual norm
+ *   of the paper's Tables 3-4 (|res(y1) - res(y2)| with res(y) = A Q y - b).
+ *   y1_dev, y2_dev (device, m x r row-major), res_dev (device, m).  Used to
+ *   hold a reduced-precision form to the FP64 one.
  * subap_apsnap_solve -- ApSnap (eq. (3.1)): y_k = argmin_c |A(p_k) X c - b|
  *   over all n rows, by Householder QR of the n x r matrix A(p_k) Q.
  *   y_dev (device, m x r row-major), rho_dev (device, m, or NULL): the full
@@ -376,6 +412,9 @@ SUBAP_API subap_status subap_output(subap_model model, const double* y_dev, int6
  */
 SUBAP_API subap_status subap_full_residual(subap_model model, const double* params_dev, int64_t m,
                                            const double* x_dev, double* res_dev, void* hip_stream);
+SUBAP_API subap_status subap_delta_residual(subap_model model, const double* params_dev, int64_t m,
+                                            const double* y1_dev, const double* y2_dev, double* res_dev,
+                                            void* hip_stream);
 SUBAP_API subap_status subap_apsnap_solve(subap_model model, const double* params_dev, int64_t m, double* y_dev,
                                           double* rho_dev, void* hip_stream);
 SUBAP_API subap_status subap_polish(subap_model model, const double* params_dev, int64_t m, double* x_dev,

@@ -250,6 +250,23 @@ class KernelRidge:
             out[idx] = self.rows(p, idx) @ x
         return out
 
+    def matvec_params(self, params, X, chunk=1024):
+        """Column i of the result is A(params[i]) @ X[:, i]: the same sums as
+        ``matvec`` one parameter at a time, with each block of squared
+        distances computed once for all parameters."""
+        P = np.atleast_2d(np.asarray(params, dtype=np.float64))
+        X = np.asarray(X, dtype=np.float64)
+        out = np.empty((self.n, P.shape[0]))
+        for a in range(0, self.n, chunk):
+            idx = np.arange(a, min(a + chunk, self.n))
+            D = self.sqdist_rows(idx)
+            for i, p in enumerate(P):
+                sigma = float(p[0])
+                K = np.exp(-D / (2.0 * sigma * sigma))
+                K[np.arange(len(idx)), idx] += self.lam
+                out[idx, i] = K @ X[:, i]
+        return out
+
     def rhs(self, p=None):
         return self._rhs.copy()
 

@@ -125,6 +125,18 @@ def delta_res(family, Q, p, y1, y2):
     return float(np.linalg.norm(family.matvec(p, Q @ dy)) / np.linalg.norm(b))
 
 
+def delta_res_params(family, Q, params, Y1, Y2):
+    """delta_res for every row of params (m x d) against coefficient rows of
+    Y1, Y2 (m x r).  Families with ``matvec_params`` evaluate all parameters
+    in one pass over A's rows; the others call ``delta_res`` per parameter."""
+    P = np.atleast_2d(np.asarray(params, dtype=np.float64))
+    dY = np.asarray(Y1, dtype=np.float64) - np.asarray(Y2, dtype=np.float64)
+    if not hasattr(family, "matvec_params"):
+        return np.array([delta_res(family, Q, p, a, b) for p, a, b in zip(P, Y1, Y2)])
+    V = family.matvec_params(P, Q @ dY.T)
+    return np.array([np.linalg.norm(V[:, i]) / np.linalg.norm(family.rhs(p)) for i, p in enumerate(P)])
+
+
 def sketched_residual(family, Q, rows, p, y, weights=None):
     """|S(A(p) Q y - b(p))|_2 / |S b(p)|_2, from the s selected rows only.
     With weights: |W S(A(p) Q y - b(p))|_2 / |b(p)|_2."""

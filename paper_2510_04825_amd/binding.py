@@ -22,11 +22,12 @@ LIB_PATH = os.path.join(_HERE, "libsubap.so")
 # subap_status
 OK, E_INVALID, E_NOMEM, E_HIP, E_RANK, E_NOCONV, E_NONFINITE, E_UNSUPPORTED = range(8)
 # subap_family
-FAMILY_DIFF2D, FAMILY_DIFF3D, FAMILY_KRR, FAMILY_DELAY = 1, 2, 3, 4
+FAMILY_DIFF2D, FAMILY_DIFF3D, FAMILY_KRR, FAMILY_DELAY, FAMILY_TRIDIAG_SHIFT, FAMILY_IDENTITY = 1, 2, 3, 4, 5, 6
 # subap_precision
 FP64, FP32, BF16X3, FP16X3 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3}
-FAMILIES = {"diff2d": FAMILY_DIFF2D, "diff3d": FAMILY_DIFF3D, "krr": FAMILY_KRR, "delay": FAMILY_DELAY}
+FAMILIES = {"diff2d": FAMILY_DIFF2D, "diff3d": FAMILY_DIFF3D, "krr": FAMILY_KRR, "delay": FAMILY_DELAY,
+            "tridiag": FAMILY_TRIDIAG_SHIFT, "identity": FAMILY_IDENTITY}
 
 EXPORTS = ("subap_offline", "subap_solve_batch", "subap_lift", "subap_sketched_residual", "subap_model_dims",
            "subap_model_rows", "subap_model_basis", "subap_model_free", "subap_profile_enable",
@@ -36,7 +37,8 @@ EXPORTS = ("subap_offline", "subap_solve_batch", "subap_lift", "subap_sketched_r
            "subap_surrogate_predict", "subap_surrogate_solve_batch", "subap_surrogate_free",
            "subap_surrogate_nparams", "subap_profile_count", "subap_status_string", "subap_last_error",
            "subap_model_weights", "subap_residual_bounds", "subap_output", "subap_full_residual",
-           "subap_apsnap_solve", "subap_polish", "subap_model_save", "subap_model_load")
+           "subap_apsnap_solve", "subap_polish", "subap_model_save", "subap_model_load",
+           "subap_delta_residual")
 PLAN_GRAPH, PLAN_AUTOTUNE = 1, 2
 # subap_selection
 SELECT_CPQR, SELECT_LEVERAGE, SELECT_LU = 0, 1, 2
@@ -56,7 +58,7 @@ class OfflineOpts(C.Structure):
 
 
 class SolveOpts(C.Structure):
-    _fields_ = [("contraction", C.c_int32), ("refine_steps", C.c_int32)]
+    _fields_ = [("contraction", C.c_int32), ("refine_steps", C.c_int32), ("refine_csne", C.c_int32)]
 
 
 class TrainOpts(C.Structure):
@@ -99,6 +101,7 @@ def load(path: str = LIB_PATH):
     lib.subap_model_load.argtypes = [C.c_char_p, vp, C.POINTER(vp)]
     lib.subap_output.argtypes = [vp, vp, i64, vp, vp]
     lib.subap_full_residual.argtypes = [vp, vp, i64, vp, vp, vp]
+    lib.subap_delta_residual.argtypes = [vp, vp, i64, vp, vp, vp, vp]
     lib.subap_apsnap_solve.argtypes = [vp, vp, i64, vp, vp, vp]
     lib.subap_polish.argtypes = [vp, vp, i64, vp, i32, C.c_double, vp, vp]
     lib.subap_residual_bounds.argtypes = [vp, vp, i64, C.c_double, vp, vp, vp]
@@ -191,7 +194,7 @@ def subap_offline(family, grid=0, n=0, dim=0, points=None, rhs=None, lam=0.0, r=
 
 
 def subap_solve_batch(model, params, y, rho=None, status=None, contraction=FP64, refine_steps=0,
-                      stream=None):
+                      stream=None, csne=False):
     """params: (m, d) float64 cuda tensor; y: (m, r) float64; rho: (m,) float64; status: (m,) int32."""
     lib = load()
     m = params.shape[0]
@@ -202,7 +205,7 @@ def subap_solve_batch(model, params, y, rho=None, status=None, contraction=FP64,
         _expect(rho, (m,), "float64", "rho")
     if status is not None:
         _expect(status, (m,), "int32", "status")
-    opts = SolveOpts(int(contraction), int(refine_steps))
+    opts = SolveOpts(int(contraction), int(refine_steps), int(bool(csne)))
     _check(lib.subap_solve_batch(C.c_void_p(model), _ptr(params), m, _ptr(y), _ptr(rho), _ptr(status),
                                  C.byref(opts), _stream(stream)))
 
@@ -283,11 +286,11 @@ def _multi_args(models, params, ys, rhos, statuses):
 
 
 def subap_plan_create(models, params, ys, rhos=None, statuses=None, contraction=FP64, refine_steps=0,
-                      flags=0, stream=None):
+                      flags=0, stream=None, csne=False):
     """Plan over model handles with per-model (m, d) params and (m, r) outputs; returns the handle."""
     lib = load()
     a = _multi_args(models, params, ys, rhos, statuses)
-    opts = SolveOpts(int(contraction), int(refine_steps))
+    opts = SolveOpts(int(contraction), int(refine_steps), int(bool(csne)))
     h = C.c_void_p()
     _check(lib.subap_plan_create(*a, C.byref(opts), int(flags), _stream(stream), C.byref(h)))
     return h.value
@@ -308,10 +311,10 @@ def subap_plan_free(plan):
 
 
 def subap_solve_multi(models, params, ys, rhos=None, statuses=None, contraction=FP64, refine_steps=0,
-                      stream=None):
+                      stream=None, csne=False):
     lib = load()
     a = _multi_args(models, params, ys, rhos, statuses)
-    opts = SolveOpts(int(contraction), int(refine_steps))
+    opts = SolveOpts(int(contraction), int(refine_steps), int(bool(csne)))
     _check(lib.subap_solve_multi(*a, C.byref(opts), _stream(stream)))
 
 
@@ -372,7 +375,7 @@ def subap_surrogate_predict(s, params, y, stream=None):
 
 
 def subap_surrogate_solve_batch(model, s, params, accept_tol, y, accepted=None, status=None, contraction=FP64,
-                                refine_steps=0, stream=None):
+                                refine_steps=0, stream=None, csne=False):
     """Returns the number of accepted predictions."""
     _, r, _, d = subap_model_dims(model)
     m = params.shape[0]
@@ -382,7 +385,7 @@ def subap_surrogate_solve_batch(model, s, params, accept_tol, y, accepted=None, 
         _expect(accepted, (m,), "uint8", "accepted")
     if status is not None:
         _expect(status, (m,), "int32", "status")
-    opts = SolveOpts(int(contraction), int(refine_steps))
+    opts = SolveOpts(int(contraction), int(refine_steps), int(bool(csne)))
     n = C.c_int64()
     _check(load().subap_surrogate_solve_batch(C.c_void_p(model), C.c_void_p(s), _ptr(params), m, float(accept_tol),
                                               _ptr(y), _ptr(accepted), _ptr(status), C.byref(opts), C.byref(n),
@@ -417,6 +420,18 @@ def subap_full_residual(model, params, x, res, stream=None):
     _expect(x, (m, n), "float64", "x")
     _expect(res, (m,), "float64", "res")
     _check(load().subap_full_residual(C.c_void_p(model), _ptr(params), m, _ptr(x), _ptr(res), _stream(stream)))
+
+
+def subap_delta_residual(model, params, y1, y2, res, stream=None):
+    """|A(p_k) Q (y1_k - y2_k)| / |b| over all n rows: params (m, d), y1 and y2 (m, r), res (m,)."""
+    _, r, _, d = subap_model_dims(model)
+    m = params.shape[0]
+    _expect(params, (m, d), "float64", "params")
+    _expect(y1, (m, r), "float64", "y1")
+    _expect(y2, (m, r), "float64", "y2")
+    _expect(res, (m,), "float64", "res")
+    _check(load().subap_delta_residual(C.c_void_p(model), _ptr(params), m, _ptr(y1), _ptr(y2), _ptr(res),
+                                       _stream(stream)))
 
 
 def subap_apsnap_solve(model, params, y, rho=None, stream=None):
@@ -507,6 +522,10 @@ class Model:
         if fam == FAMILY_KRR:
             self.handle = subap_offline(fam, n=w["n"], dim=w["dim"], points=w["points"], rhs=w["rhs"],
                                         lam=w["lam"], **kw)
+        elif fam == FAMILY_TRIDIAG_SHIFT:
+            self.handle = subap_offline(fam, n=w["n"], rhs=w["b0"], **kw)
+        elif fam == FAMILY_IDENTITY:
+            self.handle = subap_offline(fam, n=w["n"], **kw)
         elif fam == FAMILY_DELAY:
             self.handle = subap_offline(fam, n=w["n"], rhs=w["rhs"], tau=w["tau"], kappa=w["kappa"],
                                         c_out=w.get("c_out"), **kw)
@@ -548,14 +567,15 @@ class Model:
         subap_residual_bounds(self.handle, rho, lo, hi, eps, stream)
         return lo, hi
 
-    def solve(self, params, contraction=FP64, refine_steps=0, stream=None, with_status=True):
-        """params: (m, d) float64 cuda tensor -> (y, rho, status) cuda tensors."""
+    def solve(self, params, contraction=FP64, refine_steps=0, stream=None, with_status=True, csne=False):
+        """params: (m, d) float64 cuda tensor -> (y, rho, status) cuda tensors.
+        csne: refinement steps solve the corrected semi-normal equations."""
         import torch
         m = params.shape[0]
         y = torch.empty((m, self.r), dtype=torch.float64, device=params.device)
         rho = torch.empty(m, dtype=torch.float64, device=params.device)
         st = torch.empty(m, dtype=torch.int32, device=params.device) if with_status else None
-        subap_solve_batch(self.handle, params, y, rho, st, contraction, refine_steps, stream)
+        subap_solve_batch(self.handle, params, y, rho, st, contraction, refine_steps, stream, csne)
         return y, rho, st
 
     def sketched_residual(self, params, y, vector=False, stream=None):

@@ -117,7 +117,7 @@ void free_model(subap_model_s* M) {
   if (!M) return;
   void* bufs[] = {M->Q, M->rows_d, M->wS, M->cQ, M->bS, M->QS, M->rhs, M->phi, M->delta64, M->delta32, M->delta64T, M->delta32T, M->points,
                   M->Dt64, M->D32, M->Qrm, M->Q32, M->Qhi, M->Qlo, M->Qh16, M->Ql16, M->colscale_inv,
-                  M->work};
+                  M->rowdat, M->work};
   for (void* b : bufs) dfree(b);
   delete M;
 }
@@ -222,6 +222,16 @@ subap_status subap_offline(const subap_problem_desc* pd, const subap_offline_opt
       tmp.tau = pd->tau;
       tmp.kappa = pd->kappa;
       tmp.aff_c0 = 3.0;  // A_0 = 3 A_1
+    } else if (pd->family == SUBAP_FAMILY_TRIDIAG_SHIFT || pd->family == SUBAP_FAMILY_IDENTITY) {
+      if (pd->n < 2 || pd->n > 2147483647LL) return invalid("n must be in [2, 2^31 - 1]");
+      if (pd->family == SUBAP_FAMILY_TRIDIAG_SHIFT && (!pd->rhs || !all_finite(pd->rhs, pd->n)))
+        return invalid("the shifted tridiagonal family needs finite b0 in rhs");
+      tmp.n = pd->n;
+      tmp.dimx = 1;
+      tmp.d = 1;
+      tmp.F = pd->family == SUBAP_FAMILY_TRIDIAG_SHIFT ? 2 : 1;
+      tmp.h = 1.0;
+      tmp.inv_h2 = 1.0;
     } else {
       return invalid("unknown family");
     }
@@ -253,6 +263,10 @@ subap_status subap_offline(const subap_problem_desc* pd, const subap_offline_opt
           o->selection != SUBAP_SELECT_LU)
         return invalid("selection must be SUBAP_SELECT_CPQR, SUBAP_SELECT_LEVERAGE or SUBAP_SELECT_LU");
       if (o->selection == SUBAP_SELECT_LEVERAGE) {
+        if (rhs_varies(pd->family)) {
+          set_error("leverage-score selection needs a right-hand side independent of p");
+          return SUBAP_E_UNSUPPORTED;
+        }
         if (!o->sample_u) return invalid("leverage-score selection needs sample_u");
         for (int k = 0; k < o->s; ++k)
           if (!(o->sample_u[k] >= 0.0 && o->sample_u[k] < 1.0)) return invalid("sample_u must lie in [0, 1)");
@@ -303,16 +317,18 @@ subap_status subap_solve_batch(subap_model M, const double* params, int64_t m, d
     if (!params || !y) return invalid("params and y must not be NULL");
     const int prec = opts ? opts->contraction : SUBAP_FP64;
     const int refine = opts ? opts->refine_steps : 0;
+    const int csne = opts ? opts->refine_csne : 0;
     if (prec < SUBAP_FP64 || prec > SUBAP_FP16X3) return invalid("unknown contraction precision");
     if (refine < 0 || refine > 4) return invalid("refine_steps must be in [0, 4]");
+    if (csne != 0 && csne != 1) return invalid("refine_csne must be 0 or 1");
     if (m > (int64_t(1) << 31) / 64) return invalid("m too large for one call");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    if (M->family == SUBAP_FAMILY_KRR) return krr_solve(M, params, m, y, rho, status, prec, refine, st);
+    if (M->family == SUBAP_FAMILY_KRR) return krr_solve(M, params, m, y, rho, status, prec, refine, csne, st);
     if (prec == SUBAP_BF16X3 || prec == SUBAP_FP16X3) {
       set_error("the split 16-bit contractions are implemented for the kernel family only");
       return SUBAP_E_UNSUPPORTED;
     }
-    return fd_solve(M, params, m, y, rho, status, prec, refine, st);
+    return fd_solve(M, params, m, y, rho, status, prec, refine, csne, st);
   } catch (...) {
     return host_exception();
   }
@@ -373,6 +389,20 @@ subap_status subap_full_residual(subap_model M, const double* params, int64_t m,
   }
 }
 
+subap_status subap_delta_residual(subap_model M, const double* params, int64_t m, const double* y1,
+                                  const double* y2, double* res, void* hip_stream) {
+  try {
+    clear_error();
+    if (!M) return invalid("model must not be NULL");
+    if (m < 0) return invalid("m must be >= 0");
+    if (m == 0) return SUBAP_OK;
+    if (!params || !y1 || !y2 || !res) return invalid("params_dev, y1_dev, y2_dev and res_dev must not be NULL");
+    return subap::delta_residual(M, params, m, y1, y2, res, static_cast<hipStream_t>(hip_stream));
+  } catch (...) {
+    return host_exception();
+  }
+}
+
 subap_status subap_apsnap_solve(subap_model M, const double* params, int64_t m, double* y, double* rho,
                                 void* hip_stream) {
   try {
@@ -381,6 +411,10 @@ subap_status subap_apsnap_solve(subap_model M, const double* params, int64_t m, 
     if (m < 0) return invalid("m must be >= 0");
     if (m == 0) return SUBAP_OK;
     if (!params || !y) return invalid("params_dev and y_dev must not be NULL");
+    if (rhs_varies(M->family)) {
+      set_error("ApSnap is implemented for right-hand sides independent of p");
+      return SUBAP_E_UNSUPPORTED;
+    }
     return subap::apsnap_solve(M, params, m, y, rho, static_cast<hipStream_t>(hip_stream));
   } catch (...) {
     return host_exception();
@@ -397,6 +431,10 @@ subap_status subap_polish(subap_model M, const double* params, int64_t m, double
     if (!(tol >= 0.0) || !std::isfinite(tol)) return invalid("tol must be finite and >= 0");
     if (m == 0) return SUBAP_OK;
     if (!params || !x) return invalid("params_dev and x_dev must not be NULL");
+    if (rhs_varies(M->family)) {
+      set_error("polishing is implemented for right-hand sides independent of p");
+      return SUBAP_E_UNSUPPORTED;
+    }
     return subap::polish(M, params, m, x, max_iter, tol, res, static_cast<hipStream_t>(hip_stream));
   } catch (...) {
     return host_exception();
@@ -521,6 +559,11 @@ subap_status subap_model_load(const char* path, void* hip_stream, subap_model* o
       tmp.h = 1.0;
       tmp.inv_h2 = 1.0;
       tmp.aff_c0 = 3.0;
+    } else if (tmp.family == SUBAP_FAMILY_TRIDIAG_SHIFT || tmp.family == SUBAP_FAMILY_IDENTITY) {
+      geo = tmp.n >= 2 && tmp.dimx == 1 && tmp.d == 1 &&
+            tmp.F == (tmp.family == SUBAP_FAMILY_TRIDIAG_SHIFT ? 2 : 1) && tmp.selection != SUBAP_SELECT_LEVERAGE;
+      tmp.h = 1.0;
+      tmp.inv_h2 = 1.0;
     }
     if (!geo || tmp.n < 1 || tmp.n > 2147483647LL || tmp.r < 1 || tmp.r > kMaxR || tmp.s < tmp.r ||
         tmp.s > kMaxS || tmp.s > tmp.n || (tmp.family != SUBAP_FAMILY_KRR && npts != 0) ||
@@ -636,12 +679,16 @@ subap_status subap_sketched_residual(subap_model M, const double* params, int64_
 }
 
 static subap_status plan_args(const subap_model* models, int32_t k, const double* const* params, const int64_t* m,
-                              double* const* y, const subap_solve_opts* opts, int* prec, int* refine) {
+                              double* const* y, const subap_solve_opts* opts, int* prec, int* refine,
+                              bool* csne) {
   if (!models || !params || !m || !y || k < 1) return invalid("models, params, m and y must be given and k >= 1");
   *prec = opts ? opts->contraction : SUBAP_FP64;
   *refine = opts ? opts->refine_steps : 0;
+  const int cs = opts ? opts->refine_csne : 0;
   if (*prec != SUBAP_FP64 && *prec != SUBAP_FP32) return invalid("batched plans take FP64 or FP32 contractions");
   if (*refine < 0 || *refine > 4) return invalid("refine_steps must be in [0, 4]");
+  if (cs != 0 && cs != 1) return invalid("refine_csne must be 0 or 1");
+  *csne = cs != 0;
   int64_t total = 0;
   for (int i = 0; i < k; ++i) {
     if (!models[i]) return invalid("model must not be NULL");
@@ -663,10 +710,11 @@ subap_status subap_plan_create(const subap_model* models, int32_t k, const doubl
     if (!out) return invalid("out must not be NULL");
     *out = nullptr;
     int prec = 0, refine = 0;
-    SUBAP_TRY(plan_args(models, k, params, m, y, opts, &prec, &refine));
+    bool csne = false;
+    SUBAP_TRY(plan_args(models, k, params, m, y, opts, &prec, &refine, &csne));
     subap_plan_s* h = new (std::nothrow) subap_plan_s{nullptr};
     if (!h) return SUBAP_E_NOMEM;
-    subap_status rc = plan_build(models, k, params, m, y, rho, status, prec, refine, flags,
+    subap_status rc = plan_build(models, k, params, m, y, rho, status, prec, refine, csne, flags,
                                  static_cast<hipStream_t>(hip_stream), &h->impl);
     if (rc != SUBAP_OK) {
       delete h;
@@ -828,11 +876,17 @@ subap_status subap_surrogate_solve_batch(subap_model M, subap_surrogate s, const
     if (M->d != sd_ || M->r != sr_) return invalid("surrogate shape does not match the model");
     const int prec = fb ? fb->contraction : SUBAP_FP64;
     const int refine = fb ? fb->refine_steps : 0;
-    if (prec < SUBAP_FP64 || prec > SUBAP_FP16X3 || refine < 0 || refine > 4) return invalid("bad fallback options");
+    const int csne = fb ? fb->refine_csne : 0;
+    if (prec < SUBAP_FP64 || prec > SUBAP_FP16X3 || refine < 0 || refine > 4 || (csne != 0 && csne != 1))
+      return invalid("bad fallback options");
     if (M->family != SUBAP_FAMILY_KRR && (prec == SUBAP_BF16X3 || prec == SUBAP_FP16X3))
       return invalid("split 16-bit fallback is for the kernel family only");
+    if (rhs_varies(M->family)) {
+      set_error("the surrogate's acceptance test is implemented for right-hand sides independent of p");
+      return SUBAP_E_UNSUPPORTED;
+    }
     if (m > (int64_t(1) << 31) / 64) return invalid("m too large for one call");
-    return surrogate_solve(M, s->impl, P, m, tol, y, accepted, status, prec, refine, n_acc,
+    return surrogate_solve(M, s->impl, P, m, tol, y, accepted, status, prec, refine, csne != 0, n_acc,
                            static_cast<hipStream_t>(hip_stream));
   } catch (...) {
     return host_exception();

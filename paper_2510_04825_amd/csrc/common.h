@@ -71,6 +71,8 @@ struct subap_model_s {
   double* QS = nullptr;               // s x r row-major: w_k Q[rows[k], c]
   double* rhs = nullptr;              // n (device copy of b)
   double* cQ = nullptr;               // r: c^T Q (models built with an output vector)
+  double* rowdat = nullptr;           // s: per-row data of a p-dependent b (eq. (5.7): b0[i_k];
+                                      //    identity family: t at i_k)
 
   // finite-difference tables, layouts [(f * r + c) * s + k] and [(f * d + q) * s + k]
   double* phi = nullptr;              // s x F x d  mode values at face midpoints
@@ -98,6 +100,11 @@ struct subap_model_s {
 
 namespace subap {
 
+// families whose right-hand side b depends on p
+inline bool rhs_varies(int family) {
+  return family == SUBAP_FAMILY_TRIDIAG_SHIFT || family == SUBAP_FAMILY_IDENTITY;
+}
+
 // ---- offline (offline.hip) ----
 subap_status offline_build(const subap_problem_desc* pd, const subap_offline_opts* o,
                            hipStream_t st, subap_model_s* M);
@@ -108,16 +115,27 @@ subap_status restore_model(subap_model_s* M, const double* Q, const int64_t* row
                            const double* rhs, const double* points, const double* cQ, hipStream_t st);
 subap_status full_residual(subap_model_s* M, const double* params, int64_t m, const double* x, double* res,
                            hipStream_t st);
+subap_status delta_residual(subap_model_s* M, const double* params, int64_t m, const double* y1, const double* y2,
+                            double* res, hipStream_t st);
 subap_status apsnap_solve(subap_model_s* M, const double* params, int64_t m, double* y, double* rho,
                           hipStream_t st);
 subap_status polish(subap_model_s* M, const double* params, int64_t m, double* x, int max_iter, double tol,
                     double* res, hipStream_t st);
 
 // ---- online ----
+// refine: FP64 refinement steps; csne: each step solves the corrected
+// semi-normal equations R^T R dy = G^T r_S with an FP64 G^T r_S instead of
+// applying the stored factorisation of the rounded G.
 subap_status fd_solve(subap_model_s* M, const double* params, int64_t m, double* y,
-                      double* rho, int32_t* status, int prec, int refine, hipStream_t st);
+                      double* rho, int32_t* status, int prec, int refine, bool csne, hipStream_t st);
 subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double* y,
-                       double* rho, int32_t* status, int prec, int refine, hipStream_t st);
+                       double* rho, int32_t* status, int prec, int refine, bool csne, hipStream_t st);
+// krr_solve with a caller-given device workspace of at least the bytes the
+// call needs (no allocation); krr_chunk: the largest batch, a multiple of
+// the refinement's parameter block, whose workspace fits in `bytes`.
+subap_status krr_solve_ws(subap_model_s* M, const double* params, int64_t m, double* y, double* rho,
+                          int32_t* status, int prec, int refine, bool csne, void* work, hipStream_t st);
+int64_t krr_chunk(const subap_model_s* M, int prec, int refine, bool csne, size_t bytes);
 subap_status lift(subap_model_s* M, const double* y, int64_t k, void* x, int64_t ldx, int prec,
                   hipStream_t st);
 subap_status fd_residual(subap_model_s* M, const double* params, int64_t m, const double* y, double* res,
@@ -131,7 +149,7 @@ subap_status ensure_work(subap_model_s* M, size_t bytes);
 struct PlanImpl;
 subap_status plan_build(subap_model_s* const* models, int k, const double* const* params, const int64_t* m,
                         double* const* y, double* const* rho, int32_t* const* status, int prec, int refine,
-                        int flags, hipStream_t st, PlanImpl** out);
+                        bool csne, int flags, hipStream_t st, PlanImpl** out);
 subap_status plan_execute(PlanImpl* P, hipStream_t st);
 void plan_free(PlanImpl* P);
 void plan_shape(const PlanImpl* P, int* threads, int* blocks);
@@ -148,8 +166,8 @@ subap_status surrogate_train(Surrogate* S, const double* P, const double* Y, int
                              double lr, double lr_min, uint64_t seed, double* loss_out, hipStream_t st);
 subap_status surrogate_predict(Surrogate* S, const double* P, int64_t m, double* y, hipStream_t st);
 subap_status surrogate_solve(subap_model_s* M, Surrogate* S, const double* P, int64_t m, double tol, double* y,
-                             uint8_t* accepted, int32_t* status, int prec, int refine, int64_t* n_acc,
-                             hipStream_t st);
+                             uint8_t* accepted, int32_t* status, int prec, int refine, bool csne,
+                             int64_t* n_acc, hipStream_t st);
 
 }  // namespace subap
 

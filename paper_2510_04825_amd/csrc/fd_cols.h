@@ -21,9 +21,12 @@
 // the sketched residual.
 //
 // Refinement (FP64) does not need the reflectors: with r_S = S(A(p) Q y - b)
-// from the FP64 difference table, the correction solves R^T R dy = G^T r_S
-// with the G that was factorised (recomputed in the same arithmetic), which
-// equals R^{-1} Q^T r_S.
+// from the FP64 difference table, the correction solves R^T R dy = G^T r_S.
+// Simple refinement takes G^T r_S with the G that was factorised (recomputed
+// in the same arithmetic), which equals R^{-1} Q^T r_S; its fixed point is the
+// least-squares solution of that rounded G.  The corrected semi-normal
+// equations (csne) take G^T r_S with G from the FP64 table, whose fixed point
+// is the exact solution of eq. (3.3).
 //
 // The caller gives each wavefront cols_lds_doubles(rmax, smax, REF) doubles of LDS.
 #pragma once
@@ -44,6 +47,8 @@ struct ColsModel {
   const double* bS;
   double inv_h2, bS_norm;
   double aff_c0 = 0.0, aff_tau = 0.0;  // delay family: A(p) = p I - (c0 + e^{tau p}) A_1
+  const double* wS = nullptr;          // row weights (right-hand sides that vary with p)
+  const double* rowdat = nullptr;      // per-row data of those right-hand sides
 };
 
 // Coefficients of the term form G_k = sum_f a_f(p, k) Delta_{k,f} that every
@@ -52,13 +57,41 @@ struct ColsModel {
 //                   face coefficients of the diffusion stencil;
 //   kCoefDelay      F = 2, DP = 1: a_0 = p, a_1 = -(c0 + e^{tau p}), the
 //                   affine weights of S Q and S A_1 Q (Section 3.1, computing
-//                   S A(p*) X from precomputed pieces; Section 6.2.2).
-constexpr int kCoefDiffusion = 0, kCoefDelay = 1;
+//                   S A(p*) X from precomputed pieces; Section 6.2.2);
+//   kCoefTridiag    F = 2, DP = 1: a_0 = -p, a_1 = 1, the pieces S Q and
+//                   S A_0 Q of A(p) = A_0 - p I (eq. (5.7));
+//   kCoefIdentity   F = 1, DP = 1: a_0 = 1, A(p) = I (DEIM, eq. (3.5)).
+// The last two have right-hand sides that depend on p (cols_rhs).
+constexpr int kCoefDiffusion = 0, kCoefDelay = 1, kCoefTridiag = 2, kCoefIdentity = 3;
+
+template <int COEF>
+constexpr bool coef_rhs_varies() {
+  return COEF == kCoefTridiag || COEF == kCoefIdentity;
+}
+
+// entry k of W S b(p): the stored table for a fixed b; for eq. (5.7)
+// b_i(p) = exp(b0_i sin(p / 10) p) with rowdat[k] = b0 at row i_k; for the
+// identity family b_i(p) = 1 / (1 + 25 (t_i - p)^2) with rowdat[k] = t at i_k
+template <int COEF>
+__device__ __forceinline__ double cols_rhs(const ColsModel& M, const double* pv, int k) {
+  if constexpr (COEF == kCoefTridiag) {
+    return M.wS[k] * exp(M.rowdat[k] * sin(pv[0] / 10.0) * pv[0]);
+  } else if constexpr (COEF == kCoefIdentity) {
+    const double t = M.rowdat[k] - pv[0];
+    return M.wS[k] / (1.0 + 25.0 * (t * t));
+  } else {
+    return M.bS[k];
+  }
+}
 
 template <int F, int DP, int COEF>
 __device__ __forceinline__ double cols_coef(const ColsModel& M, const double* pv, int f, int k) {
   if constexpr (COEF == kCoefDelay) {
     return f == 0 ? pv[0] : -(M.aff_c0 + exp(M.aff_tau * pv[0]));
+  } else if constexpr (COEF == kCoefTridiag) {
+    return f == 0 ? -pv[0] : 1.0;
+  } else if constexpr (COEF == kCoefIdentity) {
+    return 1.0;
   } else {
     double t = 0.0;
 #pragma unroll
@@ -142,7 +175,7 @@ __device__ __forceinline__ double cols_residual_row(const ColsModel& M, const do
     if (c < r) u0 = fma(d[c], y[c], u0);
     t = fma(cols_coef<F, DP, COEF>(M, pv, f, k), u0 + u1, t);
   }
-  return t - M.bS[k];
+  return t - cols_rhs<COEF>(M, pv, k);
 }
 
 // y <- R^{-1} v in place (v in LDS, every lane computes the same values)
@@ -172,11 +205,11 @@ __device__ __forceinline__ void cols_forward_solve(const double* R, int r1, int 
 
 // One parameter.  BRED: r == 64 (S b carried by every lane).  REF: an FP32
 // contraction or refinement steps (FP64 residuals); without it prec must be
-// FP64 and refine 0.  Writes y (r values), rho and status when the pointers
-// are not NULL.
+// FP64 and refine 0.  csne: refinement steps use the FP64 G^T r_S.  Writes y
+// (r values), rho and status when the pointers are not NULL.
 template <int F, int DP, bool BRED, bool REF, int COEF = kCoefDiffusion, int RB = kColsRB>
-__device__ void cols_solve(const ColsModel& M, const double* params, int prec, int refine, double* lds, int smax,
-                           int lane, double* y_out, double* rho_out, int32_t* status_out) {
+__device__ void cols_solve(const ColsModel& M, const double* params, int prec, int refine, bool csne, double* lds,
+                           int smax, int lane, double* y_out, double* rho_out, int32_t* status_out) {
   static_assert(RB % 4 == 0, "the dot products run four rows at a time");
   static_assert(!REF || 64 % RB == 0, "the refinement's 64-row residual slices hold whole blocks");
   const int r = M.r, s = M.s, r1 = r + 1;
@@ -197,6 +230,7 @@ __device__ void cols_solve(const ColsModel& M, const double* params, int prec, i
   for (int idx = lane; idx < r1 * (r1 + 1) / 2; idx += 64) R[idx] = 0.0;
   wave_sync_lds();
   double rho2 = 0.0, r00 = 0.0;
+  double bn2 = 0.0;  // |W S b(p)|^2 (the same in every lane)
   bool full_rank = true;
   for (int k0 = 0; k0 < s; k0 += RB) {
     cols_faces<F, DP, COEF, RB>(M, pv, k0, a, lane);
@@ -205,7 +239,8 @@ __device__ void cols_solve(const ColsModel& M, const double* params, int prec, i
     double Bb[BRED ? RB : 1];
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
-      const double bk = (k0 + i < s) ? M.bS[k0 + i] : 0.0;
+      const double bk = (k0 + i < s) ? cols_rhs<COEF>(M, pv, k0 + i) : 0.0;
+      if constexpr (coef_rhs_varies<COEF>()) bn2 = fma(bk, bk, bn2);
       if constexpr (BRED) Bb[i] = bk;
       else if (lane == r) B[i] = bk;
     }
@@ -300,7 +335,9 @@ __device__ void cols_solve(const ColsModel& M, const double* params, int prec, i
   for (int j = lane; j < r; j += 64) yv[j] = R[cols_row(j, r1) + (r - j)];
   wave_sync_lds();
   cols_back_solve(R, r1, r, yv);
-  // FP64 refinement: R^T R dy = G^T r_S with the factorised G
+  // FP64 refinement: R^T R dy = G^T r_S with the factorised G, or with the
+  // FP64 G (corrected semi-normal equations)
+  const int gprec = csne ? SUBAP_FP64 : prec;
   for (int it = 0; it < (REF ? refine : 0); ++it) {
     double g = 0.0;
     for (int k0 = 0; k0 < s; k0 += RB) {
@@ -311,7 +348,7 @@ __device__ void cols_solve(const ColsModel& M, const double* params, int prec, i
       }
       cols_faces<F, DP, COEF, RB>(M, pv, k0, a, lane);
       double B[RB];
-      cols_block<F, RB>(M, prec, k0, a, lane, B);
+      cols_block<F, RB>(M, gprec, k0, a, lane, B);
 #pragma unroll
       for (int i = 0; i < RB; ++i) {
         const double rk = res[k0 % 64 + i];  // 0 beyond s
@@ -347,10 +384,11 @@ __device__ void cols_solve(const ColsModel& M, const double* params, int prec, i
   else if (!yfin) code = SUBAP_E_NONFINITE;
   if (lane < r) y_out[lane] = (code == SUBAP_OK) ? yc : __longlong_as_double(0x7ff8000000000000LL);
   if (lane == 0) {
-    if (rho_out) *rho_out = rho / M.bS_norm;
+    if (rho_out) *rho_out = rho / (coef_rhs_varies<COEF>() ? sqrt(bn2) : M.bS_norm);
     if (status_out) *status_out = code;
   }
   wave_sync_lds();  // the region is reused by the next item
 }
+
 
 }  // namespace subap

@@ -56,19 +56,20 @@ struct MultiArgs {
   int prec;
   int refine;
   int ldsw;  // LDS doubles per wavefront
+  bool csne;  // refinement by the corrected semi-normal equations
 };
 
 __global__ void k_reset(unsigned long long* c) { *c = 0ull; }
 
 template <int F, int DP, bool REF>
-__device__ __forceinline__ void multi_item(const MultiInst& I, int64_t p, int prec, int refine, double* lds,
-                                           int lane) {
+__device__ __forceinline__ void multi_item(const MultiInst& I, int64_t p, int prec, int refine, bool csne,
+                                           double* lds, int lane) {
   const ColsModel M{I.r, I.s, I.phi, I.delta64T, I.delta32T, I.bS, I.inv_h2, I.bS_norm};
   double* yo = I.y + p * I.r;
   double* ro = I.rho ? I.rho + p : nullptr;
   int32_t* so = I.status ? I.status + p : nullptr;
-  if (I.r == 64) cols_solve<F, DP, true, REF>(M, I.params + p * DP, prec, refine, lds, I.s, lane, yo, ro, so);
-  else cols_solve<F, DP, false, REF>(M, I.params + p * DP, prec, refine, lds, I.s, lane, yo, ro, so);
+  if (I.r == 64) cols_solve<F, DP, true, REF>(M, I.params + p * DP, prec, refine, csne, lds, I.s, lane, yo, ro, so);
+  else cols_solve<F, DP, false, REF>(M, I.params + p * DP, prec, refine, csne, lds, I.s, lane, yo, ro, so);
 }
 
 // REF: FP32 contraction or refinement steps (uniform over the launch).
@@ -94,10 +95,10 @@ __global__ __launch_bounds__(kMT, 2) void k_fd_multi(MultiArgs A) {
     }
     const MultiInst I = A.inst[lo];
     const int64_t p = static_cast<int64_t>(it) - I.begin;
-    if constexpr (DIMS == 1) multi_item<4, 2, REF>(I, p, A.prec, A.refine, mine, lane);
-    else if constexpr (DIMS == 2) multi_item<6, 4, REF>(I, p, A.prec, A.refine, mine, lane);
-    else if (I.F == 4) multi_item<4, 2, REF>(I, p, A.prec, A.refine, mine, lane);
-    else multi_item<6, 4, REF>(I, p, A.prec, A.refine, mine, lane);
+    if constexpr (DIMS == 1) multi_item<4, 2, REF>(I, p, A.prec, A.refine, A.csne, mine, lane);
+    else if constexpr (DIMS == 2) multi_item<6, 4, REF>(I, p, A.prec, A.refine, A.csne, mine, lane);
+    else if (I.F == 4) multi_item<4, 2, REF>(I, p, A.prec, A.refine, A.csne, mine, lane);
+    else multi_item<6, 4, REF>(I, p, A.prec, A.refine, A.csne, mine, lane);
   }
 }
 
@@ -113,6 +114,7 @@ struct PlanImpl {
   int64_t total = 0;
   int max_s = 0, max_r = 0;
   int prec = 0, refine = 0;
+  bool csne = false;
   int dims = 0;  // bit 0: some model is 2-D, bit 1: some model is 3-D
   int threads = 256, blocks = 0;
   hipGraph_t graph = nullptr;
@@ -142,7 +144,7 @@ MultiKernel plan_kernel(bool ref, int dims) {
 // counter reset + the persistent kernel, on st (also used under capture)
 void enqueue_plan(const PlanImpl* P, hipStream_t st) {
   MultiArgs a{P->inst_d, static_cast<int>(P->inst.size()), P->total, P->counter, P->prec, P->refine,
-              cols_lds_doubles(P->max_r, P->max_s, plan_ref(P))};
+              cols_lds_doubles(P->max_r, P->max_s, plan_ref(P)), P->csne};
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, st, P->counter);
   hipLaunchKernelGGL(plan_kernel(plan_ref(P), P->dims), dim3(P->blocks), dim3(P->threads),
                      plan_lds(P, P->threads), st, a);
@@ -190,7 +192,7 @@ void cache_store(const std::string& key, int threads, int blocks) {
 
 subap_status plan_build(subap_model_s* const* models, int k, const double* const* params, const int64_t* m,
                         double* const* y, double* const* rho, int32_t* const* status, int prec, int refine,
-                        int flags, hipStream_t st, PlanImpl** out) {
+                        bool csne, int flags, hipStream_t st, PlanImpl** out) {
   PlanImpl* P = new (std::nothrow) PlanImpl();
   if (!P) return SUBAP_E_NOMEM;
   auto fail = [&](subap_status rc) {
@@ -208,7 +210,7 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
     return ca > cb;
   });
   std::ostringstream key;
-  key << "fd_multi/p" << prec << "/f" << refine;
+  key << "fd_multi/p" << prec << "/f" << refine << (csne ? "c" : "");
   int64_t begin = 0;
   for (int oi : order) {
     const subap_model_s* M = models[oi];
@@ -224,6 +226,7 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
   P->total = begin;
   P->prec = prec;
   P->refine = refine;
+  P->csne = csne && refine > 0;
   P->key = key.str();
   subap_status rc = dalloc(&P->inst_d, P->inst.size());
   if (rc != SUBAP_OK) return fail(rc);

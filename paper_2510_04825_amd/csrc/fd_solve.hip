@@ -33,6 +33,9 @@ struct FDArgs {
   int prec;
   int refine;
   double aff_c0, aff_tau;  // delay family only
+  bool csne;               // refinement by the corrected semi-normal equations
+  const double* wS;        // row weights and per-row data of right-hand sides
+  const double* rowdat;    // that vary with p (eq. (5.7), identity family)
 };
 
 template <int TEAM, int R, int RM, int F, int DP>
@@ -178,8 +181,10 @@ __global__ __launch_bounds__(128, REF ? 1 : (BRED ? 2 : 4)) void k_fd_cols(FDArg
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int64_t p = static_cast<int64_t>(blockIdx.x) * 2 + wave;
   if (p >= A.m) return;  // uniform per wavefront; no block-level barrier follows
-  const ColsModel M{A.r, A.s, A.phi, A.delta64T, A.delta32T, A.bS, A.inv_h2, A.bS_norm, A.aff_c0, A.aff_tau};
-  cols_solve<F, DP, BRED, REF, COEF, RB>(M, A.params + p * DP, A.prec, A.refine, lds_cols + static_cast<int64_t>(wave) * ldsw, A.s,
+  const ColsModel M{A.r, A.s, A.phi, A.delta64T, A.delta32T, A.bS, A.inv_h2, A.bS_norm, A.aff_c0, A.aff_tau,
+                    A.wS, A.rowdat};
+  cols_solve<F, DP, BRED, REF, COEF, RB>(M, A.params + p * DP, A.prec, A.refine, A.csne,
+                                         lds_cols + static_cast<int64_t>(wave) * ldsw, A.s,
                           lane, A.y + p * A.r, A.rho ? A.rho + p : nullptr, A.status ? A.status + p : nullptr);
 }
 
@@ -189,8 +194,9 @@ template <int F, int DP, int COEF>
 __global__ __launch_bounds__(256) void k_fd_resid(const double* params, int64_t m, int r, int s,
                                                    const double* phi, const double* delta64, const double* bS,
                                                    double inv_h2, double bS_norm, double aff_c0, double aff_tau,
+                                                   const double* wS, const double* rowdat,
                                                    const double* y, double* res, double* norm) {
-  ColsModel CM{r, s, phi, nullptr, nullptr, bS, inv_h2, bS_norm, aff_c0, aff_tau};
+  ColsModel CM{r, s, phi, nullptr, nullptr, bS, inv_h2, bS_norm, aff_c0, aff_tau, wS, rowdat};
   const int64_t p = static_cast<int64_t>(blockIdx.x) * 4 + threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   if (p >= m) return;
@@ -200,7 +206,7 @@ __global__ __launch_bounds__(256) void k_fd_resid(const double* params, int64_t 
     pv[q] = params[p * DP + q];
     finite = finite && isfinite(pv[q]);
   }
-  double ss = 0.0;
+  double ss = 0.0, bb = 0.0;
   for (int k = lane; k < s; k += 64) {
     double t = 0.0;
     for (int f = 0; f < F; ++f) {
@@ -208,13 +214,16 @@ __global__ __launch_bounds__(256) void k_fd_resid(const double* params, int64_t 
       for (int c = 0; c < r; ++c) u += delta64[(f * r + c) * s + k] * y[p * r + c];
       t += cols_coef<F, DP, COEF>(CM, pv, f, k) * u;
     }
-    t -= bS[k];
+    const double bk = cols_rhs<COEF>(CM, pv, k);
+    t -= bk;
+    bb += bk * bk;
     if (!finite) t = __longlong_as_double(0x7ff8000000000000LL);
     if (res) res[p * s + k] = t;
     ss += t * t;
   }
   ss = team_sum<64>(ss);
-  if (lane == 0 && norm) norm[p] = sqrt(ss) / bS_norm;
+  if constexpr (coef_rhs_varies<COEF>()) bb = team_sum<64>(bb);
+  if (lane == 0 && norm) norm[p] = sqrt(ss) / (coef_rhs_varies<COEF>() ? sqrt(bb) : bS_norm);
 }
 
 template <int TEAM, int R, int RM, int F, int DP>
@@ -262,8 +271,10 @@ subap_status launch_cols(const FDArgs& a, hipStream_t st) {
 template <int F, int DP>
 subap_status dispatch(const FDArgs& a, hipStream_t st) {
   const int s = a.s, r = a.r;
-  // tall problems: column-per-lane Householder (any precision and refinement)
-  if (s >= 96) return launch_cols<F, DP>(a, st);
+  // tall problems: column-per-lane Householder (any precision and refinement).
+  // The corrected semi-normal equations need R^T R solves, which only the
+  // column-per-lane solver does.
+  if (s >= 96 || (a.csne && a.refine > 0)) return launch_cols<F, DP>(a, st);
 #define SUBAP_FD(TEAM, R, RM) \
   if (s <= TEAM * R && r <= RM) return launch<TEAM, R, RM, F, DP>(a, st);
   // s <= 16 / 32 / 64 / 128 / 192 rows; r up to 40 columns
@@ -276,9 +287,13 @@ subap_status dispatch(const FDArgs& a, hipStream_t st) {
 }  // namespace
 
 subap_status fd_solve(subap_model_s* M, const double* params, int64_t m, double* y, double* rho,
-                      int32_t* status, int prec, int refine, hipStream_t st) {
+                      int32_t* status, int prec, int refine, bool csne, hipStream_t st) {
   FDArgs a{params, m, M->r, M->s, M->phi, M->delta64, M->delta32, M->delta64T, M->delta32T, M->bS, M->inv_h2,
-           M->bS_norm, y, rho, status, prec, refine, M->aff_c0, M->tau};
+           M->bS_norm, y, rho, status, prec, refine, M->aff_c0, M->tau, csne, M->wS, M->rowdat};
+  // eq. (5.7) and the identity family: their affine pieces (two and one) and
+  // p-dependent right-hand sides, column-per-lane solver
+  if (M->family == SUBAP_FAMILY_TRIDIAG_SHIFT) return launch_cols<2, 1, kCoefTridiag>(a, st);
+  if (M->family == SUBAP_FAMILY_IDENTITY) return launch_cols<1, 1, kCoefIdentity>(a, st);
   // the delay family's two affine terms: column-per-lane solver for every
   // shape.  Its FP64 form fits blocks of 40 rows in registers (no spills at
   // F = 2), which shortens the reflector chain when that saves a block: at
@@ -297,15 +312,15 @@ subap_status fd_residual(subap_model_s* M, const double* params, int64_t m, cons
                          double* norm, hipStream_t st) {
   const unsigned grid = static_cast<unsigned>((m + 3) / 4);
   ProfScope prof("fd_residual", st);
-  if (M->family == SUBAP_FAMILY_DELAY)
-    hipLaunchKernelGGL((k_fd_resid<2, 1, kCoefDelay>), dim3(grid), dim3(256), 0, st, params, m, M->r, M->s, M->phi,
-                       M->delta64, M->bS, M->inv_h2, M->bS_norm, M->aff_c0, M->tau, y, res, norm);
-  else if (M->dimx == 2)
-    hipLaunchKernelGGL((k_fd_resid<4, 2, kCoefDiffusion>), dim3(grid), dim3(256), 0, st, params, m, M->r, M->s,
-                       M->phi, M->delta64, M->bS, M->inv_h2, M->bS_norm, 0.0, 0.0, y, res, norm);
-  else
-    hipLaunchKernelGGL((k_fd_resid<6, 4, kCoefDiffusion>), dim3(grid), dim3(256), 0, st, params, m, M->r, M->s,
-                       M->phi, M->delta64, M->bS, M->inv_h2, M->bS_norm, 0.0, 0.0, y, res, norm);
+#define SUBAP_RESID(F_, DP_, COEF_)                                                                              \
+  hipLaunchKernelGGL((k_fd_resid<F_, DP_, COEF_>), dim3(grid), dim3(256), 0, st, params, m, M->r, M->s, M->phi, \
+                     M->delta64, M->bS, M->inv_h2, M->bS_norm, M->aff_c0, M->tau, M->wS, M->rowdat, y, res, norm)
+  if (M->family == SUBAP_FAMILY_DELAY) SUBAP_RESID(2, 1, kCoefDelay);
+  else if (M->family == SUBAP_FAMILY_TRIDIAG_SHIFT) SUBAP_RESID(2, 1, kCoefTridiag);
+  else if (M->family == SUBAP_FAMILY_IDENTITY) SUBAP_RESID(1, 1, kCoefIdentity);
+  else if (M->dimx == 2) SUBAP_RESID(4, 2, kCoefDiffusion);
+  else SUBAP_RESID(6, 4, kCoefDiffusion);
+#undef SUBAP_RESID
   SUBAP_HIP_TRY(hipGetLastError());
   return SUBAP_OK;
 }

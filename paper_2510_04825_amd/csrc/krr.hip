@@ -12,7 +12,9 @@
 //   FP16X3    the same with fp16 halves (Q columns scaled by powers of two).
 // Then the FP64 Householder least squares (team_qr.h), and optional FP64
 // refinement: r_S = K_S(p) (Q y) + lambda (Q y)_S - b_S with FP64-accurate
-// kernel entries, correction from the stored factorisation.
+// kernel entries, correction from the stored factorisation (simple
+// refinement) or from the corrected semi-normal equations with an FP64
+// G^T r_S (a second pass over the kernel rows).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -659,6 +661,152 @@ __global__ __launch_bounds__(256) void k_resid_finish(const double* params, int6
 }
 
 // ---------------------------------------------------------------------------
+// Corrected semi-normal equations (Bjorck): the correction of a refinement
+// step solves R^T R dy = G^T r_S with R from the rounded contraction and
+//   G^T r_S = Q^T (K_S(p)^T (w o r_S)) + lambda Q_S^T r_S
+// in FP64 (G = W S A(p) Q; w the row weights, carried by Q_S already).  The
+// fixed point is G^T r_S = 0, the exact solution of eq. (3.3), where simple
+// refinement stops at the least-squares solution of the rounded G.
+//
+// Adjoint, part 1: partial sums of Q^T K_S(p)^T (w o r_S) over a range of
+// points.  Block: PB parameters x one point range (block index mod 8, the
+// same XCD split as the residual).  Thread = point j of a chunk of 256:
+//   u_j = sum_k 2^(c_p D[j, k]) w_k r_k       (kernel entries as in the residual)
+// then the block adds u_j Q[j, :] over the chunk, (parameter, column) pairs
+// over the threads.  Split 0 also adds lambda Q_S^T r_S.
+// ---------------------------------------------------------------------------
+constexpr int kAdjNJ = 256;  // points per chunk (one per thread)
+
+template <int RM, int DEG>
+__global__ __launch_bounds__(256) void k_adjoint_partial(const double* params, int64_t m, int64_t n, int r, int s,
+                                                         double dmax, const double* Dt64, const double* Qrm,
+                                                         const double* wS, const double* QS, double lambda,
+                                                         const double* rvec, double* gpart) {
+  extern __shared__ double adj_lds[];
+  double* s_t = adj_lds;                    // s x PB: w_k r_k of each parameter
+  double* s_u = adj_lds + s * kRefPB;       // kAdjNJ x PB
+  constexpr int NP = (kRefPB * RM + 255) / 256;  // (parameter, column) pairs per thread
+  const int t = threadIdx.x;
+  const int split = blockIdx.x % kRefSplit;
+  const int64_t p0 = static_cast<int64_t>(blockIdx.x / kRefSplit) * kRefPB;
+  for (int idx = t; idx < s * kRefPB; idx += 256) {
+    const int k = idx / kRefPB, w = idx % kRefPB;
+    s_t[idx] = (p0 + w < m) ? wS[k] * rvec[(p0 + w) * s + k] : 0.0;
+  }
+  double cv[kRefPB];
+  double cmax = 0.0;
+#pragma unroll
+  for (int w = 0; w < kRefPB; ++w) {
+    const double sig = p0 + w < m ? params[p0 + w] : 1.0;
+    const double c = krr_param_ok(sig) ? -0.5 * kLog2e / (sig * sig) : 0.0;
+    cv[w] = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(c)),
+                             __builtin_amdgcn_readfirstlane(__double2loint(c)));
+    cmax = fmax(cmax, -cv[w]);
+  }
+  const bool direct = cmax * dmax < kExp2Range;
+  double acc[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) acc[i] = 0.0;
+  const int64_t per = (n + kRefSplit - 1) / kRefSplit;
+  const int64_t jb = split * per, je = std::min<int64_t>(n, jb + per);
+  for (int64_t j0 = jb; j0 < je; j0 += kAdjNJ) {
+    __syncthreads();  // s_t is written; the previous chunk's s_u is consumed
+    const int64_t j = j0 + t;
+    double u[kRefPB];
+#pragma unroll
+    for (int w = 0; w < kRefPB; ++w) u[w] = 0.0;
+    if (j < je) {
+      const double* Dp = Dt64 + j * s;
+      double dn = Dp[0];
+      if (direct) {
+        for (int k = 0; k < s; ++k) {
+          const double d = dn;
+          if (k + 1 < s) dn = Dp[k + 1];
+#pragma unroll
+          for (int w = 0; w < kRefPB; ++w) u[w] = fma(exp2_mul<DEG>(cv[w], d), s_t[k * kRefPB + w], u[w]);
+        }
+      } else {
+        for (int k = 0; k < s; ++k) {
+          const double d = dn;
+          if (k + 1 < s) dn = Dp[k + 1];
+#pragma unroll
+          for (int w = 0; w < kRefPB; ++w) u[w] = fma(exp2_any<DEG>(cv[w] * d), s_t[k * kRefPB + w], u[w]);
+        }
+      }
+    }
+#pragma unroll
+    for (int w = 0; w < kRefPB; ++w) s_u[t * kRefPB + w] = u[w];
+    __syncthreads();
+    const int cnt = static_cast<int>(std::min<int64_t>(kAdjNJ, je - j0));
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int pair = t + 256 * i, w = pair / RM, c = pair % RM;
+      if (w < kRefPB && c < r) {
+        double a0 = 0.0, a1 = 0.0;
+        int jj = 0;
+        for (; jj + 1 < cnt; jj += 2) {
+          a0 = fma(s_u[jj * kRefPB + w], Qrm[(j0 + jj) * r + c], a0);
+          a1 = fma(s_u[(jj + 1) * kRefPB + w], Qrm[(j0 + jj + 1) * r + c], a1);
+        }
+        if (jj < cnt) a0 = fma(s_u[jj * kRefPB + w], Qrm[(j0 + jj) * r + c], a0);
+        acc[i] += a0 + a1;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const int pair = t + 256 * i, w = pair / RM, c = pair % RM;
+    if (w < kRefPB && c < r && p0 + w < m) {
+      double g = acc[i];
+      if (split == 0) {  // lambda Q_S^T r_S (Q_S carries the row weights)
+        double l = 0.0;
+        for (int k = 0; k < s; ++k) l = fma(QS[k * r + c], rvec[(p0 + w) * s + k], l);
+        g = fma(lambda, l, g);
+      }
+      gpart[(static_cast<int64_t>(split) * m + p0 + w) * r + c] = g;
+    }
+  }
+}
+
+// Adjoint, part 2: g = sum of the partials; y -= R^{-1} R^{-T} g with R from
+// the stored factorisation; rho from the part of the FP64 residual r_S outside
+// the range of the computed Q factor (as in k_correct).
+template <int TEAM, int R, int RM>
+__global__ __launch_bounds__(256) void k_csne_correct(CArgs A, const double* rvec, const double* gpart) {
+  constexpr int TEAMS = 256 / TEAM;
+  __shared__ double s_tau[TEAMS][RM];
+  __shared__ double s_dy[TEAMS][RM];
+  const int team = threadIdx.x / TEAM, lane = threadIdx.x % TEAM;
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * TEAMS + team;
+  if (p >= A.m) return;
+  if (A.status && A.status[p] != SUBAP_OK) return;  // y already NaN
+  const int r = A.r, s = A.s;
+  TeamQR<TEAM, R, RM> qr;
+  const double* f = A.fac + p * A.fac_stride;
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+#pragma unroll
+    for (int c = 0; c < RM; ++c) qr.a[q][c] = f[fac_index<TEAM, R, RM>(q, c, lane)];
+  for (int j = 0; j < RM; ++j) s_tau[team][j] = f[TEAM * R * RM + j];
+  double g[R], res[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = lane + TEAM * q;
+    double t = 0.0;
+    if (k < r)
+      for (int sp = 0; sp < kRefSplit; ++sp) t += gpart[(static_cast<int64_t>(sp) * A.m + p) * r + k];
+    g[q] = t;
+    res[q] = k < s ? rvec[p * s + k] : 0.0;
+  }
+  qr.forward_substitute_t(g, r, lane);
+  qr.back_substitute(g, r, lane, s_dy[team]);
+  for (int c = lane; c < r; c += TEAM) A.y[p * r + c] -= s_dy[team][c];
+  qr.apply_qt(res, r, lane, s_tau[team]);
+  const double tail = qr.tail_norm(res, r, lane);
+  if (lane == 0 && A.rho) A.rho[p] = tail / A.bS_norm;
+}
+
+// ---------------------------------------------------------------------------
 // dispatch helpers
 // ---------------------------------------------------------------------------
 struct Shape {
@@ -713,15 +861,120 @@ subap_status launch_correct(const Shape& sh, const CArgs& a, hipStream_t st) {
   return SUBAP_E_UNSUPPORTED;
 }
 
+subap_status launch_csne_correct(const Shape& sh, const CArgs& a, const double* rvec, const double* gpart,
+                                 hipStream_t st) {
+  const unsigned grid = static_cast<unsigned>((a.m * sh.team + 255) / 256);
+#define SUBAP_CSNE(T_, R_, M_)                                                                          \
+  if (sh.team == T_ && sh.R == R_ && sh.RM == M_) {                                                     \
+    hipLaunchKernelGGL((k_csne_correct<T_, R_, M_>), dim3(grid), dim3(256), 0, st, a, rvec, gpart);    \
+    SUBAP_HIP_TRY(hipGetLastError());                                                                   \
+    return SUBAP_OK;                                                                                    \
+  }
+  SUBAP_CSNE(16, 1, 8) SUBAP_CSNE(16, 1, 16) SUBAP_CSNE(32, 1, 8) SUBAP_CSNE(32, 1, 16) SUBAP_CSNE(32, 1, 32)
+  SUBAP_CSNE(64, 1, 16) SUBAP_CSNE(64, 1, 32) SUBAP_CSNE(64, 1, 40)
+  SUBAP_CSNE(64, 2, 16) SUBAP_CSNE(64, 2, 32) SUBAP_CSNE(64, 2, 40)
+  SUBAP_CSNE(64, 3, 32) SUBAP_CSNE(64, 3, 40) SUBAP_CSNE(64, 4, 40)
+#undef SUBAP_CSNE
+  set_error("no correction kernel for this (s, r)");
+  return SUBAP_E_UNSUPPORTED;
+}
+
 int rm_of(int r) { return r <= 8 ? 8 : r <= 16 ? 16 : r <= 32 ? 32 : r <= 40 ? 40 : 64; }
+
+template <int DEG>
+void launch_adjoint_deg(subap_model_s* M, const double* params, int64_t m, const double* rvec, double* gpart,
+                        hipStream_t st) {
+  const int r = M->r, s = M->s;
+  const int64_t n = M->n;
+  const dim3 grid(static_cast<unsigned>((m + kRefPB - 1) / kRefPB * kRefSplit));
+  const size_t lds = sizeof(double) * kRefPB * (static_cast<size_t>(s) + kAdjNJ);
+#define SUBAP_ADJ(RM_)                                                                                      \
+  hipLaunchKernelGGL((k_adjoint_partial<RM_, DEG>), grid, dim3(256), lds, st, params, m, n, r, s, M->dmax,  \
+                     M->Dt64, M->Qrm, M->wS, M->QS, M->lambda, rvec, gpart)
+  switch (rm_of(r)) {
+    case 8: SUBAP_ADJ(8); break;
+    case 16: SUBAP_ADJ(16); break;
+    case 32: SUBAP_ADJ(32); break;
+    case 40: SUBAP_ADJ(40); break;
+    default: SUBAP_ADJ(64); break;
+  }
+#undef SUBAP_ADJ
+}
+
+// FP64 G^T r_S partials for the corrected semi-normal equations; the first
+// step's kernel entries use the degree-7 polynomial like its residual.
+subap_status launch_adjoint(subap_model_s* M, const double* params, int64_t m, const double* rvec, double* gpart,
+                            bool exact, hipStream_t st) {
+  {
+    ProfScope prof(exact ? "krr_adjoint_partial_exact" : "krr_adjoint_partial", st);
+    if (exact) launch_adjoint_deg<11>(M, params, m, rvec, gpart, st);
+    else launch_adjoint_deg<7>(M, params, m, rvec, gpart, st);
+  }
+  SUBAP_HIP_TRY(hipGetLastError());
+  return SUBAP_OK;
+}
 
 }  // namespace
 
 subap_status launch_refine_partial(subap_model_s* M, const double* params, int64_t m, const double* y,
                                    double* part, bool exact, hipStream_t st);
 
+namespace {
+
+// Workspace of one krr_solve call, in bytes, laid out as consecutive
+// 256-byte-aligned pieces: G (FP64, plus the FP32 split partials of the MFMA
+// forms), the stored factorisation and the residual partials (refinement),
+// the status fallback, and for the corrected semi-normal equations the
+// residual vectors and the G^T r_S partials.
+struct KrrWork {
+  size_t g, f, p, st, rv, a;
+  static size_t al(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
+  size_t total() const { return al(g) + al(f) + al(p) + al(st) + al(rv) + al(a); }
+};
+
+KrrWork krr_work(const subap_model_s* M, const Shape& sh, int64_t m, int prec, int refine, bool csne) {
+  const int r = M->r, s = M->s;
+  const bool cs = csne && refine > 0;
+  const int fac_stride = sh.team * sh.R * sh.RM + sh.RM;
+  KrrWork w;
+  w.g = static_cast<size_t>(m) * s * r * (prec == SUBAP_FP64 ? 8 : 8 + 4 * kSplit);
+  w.f = refine > 0 ? static_cast<size_t>(m) * fac_stride * 8 : 0;
+  w.p = refine > 0 ? static_cast<size_t>(kRefSplit) * m * s * 8 : 0;
+  w.st = static_cast<size_t>(m) * 4;
+  w.rv = cs ? static_cast<size_t>(m) * s * 8 : 0;
+  w.a = cs ? static_cast<size_t>(kRefSplit) * m * r * 8 : 0;
+  return w;
+}
+
+}  // namespace
+
+int64_t krr_chunk(const subap_model_s* M, int prec, int refine, bool csne, size_t bytes) {
+  Shape sh;
+  if (!pick_shape(M->s, M->r, &sh)) return 0;
+  // parameters in multiples of the refinement's block of kRefPB, so that a
+  // chunked batch groups its parameters into blocks as one call would
+  int64_t lo = 0, hi = int64_t(1) << 26;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) / 2;
+    if (krr_work(M, sh, mid * kRefPB, prec, refine, csne).total() <= bytes) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo * kRefPB;
+}
+
 subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double* y, double* rho,
-                       int32_t* status, int prec, int refine, hipStream_t st) {
+                       int32_t* status, int prec, int refine, bool csne, hipStream_t st) {
+  Shape sh;
+  if (!pick_shape(M->s, M->r, &sh)) {
+    set_error("no least-squares kernel for this (s, r)");
+    return SUBAP_E_UNSUPPORTED;
+  }
+  SUBAP_TRY(ensure_work(M, krr_work(M, sh, m, prec, refine, csne).total()));
+  return krr_solve_ws(M, params, m, y, rho, status, prec, refine, csne, M->work, st);
+}
+
+subap_status krr_solve_ws(subap_model_s* M, const double* params, int64_t m, double* y, double* rho,
+                          int32_t* status, int prec, int refine, bool csne, void* work, hipStream_t st) {
   const int r = M->r, s = M->s;
   const int64_t n = M->n;
   Shape sh;
@@ -730,19 +983,19 @@ subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double
     return SUBAP_E_UNSUPPORTED;
   }
   const int RM = rm_of(r);
-  // FP64 G, plus the FP32 split partials for the MFMA forms
-  const size_t gbytes = static_cast<size_t>(m) * s * r * (prec == SUBAP_FP64 ? 8 : 8 + 4 * kSplit);
+  const KrrWork kw = krr_work(M, sh, m, prec, refine, csne);
+  const size_t gbytes = kw.g, fbytes = kw.f, pbytes = kw.p, stbytes = kw.st, rbytes = kw.rv;
   const int fac_stride = sh.team * sh.R * sh.RM + sh.RM;
-  const size_t fbytes = refine > 0 ? static_cast<size_t>(m) * fac_stride * 8 : 0;
-  const size_t pbytes = refine > 0 ? static_cast<size_t>(kRefSplit) * m * s * 8 : 0;
-  const size_t stbytes = static_cast<size_t>(m) * 4;
-  auto al = [](size_t b) { return (b + 255) & ~static_cast<size_t>(255); };
-  SUBAP_TRY(ensure_work(M, al(gbytes) + al(fbytes) + al(pbytes) + al(stbytes)));
-  char* w = static_cast<char*>(M->work);
+  const bool cs = csne && refine > 0;
+  auto al = KrrWork::al;
+  char* w = static_cast<char*>(work);
   void* G = w;
   double* fac = refine > 0 ? reinterpret_cast<double*>(w + al(gbytes)) : nullptr;
   double* part = refine > 0 ? reinterpret_cast<double*>(w + al(gbytes) + al(fbytes)) : nullptr;
   int32_t* stat = status ? status : reinterpret_cast<int32_t*>(w + al(gbytes) + al(fbytes) + al(pbytes));
+  char* wc = w + al(gbytes) + al(fbytes) + al(pbytes) + al(stbytes);
+  double* rvec = cs ? reinterpret_cast<double*>(wc) : nullptr;
+  double* gpart = cs ? reinterpret_cast<double*>(wc + al(rbytes)) : nullptr;
 
   // A1 + A2: rows and contraction
   if (prec == SUBAP_FP64) {
@@ -804,10 +1057,25 @@ subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double
   }
   // A4: refinement
   for (int it = 0; it < refine; ++it) {
-    SUBAP_TRY(launch_refine_partial(M, params, m, y, part, it > 0, st));
+    // degree-7 kernel entries only in the first step from a reduced contraction,
+    // whose own error is far larger; FP64-rounding entries otherwise
+    const bool exact = it > 0 || prec == SUBAP_FP64;
+    SUBAP_TRY(launch_refine_partial(M, params, m, y, part, exact, st));
     CArgs ca{m, r, s, part, M->wS, M->QS, M->bS, M->lambda, M->bS_norm, fac, fac_stride, y, rho, stat};
-    ProfScope prof("lsq_correct", st);
-    SUBAP_TRY(launch_correct(sh, ca, st));
+    if (cs) {
+      {
+        ProfScope prof("krr_resid_finish", st);
+        hipLaunchKernelGGL(k_resid_finish, dim3(static_cast<unsigned>((m + 3) / 4)), dim3(256), 0, st, params, m,
+                           r, s, part, M->wS, M->QS, M->bS, M->lambda, M->bS_norm, y, rvec, nullptr);
+        SUBAP_HIP_TRY(hipGetLastError());
+      }
+      SUBAP_TRY(launch_adjoint(M, params, m, rvec, gpart, exact, st));
+      ProfScope prof("lsq_csne_correct", st);
+      SUBAP_TRY(launch_csne_correct(sh, ca, rvec, gpart, st));
+    } else {
+      ProfScope prof("lsq_correct", st);
+      SUBAP_TRY(launch_correct(sh, ca, st));
+    }
   }
   return SUBAP_OK;
 }

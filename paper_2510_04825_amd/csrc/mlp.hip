@@ -491,8 +491,8 @@ __global__ void k_scatter_results(const double* ys, const int32_t* sts, int r, c
 __global__ void k_zero_u64(unsigned long long* c) { *c = 0ull; }
 
 subap_status surrogate_solve(subap_model_s* M, Surrogate* S, const double* P, int64_t m, double tol, double* y,
-                             uint8_t* accepted, int32_t* status, int prec, int refine, int64_t* n_acc,
-                             hipStream_t st) {
+                             uint8_t* accepted, int32_t* status, int prec, int refine, bool csne,
+                             int64_t* n_acc, hipStream_t st) {
   // workspace: norms (m), rejected indices (m), count, compact params (m d), y (m r), status (m)
   const size_t bytes = 8 * static_cast<size_t>(m) * (2 + M->d + M->r + 1) + 64;
   char* buf = nullptr;
@@ -524,8 +524,8 @@ subap_status surrogate_solve(subap_model_s* M, Surrogate* S, const double* P, in
   if (k == 0) return SUBAP_OK;
   hipLaunchKernelGGL(k_gather_rows_by_index, dim3(static_cast<unsigned>((k * M->d + 255) / 256)), dim3(256), 0, st,
                      P, M->d, rej, k, Pc);
-  if (M->family == SUBAP_FAMILY_KRR) SUBAP_TRY(krr_solve(M, Pc, k, Yc, nullptr, Sc, prec, refine, st));
-  else SUBAP_TRY(fd_solve(M, Pc, k, Yc, nullptr, Sc, prec, refine, st));
+  if (M->family == SUBAP_FAMILY_KRR) SUBAP_TRY(krr_solve(M, Pc, k, Yc, nullptr, Sc, prec, refine, csne, st));
+  else SUBAP_TRY(fd_solve(M, Pc, k, Yc, nullptr, Sc, prec, refine, csne, st));
   hipLaunchKernelGGL(k_scatter_results, dim3(static_cast<unsigned>((k * M->r + 255) / 256)), dim3(256), 0, st, Yc,
                      Sc, M->r, rej, k, y, status);
   SUBAP_HIP_TRY(hipGetLastError());

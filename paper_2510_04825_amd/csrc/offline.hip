@@ -109,6 +109,49 @@ __global__ void k_delay_apply(OpArgs A, const double* params, int ncol, const do
   if (diag_out) diag_out[static_cast<int64_t>(col) * A.n + i] = p - g * ((end ? 1.0 : 0.0) - A.kappa);
 }
 
+// eq. (5.7): Y[:, c] = (A_0 - p I) X[:, c] with A_0 = tridiag(-1, 2, -1);
+// identity family: Y = X.
+__global__ void k_tri_apply(OpArgs A, const double* params, int ncol, const double* X, double* Y,
+                            double* diag_out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int col = blockIdx.y;
+  if (i >= A.n || col >= ncol) return;
+  const bool ident = A.family == SUBAP_FAMILY_IDENTITY;
+  const double dg = ident ? 1.0 : 2.0 - params[col];
+  if (Y) {
+    const double* x = X + static_cast<int64_t>(col) * A.n;
+    double y = dg * x[i];
+    if (!ident) {
+      if (i > 0) y -= x[i - 1];
+      if (i + 1 < A.n) y -= x[i + 1];
+    }
+    Y[static_cast<int64_t>(col) * A.n + i] = y;
+  }
+  if (diag_out) diag_out[static_cast<int64_t>(col) * A.n + i] = dg;
+}
+
+// b(p) for the families whose right-hand side varies with p, one column per
+// parameter: eq. (5.7) b_i = exp(b0_i sin(p / 10) p) (b0 = the model's rhs);
+// identity family b_i = 1 / (1 + 25 (t_i - p)^2), t_i = i / (n - 1).
+__device__ __forceinline__ double identity_node(int64_t i, int64_t n) {
+  return i == n - 1 ? 1.0 : static_cast<double>(i) * (1.0 / static_cast<double>(n - 1));
+}
+
+__global__ void k_rhs_cols(int family, int64_t n, const double* b0, const double* params, int ncol, double* B) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int col = blockIdx.y;
+  if (i >= n || col >= ncol) return;
+  const double p = params[col];
+  double v;
+  if (family == SUBAP_FAMILY_IDENTITY) {
+    const double t = identity_node(i, n) - p;
+    v = 1.0 / (1.0 + 25.0 * (t * t));
+  } else {
+    v = exp(b0[i] * sin(p / 10.0) * p);
+  }
+  B[static_cast<int64_t>(col) * n + i] = v;
+}
+
 // KRR: Y[i, c] = sum_j exp(-|t_i - t_j|^2 / (2 p_c^2)) X[j, c] + lambda X[i, c]
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_krr_apply(OpArgs A, const double* params, int ncol,
@@ -161,6 +204,8 @@ subap_status apply_op(const OpArgs& A, const double* params_d, int ncol, const d
     }
   } else if (A.family == SUBAP_FAMILY_DELAY) {
     hipLaunchKernelGGL(k_delay_apply, grid, dim3(kBlock), 0, st, A, params_d, ncol, X, Y, diag);
+  } else if (rhs_varies(A.family)) {
+    hipLaunchKernelGGL(k_tri_apply, grid, dim3(kBlock), 0, st, A, params_d, ncol, X, Y, diag);
   } else {
     hipLaunchKernelGGL(k_fd_apply, grid, dim3(kBlock), 0, st, A, params_d, ncol, X, Y, diag);
   }
@@ -307,7 +352,7 @@ __global__ void k_sqrt_ratio(const double* num, const double* den, int ncol, dou
 // start from X instead of 0.  relres (device, ncol, optional): final
 // |b - A x| / |b|.  require_conv: SUBAP_E_NOCONV if a column misses tol.
 subap_status cg_solve(const OpArgs& A, const double* params_d, int r, const double* b_d, double tol, int maxiter,
-                      double* X, bool warm, double* relres, bool require_conv, hipStream_t st) {
+                      double* X, bool warm, double* relres, bool require_conv, hipStream_t st, int64_t ldb = 0) {
   const int64_t n = A.n;
   const int64_t nr = n * r;
   DevVec R, Z, P, Qv, Dinv, scal;
@@ -339,10 +384,10 @@ subap_status cg_solve(const OpArgs& A, const double* params_d, int r, const doub
     SUBAP_TRY(apply_op(A, params_d, r, X, R.p, nullptr, st));
     hipLaunchKernelGGL(k_cg_init_warm, g2, dim3(kBlock), 0, st, n, b_d, dinv, R.p, Z.p, P.p);
   } else {
-    hipLaunchKernelGGL(k_cg_init, g2, dim3(kBlock), 0, st, n, r, b_d, int64_t(0), dinv, X, R.p, Z.p, P.p);
+    hipLaunchKernelGGL(k_cg_init, g2, dim3(kBlock), 0, st, n, r, b_d, ldb, dinv, X, R.p, Z.p, P.p);
   }
   SUBAP_TRY(col_dots(R.p, n, Z.p, n, 0, n, r, part, rz, st));
-  SUBAP_TRY(col_dots(b_d, 0, b_d, 0, 0, n, r, part, bb, st));
+  SUBAP_TRY(col_dots(b_d, ldb, b_d, ldb, 0, n, r, part, bb, st));
   std::vector<double> h_rr(r), h_bb(r);
   std::vector<int> h_done(r, 0);
   SUBAP_HIP_TRY(hipMemcpyAsync(h_bb.data(), bb, sizeof(double) * r, hipMemcpyDeviceToHost, st));
@@ -717,6 +762,13 @@ __global__ void k_dup_param(const double* p, int d, int ncol, double* out) {
   if (t < ncol * d) out[t] = p[t % d];
 }
 
+// Y[:, c] -= B[:, c]
+__global__ void k_sub_cols(double* Y, int64_t n, const double* B) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i < n) Y[static_cast<int64_t>(c) * n + i] -= B[static_cast<int64_t>(c) * n + i];
+}
+
 // Y[:, c] -= b
 __global__ void k_sub_b(double* Y, int64_t n, const double* b) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -819,6 +871,42 @@ __global__ void k_delay_tables(const double* Qm, int64_t n, int r, int s, const 
     QS[static_cast<int64_t>(k) * r + cc] = t0;
   }
   bS[k] = wk * rhs[i];
+}
+
+// eq. (5.7) and the identity family: piece 0 of row k = w_k Q[i_k] (S Q),
+// piece 1 = w_k (A_0 Q)[i_k] with A_0 = tridiag(-1, 2, -1) (eq. (5.7) only),
+// in the layouts of the finite-difference tables; rowdat[k] is the row's
+// datum of the p-dependent right-hand side (b0[i_k], or the node t at i_k).
+__global__ void k_shift_tables(int family, const double* Qm, int64_t n, int r, int s, const int* rows,
+                               const double* wS, const double* rhs, double* delta64, float* delta32,
+                               double* delta64T, float* delta32T, double* bS, double* QS, double* rowdat) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= s) return;
+  const int64_t i = rows[k];
+  const double wk = wS[k];
+  const bool two = family == SUBAP_FAMILY_TRIDIAG_SHIFT;
+  for (int cc = 0; cc < r; ++cc) {
+    const double* q = Qm + static_cast<int64_t>(cc) * n;
+    const double qi = q[i];
+    const double t0 = wk * qi;
+    delta64[static_cast<int64_t>(cc) * s + k] = t0;
+    delta32[static_cast<int64_t>(cc) * s + k] = static_cast<float>(t0);
+    delta64T[static_cast<int64_t>(k) * r + cc] = t0;
+    delta32T[static_cast<int64_t>(k) * r + cc] = static_cast<float>(t0);
+    if (two) {
+      double aq = 2.0 * qi;
+      if (i > 0) aq -= q[i - 1];
+      if (i + 1 < n) aq -= q[i + 1];
+      const double t1 = wk * aq;
+      delta64[(static_cast<int64_t>(r) + cc) * s + k] = t1;
+      delta32[(static_cast<int64_t>(r) + cc) * s + k] = static_cast<float>(t1);
+      delta64T[(static_cast<int64_t>(s) + k) * r + cc] = t1;
+      delta32T[(static_cast<int64_t>(s) + k) * r + cc] = static_cast<float>(t1);
+    }
+    QS[static_cast<int64_t>(k) * r + cc] = t0;
+  }
+  bS[k] = 0.0;  // b(p) is generated per parameter from rowdat
+  rowdat[k] = family == SUBAP_FAMILY_IDENTITY ? identity_node(i, n) : rhs[i];
 }
 
 // out[k] = sum_c cQ[c] y[k, c]
@@ -1044,6 +1132,15 @@ subap_status build_tables(subap_model_s* M, hipStream_t st) {
     hipLaunchKernelGGL(k_fp16_split, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
                        M->Q, n, r, scale.p, M->Qh16, M->Ql16);
     SUBAP_HIP_TRY(hipStreamSynchronize(st));
+  } else if (rhs_varies(M->family)) {
+    const size_t tab = static_cast<size_t>(s) * M->F;
+    SUBAP_TRY(dalloc(&M->delta64, tab * r));
+    SUBAP_TRY(dalloc(&M->delta32, tab * r));
+    SUBAP_TRY(dalloc(&M->delta64T, tab * r));
+    SUBAP_TRY(dalloc(&M->delta32T, tab * r));
+    SUBAP_TRY(dalloc(&M->rowdat, s));
+    hipLaunchKernelGGL(k_shift_tables, dim3((s + 63) / 64), dim3(64), 0, st, M->family, M->Q, n, r, s, M->rows_d,
+                       M->wS, M->rhs, M->delta64, M->delta32, M->delta64T, M->delta32T, M->bS, M->QS, M->rowdat);
   } else if (M->family == SUBAP_FAMILY_DELAY) {
     const size_t tab = static_cast<size_t>(s) * M->F;
     SUBAP_TRY(dalloc(&M->delta64, tab * r));
@@ -1077,6 +1174,7 @@ subap_status build_tables(subap_model_s* M, hipStream_t st) {
   for (double v : hs) u += v * v;
   M->b_norm = std::sqrt(t);
   M->bS_norm = M->selection == SUBAP_SELECT_LEVERAGE ? M->b_norm : std::sqrt(u);
+  if (rhs_varies(M->family)) M->b_norm = M->bS_norm = 1.0;  // norms of b(p) are taken per parameter
   return SUBAP_OK;
 }
 
@@ -1161,15 +1259,69 @@ subap_status full_residual(subap_model_s* M, const double* params, int64_t m, co
   SUBAP_TRY(dalloc(&Y.p, static_cast<size_t>(n) * per));
   SUBAP_TRY(dalloc(&part.p, static_cast<size_t>(kMaxPartials) * per));
   SUBAP_TRY(dalloc(&ss.p, per));
+  const bool vary = rhs_varies(M->family);
+  DevVec Bp, bb;
+  if (vary) {
+    SUBAP_TRY(dalloc(&Bp.p, static_cast<size_t>(n) * per));
+    SUBAP_TRY(dalloc(&bb.p, per));
+  }
   for (int64_t c0 = 0; c0 < m; c0 += per) {
     const int cnt = static_cast<int>(std::min<int64_t>(per, m - c0));
+    const dim3 g2(static_cast<unsigned>((n + kBlock - 1) / kBlock), cnt);
     SUBAP_TRY(apply_op(A, params + c0 * M->d, cnt, x + c0 * n, Y.p, nullptr, st));
-    hipLaunchKernelGGL(k_sub_b, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock), cnt), dim3(kBlock), 0, st,
-                       Y.p, n, M->rhs);
-    SUBAP_TRY(col_dots(Y.p, n, Y.p, n, 0, n, cnt, part.p, ss.p, st));
-    hipLaunchKernelGGL(k_norm_ratio, dim3((cnt + 63) / 64), dim3(64), 0, st, ss.p, cnt, M->b_norm, res + c0);
+    if (vary) {  // b(p) per column
+      hipLaunchKernelGGL(k_rhs_cols, g2, dim3(kBlock), 0, st, M->family, n, M->rhs, params + c0 * M->d, cnt, Bp.p);
+      hipLaunchKernelGGL(k_sub_cols, g2, dim3(kBlock), 0, st, Y.p, n, Bp.p);
+      SUBAP_TRY(col_dots(Y.p, n, Y.p, n, 0, n, cnt, part.p, ss.p, st));
+      SUBAP_TRY(col_dots(Bp.p, n, Bp.p, n, 0, n, cnt, part.p, bb.p, st));
+      hipLaunchKernelGGL(k_sqrt_ratio, dim3((cnt + 63) / 64), dim3(64), 0, st, ss.p, bb.p, cnt, res + c0);
+    } else {
+      hipLaunchKernelGGL(k_sub_b, g2, dim3(kBlock), 0, st, Y.p, n, M->rhs);
+      SUBAP_TRY(col_dots(Y.p, n, Y.p, n, 0, n, cnt, part.p, ss.p, st));
+      hipLaunchKernelGGL(k_norm_ratio, dim3((cnt + 63) / 64), dim3(64), 0, st, ss.p, cnt, M->b_norm, res + c0);
+    }
   }
   SUBAP_HIP_TRY(hipGetLastError());
+  return SUBAP_OK;
+}
+
+// d = a - b elementwise
+__global__ void k_diff(const double* a, const double* b, int64_t len, double* d) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < len) d[i] = a[i] - b[i];
+}
+
+subap_status delta_residual(subap_model_s* M, const double* params, int64_t m, const double* y1, const double* y2,
+                            double* res, hipStream_t st) {
+  const OpArgs A = op_args(M);
+  const int64_t n = M->n, per = std::min<int64_t>(pass_cols(n, m), 65535);
+  const int r = M->r;
+  DevVec dy, X, Y, part, ss, bb;
+  SUBAP_TRY(dalloc(&bb.p, per));
+  SUBAP_TRY(dalloc(&dy.p, static_cast<size_t>(per) * r));
+  SUBAP_TRY(dalloc(&X.p, static_cast<size_t>(n) * per));
+  SUBAP_TRY(dalloc(&Y.p, static_cast<size_t>(n) * per));
+  SUBAP_TRY(dalloc(&part.p, static_cast<size_t>(kMaxPartials) * per));
+  SUBAP_TRY(dalloc(&ss.p, per));
+  for (int64_t c0 = 0; c0 < m; c0 += per) {
+    const int cnt = static_cast<int>(std::min<int64_t>(per, m - c0));
+    const int64_t len = static_cast<int64_t>(cnt) * r;
+    hipLaunchKernelGGL(k_diff, dim3(static_cast<unsigned>((len + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                       y1 + c0 * r, y2 + c0 * r, len, dy.p);
+    SUBAP_TRY(lift(M, dy.p, cnt, X.p, n, SUBAP_FP64, st));
+    SUBAP_TRY(apply_op(A, params + c0 * M->d, cnt, X.p, Y.p, nullptr, st));
+    SUBAP_TRY(col_dots(Y.p, n, Y.p, n, 0, n, cnt, part.p, ss.p, st));
+    if (rhs_varies(M->family)) {  // |b(p)| per column; X is free again
+      hipLaunchKernelGGL(k_rhs_cols, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock), cnt), dim3(kBlock), 0,
+                         st, M->family, n, M->rhs, params + c0 * M->d, cnt, X.p);
+      SUBAP_TRY(col_dots(X.p, n, X.p, n, 0, n, cnt, part.p, bb.p, st));
+      hipLaunchKernelGGL(k_sqrt_ratio, dim3((cnt + 63) / 64), dim3(64), 0, st, ss.p, bb.p, cnt, res + c0);
+    } else {
+      hipLaunchKernelGGL(k_norm_ratio, dim3((cnt + 63) / 64), dim3(64), 0, st, ss.p, cnt, M->b_norm, res + c0);
+    }
+  }
+  SUBAP_HIP_TRY(hipGetLastError());
+  SUBAP_HIP_TRY(hipStreamSynchronize(st));
   return SUBAP_OK;
 }
 
@@ -1305,7 +1457,15 @@ subap_status offline_build(const subap_problem_desc* pd, const subap_offline_opt
     SUBAP_HIP_TRY(hipMemcpyAsync(params.p, o->snap_params, sizeof(double) * r * d, hipMemcpyHostToDevice, st));
     const double tol = o->snap_tol > 0.0 ? o->snap_tol : 1e-12;
     const int maxit = o->snap_maxiter > 0 ? o->snap_maxiter : 20000;
-    SUBAP_TRY(cg_solve(A, params.p, r, M->rhs, tol, maxit, X.p, false, nullptr, true, st));
+    if (rhs_varies(M->family)) {  // b(p_i) per snapshot
+      DevVec Bs;
+      SUBAP_TRY(dalloc(&Bs.p, static_cast<size_t>(n) * r));
+      hipLaunchKernelGGL(k_rhs_cols, dim3(static_cast<unsigned>((n + kBlock - 1) / kBlock), r), dim3(kBlock), 0,
+                         st, M->family, n, M->rhs, params.p, r, Bs.p);
+      SUBAP_TRY(cg_solve(A, params.p, r, Bs.p, tol, maxit, X.p, false, nullptr, true, st, n));
+    } else {
+      SUBAP_TRY(cg_solve(A, params.p, r, M->rhs, tol, maxit, X.p, false, nullptr, true, st));
+    }
   }
   // 2. orthonormalise
   SUBAP_TRY(dalloc(&M->Q, static_cast<size_t>(n) * r));

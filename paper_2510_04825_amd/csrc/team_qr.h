@@ -165,6 +165,25 @@ struct TeamQR {
     }
   }
 
+  // Solve R^T z = x[0:r] in place (x distributed like b; rows >= r are left
+  // alone).  Row j needs sum_{i<j} R[i][j] z_i, a team reduction over the
+  // lanes that own rows i < j.
+  __device__ __forceinline__ void forward_substitute_t(double (&x)[R], int r, int lane) const {
+#pragma unroll
+    for (int j = 0; j < RM; ++j) {
+      if (j < r) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+          if (row(lane, q) < j) t = fma(a[q][j], x[q], t);
+        t = team_sum<TEAM>(t);
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+          if (row(lane, q) == j) x[q] = (x[q] - t) / a[q][j];
+      }
+    }
+  }
+
   // |x[r:s]|_2 for x distributed like b (x = Q^T b gives the LSQ residual).
   __device__ __forceinline__ double tail_norm(const double (&x)[R], int r, int lane) const {
     double t = 0.0;

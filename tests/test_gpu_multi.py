@@ -36,18 +36,22 @@ def _models(uneven_small):
     (B.FP64, 0, 1e-12, 0),
     (B.FP64, 0, 1e-12, B.PLAN_GRAPH | B.PLAN_AUTOTUNE),
     (B.FP32, 1, 1e-6, B.PLAN_GRAPH),
+    (B.FP32, -1, 1e-6, B.PLAN_GRAPH),  # one step of the corrected semi-normal equations
 ])
 def test_plan_matches_oracle(uneven_small, prec, refine, tol, flags, tmp_path, monkeypatch):
     import torch
     monkeypatch.setenv("SUBAP_AUTOTUNE_CACHE", str(tmp_path / "tune.txt"))
-    header(f"plan prec={prec} refine={refine} flags={flags}")
+    csne = refine < 0
+    refine = abs(refine)
+    header(f"plan prec={prec} refine={refine} csne={csne} flags={flags}")
     models = _models(uneven_small)
     try:
         params = [to_dev(w["test_params"]) for w, _, _ in uneven_small]
         ys = [torch.full((w["m"], w["r"]), -7.0, dtype=torch.float64, device=params[0].device)
               for w, _, _ in uneven_small]
         sts = [torch.full((w["m"],), -1, dtype=torch.int32, device=params[0].device) for w, _, _ in uneven_small]
-        plan = B.subap_plan_create([M.handle for M in models], params, ys, None, sts, prec, refine, flags)
+        plan = B.subap_plan_create([M.handle for M in models], params, ys, None, sts, prec, refine, flags,
+                                   csne=csne)
         try:
             for rep in range(3):  # replays with eager work between them
                 for y in ys:
@@ -181,10 +185,12 @@ def test_uneven_full_size_sampled(tmp_path, monkeypatch):
         ys = [torch.empty((w["m"], w["r"]), dtype=torch.float64, device=params[0].device) for w in insts]
         sts = [torch.empty(w["m"], dtype=torch.int32, device=params[0].device) for w in insts]
         picks = [rng.choice(w["m"], size=min(2, w["m"]), replace=False) for w in insts]
-        for prec, refine, base, scale in ((B.FP64, 0, 1e-12, 2.0 ** -46), (B.FP32, 1, 1e-6, 2.0 ** -20)):
-            header(f"uneven full size prec={prec} refine={refine}")
+        forms = ((B.FP64, 0, False, 1e-12, 2.0 ** -46), (B.FP32, 1, False, 1e-6, 2.0 ** -20),
+                 (B.FP32, 1, True, 1e-6, None))
+        for prec, refine, csne, base, scale in forms:
+            header(f"uneven full size prec={prec} refine={refine} csne={csne}")
             plan = B.subap_plan_create([M.handle for M in models], params, ys, None, sts, prec, refine,
-                                       B.PLAN_GRAPH | B.PLAN_AUTOTUNE)
+                                       B.PLAN_GRAPH | B.PLAN_AUTOTUNE, csne=csne)
             try:
                 B.subap_plan_execute(plan)
                 torch.cuda.synchronize()
@@ -199,6 +205,11 @@ def test_uneven_full_size_sampled(tmp_path, monkeypatch):
                     G = On.reduced_matrix(fam, Q, rows, p)
                     bS = fam.rhs_rows(p, rows)
                     yo, _, rho = On.householder_lsq(G, bS)
+                    if scale is None:
+                        # corrected semi-normal equations: flat bar on delta_res over all n rows
+                        d = On.delta_res(fam, Q, p, yg[i], yo)
+                        assert d <= base, (prec, w["n"], w["r"], w["s"], i, d)
+                        continue
                     sv = np.linalg.svd(G, compute_uv=False)
                     tol = base + scale * sv[0] / sv[-1] * rho / np.linalg.norm(bS)
                     d = np.linalg.norm(G @ (yg[i] - yo)) / np.linalg.norm(bS)

@@ -51,6 +51,32 @@ def test_full_residual(ref):
     np.testing.assert_allclose(res.cpu().numpy(), want, rtol=1e-10, atol=1e-14)
 
 
+def test_delta_residual_matches_oracle(ref):
+    """subap_delta_residual (|A(p) Q (y1 - y2)| / |b| over all n rows, the
+    distance the benchmark holds reduced-precision forms to) against the
+    oracle's delta_res; a NaN coefficient vector gives NaN."""
+    import torch
+    name, w, off, M = ref
+    header(f"delta residual {name}")
+    fam, Q = off["family"], off["Q"]
+    P = w["test_params"]
+    rng = np.random.default_rng(4)
+    Y1 = On.solve(fam, Q, off["rows"], P)
+    Y2 = Y1 + 10.0 ** rng.uniform(-9, -2, size=(len(P), 1)) * rng.standard_normal(Y1.shape)
+    Y2[3] = Y1[3]  # identical coefficients: exactly 0
+    res = torch.empty(len(P), dtype=torch.float64, device="cuda")
+    B.subap_delta_residual(M.handle, to_dev(P), to_dev(Y1), to_dev(Y2), res)
+    torch.cuda.synchronize()
+    want = np.array([On.delta_res(fam, Q, p, a, b) for p, a, b in zip(P, Y1, Y2)])
+    got = res.cpu().numpy()
+    assert got[3] == 0.0
+    np.testing.assert_allclose(got, want, rtol=1e-10, atol=1e-15)
+    Y2[5] = np.nan
+    B.subap_delta_residual(M.handle, to_dev(P), to_dev(Y1), to_dev(Y2), res)
+    torch.cuda.synchronize()
+    assert np.isnan(res.cpu().numpy()[5])
+
+
 def test_apsnap_matches_least_squares(ref):
     import torch
     name, w, off, M = ref

@@ -164,3 +164,46 @@ def test_checkers_against_a_dense_kernel_matrix():
     res = (A @ (Q @ y1) - rhs)[rows]
     want_s = np.linalg.norm(res) / np.linalg.norm(rhs[rows])
     assert abs(On.sketched_residual(fam, Q, rows, np.array([sig]), y1) - want_s) <= 1e-13 * want_s
+
+
+def test_delta_res_params_against_dense_kernel_matrices():
+    """The many-parameter form (one pass over the kernel rows for all length
+    scales, row blocks smaller than n) against dense matrices assembled entry
+    by entry, and against the per-parameter delta_res."""
+    rng = np.random.default_rng(16)
+    n, dim, lam = 23, 2, 1e-2
+    pts = rng.standard_normal((n, dim))
+    rhs = rng.standard_normal(n)
+    fam = F.KernelRidge(pts, rhs, lam)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, 5)))
+    sigs = np.array([[0.3], [1.0], [2.5]])
+    Y1, Y2 = rng.standard_normal((3, 5)), rng.standard_normal((3, 5))
+    got = On.delta_res_params(fam, Q, sigs, Y1, Y2)
+    for i, sig in enumerate(sigs[:, 0]):
+        K = np.empty((n, n))
+        for a in range(n):
+            for b in range(n):
+                K[a, b] = math.exp(-sum((pts[a, q] - pts[b, q]) ** 2 for q in range(dim)) / (2 * sig * sig))
+        want = np.linalg.norm((K + lam * np.eye(n)) @ (Q @ (Y1[i] - Y2[i]))) / np.linalg.norm(rhs)
+        assert abs(got[i] - want) <= 1e-13 * want
+        assert abs(got[i] - On.delta_res(fam, Q, sigs[i], Y1[i], Y2[i])) <= 1e-13 * want
+    V = fam.matvec_params(sigs, np.stack([Q @ Y1[i] for i in range(3)], axis=1), chunk=7)
+    for i in range(3):
+        assert np.allclose(V[:, i], fam.matvec(sigs[i], Q @ Y1[i]), rtol=1e-14, atol=1e-14)
+
+
+def test_delta_res_params_without_a_batched_operator():
+    """Families without matvec_params fall back to delta_res per parameter:
+    closed form on the tridiagonal eigenbasis for two shifts."""
+    n = 40
+    fam = F.ShiftedTridiag(np.zeros(n))  # b = 1 for every p
+    ks = [1, 4, 9]
+    Q = _sine_basis(n, ks)
+    lam0 = np.array([2.0 - 2.0 * math.cos(k * math.pi / (n + 1)) for k in ks])
+    P = np.array([[0.5], [-1.5]])
+    Y1 = np.array([[1.0, -2.0, 0.5], [0.3, 0.0, 1.0]])
+    Y2 = np.zeros_like(Y1)
+    got = On.delta_res_params(fam, Q, P, Y1, Y2)
+    for i, p in enumerate(P[:, 0]):
+        want = np.linalg.norm((lam0 - p) * Y1[i]) / math.sqrt(n)
+        assert abs(got[i] - want) <= 1e-12 * want
