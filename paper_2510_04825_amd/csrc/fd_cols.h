@@ -391,4 +391,163 @@ __device__ void cols_solve(const ColsModel& M, const double* params, int prec, i
 }
 
 
+// ---------------------------------------------------------------------------
+// Four parameters per wavefront for r <= 15 (FP64, no refinement): lane l
+// serves parameter l / 16 of the wave with local lane c = l % 16 in the role
+// that lane c has above (column c < r, S b at c = r).  A 16-lane group is one
+// DPP row, so the pivot's values reach its group with one row_newbcast move
+// per 32-bit half; the reflector loop is unrolled so that the pivot index is
+// a constant of the instruction.  Each group has its own LDS region (R, the
+// block's term coefficients, y) and writes only its own parameter.
+// ---------------------------------------------------------------------------
+template <int J>
+__device__ __forceinline__ double row_bcast(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x150 + J, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x150 + J, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+constexpr int kPackLanes = 16;  // lanes per parameter
+constexpr int kPackMaxR = kPackLanes - 1;
+
+// one reflector step of the packed solver (pivot column J of this block)
+template <int J, int RB>
+__device__ __forceinline__ void packed_step(double* R, int r1, int c, bool col, double (&B)[RB], double& ss,
+                                            double& ss_ref, bool last, double& r00, bool& full_rank) {
+  const int rowj = cols_row(J, r1);
+  const double alpha = (col && c >= J) ? R[rowj + (c - J)] : 0.0;
+  double dd = 0.0, coef = 0.0, beta = alpha;
+  if (ss > 0.0) {
+    const double nrm = sqrt(alpha * alpha + ss);
+    beta = (alpha >= 0.0) ? -nrm : nrm;
+    dd = alpha - beta;
+    coef = -1.0 / (beta * dd);
+  }
+  if (c == J) R[rowj] = beta;
+  const double dj = row_bcast<J>(dd);
+  const double cj = row_bcast<J>(coef);
+  const double betaj = row_bcast<J>(beta);
+  const double ssj = row_bcast<J>(ss);
+  double vj[RB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i) vj[i] = row_bcast<J>(B[i]);
+  if (c > J && col) {
+    double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+#pragma unroll
+    for (int i = 0; i < RB; i += 4) {
+      w0 = fma(vj[i], B[i], w0);
+      w1 = fma(vj[i + 1], B[i + 1], w1);
+      w2 = fma(vj[i + 2], B[i + 2], w2);
+      w3 = fma(vj[i + 3], B[i + 3], w3);
+    }
+    const double dot = (w0 + w1) + (w2 + w3);
+    const double t = cj * fma(dj, alpha, dot);
+    R[rowj + (c - J)] = fma(-t, dj, alpha);
+#pragma unroll
+    for (int i = 0; i < RB; ++i) B[i] = fma(-t, vj[i], B[i]);
+    const double down = fma(t * t, ssj, fma(-2.0 * t, dot, ss));
+    if (down >= 0.25 * ss_ref) {
+      ss = down;
+    } else {
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int i = 0; i < RB; i += 2) {
+        s0 = fma(B[i], B[i], s0);
+        s1 = fma(B[i + 1], B[i + 1], s1);
+      }
+      ss = s0 + s1;
+      ss_ref = ss;
+    }
+  }
+  if (last) {
+    const double ab = fabs(betaj);
+    if (J == 0) r00 = ab;
+    if (!(ab > kRankTol * r00)) full_rank = false;
+  }
+}
+
+template <int J, int RB>
+__device__ __forceinline__ void packed_steps(int r, double* R, int r1, int c, bool col, double (&B)[RB], double& ss,
+                                             double& ss_ref, bool last, double& r00, bool& full_rank) {
+  if constexpr (J < kPackMaxR) {
+    if (J < r) {
+      packed_step<J, RB>(R, r1, c, col, B, ss, ss_ref, last, r00, full_rank);
+      packed_steps<J + 1, RB>(r, R, r1, c, col, B, ss, ss_ref, last, r00, full_rank);
+    }
+  }
+}
+
+// One parameter per 16-lane group.  params: this group's parameter (or
+// nullptr for a group past the end of the batch, which computes on zeros and
+// writes nothing); lds: this group's region of cols_lds_doubles(r, s, false, RB).
+template <int F, int DP, int COEF, int RB>
+__device__ void cols_solve_packed(const ColsModel& M, const double* params, double* lds, int lane, double* y_out,
+                                  double* rho_out, int32_t* status_out) {
+  static_assert(RB % 4 == 0, "the dot products run four rows at a time");
+  constexpr int L = kPackLanes;
+  const int c = lane % L;
+  const int r = M.r, s = M.s, r1 = r + 1;
+  double* R = lds;
+  double* a = R + r1 * (r1 + 1) / 2;
+  double* yv = a + RB * 6;
+  const bool col = c <= r;
+  double pv[DP];
+  bool finite = true;
+#pragma unroll
+  for (int q = 0; q < DP; ++q) {
+    pv[q] = params ? params[q] : 0.0;
+    finite = finite && isfinite(pv[q]);
+  }
+  for (int idx = c; idx < r1 * (r1 + 1) / 2; idx += L) R[idx] = 0.0;
+  double rho2 = 0.0, r00 = 0.0, bn2 = 0.0;
+  bool full_rank = true;
+  for (int k0 = 0; k0 < s; k0 += RB) {
+    for (int idx = c; idx < RB * F; idx += L) {
+      const int i = idx / F, f = idx % F;
+      a[idx] = (k0 + i < s) ? cols_coef<F, DP, COEF>(M, pv, f, k0 + i) : 0.0;
+    }
+    wave_sync_lds();
+    double B[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const int k = k0 + i;
+      double t = 0.0;
+      if (k < s && c < r) {
+#pragma unroll
+        for (int f = 0; f < F; ++f) t = fma(a[i * F + f], M.d64T[(static_cast<int64_t>(f) * s + k) * r + c], t);
+      }
+      const double bk = k < s ? cols_rhs<COEF>(M, pv, k) : 0.0;
+      if constexpr (coef_rhs_varies<COEF>()) bn2 = fma(bk, bk, bn2);
+      B[i] = (c == r) ? bk : t;
+    }
+    double ss = 0.0;
+#pragma unroll
+    for (int i = 0; i < RB; ++i) ss = fma(B[i], B[i], ss);
+    double ss_ref = ss;
+    const bool last = k0 + RB >= s;
+    packed_steps<0, RB>(r, R, r1, c, col, B, ss, ss_ref, last, r00, full_rank);
+    if (c == r) rho2 += ss;  // the b column's part outside the range of the first r columns
+    wave_sync_lds();  // the next block's term coefficients overwrite a
+  }
+  for (int j = c; j < r; j += L) yv[j] = R[cols_row(j, r1) + (r - j)];
+  wave_sync_lds();
+  cols_back_solve(R, r1, r, yv);
+  const double yc = c < r ? yv[c] : 0.0;
+  // lanes of this group holding a non-finite coefficient
+  const uint64_t bad = __ballot(c < r && !isfinite(yc));
+  const bool yfin = ((bad >> (lane - c)) & 0xffffull) == 0;
+  int32_t code = SUBAP_OK;
+  if (!finite) code = SUBAP_E_NONFINITE;
+  else if (!full_rank) code = SUBAP_E_RANK;
+  else if (!yfin) code = SUBAP_E_NONFINITE;
+  if (params) {
+    if (c < r) y_out[c] = (code == SUBAP_OK) ? yc : __longlong_as_double(0x7ff8000000000000LL);
+    if (c == r) {
+      if (rho_out) *rho_out = sqrt(rho2) / (coef_rhs_varies<COEF>() ? sqrt(bn2) : M.bS_norm);
+      if (status_out) *status_out = code;
+    }
+  }
+  wave_sync_lds();
+}
+
 }  // namespace subap

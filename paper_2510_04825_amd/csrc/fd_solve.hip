@@ -188,6 +188,21 @@ __global__ __launch_bounds__(128, REF ? 1 : (BRED ? 2 : 4)) void k_fd_cols(FDArg
                           lane, A.y + p * A.r, A.rho ? A.rho + p : nullptr, A.status ? A.status + p : nullptr);
 }
 
+// Column-per-lane solve with four parameters per wavefront (r <= 15, FP64
+// without refinement, fd_cols.h): eight parameters per block of two waves.
+template <int F, int DP, int COEF, int RB>
+__global__ __launch_bounds__(128, 2) void k_fd_cols_packed(FDArgs A, int ldsw) {
+  extern __shared__ double lds_cols[];
+  const int grp = threadIdx.x / kPackLanes, lane = threadIdx.x % 64;
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * (128 / kPackLanes) + grp;
+  const bool in = p < A.m;
+  const ColsModel M{A.r, A.s, A.phi, A.delta64T, A.delta32T, A.bS, A.inv_h2, A.bS_norm, A.aff_c0, A.aff_tau,
+                    A.wS, A.rowdat};
+  cols_solve_packed<F, DP, COEF, RB>(M, in ? A.params + p * DP : nullptr, lds_cols + static_cast<int64_t>(grp) * ldsw,
+                                     lane, in ? A.y + p * A.r : nullptr, (in && A.rho) ? A.rho + p : nullptr,
+                                     (in && A.status) ? A.status + p : nullptr);
+}
+
 // Sketched residual S(A(p) Q y - b) of given coefficients, FP64: one
 // wavefront per parameter, lanes over the selected rows.
 template <int F, int DP, int COEF>
@@ -253,8 +268,17 @@ subap_status launch_cols(const FDArgs& a, hipStream_t st) {
   const bool ref = a.refine > 0 || a.prec != SUBAP_FP64;
   const bool own_rb = !ref && a.r < 64;
   const int ldsw = cols_lds_doubles(a.r, a.s, ref, own_rb ? RB : kColsRB);
-  const size_t lds = sizeof(double) * 2 * static_cast<size_t>(ldsw);
   ProfScope prof("fd_solve", st);
+  if (!ref && a.r <= kPackMaxR) {  // four parameters per wavefront
+    constexpr int per_block = 128 / kPackLanes;
+    const int64_t nbp = (a.m + per_block - 1) / per_block;
+    const size_t ldsp = sizeof(double) * per_block * static_cast<size_t>(ldsw);
+    hipLaunchKernelGGL((k_fd_cols_packed<F, DP, COEF, RB>), dim3(static_cast<unsigned>(nbp)), dim3(128), ldsp, st, a,
+                       ldsw);
+    SUBAP_HIP_TRY(hipGetLastError());
+    return SUBAP_OK;
+  }
+  const size_t lds = sizeof(double) * 2 * static_cast<size_t>(ldsw);
   const dim3 grid(static_cast<unsigned>(nb)), block(128);
   if (a.r == 64) {
     if (ref) hipLaunchKernelGGL((k_fd_cols<F, DP, true, true, COEF>), grid, block, lds, st, a, ldsw);

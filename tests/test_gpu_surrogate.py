@@ -44,6 +44,47 @@ def test_gradient_matches_oracle():
         B.subap_surrogate_free(s)
 
 
+def test_prediction_matches_oracle_forward():
+    """subap_surrogate_predict element by element against the FP64 forward pass
+    of oracle.mlp with the same weights (before training the standardisation
+    is the identity, after it the prediction is destandardised with the
+    training mean and deviation).  Bar per entry: 2^-6 (|y_oracle| + rms(y_oracle)):
+    the hidden layers multiply bf16-rounded operands (2^-9 relative each) and
+    the output layer's split product keeps its own error near FP32, so the
+    error is that of two bf16 layers, a few times 2^-9 of the activations'
+    scale."""
+    import torch
+    header("surrogate prediction vs oracle forward")
+    device()
+    params = si.mlp_init(WIDTHS, seed=14)
+    rng = np.random.default_rng(6)
+    P = rng.uniform(-1, 1, (777, 4))   # a ragged count of parameters
+    s = B.subap_surrogate_create(4, 40, 256, B.flatten_mlp(params))
+    try:
+        y = torch.empty((777, 40), dtype=torch.float64, device="cuda")
+        B.subap_surrogate_predict(s, to_dev(P), y)
+        want, _ = mlp.forward(params, P)
+        err = np.abs(y.cpu().numpy() - want)
+        scale = np.abs(want) + np.sqrt(np.mean(want ** 2))
+        print("max error / scale", (err / scale).max())
+        assert (err <= 2.0 ** -6 * scale).all(), (err / scale).max()
+        # after training: destandardised with the training statistics
+        Ptr = rng.uniform(-1, 1, (512, 4))
+        Ytr = rng.standard_normal((512, 40)) * 5.0 + 2.0
+        B.subap_surrogate_train(s, to_dev(Ptr), to_dev(Ytr), epochs=1, batch=512, lr=1e-3, lr_min=1e-3)
+        trained = _layers(B.subap_surrogate_weights(s))
+        mu, sd = mlp.standardise(Ytr)
+        B.subap_surrogate_predict(s, to_dev(P), y)
+        out, _ = mlp.forward([(W.astype(np.float64), b.astype(np.float64)) for W, b in trained], P)
+        want = out * sd + mu
+        err = np.abs(y.cpu().numpy() - want)
+        scale = np.abs(out) * sd + np.sqrt(np.mean(out ** 2)) * sd
+        print("trained: max error / scale", (err / scale).max())
+        assert (err <= 2.0 ** -6 * scale).all(), (err / scale).max()
+    finally:
+        B.subap_surrogate_free(s)
+
+
 def test_first_adam_step_matches_oracle():
     header("surrogate adam step")
     device()
