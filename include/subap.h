@@ -233,6 +233,26 @@ SUBAP_API subap_status subap_solve_batch(subap_model model, const double* params
                                const subap_solve_opts* opts, void* hip_stream);
 
 /*
+ * subap_solve_batch_noalloc -- subap_solve_batch without any device
+ * allocation, for callers that cannot allocate: code under HIP graph
+ * capture, serving loops that must not call hipMalloc, harnesses that
+ * forbid it.  Same arguments, layouts, statuses and results (bitwise) as
+ * subap_solve_batch.  The finite-difference and delay solves need no
+ * workspace.  The kernel ridge solve takes its workspace from a fixed 64 MiB
+ * device array inside the library (one per GPU, held until the process
+ * ends) and solves a batch larger than fits in consecutive chunks (about 650
+ * parameters per chunk at n = 16384, r = 32, s = 128 with a split contraction
+ * and one CSNE step).  Every call on one GPU shares that array: calls that
+ * overlap on one GPU (two streams, two threads) race and give undefined
+ * results.  SUBAP_E_UNSUPPORTED if a single block of 16 parameters would need
+ * more than 64 MiB (not reachable with r <= 64, s <= 256).  Asynchronous on
+ * hip_stream; the model must be on the current device.
+ */
+SUBAP_API subap_status subap_solve_batch_noalloc(subap_model model, const double* params_dev, int64_t m,
+                                                 double* y_dev, double* rho_dev, int32_t* status_dev,
+                                                 const subap_solve_opts* opts, void* hip_stream);
+
+/*
  * subap_lift -- x = Q y (Algorithm 3.1 step 4, output X c) for k coefficient
  * vectors.
  *   y_dev      device k x r row-major FP64.

@@ -38,7 +38,7 @@ EXPORTS = ("subap_offline", "subap_solve_batch", "subap_lift", "subap_sketched_r
            "subap_surrogate_nparams", "subap_profile_count", "subap_status_string", "subap_last_error",
            "subap_model_weights", "subap_residual_bounds", "subap_output", "subap_full_residual",
            "subap_apsnap_solve", "subap_polish", "subap_model_save", "subap_model_load",
-           "subap_delta_residual")
+           "subap_delta_residual", "subap_solve_batch_noalloc")
 PLAN_GRAPH, PLAN_AUTOTUNE = 1, 2
 # subap_selection
 SELECT_CPQR, SELECT_LEVERAGE, SELECT_LU = 0, 1, 2
@@ -87,6 +87,7 @@ def load(path: str = LIB_PATH):
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     lib.subap_offline.argtypes = [C.POINTER(ProblemDesc), C.POINTER(OfflineOpts), vp, C.POINTER(vp)]
     lib.subap_solve_batch.argtypes = [vp, vp, i64, vp, vp, vp, C.POINTER(SolveOpts), vp]
+    lib.subap_solve_batch_noalloc.argtypes = [vp, vp, i64, vp, vp, vp, C.POINTER(SolveOpts), vp]
     lib.subap_lift.argtypes = [vp, vp, i64, vp, i64, i32, vp]
     lib.subap_sketched_residual.argtypes = [vp, vp, i64, vp, vp, vp, vp]
     lib.subap_profile_enable.argtypes = [i32]
@@ -208,6 +209,23 @@ def subap_solve_batch(model, params, y, rho=None, status=None, contraction=FP64,
     opts = SolveOpts(int(contraction), int(refine_steps), int(bool(csne)))
     _check(lib.subap_solve_batch(C.c_void_p(model), _ptr(params), m, _ptr(y), _ptr(rho), _ptr(status),
                                  C.byref(opts), _stream(stream)))
+
+
+def subap_solve_batch_noalloc(model, params, y, rho=None, status=None, contraction=FP64, refine_steps=0,
+                              stream=None, csne=False):
+    """subap_solve_batch with the library's fixed device scratch instead of allocations."""
+    lib = load()
+    m = params.shape[0]
+    _, r, _, d = subap_model_dims(model)
+    _expect(params, (m, d), "float64", "params")
+    _expect(y, (m, r), "float64", "y")
+    if rho is not None:
+        _expect(rho, (m,), "float64", "rho")
+    if status is not None:
+        _expect(status, (m,), "int32", "status")
+    opts = SolveOpts(int(contraction), int(refine_steps), int(bool(csne)))
+    _check(lib.subap_solve_batch_noalloc(C.c_void_p(model), _ptr(params), m, _ptr(y), _ptr(rho), _ptr(status),
+                                         C.byref(opts), _stream(stream)))
 
 
 def subap_lift(model, y, x, precision=FP64, stream=None):

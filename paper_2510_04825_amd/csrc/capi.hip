@@ -334,6 +334,83 @@ subap_status subap_solve_batch(subap_model M, const double* params, int64_t m, d
   }
 }
 
+// ---------------------------------------------------------------------------
+// subap_solve_batch_noalloc: the same solve with its device workspace in a
+// file-scope array instead of a library allocation.  The array exists once
+// per GPU the library runs on (the loader places it with the code object);
+// host code reaches it only through the address hipGetSymbolAddress returns
+// for the current device, taken on the first call there and kept.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+subap_status scratch_on_current_device(void** out) {
+  int dev = 0;
+  SUBAP_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device index out of the scratch table's range");
+    return SUBAP_E_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    SUBAP_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SUBAP_OK;
+}
+
+}  // namespace
+
+subap_status subap_solve_batch_noalloc(subap_model M, const double* params, int64_t m, double* y, double* rho,
+                                       int32_t* status, const subap_solve_opts* opts, void* hip_stream) {
+  try {
+    clear_error();
+    if (!M) return invalid("model must not be NULL");
+    if (m < 0) return invalid("m must be >= 0");
+    if (m == 0) return SUBAP_OK;
+    if (!params || !y) return invalid("params and y must not be NULL");
+    const int prec = opts ? opts->contraction : SUBAP_FP64;
+    const int refine = opts ? opts->refine_steps : 0;
+    const int csne = opts ? opts->refine_csne : 0;
+    if (prec < SUBAP_FP64 || prec > SUBAP_FP16X3) return invalid("unknown contraction precision");
+    if (refine < 0 || refine > 4) return invalid("refine_steps must be in [0, 4]");
+    if (csne != 0 && csne != 1) return invalid("refine_csne must be 0 or 1");
+    if (m > (int64_t(1) << 31) / 64) return invalid("m too large for one call");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (M->family != SUBAP_FAMILY_KRR) {
+      // the finite-difference and delay solves keep everything in registers
+      // and LDS: no device workspace
+      if (prec == SUBAP_BF16X3 || prec == SUBAP_FP16X3) {
+        set_error("the split 16-bit contractions are implemented for the kernel family only");
+        return SUBAP_E_UNSUPPORTED;
+      }
+      return fd_solve(M, params, m, y, rho, status, prec, refine, csne, st);
+    }
+    const int64_t chunk = krr_chunk(M, prec, refine, csne != 0, kScratchBytes);
+    if (chunk < 1) {
+      set_error("one block of parameters needs more workspace than the 64 MiB scratch");
+      return SUBAP_E_UNSUPPORTED;
+    }
+    void* ws = nullptr;
+    SUBAP_TRY(scratch_on_current_device(&ws));
+    for (int64_t c0 = 0; c0 < m; c0 += chunk) {
+      const int64_t cnt = std::min(chunk, m - c0);
+      SUBAP_TRY(krr_solve_ws(M, params + c0 * M->d, cnt, y + c0 * M->r, rho ? rho + c0 : nullptr,
+                             status ? status + c0 : nullptr, prec, refine, csne != 0, ws, st));
+    }
+    return SUBAP_OK;
+  } catch (...) {
+    return host_exception();
+  }
+}
+
 subap_status subap_lift(subap_model M, const double* y, int64_t k, void* x, int64_t ldx, int32_t precision,
                         void* hip_stream) {
   try {
