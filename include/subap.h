@@ -286,6 +286,29 @@ SUBAP_API subap_status subap_sketched_residual(subap_model model, const double* 
                                                void* hip_stream);
 
 /*
+ * subap_excess_bound -- an a posteriori bound on how far given coefficients
+ * are from the SubApSnap solution, without solving: with G = S A(p) Q
+ * (weighted rows for leverage-score models) and r_S = G y - S b,
+ *   out[k] = |G^T r_S| / (sigma_min |S b|)
+ * (|S b| as in the sketched residual).  Since G^T r_S = G^T G (y - y*),
+ * out[k] >= |G (y_k - y*_k)| / |S b| whenever sigma_min <= sigma_min(G_k): the
+ * normal-equation excess over the method's own residual floor, which the
+ * sketched residual |r_S| alone cannot show (its minimum is that floor,
+ * Section 5.3.1).  Evaluated in FP64 from the generated rows: an s x n
+ * matrix-vector product and its adjoint (kernel family) or the face tables
+ * (stencil families); no contraction of S A(p) Q with Q is formed for the
+ * kernel family.  sigma_min is the caller's (e.g. a fraction of the smallest
+ * sigma_min(G) over training parameters, from subap_reduced_matrix).
+ *   y_dev device m x r; out_dev device m.  Asynchronous.
+ * subap_reduced_matrix -- G_k = S A(p_k) Q in FP64, device m x s x r (row k of
+ * G_k at G_dev + (k_param s + k) r), for calibration and analysis.
+ */
+SUBAP_API subap_status subap_excess_bound(subap_model model, const double* params_dev, int64_t m, const double* y_dev,
+                                          double sigma_min, double* out_dev, void* hip_stream);
+SUBAP_API subap_status subap_reduced_matrix(subap_model model, const double* params_dev, int64_t m, double* G_dev,
+                                            void* hip_stream);
+
+/*
  * Batched solve over many models in one persistent launch (finite-difference
  * families).  A plan fixes the models, the parameter counts and the device
  * buffers; executing it runs Algorithm 3.1 step 4 for every parameter of
@@ -375,6 +398,21 @@ SUBAP_API subap_status subap_surrogate_solve_batch(subap_model model, subap_surr
                                                    uint8_t* accepted_dev, int32_t* status_dev,
                                                    const subap_solve_opts* fallback_opts, int64_t* n_accepted,
                                                    void* hip_stream);
+/*
+ * As subap_surrogate_solve_batch, with the normal-equation excess bound of
+ * subap_excess_bound (sigma_min > 0, finite) as the acceptance measure: a
+ * prediction is accepted when |G^T r_S| / (sigma_min |S b|) <= accept_tol,
+ * which, for sigma_min <= sigma_min(S A(p) Q), guarantees
+ * |S A(p) Q (y - y*)| / |S b| <= accept_tol for the SubApSnap solution y*
+ * (Section 5.3.1 takes the sketched residual as an estimate of the full one;
+ * the bound measures the distance to y* itself, which the sketched residual
+ * cannot show below its own floor).  Blocking.
+ */
+SUBAP_API subap_status subap_surrogate_solve_batch_excess(subap_model model, subap_surrogate s,
+                                                          const double* params_dev, int64_t m, double sigma_min,
+                                                          double accept_tol, double* y_dev, uint8_t* accepted_dev,
+                                                          int32_t* status_dev, const subap_solve_opts* fallback_opts,
+                                                          int64_t* n_accepted, void* hip_stream);
 SUBAP_API subap_status subap_surrogate_free(subap_surrogate s);
 
 /*

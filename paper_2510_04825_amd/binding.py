@@ -38,7 +38,8 @@ EXPORTS = ("subap_offline", "subap_solve_batch", "subap_lift", "subap_sketched_r
            "subap_surrogate_nparams", "subap_profile_count", "subap_status_string", "subap_last_error",
            "subap_model_weights", "subap_residual_bounds", "subap_output", "subap_full_residual",
            "subap_apsnap_solve", "subap_polish", "subap_model_save", "subap_model_load",
-           "subap_delta_residual", "subap_solve_batch_noalloc")
+           "subap_delta_residual", "subap_solve_batch_noalloc", "subap_excess_bound", "subap_reduced_matrix",
+           "subap_surrogate_solve_batch_excess")
 PLAN_GRAPH, PLAN_AUTOTUNE = 1, 2
 # subap_selection
 SELECT_CPQR, SELECT_LEVERAGE, SELECT_LU = 0, 1, 2
@@ -103,6 +104,8 @@ def load(path: str = LIB_PATH):
     lib.subap_output.argtypes = [vp, vp, i64, vp, vp]
     lib.subap_full_residual.argtypes = [vp, vp, i64, vp, vp, vp]
     lib.subap_delta_residual.argtypes = [vp, vp, i64, vp, vp, vp, vp]
+    lib.subap_excess_bound.argtypes = [vp, vp, i64, vp, C.c_double, vp, vp]
+    lib.subap_reduced_matrix.argtypes = [vp, vp, i64, vp, vp]
     lib.subap_apsnap_solve.argtypes = [vp, vp, i64, vp, vp, vp]
     lib.subap_polish.argtypes = [vp, vp, i64, vp, i32, C.c_double, vp, vp]
     lib.subap_residual_bounds.argtypes = [vp, vp, i64, C.c_double, vp, vp, vp]
@@ -125,6 +128,8 @@ def load(path: str = LIB_PATH):
     lib.subap_surrogate_predict.argtypes = [vp, vp, i64, vp, vp]
     lib.subap_surrogate_solve_batch.argtypes = [vp, vp, vp, i64, C.c_double, vp, vp, vp, C.POINTER(SolveOpts),
                                                 C.POINTER(i64), vp]
+    lib.subap_surrogate_solve_batch_excess.argtypes = [vp, vp, vp, i64, C.c_double, C.c_double, vp, vp, vp,
+                                                       C.POINTER(SolveOpts), C.POINTER(i64), vp]
     lib.subap_surrogate_free.argtypes = [vp]
     for name in EXPORTS[:23]:
         getattr(lib, name).restype = C.c_int
@@ -411,6 +416,25 @@ def subap_surrogate_solve_batch(model, s, params, accept_tol, y, accepted=None, 
     return n.value
 
 
+def subap_surrogate_solve_batch_excess(model, s, params, sigma_min, accept_tol, y, accepted=None, status=None,
+                                       contraction=FP64, refine_steps=0, stream=None, csne=False):
+    """Acceptance by the normal-equation excess bound; returns the number of accepted predictions."""
+    _, r, _, d = subap_model_dims(model)
+    m = params.shape[0]
+    _expect(params, (m, d), "float64", "params")
+    _expect(y, (m, r), "float64", "y")
+    if accepted is not None:
+        _expect(accepted, (m,), "uint8", "accepted")
+    if status is not None:
+        _expect(status, (m,), "int32", "status")
+    opts = SolveOpts(int(contraction), int(refine_steps), int(bool(csne)))
+    n = C.c_int64()
+    _check(load().subap_surrogate_solve_batch_excess(C.c_void_p(model), C.c_void_p(s), _ptr(params), m,
+                                                     float(sigma_min), float(accept_tol), _ptr(y), _ptr(accepted),
+                                                     _ptr(status), C.byref(opts), C.byref(n), _stream(stream)))
+    return n.value
+
+
 def subap_surrogate_free(s):
     _check(load().subap_surrogate_free(C.c_void_p(s)))
 
@@ -450,6 +474,26 @@ def subap_delta_residual(model, params, y1, y2, res, stream=None):
     _expect(res, (m,), "float64", "res")
     _check(load().subap_delta_residual(C.c_void_p(model), _ptr(params), m, _ptr(y1), _ptr(y2), _ptr(res),
                                        _stream(stream)))
+
+
+def subap_excess_bound(model, params, y, sigma_min, out, stream=None):
+    """|G^T (G y - S b)| / (sigma_min |S b|) per parameter: params (m, d), y (m, r), out (m,)."""
+    _, r, _, d = subap_model_dims(model)
+    m = params.shape[0]
+    _expect(params, (m, d), "float64", "params")
+    _expect(y, (m, r), "float64", "y")
+    _expect(out, (m,), "float64", "out")
+    _check(load().subap_excess_bound(C.c_void_p(model), _ptr(params), m, _ptr(y), float(sigma_min), _ptr(out),
+                                     _stream(stream)))
+
+
+def subap_reduced_matrix(model, params, G, stream=None):
+    """G_k = S A(p_k) Q in FP64: params (m, d), G (m, s, r)."""
+    _, r, s, d = subap_model_dims(model)
+    m = params.shape[0]
+    _expect(params, (m, d), "float64", "params")
+    _expect(G, (m, s, r), "float64", "G")
+    _check(load().subap_reduced_matrix(C.c_void_p(model), _ptr(params), m, _ptr(G), _stream(stream)))
 
 
 def subap_apsnap_solve(model, params, y, rho=None, stream=None):

@@ -755,6 +755,40 @@ subap_status subap_sketched_residual(subap_model M, const double* params, int64_
   }
 }
 
+subap_status subap_excess_bound(subap_model M, const double* params, int64_t m, const double* y, double sigma_min,
+                                double* out, void* hip_stream) {
+  try {
+    clear_error();
+    if (!M) return invalid("model must not be NULL");
+    if (m < 0) return invalid("m must be >= 0");
+    if (!(sigma_min > 0.0) || !std::isfinite(sigma_min)) return invalid("sigma_min must be finite and > 0");
+    if (m == 0) return SUBAP_OK;
+    if (!params || !y || !out) return invalid("params, y and out must not be NULL");
+    if (m > (int64_t(1) << 31) / 64) return invalid("m too large for one call");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (M->family == SUBAP_FAMILY_KRR) return krr_excess(M, params, m, y, sigma_min, out, st);
+    return fd_excess(M, params, m, y, sigma_min, out, st);
+  } catch (...) {
+    return host_exception();
+  }
+}
+
+subap_status subap_reduced_matrix(subap_model M, const double* params, int64_t m, double* G, void* hip_stream) {
+  try {
+    clear_error();
+    if (!M) return invalid("model must not be NULL");
+    if (m < 0) return invalid("m must be >= 0");
+    if (m == 0) return SUBAP_OK;
+    if (!params || !G) return invalid("params and G must not be NULL");
+    if (m > (int64_t(1) << 40) / (static_cast<int64_t>(M->s) * M->r)) return invalid("m too large for one call");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (M->family == SUBAP_FAMILY_KRR) return krr_reduced_matrix(M, params, m, G, st);
+    return fd_reduced_matrix(M, params, m, G, st);
+  } catch (...) {
+    return host_exception();
+  }
+}
+
 static subap_status plan_args(const subap_model* models, int32_t k, const double* const* params, const int64_t* m,
                               double* const* y, const subap_solve_opts* opts, int* prec, int* refine,
                               bool* csne) {
@@ -937,9 +971,10 @@ subap_status subap_surrogate_predict(subap_surrogate s, const double* P, int64_t
   }
 }
 
-subap_status subap_surrogate_solve_batch(subap_model M, subap_surrogate s, const double* P, int64_t m, double tol,
-                                         double* y, uint8_t* accepted, int32_t* status,
-                                         const subap_solve_opts* fb, int64_t* n_acc, void* hip_stream) {
+static subap_status surrogate_solve_checked(subap_model M, subap_surrogate s, const double* P, int64_t m,
+                                            double tol, double* y, uint8_t* accepted, int32_t* status,
+                                            const subap_solve_opts* fb, int64_t* n_acc, void* hip_stream,
+                                            double sigma_min) {
   try {
     clear_error();
     if (!M || !s || !s->impl || !n_acc) return invalid("model, surrogate and n_accepted must not be NULL");
@@ -964,10 +999,27 @@ subap_status subap_surrogate_solve_batch(subap_model M, subap_surrogate s, const
     }
     if (m > (int64_t(1) << 31) / 64) return invalid("m too large for one call");
     return surrogate_solve(M, s->impl, P, m, tol, y, accepted, status, prec, refine, csne != 0, n_acc,
-                           static_cast<hipStream_t>(hip_stream));
+                           static_cast<hipStream_t>(hip_stream), sigma_min);
   } catch (...) {
     return host_exception();
   }
+}
+
+subap_status subap_surrogate_solve_batch(subap_model M, subap_surrogate s, const double* P, int64_t m, double tol,
+                                         double* y, uint8_t* accepted, int32_t* status,
+                                         const subap_solve_opts* fb, int64_t* n_acc, void* hip_stream) {
+  return surrogate_solve_checked(M, s, P, m, tol, y, accepted, status, fb, n_acc, hip_stream, 0.0);
+}
+
+subap_status subap_surrogate_solve_batch_excess(subap_model M, subap_surrogate s, const double* P, int64_t m,
+                                                double sigma_min, double tol, double* y, uint8_t* accepted,
+                                                int32_t* status, const subap_solve_opts* fb, int64_t* n_acc,
+                                                void* hip_stream) {
+  if (!(sigma_min > 0.0) || !std::isfinite(sigma_min)) {
+    clear_error();
+    return invalid("sigma_min must be finite and > 0");
+  }
+  return surrogate_solve_checked(M, s, P, m, tol, y, accepted, status, fb, n_acc, hip_stream, sigma_min);
 }
 
 subap_status subap_surrogate_free(subap_surrogate s) {

@@ -142,6 +142,14 @@ subap_status fd_residual(subap_model_s* M, const double* params, int64_t m, cons
                          double* norm, hipStream_t st);
 subap_status krr_residual(subap_model_s* M, const double* params, int64_t m, const double* y, double* res,
                           double* norm, hipStream_t st);
+// normal-equation excess |G^T (G y - S b)| / (sigma_min |S b|) and the FP64
+// reduced matrix G = S A(p) Q (s x r row-major per parameter)
+subap_status fd_excess(subap_model_s* M, const double* params, int64_t m, const double* y, double sigma_min,
+                       double* out, hipStream_t st);
+subap_status krr_excess(subap_model_s* M, const double* params, int64_t m, const double* y, double sigma_min,
+                        double* out, hipStream_t st);
+subap_status fd_reduced_matrix(subap_model_s* M, const double* params, int64_t m, double* G, hipStream_t st);
+subap_status krr_reduced_matrix(subap_model_s* M, const double* params, int64_t m, double* G, hipStream_t st);
 
 subap_status ensure_work(subap_model_s* M, size_t bytes);
 
@@ -167,7 +175,7 @@ subap_status surrogate_train(Surrogate* S, const double* P, const double* Y, int
 subap_status surrogate_predict(Surrogate* S, const double* P, int64_t m, double* y, hipStream_t st);
 subap_status surrogate_solve(subap_model_s* M, Surrogate* S, const double* P, int64_t m, double tol, double* y,
                              uint8_t* accepted, int32_t* status, int prec, int refine, bool csne,
-                             int64_t* n_acc, hipStream_t st);
+                             int64_t* n_acc, hipStream_t st, double sigma_min = 0.0);
 
 }  // namespace subap
 

@@ -241,6 +241,80 @@ __global__ __launch_bounds__(256) void k_fd_resid(const double* params, int64_t 
   if (lane == 0 && norm) norm[p] = sqrt(ss) / (coef_rhs_varies<COEF>() ? sqrt(bb) : bS_norm);
 }
 
+// A posteriori bound on the distance of given coefficients to the SubApSnap
+// solution (the normal-equation excess): with G = S A(p) Q and r_S = G y - S b,
+// G^T r_S = G^T G (y - y*), so |G (y - y*)| <= |G^T r_S| / sigma_min(G).
+// out[p] = |G^T r_S| / (sigma_min |S b(p)|), FP64 from the generated rows: one
+// wavefront per parameter, first lanes over rows (r_S and the term
+// coefficients of every row into LDS), then lanes over columns.
+template <int F, int DP, int COEF>
+__global__ __launch_bounds__(128) void k_fd_excess(const double* params, int64_t m, int r, int s, const double* phi,
+                                                   const double* delta64, const double* delta64T, const double* bS,
+                                                   double inv_h2, double bS_norm, double aff_c0, double aff_tau,
+                                                   const double* wS, const double* rowdat, const double* y,
+                                                   double sigma_min, double* out) {
+  __shared__ double sh[2][kMaxS * (F + 1)];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * 2 + wave;
+  if (p >= m) return;  // uniform per wavefront; no block-level barrier follows
+  ColsModel CM{r, s, phi, nullptr, nullptr, bS, inv_h2, bS_norm, aff_c0, aff_tau, wS, rowdat};
+  double* rs = sh[wave];          // s residual entries
+  double* af = rs + kMaxS;        // s x F term coefficients
+  double pv[DP];
+  bool finite = true;
+  for (int q = 0; q < DP; ++q) {
+    pv[q] = params[p * DP + q];
+    finite = finite && isfinite(pv[q]);
+  }
+  double bb = 0.0;
+  for (int k = lane; k < s; k += 64) {
+    double t = 0.0;
+    for (int f = 0; f < F; ++f) {
+      const double a = cols_coef<F, DP, COEF>(CM, pv, f, k);
+      af[k * F + f] = a;
+      double u = 0.0;
+      for (int c = 0; c < r; ++c) u = fma(delta64[(f * r + c) * s + k], y[p * r + c], u);
+      t = fma(a, u, t);
+    }
+    const double bk = cols_rhs<COEF>(CM, pv, k);
+    rs[k] = t - bk;
+    bb = fma(bk, bk, bb);
+  }
+  wave_sync_lds();
+  double g = 0.0;
+  if (lane < r) {
+    for (int k = 0; k < s; ++k) {
+      double gk = 0.0;
+      for (int f = 0; f < F; ++f) gk = fma(af[k * F + f], delta64T[(static_cast<int64_t>(f) * s + k) * r + lane], gk);
+      g = fma(gk, rs[k], g);
+    }
+  }
+  const double gg = team_sum<64>(g * g);
+  if constexpr (coef_rhs_varies<COEF>()) bb = team_sum<64>(bb);
+  if (lane == 0) {
+    const double den = sigma_min * (coef_rhs_varies<COEF>() ? sqrt(bb) : bS_norm);
+    out[p] = finite ? sqrt(gg) / den : __longlong_as_double(0x7ff8000000000000LL);
+  }
+}
+
+// G = S A(p) Q in FP64 (s x r row-major per parameter) from the term tables.
+template <int F, int DP, int COEF>
+__global__ __launch_bounds__(256) void k_fd_gmat(const double* params, int64_t m, int r, int s, const double* phi,
+                                                 const double* delta64T, double inv_h2, double aff_c0, double aff_tau,
+                                                 double* G) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= m * s * r) return;
+  const int64_t p = e / (static_cast<int64_t>(s) * r);
+  const int k = static_cast<int>((e / r) % s), c = static_cast<int>(e % r);
+  ColsModel CM{r, s, phi, nullptr, nullptr, nullptr, inv_h2, 0.0, aff_c0, aff_tau};
+  double pv[DP];
+  for (int q = 0; q < DP; ++q) pv[q] = params[p * DP + q];
+  double t = 0.0;
+  for (int f = 0; f < F; ++f)
+    t = fma(cols_coef<F, DP, COEF>(CM, pv, f, k), delta64T[(static_cast<int64_t>(f) * s + k) * r + c], t);
+  G[e] = t;
+}
+
 template <int TEAM, int R, int RM, int F, int DP>
 subap_status launch(const FDArgs& a, hipStream_t st) {
   constexpr int TEAMS = 256 / TEAM;
@@ -345,6 +419,40 @@ subap_status fd_residual(subap_model_s* M, const double* params, int64_t m, cons
   else if (M->dimx == 2) SUBAP_RESID(4, 2, kCoefDiffusion);
   else SUBAP_RESID(6, 4, kCoefDiffusion);
 #undef SUBAP_RESID
+  SUBAP_HIP_TRY(hipGetLastError());
+  return SUBAP_OK;
+}
+
+subap_status fd_excess(subap_model_s* M, const double* params, int64_t m, const double* y, double sigma_min,
+                       double* out, hipStream_t st) {
+  const unsigned grid = static_cast<unsigned>((m + 1) / 2);
+  ProfScope prof("fd_excess", st);
+#define SUBAP_EXC(F_, DP_, COEF_)                                                                                  \
+  hipLaunchKernelGGL((k_fd_excess<F_, DP_, COEF_>), dim3(grid), dim3(128), 0, st, params, m, M->r, M->s, M->phi,   \
+                     M->delta64, M->delta64T, M->bS, M->inv_h2, M->bS_norm, M->aff_c0, M->tau, M->wS, M->rowdat, y, \
+                     sigma_min, out)
+  if (M->family == SUBAP_FAMILY_DELAY) SUBAP_EXC(2, 1, kCoefDelay);
+  else if (M->family == SUBAP_FAMILY_TRIDIAG_SHIFT) SUBAP_EXC(2, 1, kCoefTridiag);
+  else if (M->family == SUBAP_FAMILY_IDENTITY) SUBAP_EXC(1, 1, kCoefIdentity);
+  else if (M->dimx == 2) SUBAP_EXC(4, 2, kCoefDiffusion);
+  else SUBAP_EXC(6, 4, kCoefDiffusion);
+#undef SUBAP_EXC
+  SUBAP_HIP_TRY(hipGetLastError());
+  return SUBAP_OK;
+}
+
+subap_status fd_reduced_matrix(subap_model_s* M, const double* params, int64_t m, double* G, hipStream_t st) {
+  const int64_t len = m * M->s * M->r;
+  const unsigned grid = static_cast<unsigned>((len + 255) / 256);
+#define SUBAP_GM(F_, DP_, COEF_)                                                                                  \
+  hipLaunchKernelGGL((k_fd_gmat<F_, DP_, COEF_>), dim3(grid), dim3(256), 0, st, params, m, M->r, M->s, M->phi,    \
+                     M->delta64T, M->inv_h2, M->aff_c0, M->tau, G)
+  if (M->family == SUBAP_FAMILY_DELAY) SUBAP_GM(2, 1, kCoefDelay);
+  else if (M->family == SUBAP_FAMILY_TRIDIAG_SHIFT) SUBAP_GM(2, 1, kCoefTridiag);
+  else if (M->family == SUBAP_FAMILY_IDENTITY) SUBAP_GM(1, 1, kCoefIdentity);
+  else if (M->dimx == 2) SUBAP_GM(4, 2, kCoefDiffusion);
+  else SUBAP_GM(6, 4, kCoefDiffusion);
+#undef SUBAP_GM
   SUBAP_HIP_TRY(hipGetLastError());
   return SUBAP_OK;
 }

@@ -1130,4 +1130,81 @@ subap_status launch_refine_partial(subap_model_s* M, const double* params, int64
   return SUBAP_OK;
 }
 
+namespace {
+
+// |G^T r_S| / den from the adjoint partials (one thread per parameter)
+__global__ void k_excess_finish(const double* gpart, int64_t m, int r, double den, double* out) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= m) return;
+  double gg = 0.0;
+  for (int c = 0; c < r; ++c) {
+    double g = 0.0;
+    for (int sp = 0; sp < kRefSplit; ++sp) g += gpart[(static_cast<int64_t>(sp) * m + p) * r + c];
+    gg = fma(g, g, gg);
+  }
+  out[p] = sqrt(gg) / den;
+}
+
+// G[(p s + k) r + c] <- w_k G + lambda Q_S[k, c]: the FP64 contraction of the
+// kernel part plus the ridge, as the least-squares kernels form it
+__global__ void k_krr_gfinish(double* G, int64_t m, int r, int s, const double* wS, const double* QS,
+                              double lambda) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= m * s * r) return;
+  const int k = static_cast<int>((e / r) % s), c = static_cast<int>(e % r);
+  G[e] = fma(wS[k], G[e], lambda * QS[k * r + c]);
+}
+
+}  // namespace
+
+// Normal-equation excess |G^T (G y - S b)| / (sigma_min |S b|) in FP64: the
+// residual pass, the adjoint pass of the corrected semi-normal equations, and
+// the norm.
+subap_status krr_excess(subap_model_s* M, const double* params, int64_t m, const double* y, double sigma_min,
+                        double* out, hipStream_t st) {
+  const int r = M->r, s = M->s;
+  const size_t np = static_cast<size_t>(kRefSplit) * m * s, nr = static_cast<size_t>(m) * s,
+               na = static_cast<size_t>(kRefSplit) * m * r;
+  SUBAP_TRY(ensure_work(M, 8 * (np + nr + na)));
+  double* part = static_cast<double*>(M->work);
+  double* rvec = part + np;
+  double* gpart = rvec + nr;
+  SUBAP_TRY(launch_refine_partial(M, params, m, y, part, true, st));
+  {
+    ProfScope prof("krr_resid_finish", st);
+    hipLaunchKernelGGL(k_resid_finish, dim3(static_cast<unsigned>((m + 3) / 4)), dim3(256), 0, st, params, m, r, s,
+                       part, M->wS, M->QS, M->bS, M->lambda, M->bS_norm, y, rvec, nullptr);
+    SUBAP_HIP_TRY(hipGetLastError());
+  }
+  SUBAP_TRY(launch_adjoint(M, params, m, rvec, gpart, true, st));
+  hipLaunchKernelGGL(k_excess_finish, dim3(static_cast<unsigned>((m + 255) / 256)), dim3(256), 0, st, gpart, m, r,
+                     sigma_min * M->bS_norm, out);
+  SUBAP_HIP_TRY(hipGetLastError());
+  return SUBAP_OK;
+}
+
+// G = S A(p) Q in FP64 for m parameters (s x r row-major each)
+subap_status krr_reduced_matrix(subap_model_s* M, const double* params, int64_t m, double* G, hipStream_t st) {
+  const int r = M->r, s = M->s;
+  const int64_t n = M->n;
+  const int RM = rm_of(r);
+  {
+    ProfScope prof("krr_contract_fp64", st);
+    constexpr int KR = 2;
+    const dim3 grid(static_cast<unsigned>((m + 63) / 64), static_cast<unsigned>((s + 4 * KR - 1) / (4 * KR)));
+    switch (RM) {
+      case 8: hipLaunchKernelGGL((k_contract_f64<KR, 8>), grid, dim3(256), 0, st, params, m, n, r, s, M->Dt64, M->Qrm, G); break;
+      case 16: hipLaunchKernelGGL((k_contract_f64<KR, 16>), grid, dim3(256), 0, st, params, m, n, r, s, M->Dt64, M->Qrm, G); break;
+      case 32: hipLaunchKernelGGL((k_contract_f64<KR, 32>), grid, dim3(256), 0, st, params, m, n, r, s, M->Dt64, M->Qrm, G); break;
+      case 40: hipLaunchKernelGGL((k_contract_f64<1, 40>), dim3(grid.x, (s + 3) / 4), dim3(256), 0, st, params, m, n, r, s, M->Dt64, M->Qrm, G); break;
+      default: hipLaunchKernelGGL((k_contract_f64<1, 64>), dim3(grid.x, (s + 3) / 4), dim3(256), 0, st, params, m, n, r, s, M->Dt64, M->Qrm, G); break;
+    }
+  }
+  const int64_t len = m * s * r;
+  hipLaunchKernelGGL(k_krr_gfinish, dim3(static_cast<unsigned>((len + 255) / 256)), dim3(256), 0, st, G, m, r, s, M->wS,
+                     M->QS, M->lambda);
+  SUBAP_HIP_TRY(hipGetLastError());
+  return SUBAP_OK;
+}
+
 }  // namespace subap

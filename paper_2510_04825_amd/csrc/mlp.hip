@@ -492,7 +492,7 @@ __global__ void k_zero_u64(unsigned long long* c) { *c = 0ull; }
 
 subap_status surrogate_solve(subap_model_s* M, Surrogate* S, const double* P, int64_t m, double tol, double* y,
                              uint8_t* accepted, int32_t* status, int prec, int refine, bool csne,
-                             int64_t* n_acc, hipStream_t st) {
+                             int64_t* n_acc, hipStream_t st, double sigma_min) {
   // workspace: norms (m), rejected indices (m), count, compact params (m d), y (m r), status (m)
   const size_t bytes = 8 * static_cast<size_t>(m) * (2 + M->d + M->r + 1) + 64;
   char* buf = nullptr;
@@ -508,7 +508,11 @@ subap_status surrogate_solve(subap_model_s* M, Surrogate* S, const double* P, in
   double* Yc = Pc + m * M->d;
   int32_t* Sc = reinterpret_cast<int32_t*>(Yc + m * M->r);
   SUBAP_TRY(surrogate_predict(S, P, m, y, st));
-  {
+  if (sigma_min > 0.0) {  // the normal-equation excess bound
+    ProfScope prof("surrogate_excess", st);
+    if (M->family == SUBAP_FAMILY_KRR) SUBAP_TRY(krr_excess(M, P, m, y, sigma_min, norm, st));
+    else SUBAP_TRY(fd_excess(M, P, m, y, sigma_min, norm, st));
+  } else {               // the sketched relative residual
     ProfScope prof("surrogate_residual", st);
     if (M->family == SUBAP_FAMILY_KRR) SUBAP_TRY(krr_residual(M, P, m, y, nullptr, norm, st));
     else SUBAP_TRY(fd_residual(M, P, m, y, nullptr, norm, st));
