@@ -196,14 +196,24 @@ def diffusion3d(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
     ms = timed(fp64_step, args.steps, stream)
     B.subap_profile_enable(False)
     prof = B.subap_profile_read()
-    kms = prof["fd_solve"][1] / prof["fd_solve"][0]
-    # algorithmic FP64 work per parameter: Householder QR of the s x r matrix
-    # (2 s r^2 - 2/3 r^3 flops) and the face-form contraction (2 s F r, F = 6)
+    # the solve's main kernel: the matrix-core semi-normal solve (fd_gram),
+    # followed by the Householder pass over the parameters it deferred
+    kname = "fd_gram" if "fd_gram" in prof else "fd_solve"
+    kms = prof[kname][1] / prof[kname][0]
+    # algorithmic FP64 work per parameter, as for Householder QR of the s x r
+    # matrix (2 s r^2 - 2/3 r^3 flops) plus the face-form contraction (2 s F r,
+    # F = 6); the semi-normal solve issues the Gram matrix of [G | S b] on the
+    # matrix cores (16 x 16 x 4 tiles, T (T + 1) / 2 per four rows) instead
     flops = m * (2.0 * s * r * r - 2.0 / 3.0 * r ** 3 + 2.0 * s * 6 * r)
-    roof = {"bound": "alu", "kernel": "fd_solve", "avg_ms": kms, "achieved": flops / (kms * 1e-3) / 1e12,
+    T = (r + 1 + 15) // 16
+    mfma_flops = m * 2.0 * 1024 * (T * (T + 1) // 2) * ((s + 3) // 4)
+    roof = {"bound": "mfma", "kernel": kname, "avg_ms": kms, "achieved": flops / (kms * 1e-3) / 1e12,
             "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s",
             "frac": flops / (kms * 1e-3) / 1e12 / PEAKS["fp64_tflops"],
-            "flops_per_launch": flops, "traffic": _traffic("diffusion3d")}
+            "flops_per_launch": flops, "issued_mfma_flops_per_launch": mfma_flops,
+            "deferred_pass_ms": (prof["fd_gram_fixup"][1] / prof["fd_gram_fixup"][0]
+                                 if "fd_gram_fixup" in prof else None),
+            "traffic": _traffic("diffusion3d", kname)}
     if args.profile_only:
         calibrate_copy(args, torch, dev)
         M.free()
@@ -274,7 +284,8 @@ def diffusion3d(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"diffusion3d_n{N}^3_r{r}_s{s}_m{m}", "n": n, "r": r, "s": s, "batch": m,
-                   "form": "fused FP64 rows + face-form contraction + Householder least squares (k_fd_cols)",
+                   "form": "fused FP64 rows + face-form contraction + semi-normal least squares on the FP64 "
+                           "matrix cores with corrected steps (k_fd_gram)",
                    "basis": "seeded, orthonormalised" if args.given_basis else "snapshot solves on the GPU"},
         "valid": {"count": valid64, "of": m, "status_ok": ok64, "tolerance": TOL, "oracle_check": check},
         "forms": forms,

@@ -84,6 +84,11 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with __graft_entry__.build() "
                           "(python -m paper_2510_04825_amd.build); there is no CPU fallback")
+    # torch's HIP context first: device memory and streams come from torch,
+    # and the library's first runtime call must not precede its initialisation
+    import torch
+    if torch.cuda.is_available():
+        torch.cuda.init()
     lib = C.CDLL(path)
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     lib.subap_offline.argtypes = [C.POINTER(ProblemDesc), C.POINTER(OfflineOpts), vp, C.POINTER(vp)]

@@ -11,6 +11,7 @@
 #include "common.h"
 #include "profile.h"
 #include "fd_cols.h"
+#include "fd_gram.h"
 #include "team_qr.h"
 
 namespace subap {
@@ -188,6 +189,37 @@ __global__ __launch_bounds__(128, REF ? 1 : (BRED ? 2 : 4)) void k_fd_cols(FDArg
                           lane, A.y + p * A.r, A.rho ? A.rho + p : nullptr, A.status ? A.status + p : nullptr);
 }
 
+// Semi-normal equations on the matrix cores (fd_gram.h): P parameters per
+// wavefront, two wavefronts per block.
+template <int F, int DP, int T, int P>
+__global__ __launch_bounds__(128, 2) void k_fd_gram(FDArgs A, int ldsw) {
+  extern __shared__ double lds_gram[];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int64_t p0 = (static_cast<int64_t>(blockIdx.x) * 2 + wave) * P;
+  if (p0 >= A.m) return;  // uniform per wavefront; no block-level barrier follows
+  const ColsModel M{A.r, A.s, A.phi, A.delta64T, A.delta32T, A.bS, A.inv_h2, A.bS_norm, A.aff_c0, A.aff_tau,
+                    A.wS, A.rowdat};
+  gram_solve<F, DP, T, P>(M, A.params, A.m, p0, lds_gram + static_cast<int64_t>(wave) * ldsw, lane, A.y, A.rho,
+                          A.status);
+}
+
+// The parameters the matrix-core solve deferred (first coefficient
+// kGramDefer), solved by column-per-lane Householder; a grid-stride loop over
+// all parameters.
+template <int F, int DP>
+__global__ __launch_bounds__(128, 4) void k_fd_gram_fixup(FDArgs A, int ldsw) {
+  extern __shared__ double lds_fix[];
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const ColsModel M{A.r, A.s, A.phi, A.delta64T, A.delta32T, A.bS, A.inv_h2, A.bS_norm, A.aff_c0, A.aff_tau,
+                    A.wS, A.rowdat};
+  for (int64_t p = static_cast<int64_t>(blockIdx.x) * 2 + wave; p < A.m; p += static_cast<int64_t>(gridDim.x) * 2) {
+    if (static_cast<unsigned long long>(__double_as_longlong(A.y[p * A.r])) != kGramDefer) continue;
+    cols_solve<F, DP, false, false>(M, A.params + p * DP, SUBAP_FP64, 0, false,
+                                    lds_fix + static_cast<int64_t>(wave) * ldsw, A.s, lane, A.y + p * A.r,
+                                    A.rho ? A.rho + p : nullptr, A.status ? A.status + p : nullptr);
+  }
+}
+
 // Column-per-lane solve with four parameters per wavefront (r <= 15, FP64
 // without refinement, fd_cols.h): eight parameters per block of two waves.
 template <int F, int DP, int COEF, int RB>
@@ -329,6 +361,45 @@ subap_status launch(const FDArgs& a, hipStream_t st) {
   return SUBAP_OK;
 }
 
+constexpr int kGramP = 1;  // parameters per wavefront
+
+template <int F, int DP, int T>
+subap_status launch_gram_t(const FDArgs& a, hipStream_t st) {
+  const int64_t waves = (a.m + kGramP - 1) / kGramP;
+  const int64_t nb = (waves + 1) / 2;
+  if (nb > 0x7fffffff) {
+    set_error("batch too large");
+    return SUBAP_E_INVALID;
+  }
+  const int ldsw = gram_lds_doubles(a.r, kGramP, F);
+  {
+    ProfScope prof("fd_gram", st);
+    hipLaunchKernelGGL((k_fd_gram<F, DP, T, kGramP>), dim3(static_cast<unsigned>(nb)), dim3(128),
+                       sizeof(double) * 2 * static_cast<size_t>(ldsw), st, a, ldsw);
+    SUBAP_HIP_TRY(hipGetLastError());
+  }
+  const int ldsc = cols_lds_doubles(a.r, a.s, false);
+  const unsigned grid = static_cast<unsigned>(std::min<int64_t>((a.m + 1) / 2, 2048));
+  ProfScope prof("fd_gram_fixup", st);
+  hipLaunchKernelGGL((k_fd_gram_fixup<F, DP>), dim3(grid), dim3(128), sizeof(double) * 2 * static_cast<size_t>(ldsc),
+                     st, a, ldsc);
+  SUBAP_HIP_TRY(hipGetLastError());
+  return SUBAP_OK;
+}
+
+// The FP64 form without refinement for the diffusion families at
+// 16 <= r <= 47 (G~ = [G | S b] fits three 16-column tiles).
+template <int F, int DP>
+bool gram_applies(const FDArgs& a) {
+  return a.prec == SUBAP_FP64 && a.refine == 0 && a.r > kPackMaxR && a.r + 1 <= 48;
+}
+
+template <int F, int DP>
+subap_status launch_gram(const FDArgs& a, hipStream_t st) {
+  if (a.r + 1 <= 32) return launch_gram_t<F, DP, 2>(a, st);
+  return launch_gram_t<F, DP, 3>(a, st);
+}
+
 // Column-per-lane launch.  RB is the row block of the FP64 form without
 // refinement at r < 64; the other forms keep blocks of kColsRB rows (their
 // residual slices of 64 rows hold whole blocks).
@@ -372,6 +443,7 @@ subap_status dispatch(const FDArgs& a, hipStream_t st) {
   // tall problems: column-per-lane Householder (any precision and refinement).
   // The corrected semi-normal equations need R^T R solves, which only the
   // column-per-lane solver does.
+  if (s >= 96 && gram_applies<F, DP>(a)) return launch_gram<F, DP>(a, st);
   if (s >= 96 || (a.csne && a.refine > 0)) return launch_cols<F, DP>(a, st);
 #define SUBAP_FD(TEAM, R, RM) \
   if (s <= TEAM * R && r <= RM) return launch<TEAM, R, RM, F, DP>(a, st);

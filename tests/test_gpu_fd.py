@@ -258,6 +258,59 @@ def test_rank_deficient_tall_problem():
         M.free()
 
 
+@pytest.mark.parametrize("eps", [1e-8, 1e-4])
+def test_fd_tall_ill_conditioned_rows(eps):
+    """An orthonormal basis of unit vectors at grid nodes, one column mixing a
+    node far from every selected row (weight sqrt(1 - eps^2)) with a selected
+    one (weight eps): kappa(S A(p) Q) grows like 1/eps.  At eps = 1e-8 the
+    semi-normal equations cannot resolve it and the parameters go to the
+    Householder solver; at 1e-4 the corrected semi-normal steps settle it.
+    The weak direction of S A Q is strong in A Q, so y itself is fixed only to
+    kappa^2 eps and the full-row delta_res of any two stable solvers differs
+    at that level; the bars are on what a backward-stable solver fixes to
+    about kappa eps: the fitted values |S A Q (y - y_oracle)| / |S b| and the
+    sketched residual, each within 10 eps kappa (plus 1e-13)."""
+    w = si.diffusion3d(N=20, r=40, s=160, m=13)
+    N, n, r, s = 20, w["n"], w["r"], w["s"]
+    from oracle import families as Fm
+    fam = Fm.from_workload(w)
+    far = N // 2 + N * (N // 2) + N * N * (N // 2)
+    ijk = np.stack([np.arange(n) % N, (np.arange(n) // N) % N, np.arange(n) // (N * N)], axis=1)
+    dist = np.abs(ijk - ijk[far]).sum(axis=1)
+    rng = np.random.default_rng(31)
+    cand = np.flatnonzero(dist > 2)
+    nodes = rng.choice(cand, size=r, replace=False)
+    extra = rng.choice(np.setdiff1d(cand, nodes), size=s - r, replace=False)
+    rows = np.sort(np.concatenate([nodes, extra]))
+    Q = np.zeros((n, r))
+    Q[nodes, np.arange(r)] = 1.0
+    Q[nodes[7], 7] = eps
+    Q[far, 7] = np.sqrt(1.0 - eps * eps)
+    header(f"tall ill-conditioned rows eps={eps}")
+    M = B.Model(w, basis=Q, rows=rows)
+    try:
+        P = w["test_params"]
+        y, rho, st = M.solve(to_dev(P))
+        st, y, rho = st.cpu().numpy(), y.cpu().numpy(), rho.cpu().numpy()
+        assert np.all(st == B.OK)
+        Yo = On.solve(fam, Q, rows, P)
+        worst = 0.0
+        for p, yg, yo, rg in zip(P, y, Yo, rho):
+            G = On.reduced_matrix(fam, Q, rows, p)
+            sv = np.linalg.svd(G, compute_uv=False)
+            kappa = sv[0] / sv[-1]
+            bS = np.asarray(fam.rhs_rows(p, rows))
+            fit = np.linalg.norm(G @ (yg - yo)) / np.linalg.norm(bS)
+            ro = np.linalg.norm(G @ yo - bS) / np.linalg.norm(bS)
+            bar = 10 * 2.0 ** -52 * kappa + 1e-13
+            worst = max(worst, fit / bar)
+            assert fit <= bar, (kappa, fit, bar)
+            assert abs(rg - ro) <= bar * max(ro, 1.0), (kappa, rg, ro)
+        print(f"kappa {kappa:.1e}: worst fitted-value error / bar {worst:.2e}")
+    finally:
+        M.free()
+
+
 @pytest.mark.parametrize("N,r,s", [(16, 8, 32), (24, 40, 160)])
 def test_diffusion3d_given_basis(N, r, s):
     w = si.diffusion3d(N=N, r=r, s=s, m=50)
