@@ -31,6 +31,7 @@ void clear_error();
 
 constexpr int kMaxR = 64;
 constexpr int kMaxS = 256;
+constexpr int kRowPad = 8;  // zero rows after the s rows of bS and of the diffusion delta64T
 constexpr double kRankTol = 1e-13;   // |R_jj| <= kRankTol |R_11| -> rank deficient
 constexpr double kTieRtol = 1e-6;    // pivot tie window
 

@@ -83,36 +83,87 @@ __device__ __forceinline__ double gram_wave_max(double v) {
   return v;
 }
 
-// the F x T table entries of row kc for lane column c (clamped in bounds;
-// masked by the caller)
+// Buffer resource over a table of `bytes` bytes (raw, stride 0; the gfx9
+// word 3), read with a per-lane voffset and a wave-uniform soffset.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t gram_rsrc(const double* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), 0, static_cast<int>(bytes), 0x00020000);
+}
+
+__device__ __forceinline__ double gram_bload(__amdgpu_buffer_rsrc_t rs, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0));
+}
+
+// The F x T table entries of one row group for this lane: face f's rows of
+// the group start at the wave-uniform byte offset soff + f fbytes, and the
+// lane adds its own loop-invariant offset (row g of the group, column
+// min(16 I + c, r - 1)), so no vector address arithmetic is needed per group.
+// Rows past s read the next face or the zero rows after the table
+// (kRowPad), which the zero coefficients of those rows cancel.
 template <int F, int T>
-__device__ __forceinline__ void gram_load(const double* d64T, int kc, int r, int64_t fstride, const int (&colc)[T],
-                                          double (&d)[F][T]) {
-  const double* rowp = d64T + static_cast<int64_t>(kc) * r;
+__device__ __forceinline__ void gram_load(__amdgpu_buffer_rsrc_t rs, unsigned soff, unsigned fbytes,
+                                          const unsigned (&vo)[T], double (&d)[F][T]) {
 #pragma unroll
   for (int f = 0; f < F; ++f)
 #pragma unroll
-    for (int I = 0; I < T; ++I) d[f][I] = rowp[f * fstride + colc[I]];
+    for (int I = 0; I < T; ++I) d[f][I] = gram_bload(rs, vo[I], soff + f * fbytes);
+}
+
+// the rows of one group (4 qq + g of the chunk) for the P parameters
+template <int F, int T, int P, bool GRAM>
+__device__ __forceinline__ void gram_group(const double (&d)[F][T], double bk, const double* coef, int kr, int bI,
+                                           int c16, const double (&cm)[T], gram_v4d (&acc)[P][T * (T + 1) / 2],
+                                           const double (&yreg)[P][T], double (&gacc)[P][T], double (&rr)[P]) {
+#pragma unroll
+  for (int u = 0; u < P; ++u) {
+    double a[F];  // zero beyond row s
+#pragma unroll
+    for (int f = 0; f < F; ++f) a[f] = coef[(u * 64 + kr) * F + f];
+    double Gv[T];
+#pragma unroll
+    for (int I = 0; I < T; ++I) {
+      double t = 0.0;
+#pragma unroll
+      for (int f = 0; f < F; ++f) t = fma(a[f], d[f][I], t);
+      Gv[I] = (I == bI) ? fma(cm[I], t, bk) : cm[I] * t;
+    }
+    if constexpr (GRAM) {
+      int t = 0;
+#pragma unroll
+      for (int I = 0; I < T; ++I)
+#pragma unroll
+        for (int J = I; J < T; ++J, ++t)
+          acc[u][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(Gv[I], Gv[J], acc[u][t], 0, 0, 0);
+    } else {
+      double dot = 0.0;
+#pragma unroll
+      for (int I = 0; I < T; ++I) dot = fma(Gv[I], yreg[u][I], dot);
+      const double res = gram_row_sum(dot);
+#pragma unroll
+      for (int I = 0; I < T; ++I) gacc[u][I] = fma(Gv[I], res, gacc[u][I]);
+      rr[u] = fma(res * (c16 == 0 ? 1.0 : 0.0), res, rr[u]);
+    }
+  }
 }
 
 // one pass over the s rows.  GRAM: accumulate G~^T G~ tiles.  Otherwise
 // res_k = G~_k (y, -1) (= (G y - S b)_k), gacc += G~^T res per lane column,
-// rr += |res|^2 (counted once per row, by the lanes with c = 0).  Every table
-// load is unconditional (rows clamped to s - 1, columns to r - 1) and the
-// masks multiply the results, so the loads of a row group issue together;
-// the next group's loads are in flight while this one computes.
+// rr += |res|^2 (counted once per row, by the lanes with c = 0).  The masks
+// multiply the results, so the T F loads of a group issue together,
+// unconditionally.  (Holding the next group's loads in a second register
+// buffer costs a wavefront per SIMD of occupancy, which measured slower.)
 template <int F, int DP, int T, int P, bool GRAM>
 __device__ __forceinline__ void gram_pass(const ColsModel& M, const double (&pv)[P][DP], double* coef, int lane,
                                           gram_v4d (&acc)[P][T * (T + 1) / 2], const double (&yreg)[P][T],
                                           double (&gacc)[P][T], double (&rr)[P]) {
   const int r = M.r, s = M.s, g = lane >> 4, c16 = lane & 15;
   const int bI = r >> 4;  // tile of S b
-  const int64_t fstride = static_cast<int64_t>(s) * r;
-  int colc[T];
+  const unsigned fbytes = 8u * static_cast<unsigned>(s) * r, gbytes = 32u * r;  // a face, a row group
+  const __amdgpu_buffer_rsrc_t rs = gram_rsrc(M.d64T, fbytes * F + 8u * kRowPad * r);
+  unsigned vo[T];
   double cm[T];
 #pragma unroll
   for (int I = 0; I < T; ++I) {
-    colc[I] = min(16 * I + c16, r - 1);
+    vo[I] = 8u * static_cast<unsigned>(g * r + min(16 * I + c16, r - 1));
     cm[I] = (16 * I + c16 < r) ? 1.0 : 0.0;
   }
   const double bm = (c16 == (r & 15)) ? 1.0 : 0.0;
@@ -127,54 +178,13 @@ __device__ __forceinline__ void gram_pass(const ColsModel& M, const double (&pv)
     }
     wave_sync_lds();
     const int nq = min(16, (s - c0 + 3) / 4);
-    double dn[F][T];
-    int kn = min(c0 + g, s - 1);
-    gram_load<F, T>(M.d64T, kn, r, fstride, colc, dn);
-    double bn = M.bS[kn];
+    const unsigned s0 = 8u * static_cast<unsigned>(c0) * r;
     for (int qq = 0; qq < nq; ++qq) {
-      const int kr = 4 * qq + g, k = c0 + kr;
-      double d[F][T];
-#pragma unroll
-      for (int f = 0; f < F; ++f)
-#pragma unroll
-        for (int I = 0; I < T; ++I) d[f][I] = dn[f][I];
-      const double bk = (k < s ? bm : 0.0) * bn;
-      kn = min(k + 4, s - 1);
-      gram_load<F, T>(M.d64T, kn, r, fstride, colc, dn);
-      bn = M.bS[kn];
-      // keep the next group's loads in this iteration (no instruction, no
-      // wait): without it they are moved to their use in the next one
-      asm volatile("" ::: "memory");
-#pragma unroll
-      for (int u = 0; u < P; ++u) {
-        double a[F];  // zero beyond row s
-#pragma unroll
-        for (int f = 0; f < F; ++f) a[f] = coef[(u * 64 + kr) * F + f];
-        double Gv[T];
-#pragma unroll
-        for (int I = 0; I < T; ++I) {
-          double t = 0.0;
-#pragma unroll
-          for (int f = 0; f < F; ++f) t = fma(a[f], d[f][I], t);
-          Gv[I] = (I == bI) ? fma(cm[I], t, bk) : cm[I] * t;
-        }
-        if constexpr (GRAM) {
-          int t = 0;
-#pragma unroll
-          for (int I = 0; I < T; ++I)
-#pragma unroll
-            for (int J = I; J < T; ++J, ++t)
-              acc[u][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(Gv[I], Gv[J], acc[u][t], 0, 0, 0);
-        } else {
-          double dot = 0.0;
-#pragma unroll
-          for (int I = 0; I < T; ++I) dot = fma(Gv[I], yreg[u][I], dot);
-          const double res = gram_row_sum(dot);
-#pragma unroll
-          for (int I = 0; I < T; ++I) gacc[u][I] = fma(Gv[I], res, gacc[u][I]);
-          rr[u] = fma(res * (c16 == 0 ? 1.0 : 0.0), res, rr[u]);
-        }
-      }
+      const int k = c0 + 4 * qq + g;
+      double dA[F][T];
+      gram_load<F, T>(rs, s0 + qq * gbytes, fbytes, vo, dA);
+      const double bA = M.bS[k];
+      gram_group<F, T, P, GRAM>(dA, (k < s ? bm : 0.0) * bA, coef, 4 * qq + g, bI, c16, cm, acc, yreg, gacc, rr);
     }
     wave_sync_lds();  // the next chunk's coefficients overwrite these
   }

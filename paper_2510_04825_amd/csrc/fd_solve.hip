@@ -361,7 +361,7 @@ subap_status launch(const FDArgs& a, hipStream_t st) {
   return SUBAP_OK;
 }
 
-constexpr int kGramP = 1;  // parameters per wavefront
+constexpr int kGramP = 2;  // parameters per wavefront: they share every table load
 
 template <int F, int DP, int T>
 subap_status launch_gram_t(const FDArgs& a, hipStream_t st) {

@@ -1109,7 +1109,8 @@ subap_status build_tables(subap_model_s* M, hipStream_t st) {
     SUBAP_TRY(dalloc(&M->wS, s));
     hipLaunchKernelGGL(k_fill, dim3((s + 63) / 64), dim3(64), 0, st, M->wS, static_cast<int64_t>(s), 1.0);
   }
-  SUBAP_TRY(dalloc(&M->bS, s));
+  SUBAP_TRY(dalloc(&M->bS, s + kRowPad));
+  SUBAP_HIP_TRY(hipMemsetAsync(M->bS + s, 0, sizeof(double) * kRowPad, st));
   SUBAP_TRY(dalloc(&M->QS, static_cast<size_t>(s) * r));
   if (M->family == SUBAP_FAMILY_KRR) {
     SUBAP_TRY(dalloc(&M->Dt64, static_cast<size_t>(n) * s));
@@ -1154,7 +1155,10 @@ subap_status build_tables(subap_model_s* M, hipStream_t st) {
     SUBAP_TRY(dalloc(&M->phi, tab * M->d));
     SUBAP_TRY(dalloc(&M->delta64, tab * r));
     SUBAP_TRY(dalloc(&M->delta32, tab * r));
-    SUBAP_TRY(dalloc(&M->delta64T, tab * r));
+    // kRowPad zero rows after the last face: the matrix-core solve reads
+    // row groups ahead of the ones it uses
+    SUBAP_TRY(dalloc(&M->delta64T, (tab + kRowPad) * r));
+    SUBAP_HIP_TRY(hipMemsetAsync(M->delta64T + tab * r, 0, sizeof(double) * kRowPad * r, st));
     SUBAP_TRY(dalloc(&M->delta32T, tab * r));
     hipLaunchKernelGGL(k_fd_tables, dim3((s + 63) / 64), dim3(64), 0, st, M->Q, n, r, s, M->N, M->dimx, M->d, M->h,
                        M->rows_d, M->wS, M->rhs, M->phi, M->delta64, M->delta32, M->delta64T, M->delta32T, M->bS,
