@@ -46,9 +46,9 @@ import numpy as np
 # the hash covers them, and a changed source reports traffic null.
 FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 TRAFFIC = {
-    # k_fd_cols<6, 4, false, false, 0, 32>, one launch of 65,536 parameters
-    "diffusion3d": {"sources": ("fd_solve.hip", "fd_cols.h", "common.h"), "sha256_16": "a92a869da535684e",
-                    "fetch_kib": 6607.4, "write_kib": 29655.2},
+    # k_fd_gram<6, 4, 3, 2>, one launch of 65,536 parameters
+    "diffusion3d": {"kernel": "fd_gram", "sources": ("fd_solve.hip", "fd_gram.h", "fd_cols.h", "common.h"),
+                    "sha256_16": "a615831be828e065", "fetch_kib": 3163.0, "write_kib": 21504.0},
     # k_fd_cols<2, 1, false, false, 1, 40>, one launch of 65,536 parameters
     "delay": {"sources": ("fd_solve.hip", "fd_cols.h", "common.h"), "sha256_16": "a92a869da535684e",
               "fetch_kib": 2201.1, "write_kib": 7168.0},

@@ -205,9 +205,10 @@ __global__ __launch_bounds__(128, 2) void k_fd_gram(FDArgs A, int ldsw) {
 
 // The parameters the matrix-core solve deferred (first coefficient
 // kGramDefer), solved by column-per-lane Householder; a grid-stride loop over
-// all parameters.
+// all parameters.  Its occupancy does not matter (it solves few parameters),
+// so it takes the registers that keep the solver from spilling.
 template <int F, int DP>
-__global__ __launch_bounds__(128, 4) void k_fd_gram_fixup(FDArgs A, int ldsw) {
+__global__ __launch_bounds__(128, 1) void k_fd_gram_fixup(FDArgs A, int ldsw) {
   extern __shared__ double lds_fix[];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const ColsModel M{A.r, A.s, A.phi, A.delta64T, A.delta32T, A.bS, A.inv_h2, A.bS_norm, A.aff_c0, A.aff_tau,
