@@ -48,7 +48,7 @@ FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 TRAFFIC = {
     # k_fd_gram<6, 4, 3, 2>, one launch of 65,536 parameters
     "diffusion3d": {"kernel": "fd_gram", "sources": ("fd_solve.hip", "fd_gram.h", "fd_cols.h", "common.h"),
-                    "sha256_16": "a615831be828e065", "fetch_kib": 3163.0, "write_kib": 21504.0},
+                    "sha256_16": "1847a2fbf8651915", "fetch_kib": 3163.0, "write_kib": 21504.0},
     # k_fd_cols<2, 1, false, false, 1, 40>, one launch of 65,536 parameters
     "delay": {"sources": ("fd_solve.hip", "fd_cols.h", "common.h"), "sha256_16": "a92a869da535684e",
               "fetch_kib": 2201.1, "write_kib": 7168.0},
@@ -406,6 +406,14 @@ def krr(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
                      "issued_flops_per_launch": m * (REFINE_ISSUED_FLOPS_PER_ENTRY * s * n + 2.0 * n * r),
                      "exp2_per_launch": m * s * n,
                      "exp2_per_s": m * s * n / (avg[dname] * 1e-3)})
+        # the transcendental co-bound, measured: FP64-accurate 2^(c d) per
+        # second of the polynomial the pass uses (degree 7 for the first
+        # refinement step, 11 after), and of v_exp_f32 for reference
+        deg = 11 if "exact" in dname else 7
+        rates = {f"deg{g}": B.subap_exp2_rate(g) for g in (7, 11)}
+        rates["v_exp_f32"] = B.subap_exp2_rate(0)
+        roof["exp2_rate"] = {**rates, "pass_degree": deg,
+                             "frac": roof["exp2_per_s"] / rates[f"deg{deg}"]}
     roof["achieved"] = fl / (avg[dname] * 1e-3) / 1e12
     roof["frac"] = roof["achieved"] / roof["peak"]
     for k in avg:

@@ -416,6 +416,18 @@ SUBAP_API subap_status subap_surrogate_solve_batch_excess(subap_model model, sub
 SUBAP_API subap_status subap_surrogate_free(subap_surrogate s);
 
 /*
+ * subap_exp2_rate -- transcendental-rate microbenchmark for the kernel family's
+ * entries K = 2^(c D) (eq. (6.4) with c = -log2(e) / (2 p^2)): times about
+ * `evals` evaluations on the whole device, 16 independent ones per lane as the
+ * refinement issues them, each accumulated in FP64, and writes evaluations
+ * per second to *evals_per_s (host).  form 7, 9 or 11: the FP64 polynomial
+ * of that degree after exact range reduction (relative error 5.5e-11,
+ * 1.9e-14, 2.2e-16); form 0: the FP32 hardware v_exp_f32 that the 16-bit and
+ * FP32 contractions use.  Blocking; allocates a small device buffer.
+ */
+SUBAP_API subap_status subap_exp2_rate(int32_t form, int64_t evals, double* evals_per_s, void* hip_stream);
+
+/*
  * Per-kernel timing for benchmarks.  While enabled, the library records a
  * HIP event pair on the launching stream around every kernel it enqueues.
  * subap_profile_count() waits for the recorded events and returns the

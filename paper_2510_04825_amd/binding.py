@@ -39,7 +39,7 @@ EXPORTS = ("subap_offline", "subap_solve_batch", "subap_lift", "subap_sketched_r
            "subap_model_weights", "subap_residual_bounds", "subap_output", "subap_full_residual",
            "subap_apsnap_solve", "subap_polish", "subap_model_save", "subap_model_load",
            "subap_delta_residual", "subap_solve_batch_noalloc", "subap_excess_bound", "subap_reduced_matrix",
-           "subap_surrogate_solve_batch_excess")
+           "subap_surrogate_solve_batch_excess", "subap_exp2_rate")
 PLAN_GRAPH, PLAN_AUTOTUNE = 1, 2
 # subap_selection
 SELECT_CPQR, SELECT_LEVERAGE, SELECT_LU = 0, 1, 2
@@ -135,6 +135,7 @@ def load(path: str = LIB_PATH):
                                                 C.POINTER(i64), vp]
     lib.subap_surrogate_solve_batch_excess.argtypes = [vp, vp, vp, i64, C.c_double, C.c_double, vp, vp, vp,
                                                        C.POINTER(SolveOpts), C.POINTER(i64), vp]
+    lib.subap_exp2_rate.argtypes = [i32, i64, C.POINTER(C.c_double), vp]
     lib.subap_surrogate_free.argtypes = [vp]
     for name in EXPORTS[:23]:
         getattr(lib, name).restype = C.c_int
@@ -438,6 +439,13 @@ def subap_surrogate_solve_batch_excess(model, s, params, sigma_min, accept_tol, 
                                                      float(sigma_min), float(accept_tol), _ptr(y), _ptr(accepted),
                                                      _ptr(status), C.byref(opts), C.byref(n), _stream(stream)))
     return n.value
+
+
+def subap_exp2_rate(form, evals=1 << 34, stream=None):
+    """2^(c d) evaluations per second on the device (form 7/9/11: FP64 polynomial degree; 0: v_exp_f32)."""
+    rate = C.c_double()
+    _check(load().subap_exp2_rate(int(form), int(evals), C.byref(rate), _stream(stream)))
+    return rate.value
 
 
 def subap_surrogate_free(s):

@@ -1035,6 +1035,18 @@ subap_status subap_surrogate_free(subap_surrogate s) {
   }
 }
 
+subap_status subap_exp2_rate(int32_t form, int64_t evals, double* evals_per_s, void* hip_stream) {
+  try {
+    clear_error();
+    if (!evals_per_s) return invalid("evals_per_s must not be NULL");
+    if (form != 0 && form != 7 && form != 9 && form != 11) return invalid("form must be 0, 7, 9 or 11");
+    if (evals < 1 || evals > (int64_t(1) << 40)) return invalid("evals must be in [1, 2^40]");
+    return exp2_rate(form, evals, evals_per_s, static_cast<hipStream_t>(hip_stream));
+  } catch (...) {
+    return host_exception();
+  }
+}
+
 subap_status subap_profile_enable(int32_t on) {
   try {
     std::lock_guard<std::mutex> lk(g_prof_mu);

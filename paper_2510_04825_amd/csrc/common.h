@@ -129,6 +129,7 @@ subap_status polish(subap_model_s* M, const double* params, int64_t m, double* x
 // applying the stored factorisation of the rounded G.
 subap_status fd_solve(subap_model_s* M, const double* params, int64_t m, double* y,
                       double* rho, int32_t* status, int prec, int refine, bool csne, hipStream_t st);
+subap_status exp2_rate(int form, int64_t evals, double* rate, hipStream_t st);
 subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double* y,
                        double* rho, int32_t* status, int prec, int refine, bool csne, hipStream_t st);
 // krr_solve with a caller-given device workspace of at least the bytes the

@@ -1207,4 +1207,79 @@ subap_status krr_reduced_matrix(subap_model_s* M, const double* params, int64_t 
   return SUBAP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Transcendental-rate microbenchmark: 2^(c d) evaluations per second as the
+// refinement issues them (16 independent evaluations per lane and point,
+// accumulated), for the FP64 polynomial forms and for v_exp_f32.
+namespace {
+
+constexpr int kRateChains = 16;
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_exp2_rate(int64_t iters, double* out) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  double c[kRateChains], acc[kRateChains];
+#pragma unroll
+  for (int w = 0; w < kRateChains; ++w) {
+    c[w] = -0.05 - 0.01 * w;
+    acc[w] = 0.0;
+  }
+  double d = 0.5 + 1e-6 * static_cast<double>(t & 1023);
+  for (int64_t i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int w = 0; w < kRateChains; ++w) {
+      if constexpr (DEG == 0)
+        acc[w] += static_cast<double>(__builtin_amdgcn_exp2f(static_cast<float>(c[w] * d)));
+      else
+        acc[w] = fma(exp2_mul<DEG>(c[w], d), 0.5, acc[w]);
+    }
+    d += 0.001;
+  }
+  double sum = 0.0;
+#pragma unroll
+  for (int w = 0; w < kRateChains; ++w) sum += acc[w];
+  out[t] = sum;
+}
+
+}  // namespace
+
+subap_status exp2_rate(int form, int64_t evals, double* rate, hipStream_t st) {
+  constexpr int kThreads = 256, kBlocks = 256 * 16;
+  const int64_t lanes = static_cast<int64_t>(kThreads) * kBlocks;
+  const int64_t iters = std::max<int64_t>(1, evals / (lanes * kRateChains));
+  struct Buf {
+    double* p = nullptr;
+    ~Buf() { dfree(p); }
+  } out;
+  SUBAP_TRY(dalloc(&out.p, static_cast<size_t>(lanes)));
+  hipEvent_t e0, e1;
+  SUBAP_HIP_TRY(hipEventCreate(&e0));
+  SUBAP_HIP_TRY(hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } ev{e0, e1};
+  auto launch = [&](int64_t it) {
+    switch (form) {
+      case 0: hipLaunchKernelGGL(k_exp2_rate<0>, dim3(kBlocks), dim3(kThreads), 0, st, it, out.p); break;
+      case 7: hipLaunchKernelGGL(k_exp2_rate<7>, dim3(kBlocks), dim3(kThreads), 0, st, it, out.p); break;
+      case 9: hipLaunchKernelGGL(k_exp2_rate<9>, dim3(kBlocks), dim3(kThreads), 0, st, it, out.p); break;
+      default: hipLaunchKernelGGL(k_exp2_rate<11>, dim3(kBlocks), dim3(kThreads), 0, st, it, out.p); break;
+    }
+  };
+  launch(1);  // warm-up
+  SUBAP_HIP_TRY(hipEventRecord(e0, st));
+  launch(iters);
+  SUBAP_HIP_TRY(hipEventRecord(e1, st));
+  SUBAP_HIP_TRY(hipGetLastError());
+  SUBAP_HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.0f;
+  SUBAP_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  *rate = static_cast<double>(lanes) * kRateChains * static_cast<double>(iters) / (ms * 1e-3);
+  return SUBAP_OK;
+}
+
 }  // namespace subap

@@ -327,3 +327,21 @@ def test_krr_full_size_interpolation(krr_full, prec):
             assert d <= 1e-6, (i, d)
     finally:
         M.free()
+
+
+def test_exp2_rate_microbenchmark():
+    """subap_exp2_rate: positive, finite rates; the degree-11 polynomial costs
+    more than degree 7 (four more FMAs per evaluation); bad forms and counts
+    are rejected before any device work."""
+    import ctypes as C
+    header("exp2 rate")
+    device()
+    r7, r11, r0 = (B.subap_exp2_rate(f, 1 << 30) for f in (7, 11, 0))
+    print(f"2^(c d) per second: degree 7 {r7:.3e}, degree 11 {r11:.3e}, v_exp_f32 {r0:.3e}")
+    assert all(np.isfinite(v) and v > 0 for v in (r7, r11, r0))
+    assert r11 < r7
+    lib = B.load()
+    out = C.c_double()
+    assert lib.subap_exp2_rate(5, 1 << 20, C.byref(out), None) == B.E_INVALID
+    assert lib.subap_exp2_rate(7, 0, C.byref(out), None) == B.E_INVALID
+    assert lib.subap_exp2_rate(7, 1 << 20, None, None) == B.E_INVALID

@@ -2,8 +2,9 @@
 (oracle.mlp): gradients of the mean-squared error, one Adam step, training
 that reduces the loss, prediction, and the accept-or-fall-back solve.
 
-Bars: gradients within 3e-2 relative per layer (BF16 products with FP32
-accumulation, about 2^-8 per product); the first Adam step within 5e-2 lr
+Bars: gradients within 1e-2 relative per layer (BF16 products with FP32
+accumulation, about 2^-9 per rounded operand; measured at most 3.8e-3); the
+first Adam step within 5e-2 lr
 per entry where the gradient is not negligible (Adam's first step is close to
 lr sign(g), so BF16 gradient error moves it little); fallback results equal
 the plain batched solve bit for bit."""
@@ -37,9 +38,10 @@ def test_gradient_matches_oracle():
         g, loss = B.subap_surrogate_gradient(s, to_dev(P), to_dev(T))
         lo, go = mlp.loss_and_grads(params, P, T)
         assert abs(loss - lo) <= 2e-2 * lo
-        for (gW, gb), (oW, ob) in zip(_layers(g), go):
-            for a, b in ((gW, oW), (gb, ob)):
-                assert np.linalg.norm(a - b) <= 3e-2 * np.linalg.norm(b), np.linalg.norm(a - b) / np.linalg.norm(b)
+        rel = [np.linalg.norm(a - b) / np.linalg.norm(b)
+               for (gW, gb), (oW, ob) in zip(_layers(g), go) for a, b in ((gW, oW), (gb, ob))]
+        print("gradient relative errors per layer (W, b):", ["%.2e" % v for v in rel])
+        assert max(rel) <= 1e-2, rel
     finally:
         B.subap_surrogate_free(s)
 
