@@ -1,14 +1,22 @@
 // Batched online solve over many finite-difference models of uneven size in
 // one persistent launch.  Each wavefront repeatedly takes the next work item
-// (one parameter of one instance) from a global counter and solves it with
-// the column-per-lane Householder routine of fd_cols.h (rows generated on the
+// (one parameter of one instance) from a work counter and solves it with the
+// column-per-lane Householder routine of fd_cols.h (rows generated on the
 // fly, eq. (3.4) contraction in FP64 or FP32, eq. (3.3) least squares,
 // optional FP64 refinement).  Every instance with r <= 64 and s <= 256 shares
-// the kernel; items are ordered largest instance first so the long solves
-// start early, and every wavefront leaves once the counter passes the last
-// item.  The kernel is built for two waves per SIMD and instantiated per set
-// of model dimensions (2-D, 3-D, both), so a plan of one kind carries one
-// solver.
+// the kernel.
+//
+// The instances are split into kXcds groups of about equal work (largest
+// first, each to the least-loaded group), one group per XCD: workgroups are
+// dispatched to the XCDs in turn (block b to XCD b mod 8), and a wavefront
+// takes items from its own XCD's counter first, so each XCD's L2 holds the
+// tables of its own instances.  When its group is done it takes items from
+// the other groups' counters in turn, and it leaves once every counter has
+// passed the end of its group.  Within a group, the largest instances come
+// first so the long solves start early.  The FP64 kernel is built for two
+// waves per SIMD; the refining kernel, whose solver needs more registers,
+// for one.  Both are instantiated per set of model dimensions (2-D, 3-D,
+// both), so a plan of one kind carries one solver.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,21 +53,27 @@ struct MultiInst {
 
 namespace {
 
-constexpr int kMT = 256;        // threads per block (upper bound; launch may use 64 or 128)
-constexpr int kWavesPerCU = 8;  // the kernel is built for two waves per SIMD
+constexpr int kMT = 256;  // threads per block (upper bound; launch may use 64 or 128)
+constexpr int kXcds = 8;  // XCDs of the device: one work group each
+
+// waves per CU the kernel is built for: two per SIMD, one when refining
+constexpr int waves_per_cu(bool ref) { return ref ? 4 : 8; }
 
 struct MultiArgs {
   const MultiInst* inst;
   int k;
   int64_t total;
-  unsigned long long* counter;
+  unsigned long long* counter;  // kXcds counters
+  int64_t group[kXcds + 1];     // items [group[x], group[x + 1]) belong to XCD x
   int prec;
   int refine;
   int ldsw;  // LDS doubles per wavefront
   bool csne;  // refinement by the corrected semi-normal equations
 };
 
-__global__ void k_reset(unsigned long long* c) { *c = 0ull; }
+__global__ void k_reset(unsigned long long* c) {
+  if (threadIdx.x < kXcds) c[threadIdx.x] = 0ull;
+}
 
 template <int F, int DP, bool REF>
 __device__ __forceinline__ void multi_item(const MultiInst& I, int64_t p, int prec, int refine, bool csne,
@@ -76,25 +90,32 @@ __device__ __forceinline__ void multi_item(const MultiInst& I, int64_t p, int pr
 // DIMS: bit 0 = the plan holds 2-D models, bit 1 = 3-D models; a kernel that
 // serves one kind only carries one solver and needs fewer registers.
 template <bool REF, int DIMS>
-__global__ __launch_bounds__(kMT, 2) void k_fd_multi(MultiArgs A) {
+__global__ __launch_bounds__(kMT, REF ? 1 : 2) void k_fd_multi(MultiArgs A) {
   extern __shared__ double lds[];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   double* mine = lds + static_cast<int64_t>(wave) * A.ldsw;
-  while (true) {
-    unsigned long long it = 0;
-    if (lane == 0) it = atomicAdd(A.counter, 1ull);
-    it = (static_cast<unsigned long long>(static_cast<unsigned>(__builtin_amdgcn_readfirstlane(static_cast<int>(it >> 32))))
-          << 32) |
-         static_cast<unsigned>(__builtin_amdgcn_readfirstlane(static_cast<int>(it & 0xffffffffull)));
-    if (it >= static_cast<unsigned long long>(A.total)) return;  // uniform per wavefront
+  const int home = static_cast<int>(blockIdx.x % kXcds);
+  int d = 0;  // groups passed: own first, then the others in turn
+  while (d < kXcds) {
+    const int x = (home + d) % kXcds;
+    unsigned long long c = 0;
+    if (lane == 0) c = atomicAdd(A.counter + x, 1ull);
+    c = (static_cast<unsigned long long>(static_cast<unsigned>(__builtin_amdgcn_readfirstlane(static_cast<int>(c >> 32))))
+         << 32) |
+        static_cast<unsigned>(__builtin_amdgcn_readfirstlane(static_cast<int>(c & 0xffffffffull)));
+    const int64_t it = A.group[x] + static_cast<int64_t>(c);
+    if (it >= A.group[x + 1]) {  // uniform per wavefront
+      ++d;
+      continue;
+    }
     int lo = 0, hi = A.k - 1;  // instance with begin <= it (begins are increasing)
     while (lo < hi) {
       const int mid = (lo + hi + 1) / 2;
-      if (A.inst[mid].begin <= static_cast<int64_t>(it)) lo = mid;
+      if (A.inst[mid].begin <= it) lo = mid;
       else hi = mid - 1;
     }
     const MultiInst I = A.inst[lo];
-    const int64_t p = static_cast<int64_t>(it) - I.begin;
+    const int64_t p = it - I.begin;
     if constexpr (DIMS == 1) multi_item<4, 2, REF>(I, p, A.prec, A.refine, A.csne, mine, lane);
     else if constexpr (DIMS == 2) multi_item<6, 4, REF>(I, p, A.prec, A.refine, A.csne, mine, lane);
     else if (I.F == 4) multi_item<4, 2, REF>(I, p, A.prec, A.refine, A.csne, mine, lane);
@@ -116,6 +137,7 @@ struct PlanImpl {
   int prec = 0, refine = 0;
   bool csne = false;
   int dims = 0;  // bit 0: some model is 2-D, bit 1: some model is 3-D
+  int64_t group[kXcds + 1] = {};  // item range of each XCD's group
   int threads = 256, blocks = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -143,9 +165,17 @@ MultiKernel plan_kernel(bool ref, int dims) {
 
 // counter reset + the persistent kernel, on st (also used under capture)
 void enqueue_plan(const PlanImpl* P, hipStream_t st) {
-  MultiArgs a{P->inst_d, static_cast<int>(P->inst.size()), P->total, P->counter, P->prec, P->refine,
-              cols_lds_doubles(P->max_r, P->max_s, plan_ref(P)), P->csne};
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, st, P->counter);
+  MultiArgs a{};
+  a.inst = P->inst_d;
+  a.k = static_cast<int>(P->inst.size());
+  a.total = P->total;
+  a.counter = P->counter;
+  for (int x = 0; x <= kXcds; ++x) a.group[x] = P->group[x];
+  a.prec = P->prec;
+  a.refine = P->refine;
+  a.ldsw = cols_lds_doubles(P->max_r, P->max_s, plan_ref(P));
+  a.csne = P->csne;
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, P->counter);
   hipLaunchKernelGGL(plan_kernel(plan_ref(P), P->dims), dim3(P->blocks), dim3(P->threads),
                      plan_lds(P, P->threads), st, a);
 }
@@ -204,15 +234,27 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
   std::vector<int> order(k);
   std::iota(order.begin(), order.end(), 0);
   // largest per-item cost first (s r^2 dominates)
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    const double ca = double(models[a]->s) * models[a]->r * models[a]->r;
-    const double cb = double(models[b]->s) * models[b]->r * models[b]->r;
-    return ca > cb;
-  });
+  auto item_cost = [&](int a) { return double(models[a]->s) * models[a]->r * models[a]->r; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return item_cost(a) > item_cost(b); });
+  // instances to XCD groups: largest total work first, each to the group with
+  // the least work so far; then group by group, largest items first
+  std::vector<int> by_work(order);
+  std::stable_sort(by_work.begin(), by_work.end(),
+                   [&](int a, int b) { return item_cost(a) * m[a] > item_cost(b) * m[b]; });
+  std::vector<int> grp(k, 0);
+  double load[kXcds] = {};
+  for (int oi : by_work) {
+    const int g = static_cast<int>(std::min_element(load, load + kXcds) - load);
+    grp[oi] = g;
+    load[g] += item_cost(oi) * m[oi];
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return grp[a] < grp[b]; });
   std::ostringstream key;
   key << "fd_multi/p" << prec << "/f" << refine << (csne ? "c" : "");
   int64_t begin = 0;
+  for (int x = 0; x <= kXcds; ++x) P->group[x] = 0;
   for (int oi : order) {
+    for (int x = grp[oi] + 1; x <= kXcds; ++x) P->group[x] += m[oi];
     const subap_model_s* M = models[oi];
     MultiInst I{M->r, M->s, M->F, M->d, M->phi, M->delta64T, M->delta32T, M->bS, M->inv_h2, M->bS_norm,
                 params[oi], m[oi], y[oi], rho ? rho[oi] : nullptr, status ? status[oi] : nullptr, begin};
@@ -230,7 +272,7 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
   P->key = key.str();
   subap_status rc = dalloc(&P->inst_d, P->inst.size());
   if (rc != SUBAP_OK) return fail(rc);
-  rc = dalloc(&P->counter, 1);
+  rc = dalloc(&P->counter, kXcds);
   if (rc != SUBAP_OK) return fail(rc);
   if (hipMemcpyAsync(P->inst_d, P->inst.data(), sizeof(MultiInst) * P->inst.size(), hipMemcpyHostToDevice, st) !=
           hipSuccess ||
@@ -247,10 +289,11 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  // blocks of th threads that fit one CU: LDS (160 KiB) and two waves per SIMD
+  // blocks of th threads that fit one CU: LDS (160 KiB) and the waves per
+  // SIMD the kernel is built for
   auto per_cu = [&](int th) {
     const int by_lds = static_cast<int>((160 * 1024) / std::max<size_t>(plan_lds(P, th), 1));
-    return std::max(1, std::min(by_lds, kWavesPerCU / (th / 64)));
+    return std::max(1, std::min(by_lds, waves_per_cu(plan_ref(P)) / (th / 64)));
   };
   P->threads = 128;
   P->blocks = cus * per_cu(128);

@@ -114,6 +114,46 @@ def test_autotune_cache_is_reused(uneven_small, tmp_path, monkeypatch):
             M.free()
 
 
+@pytest.mark.parametrize("prec,refine", [(B.FP64, 0), (B.FP32, 1)])
+def test_plan_with_fewer_blocks_than_xcd_groups(uneven_small, prec, refine, tmp_path, monkeypatch):
+    """The instances are split into eight groups, one per XCD (block id mod
+    8), and a wavefront takes items from its own group first, then from the
+    others.  With three blocks, five groups have no block of their own and are
+    solved only by taking items from them: every output must still equal the
+    default launch's, bit for bit (the same kernel and per-item arithmetic).
+    The shape is forced through the autotune cache."""
+    import torch
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("SUBAP_AUTOTUNE_CACHE", str(cache))
+    header(f"plan on 3 blocks prec={prec} refine={refine}")
+    models = _models(uneven_small)
+    try:
+        params = [to_dev(w["test_params"]) for w, _, _ in uneven_small]
+        dev = params[0].device
+        ref = [torch.full((w["m"], w["r"]), -7.0, dtype=torch.float64, device=dev) for w, _, _ in uneven_small]
+        p1 = B.subap_plan_create([M.handle for M in models], params, ref, contraction=prec, refine_steps=refine,
+                                 flags=B.PLAN_AUTOTUNE)
+        B.subap_plan_execute(p1)
+        torch.cuda.synchronize()
+        B.subap_plan_free(p1)
+        key = cache.read_text().split()[0]
+        cache.write_text(f"{key} 64 3\n")
+        ys = [torch.full((w["m"], w["r"]), -7.0, dtype=torch.float64, device=dev) for w, _, _ in uneven_small]
+        p2 = B.subap_plan_create([M.handle for M in models], params, ys, contraction=prec, refine_steps=refine,
+                                 flags=B.PLAN_AUTOTUNE)
+        try:
+            assert B.subap_plan_shape(p2) == (64, 3)
+            B.subap_plan_execute(p2)
+            torch.cuda.synchronize()
+        finally:
+            B.subap_plan_free(p2)
+        for a, b in zip(ys, ref):
+            assert torch.equal(a, b)
+    finally:
+        for M in models:
+            M.free()
+
+
 @pytest.fixture(scope="module")
 def cubes_small():
     # 3-D models for plans that hold 3-D instances only or mix them with 2-D ones
