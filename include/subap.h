@@ -309,11 +309,16 @@ SUBAP_API subap_status subap_reduced_matrix(subap_model model, const double* par
                                             void* hip_stream);
 
 /*
- * Batched solve over many models in one persistent launch (finite-difference
- * families).  A plan fixes the models, the parameter counts and the device
- * buffers; executing it runs Algorithm 3.1 step 4 for every parameter of
- * every model.  All buffers keep the layouts of subap_solve_batch, one per
- * model (rho_dev and status_dev may be NULL, or contain NULL entries).
+ * Batched solve over many models.  A plan fixes the models, the parameter
+ * counts and the device buffers; executing it runs Algorithm 3.1 step 4 for
+ * every parameter of every model.  The diffusion models share one persistent
+ * launch; every other member (the kernel family, the delay system, eq.
+ * (5.7), the identity family) is solved by its family's batched solver after
+ * it, on the same stream, with a workspace the plan owns.  All buffers keep
+ * the layouts of subap_solve_batch, one per model (rho_dev and status_dev may
+ * be NULL, or contain NULL entries); a member's results equal those of
+ * subap_solve_batch with the same options, bit for bit, except the diffusion
+ * members, which the persistent launch solves by Householder QR.
  *   flags  SUBAP_PLAN_GRAPH:    capture the launch in a hipGraph once and
  *                               replay it on every execute;
  *          SUBAP_PLAN_AUTOTUNE: time the candidate launch shapes (threads per

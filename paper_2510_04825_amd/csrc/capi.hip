@@ -803,8 +803,6 @@ static subap_status plan_args(const subap_model* models, int32_t k, const double
   int64_t total = 0;
   for (int i = 0; i < k; ++i) {
     if (!models[i]) return invalid("model must not be NULL");
-    if (models[i]->family != SUBAP_FAMILY_DIFF2D && models[i]->family != SUBAP_FAMILY_DIFF3D)
-      return invalid("batched plans take finite-difference models");
     if (m[i] < 0) return invalid("m must be >= 0");
     if (m[i] > 0 && (!params[i] || !y[i])) return invalid("params and y must not be NULL when m > 0");
     total += m[i];

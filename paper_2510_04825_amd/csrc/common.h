@@ -138,6 +138,8 @@ subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double
 subap_status krr_solve_ws(subap_model_s* M, const double* params, int64_t m, double* y, double* rho,
                           int32_t* status, int prec, int refine, bool csne, void* work, hipStream_t st);
 int64_t krr_chunk(const subap_model_s* M, int prec, int refine, bool csne, size_t bytes);
+// workspace bytes of krr_solve_ws for m parameters (0: no least-squares kernel for (s, r))
+size_t krr_work_bytes(const subap_model_s* M, int64_t m, int prec, int refine, bool csne);
 subap_status lift(subap_model_s* M, const double* y, int64_t k, void* x, int64_t ldx, int prec,
                   hipStream_t st);
 subap_status fd_residual(subap_model_s* M, const double* params, int64_t m, const double* y, double* res,

@@ -128,9 +128,23 @@ __global__ __launch_bounds__(kMT, REF ? 1 : 2) void k_fd_multi(MultiArgs A) {
 // ---------------------------------------------------------------------------
 // plans: instance table, launch shape (autotuned, cached), hipGraph
 // ---------------------------------------------------------------------------
+// A plan member that is not a diffusion model (the kernel family, the delay
+// system, eq. (5.7), the identity family): solved by its family's batched
+// solver, enqueued after the persistent kernel on the same stream.
+struct OtherInst {
+  subap_model_s* M;
+  const double* params;
+  int64_t m;
+  double* y;
+  double* rho;
+  int32_t* status;
+};
+
 struct PlanImpl {
-  std::vector<MultiInst> inst;   // host copy, largest first
+  std::vector<MultiInst> inst;   // host copy of the diffusion members, largest first
   MultiInst* inst_d = nullptr;
+  std::vector<OtherInst> other;  // the other members, in the caller's order
+  void* work = nullptr;          // workspace of the kernel-family members (the largest one's)
   unsigned long long* counter = nullptr;
   int64_t total = 0;
   int max_s = 0, max_r = 0;
@@ -163,8 +177,10 @@ MultiKernel plan_kernel(bool ref, int dims) {
   return tab[ref ? 1 : 0][dims - 1];
 }
 
-// counter reset + the persistent kernel, on st (also used under capture)
-void enqueue_plan(const PlanImpl* P, hipStream_t st) {
+// counter reset + the persistent kernel, then the other members' solves, on
+// st (also used under capture; nothing here allocates or synchronizes)
+subap_status enqueue_plan(const PlanImpl* P, hipStream_t st, bool others = true) {
+  if (!P->inst.empty()) {
   MultiArgs a{};
   a.inst = P->inst_d;
   a.k = static_cast<int>(P->inst.size());
@@ -178,11 +194,21 @@ void enqueue_plan(const PlanImpl* P, hipStream_t st) {
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, P->counter);
   hipLaunchKernelGGL(plan_kernel(plan_ref(P), P->dims), dim3(P->blocks), dim3(P->threads),
                      plan_lds(P, P->threads), st, a);
+  }
+  if (!others) return SUBAP_OK;
+  for (const OtherInst& o : P->other) {
+    if (o.m == 0) continue;
+    if (o.M->family == SUBAP_FAMILY_KRR)
+      SUBAP_TRY(krr_solve_ws(o.M, o.params, o.m, o.y, o.rho, o.status, P->prec, P->refine, P->csne, P->work, st));
+    else
+      SUBAP_TRY(fd_solve(o.M, o.params, o.m, o.y, o.rho, o.status, P->prec, P->refine, P->csne, st));
+  }
+  return SUBAP_OK;
 }
 
-subap_status launch_plan(PlanImpl* P, hipStream_t st) {
+subap_status launch_plan(PlanImpl* P, hipStream_t st, bool others = true) {
   ProfScope prof("fd_multi_persistent", st);
-  enqueue_plan(P, st);
+  SUBAP_TRY(enqueue_plan(P, st, others));
   SUBAP_HIP_TRY(hipGetLastError());
   return SUBAP_OK;
 }
@@ -228,11 +254,38 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
   auto fail = [&](subap_status rc) {
     dfree(P->inst_d);
     dfree(P->counter);
+    dfree(P->work);
     delete P;
     return rc;
   };
-  std::vector<int> order(k);
-  std::iota(order.begin(), order.end(), 0);
+  P->prec = prec;
+  P->refine = refine;
+  P->csne = csne && refine > 0;
+  // members the persistent kernel takes (diffusion models) and the others
+  std::vector<int> order;
+  size_t work_bytes = 0;
+  for (int i = 0; i < k; ++i) {
+    subap_model_s* M = models[i];
+    if (M->family == SUBAP_FAMILY_DIFF2D || M->family == SUBAP_FAMILY_DIFF3D) {
+      order.push_back(i);
+      continue;
+    }
+    P->other.push_back(OtherInst{M, params[i], m[i], y[i], rho ? rho[i] : nullptr, status ? status[i] : nullptr});
+    if (M->family == SUBAP_FAMILY_KRR && m[i] > 0) {
+      const size_t b = krr_work_bytes(M, m[i], prec, refine, P->csne);
+      if (b == 0) {
+        set_error("no least-squares kernel for a kernel-family member's (s, r)");
+        return fail(SUBAP_E_UNSUPPORTED);
+      }
+      work_bytes = std::max(work_bytes, b);
+    }
+  }
+  if (work_bytes > 0) {
+    char* w = nullptr;
+    subap_status rw = dalloc(&w, work_bytes);
+    if (rw != SUBAP_OK) return fail(rw);
+    P->work = w;
+  }
   // largest per-item cost first (s r^2 dominates)
   auto item_cost = [&](int a) { return double(models[a]->s) * models[a]->r * models[a]->r; };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return item_cost(a) > item_cost(b); });
@@ -266,11 +319,10 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
     key << '/' << (M->F == 4 ? 2 : 3) << 'd' << M->s << 'x' << M->r << 'x' << m[oi];
   }
   P->total = begin;
-  P->prec = prec;
-  P->refine = refine;
-  P->csne = csne && refine > 0;
   P->key = key.str();
-  subap_status rc = dalloc(&P->inst_d, P->inst.size());
+  subap_status rc = SUBAP_OK;
+  if (!P->inst.empty()) {
+  rc = dalloc(&P->inst_d, P->inst.size());
   if (rc != SUBAP_OK) return fail(rc);
   rc = dalloc(&P->counter, kXcds);
   if (rc != SUBAP_OK) return fail(rc);
@@ -319,7 +371,7 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
         float tot = 0.0f;
         for (int rep = 0; rep < 2; ++rep) {
           (void)hipEventRecord(e0, st);
-          rc = launch_plan(P, st);
+          rc = launch_plan(P, st, false);  // the persistent kernel alone
           if (rc != SUBAP_OK) return fail(rc);
           (void)hipEventRecord(e1, st);
           (void)hipEventSynchronize(e1);
@@ -340,6 +392,7 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
     P->blocks = bb;
     cache_store(P->key, bt, bb);
   }
+  }  // diffusion members
   if (flags & SUBAP_PLAN_GRAPH) {
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
@@ -348,8 +401,8 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
     }
     bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (ok) {
-      enqueue_plan(P, cs);
-      ok = hipStreamEndCapture(cs, &P->graph) == hipSuccess;
+      const subap_status er = enqueue_plan(P, cs);
+      ok = hipStreamEndCapture(cs, &P->graph) == hipSuccess && er == SUBAP_OK;
     }
     ok = ok && hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0) == hipSuccess;
     (void)hipStreamDestroy(cs);
@@ -380,6 +433,7 @@ void plan_free(PlanImpl* P) {
   if (P->graph) (void)hipGraphDestroy(P->graph);
   dfree(P->inst_d);
   dfree(P->counter);
+  dfree(P->work);
   delete P;
 }
 

@@ -962,6 +962,12 @@ int64_t krr_chunk(const subap_model_s* M, int prec, int refine, bool csne, size_
   return lo * kRefPB;
 }
 
+size_t krr_work_bytes(const subap_model_s* M, int64_t m, int prec, int refine, bool csne) {
+  Shape sh;
+  if (!pick_shape(M->s, M->r, &sh)) return 0;
+  return krr_work(M, sh, m, prec, refine, csne).total();
+}
+
 subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double* y, double* rho,
                        int32_t* status, int prec, int refine, bool csne, hipStream_t st) {
   Shape sh;

@@ -15,7 +15,10 @@ hipEvent_t profile_event();
 class ProfScope {
  public:
   ProfScope(const char* name, hipStream_t st) : name_(name), st_(st) {
-    if (profiling_enabled()) {
+    // no events inside a graph capture: the launch is recorded, not run
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (profiling_enabled() && hipStreamIsCapturing(st_, &cap) == hipSuccess &&
+        cap == hipStreamCaptureStatusNone) {
       a_ = profile_event();
       if (a_) (void)hipEventRecord(a_, st_);
     }

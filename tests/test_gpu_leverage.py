@@ -111,8 +111,6 @@ def test_residual_bounds_match_oracle_and_hold_at_select_param(lev):
 def test_weighted_model_in_a_plan(lev):
     import torch
     name, w, off, u, sc, M = lev
-    if name == "krr":
-        pytest.skip("plans hold finite-difference models")
     header(f"leverage plan {name}")
     P = to_dev(w["test_params"])
     y1, _, _ = M.solve(P)

@@ -154,6 +154,56 @@ def test_plan_with_fewer_blocks_than_xcd_groups(uneven_small, prec, refine, tmp_
             M.free()
 
 
+@pytest.mark.parametrize("prec,refine,csne", [(B.FP64, 0, False), (B.FP32, 1, True)])
+def test_plan_with_every_family(uneven_small, prec, refine, csne):
+    """A plan holding two diffusion models with a kernel-family model, the
+    delay system, eq. (5.7) and the identity family, captured in one hipGraph
+    and replayed three times with eager work between the replays.  Every other
+    member equals subap_solve_batch with the same options bit for bit (its
+    family's solver, the plan's workspace); the diffusion members stay within
+    delta_res 1e-12 (FP64) or 1e-6 (FP32 + one CSNE step) of the oracle."""
+    import torch
+    header(f"plan with every family prec={prec} refine={refine} csne={csne}")
+    dev = device()
+    ws = [si.krr(n=1024, r=8, s=24, m=40), si.delay(n=3000, r=10, s=40, m=33), si.tridiag(m=50),
+          si.identity(m=20)]
+    others = [B.Model(w, basis=O.offline(w)["Q"]) for w in ws]
+    diff = uneven_small[:2]
+    dmodels = [B.Model(w, basis=off["Q"], rows=off["rows"]) for w, off, _ in diff]
+    try:
+        models = dmodels + others
+        allw = [w for w, _, _ in diff] + ws
+        params = [to_dev(w["test_params"]) for w in allw]
+        ys = [torch.full((w["m"], w["r"]), -7.0, dtype=torch.float64, device=dev) for w in allw]
+        sts = [torch.full((w["m"],), -1, dtype=torch.int32, device=dev) for w in allw]
+        plan = B.subap_plan_create([M.handle for M in models], params, ys, None, sts, prec, refine,
+                                   B.PLAN_GRAPH, csne=csne)
+        try:
+            refs = []
+            for M, P in zip(others, params[2:]):
+                y1, _, st1 = M.solve(P, contraction=prec, refine_steps=refine, csne=csne)
+                refs.append((y1, st1))
+            for rep in range(3):
+                for y in ys:
+                    y.fill_(-7.0)
+                B.subap_plan_execute(plan)
+                torch.cuda.synchronize()
+                for (y1, st1), y, st in zip(refs, ys[2:], sts[2:]):
+                    assert torch.equal(y, y1) and torch.equal(st, st1)
+                tol = 1e-12 if prec == B.FP64 else 1e-6
+                for (w, off, yo), y, st in zip(diff, ys[:2], sts[:2]):
+                    assert np.all(st.cpu().numpy() == B.OK)
+                    d = max(On.delta_res(off["family"], off["Q"], p, a, b)
+                            for p, a, b in zip(w["test_params"], y.cpu().numpy(), yo))
+                    assert d <= tol, d
+                torch.zeros(1 << 20, device=dev).sum()  # eager work between replays
+        finally:
+            B.subap_plan_free(plan)
+    finally:
+        for M in dmodels + others:
+            M.free()
+
+
 @pytest.fixture(scope="module")
 def cubes_small():
     # 3-D models for plans that hold 3-D instances only or mix them with 2-D ones
