@@ -41,6 +41,13 @@ interest is H(p) = c^T x(p).  The paper evaluates the transfer function; here
 p is real, which keeps A(p) symmetric positive definite for p > -3 (kappa - 2)
 / tau.
 
+Affine (Section 3.1, "Computing S A(p*) X")
+-------------------------------------------
+A(theta) = sum_q theta_q A_q with given sparse terms A_q and a fixed b; the
+parameter is the coefficient vector theta itself (any theta_q(p) of a
+physical parameter p is evaluated by the caller).  The delay system is the
+two-term case A_q = (I, A_1), theta = (p, -(3 + e^{tau p})).
+
 Identity (DEIM special case, eq. (3.5))
 ---------------------------------------
 A(p) = I; b(p) = y(p) with y_i(p) = 1 / (1 + 25 (t_i - p)^2) on t_i = i/(n-1),
@@ -367,6 +374,39 @@ class Delay:
         return self._rhs[np.asarray(idx, dtype=np.int64)]
 
 
+class Affine:
+    """A(theta) = sum_q theta_q A_q, terms given as sparse matrices, b fixed."""
+
+    def __init__(self, terms, rhs):
+        self.terms = [sp.csr_matrix(T, dtype=np.float64) for T in terms]
+        self.n = self.terms[0].shape[0]
+        self.d = len(self.terms)
+        self._rhs = np.asarray(rhs, dtype=np.float64)
+
+    def matrix(self, theta):
+        th = np.asarray(theta, dtype=np.float64).reshape(-1)
+        A = th[0] * self.terms[0]
+        for t, T in zip(th[1:], self.terms[1:]):
+            A = A + t * T
+        return sp.csr_matrix(A)
+
+    def rows(self, theta, idx):
+        return self.matrix(theta)[np.asarray(idx, dtype=np.int64)]
+
+    def matvec(self, theta, x):
+        th = np.asarray(theta, dtype=np.float64).reshape(-1)
+        y = th[0] * (self.terms[0] @ x)
+        for t, T in zip(th[1:], self.terms[1:]):
+            y = y + t * (T @ x)
+        return y
+
+    def rhs(self, theta=None):
+        return self._rhs.copy()
+
+    def rhs_rows(self, theta, idx):
+        return self._rhs[np.asarray(idx, dtype=np.int64)]
+
+
 def from_workload(w: dict):
     """Build the family object described by a ``subap_inputs`` workload dict."""
     fam = w["family"]
@@ -380,4 +420,6 @@ def from_workload(w: dict):
         return Identity(w["n"])
     if fam == "delay":
         return Delay(w["n"], w["tau"], w["kappa"], w["rhs"], w.get("c_out"))
+    if fam == "affine":
+        return Affine(w["terms"], w["rhs"])
     raise ValueError(f"unknown family {fam!r}")

@@ -23,6 +23,9 @@ Section 6.3, eqs. (6.3)-(6.4)):
   p log-uniform in [0.5, 2].
 * ``uneven``       64 independent 2-D diffusion instances of varied size.
 * ``tridiag``      the shifted tridiagonal family of eq. (5.7).
+* ``affine``       a general affine family A(theta) = sum_q theta_q A_q
+  (Section 3.1, "Computing S A(p*) X"): its terms are inputs of the family,
+  given as sparse matrices, like the data points of ``krr``.
 """
 from __future__ import annotations
 
@@ -30,7 +33,7 @@ import numpy as np
 
 __all__ = [
     "diffusion2d", "diffusion3d", "krr", "uneven", "tridiag", "identity",
-    "surrogate", "sample_uniforms", "delay",
+    "surrogate", "sample_uniforms", "delay", "affine",
 ]
 
 
@@ -154,6 +157,43 @@ def identity(n: int = 200, r: int = 6, m: int = 32, seed: int = 58) -> dict:
         snap_params=g_snap.uniform(0.0, 1.0, size=(r, 1)),
         test_params=g_test.uniform(0.0, 1.0, size=(m, 1)),
         select_param=np.array([0.5]),
+    )
+
+
+def affine(N: int = 64, r: int = 12, s: int = 48, m: int = 4096, seed: int = 707) -> dict:
+    """Three-term affine family on the N x N interior grid of the unit square,
+    A(theta) = theta_0 L + theta_1 C + theta_2 R: L the 5-point negative
+    Laplacian (h^-2 scaled), C the centred first difference in x (a
+    convection term, skew-symmetric), R = diag(rho) with a seeded reaction
+    field rho in [0.5, 1.5].  A(theta) is nonsymmetric, and its symmetric part
+    theta_0 L + theta_2 R is positive definite, so it is nonsingular.  b is a
+    seeded smooth source; theta_0 in [1, 2], theta_1 in [0, 500], theta_2 in
+    [0, 5000], uniform."""
+    import scipy.sparse as sps
+    g_snap, g_test, g_field = _streams(seed, 3)
+    n = N * N
+    h = 1.0 / (N + 1)
+    one = np.ones(N)
+    d2 = sps.diags([-one[:-1], 2 * one, -one[:-1]], [-1, 0, 1])
+    eye = sps.identity(N)
+    lap = ((sps.kron(eye, d2) + sps.kron(d2, eye)) / (h * h)).tocsr()
+    d1 = sps.diags([-0.5 * one[:-1], 0.5 * one[:-1]], [-1, 1])
+    conv = (sps.kron(eye, d1) / h).tocsr()
+    x = (np.arange(N) + 1) * h
+    X, Y = np.meshgrid(x, x)
+    amp = g_field.uniform(-0.5, 0.5, size=3)
+    rho = 1.0 + amp[0] * np.sin(2 * np.pi * X) * np.cos(np.pi * Y) + amp[1] * X * Y
+    rho = np.clip(rho, 0.5, 1.5).reshape(-1)
+    react = sps.diags(rho).tocsr()
+    rhs = (np.sin(np.pi * X) * np.sin(2 * np.pi * Y) + 1.0 + 0.1 * amp[2]).reshape(-1)
+    lo = np.array([1.0, 0.0, 0.0])
+    hi = np.array([2.0, 500.0, 5000.0])
+    return dict(
+        family="affine", n=n, d=3, r=r, s=s, m=m, grid=(N, N),
+        terms=[lap, conv, react], rhs=rhs,
+        snap_params=lo + (hi - lo) * g_snap.random((r, 3)),
+        test_params=lo + (hi - lo) * g_test.random((m, 3)),
+        select_param=0.5 * (lo + hi),
     )
 
 
