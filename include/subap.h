@@ -46,8 +46,22 @@
  *   For these two families the right-hand side varies with p: the sketched
  *   residual of subap_solve_batch and subap_sketched_residual is relative to
  *   |S b(p)| and subap_delta_residual to |b(p)|.  Leverage-score selection,
- *   subap_apsnap_solve, subap_polish, plans and the surrogate are not
- *   available for them (SUBAP_E_UNSUPPORTED).
+ *   subap_apsnap_solve, subap_polish and the surrogate are not available for
+ *   them (SUBAP_E_UNSUPPORTED).
+ *   SUBAP_FAMILY_AFFINE   a general affine family (Section 3.1, "Computing
+ *                         S A(p*) X"): A(theta) = sum_q theta_q A_q with
+ *                         nterms (1..4) given sparse n x n terms and a fixed
+ *                         b = problem->rhs; the parameter is theta itself,
+ *                         d = nterms (a caller with a physical parameter p
+ *                         evaluates theta_q(p)).  The offline phase stores the
+ *                         s x r pieces S A_q X, and the online solve assembles
+ *                         S A(theta) X = sum_q theta_q S A_q X in O(nterms s r).
+ *                         The snapshot solver needs symmetric positive
+ *                         definite systems, so this family takes its basis
+ *                         from basis_in (SUBAP_E_UNSUPPORTED without it);
+ *                         rows come from rows_in or any selection at
+ *                         select_param (theta).  subap_polish and
+ *                         subap_model_save are not available for it.
  * Finite-difference layout: node (ix, iy[, iz]) sits at ((ix+1) h, ...),
  * h = 1/(N+1), index ix + N iy (+ N^2 iz); the face coefficient is a at
  * the face midpoint; row i holds sum_f a_f / h^2 on the diagonal and
@@ -98,7 +112,8 @@ typedef enum {
   SUBAP_FAMILY_KRR = 3,
   SUBAP_FAMILY_DELAY = 4,
   SUBAP_FAMILY_TRIDIAG_SHIFT = 5,
-  SUBAP_FAMILY_IDENTITY = 6
+  SUBAP_FAMILY_IDENTITY = 6,
+  SUBAP_FAMILY_AFFINE = 7
 } subap_family;
 
 /* Arithmetic of the bulk contraction S A(p) X.  The least-squares solve is
@@ -125,6 +140,14 @@ typedef struct {
   double kappa;            /* DELAY: shift kappa (> 2)                        */
   const double* c_out;     /* optional host n entries: output vector c of
                               subap_output (the transfer function's c)        */
+  /* AFFINE: nterms (1..4) terms A_q in CSR form, host arrays: row offsets
+   * term_rowptr[q] (n + 1 entries, term_rowptr[q][0] = 0, non-decreasing),
+   * column indices term_cols[q] and values term_vals[q]
+   * (term_rowptr[q][n] entries each, columns in [0, n)).                      */
+  int32_t nterms;
+  const int64_t* const* term_rowptr;
+  const int32_t* const* term_cols;
+  const double* const* term_vals;
 } subap_problem_desc;
 
 typedef struct subap_model_s* subap_model;   /* opaque; owns device buffers */

@@ -23,11 +23,12 @@ LIB_PATH = os.path.join(_HERE, "libsubap.so")
 OK, E_INVALID, E_NOMEM, E_HIP, E_RANK, E_NOCONV, E_NONFINITE, E_UNSUPPORTED = range(8)
 # subap_family
 FAMILY_DIFF2D, FAMILY_DIFF3D, FAMILY_KRR, FAMILY_DELAY, FAMILY_TRIDIAG_SHIFT, FAMILY_IDENTITY = 1, 2, 3, 4, 5, 6
+FAMILY_AFFINE = 7
 # subap_precision
 FP64, FP32, BF16X3, FP16X3 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3}
 FAMILIES = {"diff2d": FAMILY_DIFF2D, "diff3d": FAMILY_DIFF3D, "krr": FAMILY_KRR, "delay": FAMILY_DELAY,
-            "tridiag": FAMILY_TRIDIAG_SHIFT, "identity": FAMILY_IDENTITY}
+            "tridiag": FAMILY_TRIDIAG_SHIFT, "identity": FAMILY_IDENTITY, "affine": FAMILY_AFFINE}
 
 EXPORTS = ("subap_offline", "subap_solve_batch", "subap_lift", "subap_sketched_residual", "subap_model_dims",
            "subap_model_rows", "subap_model_basis", "subap_model_free", "subap_profile_enable",
@@ -48,7 +49,8 @@ SELECT_CPQR, SELECT_LEVERAGE, SELECT_LU = 0, 1, 2
 class ProblemDesc(C.Structure):
     _fields_ = [("family", C.c_int32), ("grid", C.c_int32), ("n", C.c_int64), ("dim", C.c_int32),
                 ("points", C.c_void_p), ("rhs", C.c_void_p), ("lam", C.c_double), ("tau", C.c_double),
-                ("kappa", C.c_double), ("c_out", C.c_void_p)]
+                ("kappa", C.c_double), ("c_out", C.c_void_p), ("nterms", C.c_int32),
+                ("term_rowptr", C.c_void_p), ("term_cols", C.c_void_p), ("term_vals", C.c_void_p)]
 
 
 class OfflineOpts(C.Structure):
@@ -184,17 +186,27 @@ def _host(a, dtype):
 def subap_offline(family, grid=0, n=0, dim=0, points=None, rhs=None, lam=0.0, r=1, s=1,
                   snap_params=None, select_param=None, snap_tol=0.0, snap_maxiter=0,
                   basis_in=None, rows_in=None, sample_u=None, tau=0.0, kappa=0.0, c_out=None, selection=None,
-                  select_params=None, stream=None):
+                  select_params=None, stream=None, terms=None):
     """Run the offline phase; returns the opaque model handle (int).  With
     sample_u (s uniforms in [0, 1)) the rows come from leverage-score sampling;
     selection SELECT_LU picks rows by LU with partial pivoting; select_params
-    (t x d, t > 1) takes the union of the r pivots at each point."""
+    (t x d, t > 1) takes the union of the r pivots at each point.  terms
+    (affine family): the sparse matrices A_q (anything with indptr, indices
+    and data in CSR form)."""
     lib = load()
     keep = [_host(points, np.float64), _host(rhs, np.float64), _host(snap_params, np.float64),
             _host(select_param, np.float64), _host(basis_in, np.float64), _host(rows_in, np.int64),
             _host(sample_u, np.float64), _host(c_out, np.float64), _host(select_params, np.float64)]
     addr = [None if a is None else a.ctypes.data for a in keep]
     pd = ProblemDesc(family, grid, n, dim, addr[0], addr[1], lam, tau, kappa, addr[7])
+    if terms is not None:
+        csr = [(np.ascontiguousarray(T.indptr, dtype=np.int64), np.ascontiguousarray(T.indices, dtype=np.int32),
+                np.ascontiguousarray(T.data, dtype=np.float64)) for T in terms]
+        keep.append(csr)
+        ptrs = [(C.c_void_p * len(csr))(*[c[i].ctypes.data for c in csr]) for i in range(3)]
+        keep.append(ptrs)
+        pd.nterms = len(csr)
+        pd.term_rowptr, pd.term_cols, pd.term_vals = (C.cast(a, C.c_void_p).value for a in ptrs)
     if selection is None:
         selection = SELECT_LEVERAGE if sample_u is not None else SELECT_CPQR
     nsel = 0 if select_params is None else int(np.atleast_2d(select_params).shape[0])
@@ -601,6 +613,8 @@ class Model:
             self.handle = subap_offline(fam, n=w["n"], rhs=w["b0"], **kw)
         elif fam == FAMILY_IDENTITY:
             self.handle = subap_offline(fam, n=w["n"], **kw)
+        elif fam == FAMILY_AFFINE:
+            self.handle = subap_offline(fam, n=w["n"], rhs=w["rhs"], terms=[T.tocsr() for T in w["terms"]], **kw)
         elif fam == FAMILY_DELAY:
             self.handle = subap_offline(fam, n=w["n"], rhs=w["rhs"], tau=w["tau"], kappa=w["kappa"],
                                         c_out=w.get("c_out"), **kw)

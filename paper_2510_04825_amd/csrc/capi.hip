@@ -117,7 +117,7 @@ void free_model(subap_model_s* M) {
   if (!M) return;
   void* bufs[] = {M->Q, M->rows_d, M->wS, M->cQ, M->bS, M->QS, M->rhs, M->phi, M->delta64, M->delta32, M->delta64T, M->delta32T, M->points,
                   M->Dt64, M->D32, M->Qrm, M->Q32, M->Qhi, M->Qlo, M->Qh16, M->Ql16, M->colscale_inv,
-                  M->rowdat, M->work};
+                  M->rowdat, M->work, M->aff_rp, M->aff_ci, M->aff_v};
   for (void* b : bufs) dfree(b);
   delete M;
 }
@@ -230,6 +230,33 @@ subap_status subap_offline(const subap_problem_desc* pd, const subap_offline_opt
       tmp.dimx = 1;
       tmp.d = 1;
       tmp.F = pd->family == SUBAP_FAMILY_TRIDIAG_SHIFT ? 2 : 1;
+      tmp.h = 1.0;
+      tmp.inv_h2 = 1.0;
+    } else if (pd->family == SUBAP_FAMILY_AFFINE) {
+      if (pd->n < 1 || pd->n > 2147483647LL) return invalid("affine n must be in [1, 2^31 - 1]");
+      if (pd->nterms < 1 || pd->nterms > kMaxAffineTerms) return invalid("affine nterms must be in [1, 4]");
+      if (!pd->term_rowptr || !pd->term_cols || !pd->term_vals || !pd->rhs)
+        return invalid("the affine family needs its terms and rhs");
+      for (int q = 0; q < pd->nterms; ++q) {
+        const int64_t* rp = pd->term_rowptr[q];
+        if (!rp || rp[0] != 0) return invalid("affine term row offsets must start at 0");
+        for (int64_t i = 0; i < pd->n; ++i)
+          if (rp[i + 1] < rp[i]) return invalid("affine term row offsets must not decrease");
+        const int64_t nnz = rp[pd->n];
+        if (nnz > 0 && (!pd->term_cols[q] || !pd->term_vals[q])) return invalid("affine term arrays missing");
+        for (int64_t e = 0; e < nnz; ++e)
+          if (pd->term_cols[q][e] < 0 || pd->term_cols[q][e] >= pd->n) return invalid("affine column out of range");
+        if (!all_finite(pd->term_vals[q], nnz)) return invalid("affine term values not finite");
+      }
+      if (!all_finite(pd->rhs, pd->n)) return invalid("rhs has non-finite entries");
+      if (!o->basis_in) {
+        set_error("the affine family takes its basis from basis_in (no snapshot solver for general terms)");
+        return SUBAP_E_UNSUPPORTED;
+      }
+      tmp.n = pd->n;
+      tmp.dimx = 1;
+      tmp.d = pd->nterms;
+      tmp.F = pd->nterms;
       tmp.h = 1.0;
       tmp.inv_h2 = 1.0;
     } else {
@@ -508,6 +535,10 @@ subap_status subap_polish(subap_model M, const double* params, int64_t m, double
     if (!(tol >= 0.0) || !std::isfinite(tol)) return invalid("tol must be finite and >= 0");
     if (m == 0) return SUBAP_OK;
     if (!params || !x) return invalid("params_dev and x_dev must not be NULL");
+    if (M->family == SUBAP_FAMILY_AFFINE) {
+      set_error("polishing runs conjugate gradients, which the affine family's general terms do not allow");
+      return SUBAP_E_UNSUPPORTED;
+    }
     if (rhs_varies(M->family)) {
       set_error("polishing is implemented for right-hand sides independent of p");
       return SUBAP_E_UNSUPPORTED;
@@ -555,6 +586,10 @@ subap_status subap_model_save(subap_model M, const char* path) {
   try {
     clear_error();
     if (!M || !path) return invalid("model and path must not be NULL");
+    if (M->family == SUBAP_FAMILY_AFFINE) {
+      set_error("model files do not hold the affine family's terms");
+      return SUBAP_E_UNSUPPORTED;
+    }
     const int64_t n = M->n;
     const int r = M->r, s = M->s;
     std::vector<double> Q(static_cast<size_t>(n) * r), rhs(static_cast<size_t>(n)), pts, cq;

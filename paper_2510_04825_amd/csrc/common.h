@@ -31,6 +31,7 @@ void clear_error();
 
 constexpr int kMaxR = 64;
 constexpr int kMaxS = 256;
+constexpr int kMaxAffineTerms = 4;  // terms of the affine family
 constexpr int kRowPad = 8;  // zero rows after the s rows of bS and of the diffusion delta64T
 constexpr double kRankTol = 1e-13;   // |R_jj| <= kRankTol |R_11| -> rank deficient
 constexpr double kTieRtol = 1e-6;    // pivot tie window
@@ -81,6 +82,12 @@ struct subap_model_s {
   float* delta32 = nullptr;
   double* delta64T = nullptr;         // the same at [(f * s + k) * r + c] (lanes = columns)
   float* delta32T = nullptr;
+
+  // affine family: the nterms (= F) terms, CSR, concatenated; term q's row i
+  // holds entries [aff_rp[q (n + 1) + i], aff_rp[q (n + 1) + i + 1])
+  int64_t* aff_rp = nullptr;
+  int* aff_ci = nullptr;
+  double* aff_v = nullptr;
 
   // kernel ridge regression tables
   double* points = nullptr;           // n x dimx row-major

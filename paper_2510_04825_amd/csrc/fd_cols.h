@@ -60,9 +60,11 @@ struct ColsModel {
 //                   S A(p*) X from precomputed pieces; Section 6.2.2);
 //   kCoefTridiag    F = 2, DP = 1: a_0 = -p, a_1 = 1, the pieces S Q and
 //                   S A_0 Q of A(p) = A_0 - p I (eq. (5.7));
-//   kCoefIdentity   F = 1, DP = 1: a_0 = 1, A(p) = I (DEIM, eq. (3.5)).
-// The last two have right-hand sides that depend on p (cols_rhs).
-constexpr int kCoefDiffusion = 0, kCoefDelay = 1, kCoefTridiag = 2, kCoefIdentity = 3;
+//   kCoefIdentity   F = 1, DP = 1: a_0 = 1, A(p) = I (DEIM, eq. (3.5));
+//   kCoefAffine     DP = F: a_q = theta_q, the weights of the pieces S A_q Q
+//                   of a general affine family (Section 3.1).
+// Tridiag and identity have right-hand sides that depend on p (cols_rhs).
+constexpr int kCoefDiffusion = 0, kCoefDelay = 1, kCoefTridiag = 2, kCoefIdentity = 3, kCoefAffine = 4;
 
 template <int COEF>
 constexpr bool coef_rhs_varies() {
@@ -92,6 +94,8 @@ __device__ __forceinline__ double cols_coef(const ColsModel& M, const double* pv
     return f == 0 ? -pv[0] : 1.0;
   } else if constexpr (COEF == kCoefIdentity) {
     return 1.0;
+  } else if constexpr (COEF == kCoefAffine) {
+    return pv[f];
   } else {
     double t = 0.0;
 #pragma unroll

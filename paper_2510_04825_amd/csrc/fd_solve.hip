@@ -463,6 +463,15 @@ subap_status fd_solve(subap_model_s* M, const double* params, int64_t m, double*
            M->bS_norm, y, rho, status, prec, refine, M->aff_c0, M->tau, csne, M->wS, M->rowdat};
   // eq. (5.7) and the identity family: their affine pieces (two and one) and
   // p-dependent right-hand sides, column-per-lane solver
+  // the affine family: S A(theta) Q = sum_q theta_q S A_q Q from its pieces
+  if (M->family == SUBAP_FAMILY_AFFINE) {
+    switch (M->F) {
+      case 1: return launch_cols<1, 1, kCoefAffine>(a, st);
+      case 2: return launch_cols<2, 2, kCoefAffine>(a, st);
+      case 3: return launch_cols<3, 3, kCoefAffine>(a, st);
+      default: return launch_cols<4, 4, kCoefAffine>(a, st);
+    }
+  }
   if (M->family == SUBAP_FAMILY_TRIDIAG_SHIFT) return launch_cols<2, 1, kCoefTridiag>(a, st);
   if (M->family == SUBAP_FAMILY_IDENTITY) return launch_cols<1, 1, kCoefIdentity>(a, st);
   // the delay family's two affine terms: column-per-lane solver for every
@@ -486,7 +495,12 @@ subap_status fd_residual(subap_model_s* M, const double* params, int64_t m, cons
 #define SUBAP_RESID(F_, DP_, COEF_)                                                                              \
   hipLaunchKernelGGL((k_fd_resid<F_, DP_, COEF_>), dim3(grid), dim3(256), 0, st, params, m, M->r, M->s, M->phi, \
                      M->delta64, M->bS, M->inv_h2, M->bS_norm, M->aff_c0, M->tau, M->wS, M->rowdat, y, res, norm)
-  if (M->family == SUBAP_FAMILY_DELAY) SUBAP_RESID(2, 1, kCoefDelay);
+  if (M->family == SUBAP_FAMILY_AFFINE) {
+    if (M->F == 1) SUBAP_RESID(1, 1, kCoefAffine);
+    else if (M->F == 2) SUBAP_RESID(2, 2, kCoefAffine);
+    else if (M->F == 3) SUBAP_RESID(3, 3, kCoefAffine);
+    else SUBAP_RESID(4, 4, kCoefAffine);
+  } else if (M->family == SUBAP_FAMILY_DELAY) SUBAP_RESID(2, 1, kCoefDelay);
   else if (M->family == SUBAP_FAMILY_TRIDIAG_SHIFT) SUBAP_RESID(2, 1, kCoefTridiag);
   else if (M->family == SUBAP_FAMILY_IDENTITY) SUBAP_RESID(1, 1, kCoefIdentity);
   else if (M->dimx == 2) SUBAP_RESID(4, 2, kCoefDiffusion);
@@ -504,7 +518,12 @@ subap_status fd_excess(subap_model_s* M, const double* params, int64_t m, const 
   hipLaunchKernelGGL((k_fd_excess<F_, DP_, COEF_>), dim3(grid), dim3(128), 0, st, params, m, M->r, M->s, M->phi,   \
                      M->delta64, M->delta64T, M->bS, M->inv_h2, M->bS_norm, M->aff_c0, M->tau, M->wS, M->rowdat, y, \
                      sigma_min, out)
-  if (M->family == SUBAP_FAMILY_DELAY) SUBAP_EXC(2, 1, kCoefDelay);
+  if (M->family == SUBAP_FAMILY_AFFINE) {
+    if (M->F == 1) SUBAP_EXC(1, 1, kCoefAffine);
+    else if (M->F == 2) SUBAP_EXC(2, 2, kCoefAffine);
+    else if (M->F == 3) SUBAP_EXC(3, 3, kCoefAffine);
+    else SUBAP_EXC(4, 4, kCoefAffine);
+  } else if (M->family == SUBAP_FAMILY_DELAY) SUBAP_EXC(2, 1, kCoefDelay);
   else if (M->family == SUBAP_FAMILY_TRIDIAG_SHIFT) SUBAP_EXC(2, 1, kCoefTridiag);
   else if (M->family == SUBAP_FAMILY_IDENTITY) SUBAP_EXC(1, 1, kCoefIdentity);
   else if (M->dimx == 2) SUBAP_EXC(4, 2, kCoefDiffusion);
@@ -520,7 +539,12 @@ subap_status fd_reduced_matrix(subap_model_s* M, const double* params, int64_t m
 #define SUBAP_GM(F_, DP_, COEF_)                                                                                  \
   hipLaunchKernelGGL((k_fd_gmat<F_, DP_, COEF_>), dim3(grid), dim3(256), 0, st, params, m, M->r, M->s, M->phi,    \
                      M->delta64T, M->inv_h2, M->aff_c0, M->tau, G)
-  if (M->family == SUBAP_FAMILY_DELAY) SUBAP_GM(2, 1, kCoefDelay);
+  if (M->family == SUBAP_FAMILY_AFFINE) {
+    if (M->F == 1) SUBAP_GM(1, 1, kCoefAffine);
+    else if (M->F == 2) SUBAP_GM(2, 2, kCoefAffine);
+    else if (M->F == 3) SUBAP_GM(3, 3, kCoefAffine);
+    else SUBAP_GM(4, 4, kCoefAffine);
+  } else if (M->family == SUBAP_FAMILY_DELAY) SUBAP_GM(2, 1, kCoefDelay);
   else if (M->family == SUBAP_FAMILY_TRIDIAG_SHIFT) SUBAP_GM(2, 1, kCoefTridiag);
   else if (M->family == SUBAP_FAMILY_IDENTITY) SUBAP_GM(1, 1, kCoefIdentity);
   else if (M->dimx == 2) SUBAP_GM(4, 2, kCoefDiffusion);

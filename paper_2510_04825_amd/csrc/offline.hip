@@ -36,6 +36,10 @@ struct OpArgs {
   double lambda;
   const double* points;   // KRR n x dimx
   double tau, kappa, c0;  // delay family
+  int nterms;             // affine family: F terms, CSR (see subap_model_s)
+  const int64_t* aff_rp;
+  const int* aff_ci;
+  const double* aff_v;
 };
 
 __device__ __forceinline__ void fd_node(int64_t i, int N, int dimx, int* c) {
@@ -152,6 +156,31 @@ __global__ void k_rhs_cols(int family, int64_t n, const double* b0, const double
   B[static_cast<int64_t>(col) * n + i] = v;
 }
 
+// affine family: Y[i, c] = sum_q theta_{c,q} (A_q X[:, c])_i, one thread per
+// row and column; diag_out = the diagonal of A(theta_c)
+__global__ void k_affine_apply(OpArgs A, const double* params, int ncol, const double* X, double* Y,
+                               double* diag_out) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int col = blockIdx.y;
+  if (i >= A.n || col >= ncol) return;
+  const double* x = X ? X + static_cast<int64_t>(col) * A.n : nullptr;
+  double y = 0.0, dg = 0.0;
+  for (int q = 0; q < A.nterms; ++q) {
+    const double th = params[static_cast<int64_t>(col) * A.nterms + q];
+    const int64_t* rp = A.aff_rp + static_cast<int64_t>(q) * (A.n + 1);
+    double t = 0.0, tdg = 0.0;
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+      const int j = A.aff_ci[e];
+      if (x) t = fma(A.aff_v[e], x[j], t);
+      if (j == i) tdg += A.aff_v[e];
+    }
+    y = fma(th, t, y);
+    dg = fma(th, tdg, dg);
+  }
+  if (Y) Y[static_cast<int64_t>(col) * A.n + i] = y;
+  if (diag_out) diag_out[static_cast<int64_t>(col) * A.n + i] = dg;
+}
+
 // KRR: Y[i, c] = sum_j exp(-|t_i - t_j|^2 / (2 p_c^2)) X[j, c] + lambda X[i, c]
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_krr_apply(OpArgs A, const double* params, int ncol,
@@ -202,6 +231,8 @@ subap_status apply_op(const OpArgs& A, const double* params_d, int ncol, const d
         set_error("KRR point dimension must be 1..16");
         return SUBAP_E_INVALID;
     }
+  } else if (A.family == SUBAP_FAMILY_AFFINE) {
+    hipLaunchKernelGGL(k_affine_apply, grid, dim3(kBlock), 0, st, A, params_d, ncol, X, Y, diag);
   } else if (A.family == SUBAP_FAMILY_DELAY) {
     hipLaunchKernelGGL(k_delay_apply, grid, dim3(kBlock), 0, st, A, params_d, ncol, X, Y, diag);
   } else if (rhs_varies(A.family)) {
@@ -1100,6 +1131,31 @@ __global__ void k_copy_rows_i32(const int64_t* a, int* b, int s) {
   if (k < s) b[k] = static_cast<int>(a[k]);
 }
 
+// affine family: the pieces T_q = W S A_q Q at [(q s + k) r + c] (and the
+// other layouts), W S b and W S Q; one thread per (row k, column c)
+__global__ void k_affine_tables(const double* Qm, int64_t n, int r, int s, int F, const int* rows, const double* wS,
+                                const double* rhs, const int64_t* rp, const int* ci, const double* v,
+                                double* delta64, float* delta32, double* delta64T, float* delta32T, double* bS,
+                                double* QS) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= static_cast<int64_t>(s) * r) return;
+  const int k = static_cast<int>(t / r), cc = static_cast<int>(t % r);
+  const int64_t i = rows[k];
+  const double wk = wS[k];
+  for (int f = 0; f < F; ++f) {
+    const int64_t* rq = rp + static_cast<int64_t>(f) * (n + 1);
+    double acc = 0.0;
+    for (int64_t e = rq[i]; e < rq[i + 1]; ++e) acc = fma(v[e], Qm[static_cast<int64_t>(cc) * n + ci[e]], acc);
+    const double dv = wk * acc;
+    delta64[(static_cast<int64_t>(f) * r + cc) * s + k] = dv;
+    delta32[(static_cast<int64_t>(f) * r + cc) * s + k] = static_cast<float>(dv);
+    delta64T[(static_cast<int64_t>(f) * s + k) * r + cc] = dv;
+    delta32T[(static_cast<int64_t>(f) * s + k) * r + cc] = static_cast<float>(dv);
+  }
+  QS[static_cast<int64_t>(k) * r + cc] = wk * Qm[static_cast<int64_t>(cc) * n + i];
+  if (cc == 0) bS[k] = wk * rhs[i];
+}
+
 }  // namespace
 
 subap_status build_tables(subap_model_s* M, hipStream_t st) {
@@ -1142,6 +1198,16 @@ subap_status build_tables(subap_model_s* M, hipStream_t st) {
     SUBAP_TRY(dalloc(&M->rowdat, s));
     hipLaunchKernelGGL(k_shift_tables, dim3((s + 63) / 64), dim3(64), 0, st, M->family, M->Q, n, r, s, M->rows_d,
                        M->wS, M->rhs, M->delta64, M->delta32, M->delta64T, M->delta32T, M->bS, M->QS, M->rowdat);
+  } else if (M->family == SUBAP_FAMILY_AFFINE) {
+    const size_t tab = static_cast<size_t>(s) * M->F;
+    SUBAP_TRY(dalloc(&M->delta64, tab * r));
+    SUBAP_TRY(dalloc(&M->delta32, tab * r));
+    SUBAP_TRY(dalloc(&M->delta64T, tab * r));
+    SUBAP_TRY(dalloc(&M->delta32T, tab * r));
+    const int64_t cnt = static_cast<int64_t>(s) * r;
+    hipLaunchKernelGGL(k_affine_tables, dim3(static_cast<unsigned>((cnt + 255) / 256)), dim3(256), 0, st, M->Q, n,
+                       r, s, M->F, M->rows_d, M->wS, M->rhs, M->aff_rp, M->aff_ci, M->aff_v, M->delta64, M->delta32,
+                       M->delta64T, M->delta32T, M->bS, M->QS);
   } else if (M->family == SUBAP_FAMILY_DELAY) {
     const size_t tab = static_cast<size_t>(s) * M->F;
     SUBAP_TRY(dalloc(&M->delta64, tab * r));
@@ -1247,7 +1313,7 @@ static subap_status select_leverage(const OpArgs& A, subap_model_s* M, const sub
 
 static OpArgs op_args(const subap_model_s* M) {
   return OpArgs{M->family, M->N, M->dimx, M->n, M->d, M->h, M->inv_h2, M->lambda, M->points, M->tau, M->kappa,
-                M->aff_c0};
+                M->aff_c0, M->F, M->aff_rp, M->aff_ci, M->aff_v};
 }
 
 // columns per pass so that one n x cols FP64 work array stays near 2 GiB
@@ -1450,7 +1516,31 @@ subap_status offline_build(const subap_problem_desc* pd, const subap_offline_opt
     }
     M->dmax = 4.0 * rmax;
   }
-  OpArgs A{M->family, M->N, M->dimx, n, d, M->h, M->inv_h2, M->lambda, M->points, M->tau, M->kappa, M->aff_c0};
+  if (M->family == SUBAP_FAMILY_AFFINE) {  // the terms, concatenated
+    const int F = M->F;
+    std::vector<int64_t> rp(static_cast<size_t>(F) * (n + 1));
+    int64_t nnz = 0;
+    for (int q = 0; q < F; ++q) {
+      for (int64_t i = 0; i <= n; ++i) rp[static_cast<size_t>(q) * (n + 1) + i] = nnz + pd->term_rowptr[q][i];
+      nnz += pd->term_rowptr[q][n];
+    }
+    SUBAP_TRY(dalloc(&M->aff_rp, rp.size()));
+    SUBAP_TRY(dalloc(&M->aff_ci, static_cast<size_t>(std::max<int64_t>(nnz, 1))));
+    SUBAP_TRY(dalloc(&M->aff_v, static_cast<size_t>(std::max<int64_t>(nnz, 1))));
+    SUBAP_HIP_TRY(hipMemcpyAsync(M->aff_rp, rp.data(), sizeof(int64_t) * rp.size(), hipMemcpyHostToDevice, st));
+    int64_t off = 0;
+    for (int q = 0; q < F; ++q) {
+      const int64_t c = pd->term_rowptr[q][n];
+      if (c > 0) {
+        SUBAP_HIP_TRY(hipMemcpyAsync(M->aff_ci + off, pd->term_cols[q], sizeof(int) * c, hipMemcpyHostToDevice, st));
+        SUBAP_HIP_TRY(hipMemcpyAsync(M->aff_v + off, pd->term_vals[q], sizeof(double) * c, hipMemcpyHostToDevice, st));
+      }
+      off += c;
+    }
+    SUBAP_HIP_TRY(hipStreamSynchronize(st));  // the host arrays may go once the call returns
+  }
+  OpArgs A{M->family, M->N, M->dimx, n, d, M->h, M->inv_h2, M->lambda, M->points, M->tau, M->kappa, M->aff_c0,
+           M->F, M->aff_rp, M->aff_ci, M->aff_v};
 
   DevVec X, params, diagR, W, pdup;
   SUBAP_TRY(dalloc(&X.p, static_cast<size_t>(n) * r));

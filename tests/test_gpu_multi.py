@@ -157,7 +157,8 @@ def test_plan_with_fewer_blocks_than_xcd_groups(uneven_small, prec, refine, tmp_
 @pytest.mark.parametrize("prec,refine,csne", [(B.FP64, 0, False), (B.FP32, 1, True)])
 def test_plan_with_every_family(uneven_small, prec, refine, csne):
     """A plan holding two diffusion models with a kernel-family model, the
-    delay system, eq. (5.7) and the identity family, captured in one hipGraph
+    delay system, eq. (5.7), the identity family and an affine family,
+    captured in one hipGraph
     and replayed three times with eager work between the replays.  Every other
     member equals subap_solve_batch with the same options bit for bit (its
     family's solver, the plan's workspace); the diffusion members stay within
@@ -166,7 +167,7 @@ def test_plan_with_every_family(uneven_small, prec, refine, csne):
     header(f"plan with every family prec={prec} refine={refine} csne={csne}")
     dev = device()
     ws = [si.krr(n=1024, r=8, s=24, m=40), si.delay(n=3000, r=10, s=40, m=33), si.tridiag(m=50),
-          si.identity(m=20)]
+          si.identity(m=20), si.affine(N=16, r=6, s=18, m=24)]
     others = [B.Model(w, basis=O.offline(w)["Q"]) for w in ws]
     diff = uneven_small[:2]
     dmodels = [B.Model(w, basis=off["Q"], rows=off["rows"]) for w, off, _ in diff]
