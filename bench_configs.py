@@ -48,14 +48,14 @@ FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 TRAFFIC = {
     # k_fd_gram<6, 4, 3, 2>, one launch of 65,536 parameters
     "diffusion3d": {"kernel": "fd_gram", "sources": ("fd_solve.hip", "fd_gram.h", "fd_cols.h", "common.h"),
-                    "sha256_16": "1847a2fbf8651915", "fetch_kib": 3163.0, "write_kib": 21504.0},
-    # k_fd_cols<2, 1, false, false, 1, 40>, one launch of 65,536 parameters
-    "delay": {"sources": ("fd_solve.hip", "fd_cols.h", "common.h"), "sha256_16": "a92a869da535684e",
-              "fetch_kib": 2201.1, "write_kib": 7168.0},
+                    "sha256_16": "8c54ac5054cc933b", "fetch_kib": 3183.9, "write_kib": 21504.0},
+    # k_fd_cols_packed<2, 1, kCoefDelay, 40>, one launch of 65,536 parameters
+    "delay": {"sources": ("fd_solve.hip", "fd_cols.h", "common.h"), "sha256_16": "f4c9ab08e6747158",
+              "fetch_kib": 774.1, "write_kib": 5888.0},
     # k_fd_multi<false, 1>, one replay over the 64 instances (autotuned shape),
     # instances grouped per XCD
-    "uneven": {"sources": ("fd_multi.hip", "fd_cols.h", "common.h"), "sha256_16": "94f51490d85a156a",
-               "fetch_kib": 9546.8, "write_kib": 15993.4},
+    "uneven": {"sources": ("fd_multi.hip", "fd_cols.h", "common.h"), "sha256_16": "e49ed0a6527b46ef",
+               "fetch_kib": 9537.0, "write_kib": 15989.6},
     # k_lift_x6<3>, 1,024 vectors on 215^3 nodes with a 32-aligned leading dimension
     # (FETCH: mean over the three leading dimensions, which differ by under 0.2%)
     "lift": {"sources": ("lift.hip", "common.h"), "sha256_16": "1816906d6d95b44a",
@@ -909,8 +909,7 @@ def delay(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
         "forms": forms, "offline_s": offline_s, "leverage_selection_s_given_basis": lev_s,
         "lu_selection_s_given_basis": lu_s, "lu_union_selection_s_given_basis": union_s,
         "table4_columns": table,
-        "roofline": {"bound": "mfma" if kname == "fd_gram" else "alu", "kernel": kname,
-                     "achieved": flops / (kms * 1e-3) / 1e12,
+        "roofline": {"bound": "alu", "kernel": "fd_solve", "achieved": flops / (kms * 1e-3) / 1e12,
                      "peak": PEAKS["fp64_tflops"], "unit": "TFLOP/s",
                      "frac": flops / (kms * 1e-3) / 1e12 / PEAKS["fp64_tflops"],
                      "traffic": _traffic("delay") if (r, s) == (10, 40) else None},

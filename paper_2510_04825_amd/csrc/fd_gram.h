@@ -96,9 +96,11 @@ __device__ __forceinline__ double gram_bload(__amdgpu_buffer_rsrc_t rs, unsigned
 // The F x T table entries of one row group for this lane: face f's rows of
 // the group start at the wave-uniform byte offset soff + f fbytes, and the
 // lane adds its own loop-invariant offset (row g of the group, column
-// min(16 I + c, r - 1)), so no vector address arithmetic is needed per group.
-// Rows past s read the next face or the zero rows after the table
-// (kRowPad), which the zero coefficients of those rows cancel.
+// 16 I + c), so no vector address arithmetic is needed per group.  A lane
+// whose column is past r has an offset beyond the table: the buffer's range
+// check returns 0 without a memory access.  Rows past s read the next face
+// or the zero rows after the table (kRowPad), which the zero coefficients of
+// those rows cancel.
 template <int F, int T>
 __device__ __forceinline__ void gram_load(__amdgpu_buffer_rsrc_t rs, unsigned soff, unsigned fbytes,
                                           const unsigned (&vo)[T], double (&d)[F][T]) {
@@ -111,7 +113,7 @@ __device__ __forceinline__ void gram_load(__amdgpu_buffer_rsrc_t rs, unsigned so
 // the rows of one group (4 qq + g of the chunk) for the P parameters
 template <int F, int T, int P, bool GRAM>
 __device__ __forceinline__ void gram_group(const double (&d)[F][T], double bk, const double* coef, int kr, int bI,
-                                           int c16, const double (&cm)[T], gram_v4d (&acc)[P][T * (T + 1) / 2],
+                                           int c16, gram_v4d (&acc)[P][T * (T + 1) / 2],
                                            const double (&yreg)[P][T], double (&gacc)[P][T], double (&rr)[P]) {
 #pragma unroll
   for (int u = 0; u < P; ++u) {
@@ -124,7 +126,7 @@ __device__ __forceinline__ void gram_group(const double (&d)[F][T], double bk, c
       double t = 0.0;
 #pragma unroll
       for (int f = 0; f < F; ++f) t = fma(a[f], d[f][I], t);
-      Gv[I] = (I == bI) ? fma(cm[I], t, bk) : cm[I] * t;
+      Gv[I] = (I == bI) ? t + bk : t;
     }
     if constexpr (GRAM) {
       int t = 0;
@@ -147,10 +149,12 @@ __device__ __forceinline__ void gram_group(const double (&d)[F][T], double bk, c
 
 // one pass over the s rows.  GRAM: accumulate G~^T G~ tiles.  Otherwise
 // res_k = G~_k (y, -1) (= (G y - S b)_k), gacc += G~^T res per lane column,
-// rr += |res|^2 (counted once per row, by the lanes with c = 0).  The masks
-// multiply the results, so the T F loads of a group issue together,
-// unconditionally.  (Holding the next group's loads in a second register
-// buffer costs a wavefront per SIMD of occupancy, which measured slower.)
+// rr += |res|^2 (counted once per row, by the lanes with c = 0).  The T F
+// loads of a group issue together, unconditionally, and two register
+// buffers alternate: the next group's loads are in flight while one
+// computes.  (With one parameter per wavefront the second buffer cost a
+// wavefront per SIMD of occupancy and measured slower; with two, the
+// kernel sits at two wavefronts per SIMD either way.)
 template <int F, int DP, int T, int P, bool GRAM>
 __device__ __forceinline__ void gram_pass(const ColsModel& M, const double (&pv)[P][DP], double* coef, int lane,
                                           gram_v4d (&acc)[P][T * (T + 1) / 2], const double (&yreg)[P][T],
@@ -160,12 +164,9 @@ __device__ __forceinline__ void gram_pass(const ColsModel& M, const double (&pv)
   const unsigned fbytes = 8u * static_cast<unsigned>(s) * r, gbytes = 32u * r;  // a face, a row group
   const __amdgpu_buffer_rsrc_t rs = gram_rsrc(M.d64T, fbytes * F + 8u * kRowPad * r);
   unsigned vo[T];
-  double cm[T];
 #pragma unroll
-  for (int I = 0; I < T; ++I) {
-    vo[I] = 8u * static_cast<unsigned>(g * r + min(16 * I + c16, r - 1));
-    cm[I] = (16 * I + c16 < r) ? 1.0 : 0.0;
-  }
+  for (int I = 0; I < T; ++I)  // past the table for columns >= r (the range check gives 0)
+    vo[I] = (16 * I + c16 < r) ? 8u * static_cast<unsigned>(g * r + 16 * I + c16) : 0x80000000u;
   const double bm = (c16 == (r & 15)) ? 1.0 : 0.0;
   for (int c0 = 0; c0 < s; c0 += 64) {
     {
@@ -179,12 +180,24 @@ __device__ __forceinline__ void gram_pass(const ColsModel& M, const double (&pv)
     wave_sync_lds();
     const int nq = min(16, (s - c0 + 3) / 4);
     const unsigned s0 = 8u * static_cast<unsigned>(c0) * r;
-    for (int qq = 0; qq < nq; ++qq) {
+    double dA[F][T], dB[F][T];
+    gram_load<F, T>(rs, s0, fbytes, vo, dA);
+    double bA = M.bS[c0 + g], bB;
+    for (int qq = 0; qq < nq; qq += 2) {
       const int k = c0 + 4 * qq + g;
-      double dA[F][T];
-      gram_load<F, T>(rs, s0 + qq * gbytes, fbytes, vo, dA);
-      const double bA = M.bS[k];
-      gram_group<F, T, P, GRAM>(dA, (k < s ? bm : 0.0) * bA, coef, 4 * qq + g, bI, c16, cm, acc, yreg, gacc, rr);
+      gram_load<F, T>(rs, s0 + (qq + 1) * gbytes, fbytes, vo, dB);
+      bB = M.bS[k + 4];
+      // keep these loads here (no instruction, no wait): otherwise they are
+      // moved to their use in the next group
+      asm volatile("" ::: "memory");
+      gram_group<F, T, P, GRAM>(dA, (k < s ? bm : 0.0) * bA, coef, 4 * qq + g, bI, c16, acc, yreg, gacc, rr);
+      if (qq + 1 < nq) {
+        gram_load<F, T>(rs, s0 + (qq + 2) * gbytes, fbytes, vo, dA);
+        bA = M.bS[k + 8];
+        asm volatile("" ::: "memory");
+        gram_group<F, T, P, GRAM>(dB, (k + 4 < s ? bm : 0.0) * bB, coef, 4 * qq + 4 + g, bI, c16, acc, yreg,
+                                  gacc, rr);
+      }
     }
     wave_sync_lds();  // the next chunk's coefficients overwrite these
   }
