@@ -58,8 +58,12 @@ TRAFFIC = {
                "fetch_kib": 9537.0, "write_kib": 15989.6},
     # k_lift_x6<3>, 1,024 vectors on 215^3 nodes with a 32-aligned leading dimension
     # (FETCH: mean over the three leading dimensions, which differ by under 0.2%)
-    "lift": {"sources": ("lift.hip", "common.h"), "sha256_16": "1816906d6d95b44a",
-             "fetch_kib": 1768981.0, "write_kib": 39753504.0},
+    "lift": {"sources": ("lift.hip", "common.h"), "sha256_16": "69e6a51647f357b3",
+             "fetch_kib": 1767024.8, "write_kib": 39753504.0},
+    # k_refine_partial<32, 7>, the first refinement pass of 4,096 parameters
+    # (FETCH: median of the warm dispatches)
+    "krr": {"kernel": "krr_refine_partial", "sources": ("krr.hip", "common.h"),
+            "sha256_16": "9599e497e31069a8", "fetch_kib": 14646.6, "write_kib": 32768.0},
 }
 
 
