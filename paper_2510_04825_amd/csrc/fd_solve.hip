@@ -373,10 +373,11 @@ subap_status launch_gram_t(const FDArgs& a, hipStream_t st) {
     return SUBAP_E_INVALID;
   }
   const int ldsw = gram_lds_doubles(a.r, kGramP, F);
+  const size_t lds = sizeof(double) * 2 * static_cast<size_t>(ldsw);
   {
     ProfScope prof("fd_gram", st);
-    hipLaunchKernelGGL((k_fd_gram<F, DP, T, kGramP>), dim3(static_cast<unsigned>(nb)), dim3(128),
-                       sizeof(double) * 2 * static_cast<size_t>(ldsw), st, a, ldsw);
+    hipLaunchKernelGGL((k_fd_gram<F, DP, T, kGramP>), dim3(static_cast<unsigned>(nb)), dim3(128), lds, st, a,
+                       ldsw);
     SUBAP_HIP_TRY(hipGetLastError());
   }
   const int ldsc = cols_lds_doubles(a.r, a.s, false);
