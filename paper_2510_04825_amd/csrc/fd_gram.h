@@ -177,11 +177,13 @@ __device__ __forceinline__ void gram_coef_load(const double* coef, int kr, doubl
     for (int f = 0; f < F; ++f) a[u][f] = coef[(u * 64 + kr) * F + f];
 }
 
-// the rows of one group (lane row g of rows 4 qq .. 4 qq + 3) for the P parameters
+// the rows of one group (lane row g of rows 4 qq .. 4 qq + 3) for the P
+// parameters; S b is column r, in the last tile (T is the least number of
+// 16-column tiles that hold r + 1 columns), and bk is 0 in the other lanes
 template <int F, int T, int P, bool GRAM>
-__device__ __forceinline__ void gram_group(const double (&d)[F][T], double bk, const double (&a)[P][F], int bI,
-                                           int c16, gram_v4d (&acc)[P][T * (T + 1) / 2],
-                                           const double (&yreg)[P][T], double (&gacc)[P][T], double (&rr)[P]) {
+__device__ __forceinline__ void gram_group(const double (&d)[F][T], double bk, const double (&a)[P][F],
+                                           gram_v4d (&acc)[P][T * (T + 1) / 2], const double (&yreg)[P][T],
+                                           double (&gacc)[P][T], double (&rr)[P]) {
 #pragma unroll
   for (int u = 0; u < P; ++u) {
     double Gv[T];
@@ -190,8 +192,9 @@ __device__ __forceinline__ void gram_group(const double (&d)[F][T], double bk, c
       double t = 0.0;
 #pragma unroll
       for (int f = 0; f < F; ++f) t = fma(a[u][f], d[f][I], t);
-      Gv[I] = (I == bI) ? t + bk : t;
+      Gv[I] = t;
     }
+    Gv[T - 1] += bk;
     if constexpr (GRAM) {
       int t = 0;
 #pragma unroll
@@ -206,15 +209,15 @@ __device__ __forceinline__ void gram_group(const double (&d)[F][T], double bk, c
       const double res = gram_row_sum(dot);
 #pragma unroll
       for (int I = 0; I < T; ++I) gacc[u][I] = fma(Gv[I], res, gacc[u][I]);
-      rr[u] = fma(res * (c16 == 0 ? 1.0 : 0.0), res, rr[u]);
+      rr[u] = fma(res, res, rr[u]);  // in all 16 lanes of the row
     }
   }
 }
 
 // one pass over the s rows in 64-row chunks of groups of four.  GRAM:
 // accumulate G~^T G~ tiles.  Otherwise res_k = G~_k (y, -1) (= (G y - S
-// b)_k), gacc += G~^T res per lane column, rr += |res|^2 (counted once per
-// row, by the lanes with c = 0).  The table loads of a group issue
+// b)_k), gacc += G~^T res per lane column, rr += |res|^2 (in each of the 16
+// lanes of the row: a wave sum of rr counts every row 16 times, exactly).  The table loads of a group issue
 // together, unconditionally, one group ahead: two register buffers
 // alternate.  (With one parameter per wavefront the second buffer
 // cost a wavefront per SIMD of occupancy and measured slower; with two, the
@@ -224,7 +227,6 @@ __device__ __forceinline__ void gram_pass(const ColsModel& M, const double (&pv)
                                           gram_v4d (&acc)[P][T * (T + 1) / 2], const double (&yreg)[P][T],
                                           double (&gacc)[P][T], double (&rr)[P]) {
   const int r = M.r, s = M.s, g = lane >> 4, c16 = lane & 15;
-  const int bI = r >> 4;  // tile of S b
   const unsigned fbytes = 8u * static_cast<unsigned>(s) * r, gbytes = 32u * r;  // a face, a row group
   const __amdgpu_buffer_rsrc_t rs = gram_rsrc(M.d64T, fbytes * F + 8u * kRowPad * r);
   unsigned vo[T];
@@ -250,13 +252,13 @@ __device__ __forceinline__ void gram_pass(const ColsModel& M, const double (&pv)
       // moved to their use in the next group
       asm volatile("" ::: "memory");
       gram_coef_load<F, P>(coef, 4 * qq + g, a);
-      gram_group<F, T, P, GRAM>(dA, (k < s ? bm : 0.0) * bA, a, bI, c16, acc, yreg, gacc, rr);
+      gram_group<F, T, P, GRAM>(dA, (k < s ? bm : 0.0) * bA, a, acc, yreg, gacc, rr);
       if (qq + 1 < nq) {
         gram_load<F, T>(rs, s0 + (qq + 2) * gbytes, fbytes, vo, dA);
         bA = M.bS[k + 8];
         asm volatile("" ::: "memory");
         gram_coef_load<F, P>(coef, 4 * qq + 4 + g, a);
-        gram_group<F, T, P, GRAM>(dB, (k + 4 < s ? bm : 0.0) * bB, a, bI, c16, acc, yreg, gacc, rr);
+        gram_group<F, T, P, GRAM>(dB, (k + 4 < s ? bm : 0.0) * bB, a, acc, yreg, gacc, rr);
       }
     }
     wave_sync_lds();  // the next chunk's coefficients overwrite these
@@ -520,7 +522,7 @@ __device__ __forceinline__ void gram_solve(const ColsModel& M, const double* par
     for (int u = 0; u < P; ++u) {
       if (done[u]) continue;
       if (lane < r) yv[u] += dy[u];
-      const double rrs = gram_wave_sum(rr[u]);
+      const double rrs = gram_wave_sum(rr[u]) * 0.0625;  // every row counted by its 16 lanes
       const double ww = gram_wave_sum(lane < r ? w[u] * w[u] : 0.0);
       const double ndy = sqrt(gram_wave_sum(lane < r ? dy[u] * dy[u] : 0.0));
       const double ny = sqrt(gram_wave_sum(lane < r ? yv[u] * yv[u] : 0.0));

@@ -396,6 +396,8 @@ bool gram_applies(const FDArgs& a) {
   return a.prec == SUBAP_FP64 && a.refine == 0 && a.r > kPackMaxR && a.r + 1 <= 48;
 }
 
+// T is the least number of 16-column tiles holding the r + 1 columns of
+// [G | S b] (r >= 16 here), so S b always sits in tile T - 1
 template <int F, int DP>
 subap_status launch_gram(const FDArgs& a, hipStream_t st) {
   if (a.r + 1 <= 32) return launch_gram_t<F, DP, 2>(a, st);
