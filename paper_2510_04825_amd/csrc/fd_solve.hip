@@ -204,20 +204,30 @@ __global__ __launch_bounds__(128, 2) void k_fd_gram(FDArgs A, int ldsw) {
 }
 
 // The parameters the matrix-core solve deferred (first coefficient
-// kGramDefer), solved by column-per-lane Householder; a grid-stride loop over
-// all parameters.  Its occupancy does not matter (it solves few parameters),
-// so it takes the registers that keep the solver from spilling.
+// kGramDefer), solved by column-per-lane Householder.  Each wavefront checks
+// 64 parameters with one load per lane and solves the marked ones in turn
+// (usually none); a grid-stride loop covers any batch.  Its occupancy does
+// not matter (it solves few parameters), so it takes the registers that keep
+// the solver from spilling.
 template <int F, int DP>
 __global__ __launch_bounds__(128, 1) void k_fd_gram_fixup(FDArgs A, int ldsw) {
   extern __shared__ double lds_fix[];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const ColsModel M{A.r, A.s, A.phi, A.delta64T, A.delta32T, A.bS, A.inv_h2, A.bS_norm, A.aff_c0, A.aff_tau,
                     A.wS, A.rowdat};
-  for (int64_t p = static_cast<int64_t>(blockIdx.x) * 2 + wave; p < A.m; p += static_cast<int64_t>(gridDim.x) * 2) {
-    if (static_cast<unsigned long long>(__double_as_longlong(A.y[p * A.r])) != kGramDefer) continue;
-    cols_solve<F, DP, false, false>(M, A.params + p * DP, SUBAP_FP64, 0, false,
-                                    lds_fix + static_cast<int64_t>(wave) * ldsw, A.s, lane, A.y + p * A.r,
-                                    A.rho ? A.rho + p : nullptr, A.status ? A.status + p : nullptr);
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * 128;
+  for (int64_t base = (static_cast<int64_t>(blockIdx.x) * 2 + wave) * 64; base < A.m; base += stride) {
+    const int64_t p = base + lane;
+    const bool mark =
+        p < A.m && static_cast<unsigned long long>(__double_as_longlong(A.y[p * A.r])) == kGramDefer;
+    unsigned long long todo = __ballot(mark);  // wave-uniform
+    while (todo != 0) {
+      const int64_t q = base + __builtin_ctzll(todo);
+      todo &= todo - 1;
+      cols_solve<F, DP, false, false>(M, A.params + q * DP, SUBAP_FP64, 0, false,
+                                      lds_fix + static_cast<int64_t>(wave) * ldsw, A.s, lane, A.y + q * A.r,
+                                      A.rho ? A.rho + q : nullptr, A.status ? A.status + q : nullptr);
+    }
   }
 }
 
@@ -381,7 +391,7 @@ subap_status launch_gram_t(const FDArgs& a, hipStream_t st) {
     SUBAP_HIP_TRY(hipGetLastError());
   }
   const int ldsc = cols_lds_doubles(a.r, a.s, false);
-  const unsigned grid = static_cast<unsigned>(std::min<int64_t>((a.m + 1) / 2, 2048));
+  const unsigned grid = static_cast<unsigned>(std::min<int64_t>((a.m + 127) / 128, 2048));  // 64 per wave
   ProfScope prof("fd_gram_fixup", st);
   hipLaunchKernelGGL((k_fd_gram_fixup<F, DP>), dim3(grid), dim3(128), sizeof(double) * 2 * static_cast<size_t>(ldsc),
                      st, a, ldsc);
