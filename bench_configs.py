@@ -48,10 +48,10 @@ FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 TRAFFIC = {
     # k_fd_gram<6, 4, 3, 2>, one launch of 65,536 parameters
     "diffusion3d": {"kernel": "fd_gram", "sources": ("fd_solve.hip", "fd_gram.h", "fd_cols.h", "common.h"),
-                    "sha256_16": "8c5c232efec7c615", "fetch_kib": 3296.0, "write_kib": 21504.0},
+                    "sha256_16": "828160b902714c1a", "fetch_kib": 3290.0, "write_kib": 21504.0},
     # k_fd_cols_packed<2, 1, kCoefDelay, 40>, one launch of 65,536 parameters
-    "delay": {"sources": ("fd_solve.hip", "fd_cols.h", "common.h"), "sha256_16": "f4c9ab08e6747158",
-              "fetch_kib": 774.1, "write_kib": 5888.0},
+    "delay": {"sources": ("fd_solve.hip", "fd_cols.h", "common.h"), "sha256_16": "531f7abd4a8983e2",
+              "fetch_kib": 774.0, "write_kib": 5888.0},
     # k_fd_multi<false, 1>, one replay over the 64 instances (autotuned shape),
     # instances grouped per XCD
     "uneven": {"sources": ("fd_multi.hip", "fd_cols.h", "common.h"), "sha256_16": "e49ed0a6527b46ef",
