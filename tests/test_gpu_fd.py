@@ -169,14 +169,16 @@ def test_rank_deficient_rows_report_rank_status():
 
 
 @pytest.mark.parametrize("dim,N,r,s,m", [(2, 32, 16, 100, 37), (2, 40, 32, 131, 21), (3, 16, 40, 96, 9),
-                                         (3, 20, 40, 191, 15), (2, 32, 31, 97, 6), (3, 20, 47, 256, 13)])
+                                         (3, 20, 40, 191, 15), (2, 32, 31, 97, 6), (3, 20, 47, 256, 13),
+                                         (3, 16, 24, 120, 11)])
 def test_fd_tall_fp64_shapes(dim, N, r, s, m):
     """FP64 solves of tall problems (s >= 96: the matrix-core semi-normal
     solve for 16 <= r <= 47) with ragged row groups, an odd batch and a
     non-finite parameter; y within delta_res 1e-12 of the oracle and rho equal
     to the oracle's sketched residual.  r = 31 puts S b in the last column of
     the second 16-column tile; r = 47, s = 256 in 3-D takes the largest
-    factors (three 16-column tiles full) and four full 64-row chunks."""
+    factors (three 16-column tiles full) and four full 64-row chunks; r = 24
+    in 3-D is the two-tile build with six faces."""
     w = si.diffusion2d(N=N, r=r, s=s, m=m) if dim == 2 else si.diffusion3d(N=N, r=r, s=s, m=m)
     off = O.offline(w)
     fam, Q, rows = off["family"], off["Q"], off["rows"]
