@@ -3,7 +3,7 @@
 diffusion3d  (default) 3-D diffusion, 7-point stencil, N^3 nodes (N = 215:
              n = 9,938,375), r = 40, s = 160, 65,536 parameters in one launch:
              the fused FP64 solve, FP32 + one step of the corrected
-             semi-normal equations, a persistent graph-replayed plan, and the
+             semi-normal equations, a graph-replayed one-model plan, and the
              lift x = Q y of 1,024 of them (FP32).
 krr          kernel ridge regression, n = 16384 points in R^8, r = 32, s = 128,
              4096 length scales: FP64, FP32 and split 16-bit MFMA
@@ -48,22 +48,22 @@ FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 TRAFFIC = {
     # k_fd_gram<6, 4, 3, 2>, one launch of 65,536 parameters
     "diffusion3d": {"kernel": "fd_gram", "sources": ("fd_solve.hip", "fd_gram.h", "fd_cols.h", "common.h"),
-                    "sha256_16": "828160b902714c1a", "fetch_kib": 3290.0, "write_kib": 21504.0},
+                    "sha256_16": "98741737007ee15e", "fetch_kib": 3290.0, "write_kib": 21504.0},
     # k_fd_cols_packed<2, 1, kCoefDelay, 40>, one launch of 65,536 parameters
-    "delay": {"sources": ("fd_solve.hip", "fd_cols.h", "common.h"), "sha256_16": "531f7abd4a8983e2",
+    "delay": {"sources": ("fd_solve.hip", "fd_cols.h", "common.h"), "sha256_16": "04c8f2b6bc170919",
               "fetch_kib": 774.0, "write_kib": 5888.0},
     # k_fd_multi<false, 1>, one replay over the 64 instances (autotuned shape),
     # instances grouped per XCD
-    "uneven": {"sources": ("fd_multi.hip", "fd_cols.h", "common.h"), "sha256_16": "e49ed0a6527b46ef",
-               "fetch_kib": 9537.0, "write_kib": 15989.6},
+    "uneven": {"sources": ("fd_multi.hip", "fd_cols.h", "common.h"), "sha256_16": "3ba66b0d4ff7f187",
+               "fetch_kib": 9524.3, "write_kib": 16006.0},
     # k_lift_x6<3>, 1,024 vectors on 215^3 nodes with a 32-aligned leading dimension
     # (FETCH: mean over the three leading dimensions, which differ by under 0.2%)
-    "lift": {"sources": ("lift.hip", "common.h"), "sha256_16": "69e6a51647f357b3",
-             "fetch_kib": 1767024.8, "write_kib": 39753504.0},
+    "lift": {"sources": ("lift.hip", "common.h"), "sha256_16": "75f9582b60f48d80",
+             "fetch_kib": 1768804.0, "write_kib": 39753504.0},
     # k_refine_partial<32, 7>, the first refinement pass of 4,096 parameters
-    # (FETCH: median of the warm dispatches)
+    # (FETCH: median of the dispatches)
     "krr": {"kernel": "krr_refine_partial", "sources": ("krr.hip", "common.h"),
-            "sha256_16": "9599e497e31069a8", "fetch_kib": 14646.6, "write_kib": 32768.0},
+            "sha256_16": "34063b52bb9e6991", "fetch_kib": 14642.3, "write_kib": 32768.0},
 }
 
 
@@ -170,10 +170,11 @@ def _gpu_delta(B, M, P, y, y_ref, st, tol, torch, dev, sample=None, seed=5):
 def diffusion3d(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
     """The default line: 3-D diffusion on N^3 nodes (N = 215: n = 9,938,375),
     r = 40, s = 160, 65,536 parameters in one launch.  Headline form: the
-    fused FP64 solve (k_fd_cols).  Also timed: FP32 contraction + one step of
-    the corrected semi-normal equations, the same FP64 batch as a persistent
-    graph-replayed plan, the plain per-parameter solve, and the FP32 lift of
-    1,024 solutions."""
+    fused FP64 solve (k_fd_gram, the semi-normal equations on the FP64 matrix
+    cores).  Also timed: FP32 contraction + one step of the corrected
+    semi-normal equations, the same FP64 batch as a graph-replayed one-model
+    plan, the plain per-parameter solve, and the FP32 lift of 1,024
+    solutions."""
     N = args.grid
     w = si.diffusion3d(N=N)
     m, n, r, s = w["m"], w["n"], w["r"], w["s"]
@@ -247,7 +248,8 @@ def diffusion3d(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
                            **_gpu_delta(B, M, P, y, y64, st, TOL, torch, dev, sample=256)}
     tp = _plain(B, M, P, r, min(256, args.plain_sample), stream, timed, torch, dev)
     forms["fp64_per_p_plain"] = {"solves_per_s": 1e3 / tp}
-    # the same FP64 batch as one persistent, graph-captured launch (a one-model plan)
+    # the same FP64 batch as a graph-captured one-model plan (a plan gives this
+    # shape to the matrix-core solve, not to its persistent launch)
     plan = B.subap_plan_create([M.handle], [P], [y], [rho], [st], B.FP64, 0, B.PLAN_GRAPH | B.PLAN_AUTOTUNE,
                                stream)
     B.subap_plan_execute(plan, stream)
@@ -255,9 +257,10 @@ def diffusion3d(args, B, si, torch, dev, stream, timed, PEAKS, TOL):
     t = timed(lambda: B.subap_plan_execute(plan, stream), args.steps, stream)
     threads, blocks = B.subap_plan_shape(plan)
     B.subap_plan_free(plan)
-    forms["fp64_persistent_plan_graph"] = {"ms_per_batch": t, "solves_per_s": m / (t / 1e3),
-                                           **_gpu_delta(B, M, P, y, y64, st, TOL, torch, dev, sample=256),
-                                           "autotuned_shape": {"threads": threads, "blocks": blocks}}
+    forms["fp64_plan_graph"] = {"ms_per_batch": t, "solves_per_s": m / (t / 1e3),
+                                **_gpu_delta(B, M, P, y, y64, st, TOL, torch, dev, sample=256),
+                                "persistent_launch": ({"threads": threads, "blocks": blocks} if blocks > 0
+                                                      else None)}
     # lift of 1024 coefficient vectors to FP32 x (column-major, n rows per column):
     # leading dimension n (odd for this grid) and n rounded up to 32 (line-aligned
     # columns); bytes = Q read once (FP64) + x written once + y

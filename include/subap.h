@@ -335,13 +335,17 @@ SUBAP_API subap_status subap_reduced_matrix(subap_model model, const double* par
  * Batched solve over many models.  A plan fixes the models, the parameter
  * counts and the device buffers; executing it runs Algorithm 3.1 step 4 for
  * every parameter of every model.  The diffusion models share one persistent
- * launch; every other member (the kernel family, the delay system, eq.
- * (5.7), the identity family) is solved by its family's batched solver after
- * it, on the same stream, with a workspace the plan owns.  All buffers keep
- * the layouts of subap_solve_batch, one per model (rho_dev and status_dev may
- * be NULL, or contain NULL entries); a member's results equal those of
- * subap_solve_batch with the same options, bit for bit, except the diffusion
- * members, which the persistent launch solves by Householder QR.
+ * launch, except those that subap_solve_batch gives to the matrix-core
+ * semi-normal solve (FP64 without refinement, s >= 96, 16 <= r <= 47) with
+ * at least 16 parameters per compute unit (4096 on MI355X); those and every
+ * other member (the kernel family, the delay system, eq. (5.7),
+ * the identity and affine families) are solved by their family's batched
+ * solver after it, on the same stream, with a workspace the plan owns.  All
+ * buffers keep the layouts of subap_solve_batch, one per model (rho_dev and
+ * status_dev may be NULL, or contain NULL entries); a member's results equal
+ * those of subap_solve_batch with the same options, bit for bit, except the
+ * diffusion members of the persistent launch, which it solves by Householder
+ * QR.
  *   flags  SUBAP_PLAN_GRAPH:    capture the launch in a hipGraph once and
  *                               replay it on every execute;
  *          SUBAP_PLAN_AUTOTUNE: time the candidate launch shapes (threads per
@@ -363,7 +367,8 @@ SUBAP_API subap_status subap_plan_create(const subap_model* models, int32_t k, c
                                          int32_t* const* status_dev, const subap_solve_opts* opts,
                                          int32_t flags, void* hip_stream, subap_plan* out);
 SUBAP_API subap_status subap_plan_execute(subap_plan plan, void* hip_stream);
-/* Launch shape in use (after autotuning): threads per block, blocks. */
+/* Launch shape of the persistent launch in use (after autotuning): threads
+ * per block, blocks; blocks is 0 when no member takes the persistent launch. */
 SUBAP_API subap_status subap_plan_shape(subap_plan plan, int32_t* threads, int32_t* blocks);
 SUBAP_API subap_status subap_plan_free(subap_plan plan);
 SUBAP_API subap_status subap_solve_multi(const subap_model* models, int32_t k, const double* const* params_dev,

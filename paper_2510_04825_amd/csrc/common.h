@@ -136,6 +136,9 @@ subap_status polish(subap_model_s* M, const double* params, int64_t m, double* x
 // applying the stored factorisation of the rounded G.
 subap_status fd_solve(subap_model_s* M, const double* params, int64_t m, double* y,
                       double* rho, int32_t* status, int prec, int refine, bool csne, hipStream_t st);
+// true when fd_solve takes the matrix-core semi-normal solve for this model
+// and form (a diffusion model, FP64 without refinement, s >= 96, 16 <= r <= 47)
+bool fd_solve_on_matrix_cores(const subap_model_s* M, int prec, int refine);
 subap_status exp2_rate(int form, int64_t evals, double* rate, hipStream_t st);
 subap_status krr_solve(subap_model_s* M, const double* params, int64_t m, double* y,
                        double* rho, int32_t* status, int prec, int refine, bool csne, hipStream_t st);

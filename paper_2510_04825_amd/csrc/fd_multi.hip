@@ -128,9 +128,16 @@ __global__ __launch_bounds__(kMT, REF ? 1 : 2) void k_fd_multi(MultiArgs A) {
 // ---------------------------------------------------------------------------
 // plans: instance table, launch shape (autotuned, cached), hipGraph
 // ---------------------------------------------------------------------------
-// A plan member that is not a diffusion model (the kernel family, the delay
-// system, eq. (5.7), the identity family): solved by its family's batched
-// solver, enqueued after the persistent kernel on the same stream.
+// A plan member that the persistent kernel does not take: a model of another
+// family (the kernel family, the delay system, eq. (5.7), the identity
+// family, the affine family), or a diffusion model whose form fd_solve gives
+// to the matrix-core semi-normal solve (FP64 without refinement, s >= 96,
+// 16 <= r <= 47) with a batch that fills that kernel's first round on the
+// device (two parameters per wavefront, eight wavefronts per CU); smaller
+// ones stay in the persistent launch, where they overlap the other members
+// instead of adding an underfilled launch after it.  Each is solved by its
+// family's batched solver, enqueued after the persistent kernel on the same
+// stream.
 struct OtherInst {
   subap_model_s* M;
   const double* params;
@@ -264,9 +271,17 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
   // members the persistent kernel takes (diffusion models) and the others
   std::vector<int> order;
   size_t work_bytes = 0;
+  int cus = 256;
+  {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  }
+  const int64_t gram_min_m = int64_t(16) * cus;
   for (int i = 0; i < k; ++i) {
     subap_model_s* M = models[i];
-    if (M->family == SUBAP_FAMILY_DIFF2D || M->family == SUBAP_FAMILY_DIFF3D) {
+    if ((M->family == SUBAP_FAMILY_DIFF2D || M->family == SUBAP_FAMILY_DIFF3D) &&
+        !(m[i] >= gram_min_m && fd_solve_on_matrix_cores(M, prec, refine))) {
       order.push_back(i);
       continue;
     }
@@ -338,9 +353,6 @@ subap_status plan_build(subap_model_s* const* models, int k, const double* const
     set_error("cannot reserve LDS for the persistent kernel");
     return fail(SUBAP_E_HIP);
   }
-  int dev = 0, cus = 256;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   // blocks of th threads that fit one CU: LDS (160 KiB) and the waves per
   // SIMD the kernel is built for
   auto per_cu = [&](int th) {

@@ -399,11 +399,10 @@ subap_status launch_gram_t(const FDArgs& a, hipStream_t st) {
   return SUBAP_OK;
 }
 
-// The FP64 form without refinement for the diffusion families at
+// The FP64 form without refinement of tall row sets (s >= 96) at
 // 16 <= r <= 47 (G~ = [G | S b] fits three 16-column tiles).
-template <int F, int DP>
-bool gram_applies(const FDArgs& a) {
-  return a.prec == SUBAP_FP64 && a.refine == 0 && a.r > kPackMaxR && a.r + 1 <= 48;
+bool gram_form(int prec, int refine, int r, int s) {
+  return s >= 96 && prec == SUBAP_FP64 && refine == 0 && r > kPackMaxR && r + 1 <= 48;
 }
 
 // T is the least number of 16-column tiles holding the r + 1 columns of
@@ -457,7 +456,7 @@ subap_status dispatch(const FDArgs& a, hipStream_t st) {
   // tall problems: column-per-lane Householder (any precision and refinement).
   // The corrected semi-normal equations need R^T R solves, which only the
   // column-per-lane solver does.
-  if (s >= 96 && gram_applies<F, DP>(a)) return launch_gram<F, DP>(a, st);
+  if (gram_form(a.prec, a.refine, r, s)) return launch_gram<F, DP>(a, st);
   if (s >= 96 || (a.csne && a.refine > 0)) return launch_cols<F, DP>(a, st);
 #define SUBAP_FD(TEAM, R, RM) \
   if (s <= TEAM * R && r <= RM) return launch<TEAM, R, RM, F, DP>(a, st);
@@ -499,6 +498,11 @@ subap_status fd_solve(subap_model_s* M, const double* params, int64_t m, double*
     return launch_cols<2, 1, kCoefDelay>(a, st);
   }
   return M->dimx == 2 ? dispatch<4, 2>(a, st) : dispatch<6, 4>(a, st);
+}
+
+bool fd_solve_on_matrix_cores(const subap_model_s* M, int prec, int refine) {
+  return (M->family == SUBAP_FAMILY_DIFF2D || M->family == SUBAP_FAMILY_DIFF3D) &&
+         gram_form(prec, refine, M->r, M->s);
 }
 
 subap_status fd_residual(subap_model_s* M, const double* params, int64_t m, const double* y, double* res,

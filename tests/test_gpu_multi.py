@@ -308,3 +308,78 @@ def test_uneven_full_size_sampled(tmp_path, monkeypatch):
     finally:
         for M in models:
             M.free()
+
+
+@pytest.fixture(scope="module")
+def tall_small():
+    # diffusion models whose FP64 form without refinement the matrix-core
+    # semi-normal solve takes (s >= 96, 16 <= r <= 47): a 3-D one with 16
+    # parameters per CU (a plan routes it to that solve; the oracle checks
+    # every 16th parameter) and a 2-D one with 21 (it stays in the
+    # persistent launch)
+    import torch
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = []
+    for w, step in ((si.diffusion3d(N=12, r=20, s=100, m=16 * cus, seed=710), 16),
+                    (si.diffusion2d(N=24, r=24, s=104, m=21, seed=711), 1)):
+        off = O.offline(w)
+        sample = np.arange(0, w["m"], step)
+        out.append((w, off, sample, On.solve(off["family"], off["Q"], off["rows"], w["test_params"][sample])))
+    return out
+
+
+def _check_oracle(w, off, sample, yo, y, tol):
+    yg = y.cpu().numpy()
+    d = max(On.delta_res(off["family"], off["Q"], w["test_params"][j], yg[j], b) for j, b in zip(sample, yo))
+    assert d <= tol, (w["r"], w["s"], d)
+
+
+@pytest.mark.parametrize("prec,refine,tol", [(B.FP64, 0, 1e-12), (B.FP32, 1, 1e-6)])
+def test_plan_gives_tall_members_to_the_matrix_core_solve(uneven_small, tall_small, prec, refine, tol):
+    """A graph-captured plan of a large tall model, a small tall model and one
+    other diffusion member.  In FP64 without refinement the large tall model
+    leaves the persistent launch for the matrix-core semi-normal solve: it
+    equals subap_solve_batch bit for bit, on three replays with eager work
+    between them.  Every member is held to the oracle (the large one on every
+    16th parameter); in the refined form all stay in the persistent launch."""
+    import torch
+    header(f"plan with tall members prec={prec} refine={refine}")
+    dev = device()
+    w0, off0, yo0 = uneven_small[0]
+    cases = list(tall_small) + [(w0, off0, np.arange(w0["m"]), yo0)]
+    models = [B.Model(w, basis=off["Q"], rows=off["rows"]) for w, off, _, _ in cases]
+    try:
+        params = [to_dev(w["test_params"]) for w, _, _, _ in cases]
+        ys = [torch.full((w["m"], w["r"]), -7.0, dtype=torch.float64, device=dev) for w, _, _, _ in cases]
+        sts = [torch.full((w["m"],), -1, dtype=torch.int32, device=dev) for w, _, _, _ in cases]
+        plan = B.subap_plan_create([M.handle for M in models], params, ys, None, sts, prec, refine, B.PLAN_GRAPH)
+        try:
+            y1, _, st1 = models[0].solve(params[0], contraction=prec, refine_steps=refine)
+            for rep in range(3):
+                for y in ys:
+                    y.fill_(-7.0)
+                B.subap_plan_execute(plan)
+                torch.cuda.synchronize()
+                for (w, off, sample, yo), y, st in zip(cases, ys, sts):
+                    assert np.all(st.cpu().numpy() == B.OK)
+                    _check_oracle(w, off, sample, yo, y, tol)
+                if prec == B.FP64:
+                    assert torch.equal(ys[0], y1) and torch.equal(sts[0], st1)
+                torch.zeros(1 << 20, device=dev).sum()  # eager work between replays
+        finally:
+            B.subap_plan_free(plan)
+        if prec == B.FP64:
+            # a plan of the large tall model alone has no persistent launch
+            plan = B.subap_plan_create([models[0].handle], params[:1], ys[:1], None, sts[:1], prec, refine,
+                                       B.PLAN_GRAPH)
+            try:
+                ys[0].fill_(-7.0)
+                B.subap_plan_execute(plan)
+                torch.cuda.synchronize()
+                assert B.subap_plan_shape(plan)[1] == 0
+                assert torch.equal(ys[0], y1)
+            finally:
+                B.subap_plan_free(plan)
+    finally:
+        for M in models:
+            M.free()
