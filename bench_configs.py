@@ -48,7 +48,7 @@ FETCH_FACTOR, WRITE_FACTOR = 2.0, 1.0
 TRAFFIC = {
     # k_fd_gram<6, 4, 3, 2>, one launch of 65,536 parameters
     "diffusion3d": {"kernel": "fd_gram", "sources": ("fd_solve.hip", "fd_gram.h", "fd_cols.h", "common.h"),
-                    "sha256_16": "98741737007ee15e", "fetch_kib": 3290.0, "write_kib": 21504.0},
+                    "sha256_16": "23e9f512621a25b8", "fetch_kib": 3290.0, "write_kib": 21504.0},
     # k_fd_cols_packed<2, 1, kCoefDelay, 40>, one launch of 65,536 parameters
     "delay": {"sources": ("fd_solve.hip", "fd_cols.h", "common.h"), "sha256_16": "04c8f2b6bc170919",
               "fetch_kib": 774.0, "write_kib": 5888.0},

@@ -16,25 +16,25 @@
 // each 16-column tile I, which is the operand layout of
 // v_mfma_f64_16x16x4f64 (A[m][kk] and B[kk][n] at lane 16 kk + m / n), so
 // G~^T G~ accumulates with no data movement: one MFMA per tile pair (I <= J)
-// per four rows.  The face coefficients of all s rows are computed once,
-// lanes over rows, into LDS, and both passes over the rows read them back as
-// broadcasts one group ahead.  P parameters share every load of the
-// difference table.
+// per four rows.  The face coefficients of 64 rows at a time are computed
+// with lanes over rows into LDS (in each pass: the LDS holds the two factors
+// and one 64-row chunk, which keeps four blocks per CU) and read back as
+// broadcasts.  P parameters share every load of the difference table.
 //
 // The Cholesky factorisation runs with lanes over columns (column c of the
 // Gram matrix in registers of lane c), one pivot row per parameter broadcast
 // through LDS per step; the P factorisations advance together.  The pivots
 // take the hardware reciprocal square root with Newton corrections.  The
 // triangular solves keep vectors distributed one entry per lane: each lane
-// loads its column (R^T w = v) or its row (R y = v) of R,
-// scaled by its own 1 / R_jj, into registers eight entries ahead, so a step
-// is one lane broadcast and one FMA, and the P parameters' solves
-// interleave.  The residual pass reduces each row over its 16 lanes with DPP
+// loads its column (R^T w = v) or its row (R y = v) of R, scaled by its own
+// 1 / R_jj, into registers eight entries ahead, so a step is one lane
+// broadcast and one FMA, and the P parameters' solves interleave.  The residual pass reduces each row over its 16 lanes with DPP
 // row rotations; wave-wide sums add the four row sums by lane reads.
 //
 // A parameter whose Cholesky pivot falls below kGramPivTol times the largest
-// column norm (kappa beyond about 1e6), whose corrected steps do not settle,
-// or whose result is not finite is left to the column-per-lane Householder
+// column norm (kappa beyond about 1e6), whose Gram diagonal leaves [1e-200,
+// 1e200], whose corrected steps do not settle, or whose result is not finite
+// is left to the column-per-lane Householder
 // solver: its first output coefficient is set to kGramDefer and no status or
 // residual is written.  Non-finite parameters get SUBAP_E_NONFINITE directly.
 #pragma once
